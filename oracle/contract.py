@@ -1,0 +1,154 @@
+"""Renormalised-operator contractions of the two-site sweep, by definition.
+
+With the MPO written as operator-valued matrices W^(k) whose site operators
+already carry the Jordan-Wigner parity strings, every product below is a plain
+tensor (Kronecker) product, so the paper's "MPO multiplication reproducing the
+DMRG equations" (Sec. II.C.1) becomes:
+
+  sigma[l', s1', s2', r'] = sum_{a,b,c} sum_{l,s1,s2,r}
+        L_a[l', l] W1_ab[s1', s1] W2_bc[s2', s2] R_c[r', r] psi[l, s1, s2, r]
+
+  L'_b[m, n] = sum_{a, s, t, x, y} A[x, s, m] L_a[x, y] W_ab[s, t] A[y, t, n]
+  R'_a[m, n] = sum_{b, s, t, x, y} B[m, s, x] W_ab[s, t] R_b[x, y] B[n, t, y]
+
+  diag(H_eff)[l, s1, s2, r] = sum_{a,b,c} L_a[l,l] W1_ab[s1,s1] W2_bc[s2,s2] R_c[r,r]
+
+Each is one einsum over dense zero-padded arrays (the library primitive decides
+the pairwise order; no blocking is done here).  `sigma_rows` evaluates selected
+output rows of the first formula at full size, summing over b in order.
+"""
+
+import numpy as np
+
+from .mps import bond_offsets
+
+
+def dense_env(ops, bond):
+    offs, D = bond_offsets(bond)
+    idx = {q: i for i, (q, _) in enumerate(bond)}
+    out = np.zeros((len(ops), D, D))
+    for a, op in enumerate(ops):
+        for isrc, blk in op["blocks"].items():
+            q = bond[isrc][0]
+            idst = idx[(q[0] + op["dq"][0], q[1] + op["dq"][1])]
+            out[a, offs[idst]:offs[idst] + blk.shape[0], offs[isrc]:offs[isrc] + blk.shape[1]] = blk
+    return out
+
+
+def env_blocks_from_dense(arr, bond, dqs):
+    offs, _ = bond_offsets(bond)
+    idx = {q: i for i, (q, _) in enumerate(bond)}
+    ops = []
+    for a, dq in enumerate(dqs):
+        blocks = {}
+        for isrc, (q, m) in enumerate(bond):
+            qd = (q[0] + dq[0], q[1] + dq[1])
+            if qd in idx:
+                idst = idx[qd]
+                blocks[isrc] = arr[a, offs[idst]:offs[idst] + bond[idst][1], offs[isrc]:offs[isrc] + m].copy()
+        ops.append({"dq": tuple(dq), "blocks": blocks})
+    return ops
+
+
+def dense_mpo(entries, nrow, ncol):
+    w = np.zeros((nrow, ncol, 4, 4))
+    for a, b, op in entries:
+        w[a, b] += op
+    return w
+
+
+def heff_apply(Ld, W1, W2, Rd, psi):
+    """sigma for dense L[a,l',l], W1[a,b,s',s], W2[b,c,t',t], R[c,r',r], psi[l,s,t,r]."""
+    return np.einsum("axy,abst,bcuv,czw,ytvw->xsuz", Ld, W1, W2, Rd, psi, optimize=True)
+
+
+def heff_diag(Ld, W1, W2, Rd):
+    return np.einsum("axx,abss,bcuu,czz->xsuz", Ld, W1, W2, Rd, optimize=True)
+
+
+def heff_matrix_kron(Ld, W1, W2, Rd):
+    """Brute force: H_eff = sum_abc kron(L_a, W1_ab, W2_bc, R_c) (tiny sizes only)."""
+    n = Ld.shape[1] * 16 * Rd.shape[1]
+    H = np.zeros((n, n))
+    for a in range(Ld.shape[0]):
+        for b in range(W1.shape[1]):
+            if not np.any(W1[a, b]):
+                continue
+            for c in range(Rd.shape[0]):
+                if not np.any(W2[b, c]):
+                    continue
+                H += np.kron(np.kron(np.kron(Ld[a], W1[a, b]), W2[b, c]), Rd[c])
+    return H
+
+
+def env_update_left(Ld, W, A):
+    """L'_b = sum A^T (L_a (x) W_ab) A with A[l, s, m] (dense)."""
+    return np.einsum("xsm,axy,abst,ytn->bmn", A, Ld, W, A, optimize=True)
+
+
+def env_update_right(Rd, W, B):
+    """R'_a = sum B (W_ab (x) R_b) B^T with B[m, s, x] (dense)."""
+    return np.einsum("msx,abst,bxy,nty->amn", B, W, Rd, B, optimize=True)
+
+
+def sigma_rows(lbond, rbond, L, W1e, W2e, R, psi, rows):
+    """Selected rows of sigma at any size, straight from the block formats.
+
+    rows: list of (il', s1', x) -- left sector, first site state, row within block.
+    Returns {(il', s1', x): {(s2', ir'): row vector of length dim(ir')}}.
+    Sums run over b in increasing order; within b over (a, s1) then (c, s2).
+    """
+    lidx = {q: i for i, (q, _) in enumerate(lbond)}
+    ridx = {q: i for i, (q, _) in enumerate(rbond)}
+    by_b1 = {}
+    for a, b, op in W1e:
+        by_b1.setdefault(b, []).append((a, op))
+    by_b2 = {}
+    for b, c, op in W2e:
+        by_b2.setdefault(b, []).append((c, op))
+    psi_by_l = {}
+    for (il, s1, s2, ir), blk in psi.items():
+        psi_by_l.setdefault((il, s1), []).append((s2, ir, blk))
+    out = {}
+    for (ilp, s1p, x) in rows:
+        qlp = lbond[ilp][0]
+        acc = {}
+        for b in sorted(set(by_b1) & set(by_b2)):
+            # u_b[(il, s1)] = sum_a W1_ab[s1', s1] L_a[l' <- l][x, :]
+            u = {}
+            for a, op in by_b1[b]:
+                dq = L[a]["dq"]
+                ql = (qlp[0] - dq[0], qlp[1] - dq[1])
+                if ql not in lidx:
+                    continue
+                il = lidx[ql]
+                if il not in L[a]["blocks"]:
+                    continue
+                lrow = L[a]["blocks"][il][x]
+                for s1 in range(4):
+                    if op[s1p, s1] != 0.0:
+                        key = (il, s1)
+                        u[key] = u.get(key, 0.0) + op[s1p, s1] * lrow
+            if not u:
+                continue
+            # v_b[(s2, ir)] = sum_{il,s1} u . psi[il, s1, s2, ir]
+            v = {}
+            for (il, s1), vec in u.items():
+                for s2, ir, blk in psi_by_l.get((il, s1), []):
+                    v[(s2, ir)] = v.get((s2, ir), 0.0) + vec @ blk
+            # acc[(s2', ir')] += sum_{c,s2} W2_bc[s2', s2] v[(s2, ir)] R_c[r' <- r]^T
+            for c, op in by_b2[b]:
+                dq = R[c]["dq"]
+                for (s2, ir), vec in v.items():
+                    if ir not in R[c]["blocks"]:
+                        continue
+                    qr = rbond[ir][0]
+                    irp = ridx.get((qr[0] + dq[0], qr[1] + dq[1]))
+                    if irp is None:
+                        continue
+                    contrib = R[c]["blocks"][ir] @ vec
+                    for s2p in range(4):
+                        if op[s2p, s2] != 0.0:
+                            acc[(s2p, irp)] = acc.get((s2p, irp), 0.0) + op[s2p, s2] * contrib
+        out[(ilp, s1p, x)] = acc
+    return out

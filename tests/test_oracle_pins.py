@@ -1,0 +1,274 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+closed forms, textbook special cases, brute force on tiny inputs, invariants, and
+the one energy the paper prints (Listing 1)."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import contract, davidson, fock, holstein, mps
+from synth import (bond_sector_tables, hubbard_integrals, make_integrals,
+                   random_left_canonical_mps, random_right_canonical_mps)
+from synth.blocks import random_env, random_psi, random_site_ops, random_site_tensor, two_site_blocks
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- Fock space
+
+def test_canonical_anticommutation():
+    K = 2
+    dets = fock.all_dets(K)
+    ops = {}
+    for j in range(2 * K):
+        ops[(j, True)] = fock.op_matrix(dets, [(j, True)]).toarray()
+        ops[(j, False)] = fock.op_matrix(dets, [(j, False)]).toarray()
+    eye = np.eye(len(dets))
+    for i in range(2 * K):
+        for j in range(2 * K):
+            a, ad = ops[(i, False)], ops[(j, True)]
+            np.testing.assert_allclose(a @ ad + ad @ a, eye * (i == j), atol=0)
+            b = ops[(j, False)]
+            np.testing.assert_allclose(a @ b + b @ a, 0 * eye, atol=0)
+        np.testing.assert_allclose(ops[(i, True)], ops[(i, False)].T, atol=0)
+
+
+def test_listing1_site_matrices_are_jordan_wigner_site_operators():
+    """The printed on-site matrices equal a+_alpha, a_alpha, a+_beta, a_beta of one
+    orbital in the determinant convention (alpha before beta)."""
+    dets = fock.all_dets(1)  # bit0 = alpha, bit1 = beta -> [0, a, b, ab] = site basis order
+    printed = {
+        (0, True): [[0, 0, 0, 0], [1, 0, 0, 0], [0, 0, 0, 0], [0, 0, 1, 0]],
+        (0, False): [[0, 1, 0, 0], [0, 0, 0, 0], [0, 0, 0, 1], [0, 0, 0, 0]],
+        (1, True): [[0, 0, 0, 0], [0, 0, 0, 0], [1, 0, 0, 0], [0, -1, 0, 0]],
+        (1, False): [[0, 0, 1, 0], [0, 0, 0, -1], [0, 0, 0, 0], [0, 0, 0, 0]],
+    }
+    for (j, dag), m in printed.items():
+        np.testing.assert_array_equal(fock.op_matrix(dets, [(j, dag)]).toarray(), np.array(m, float))
+
+
+@pytest.mark.parametrize("K,N,twosz", [(3, 3, 1), (3, 2, 0), (2, 2, 0)])
+def test_hamiltonian_matches_term_by_term_bruteforce(K, N, twosz):
+    h, g = make_integrals(K, seed=11)
+    d = fock.sector_dets(K, N, twosz)
+    A = fock.hamiltonian(h, g, d).toarray()
+    B = fock.hamiltonian_bruteforce(h, g, d).toarray()
+    np.testing.assert_allclose(A, B, atol=1e-13)
+    np.testing.assert_allclose(A, A.T, atol=1e-13)
+
+
+def test_hamiltonian_conserves_n_and_sz():
+    K = 3
+    h, g = make_integrals(K, seed=3)
+    dets = fock.all_dets(K)
+    H = fock.hamiltonian(h, g, dets).tocoo()
+    na = lambda x: fock.popcount(x & 0b010101)  # noqa: E731
+    nb = lambda x: fock.popcount(x & 0b101010)  # noqa: E731
+    r, c = dets[H.row], dets[H.col]
+    keep = np.abs(H.data) > 1e-14
+    assert np.all(na(r[keep]) == na(c[keep])) and np.all(nb(r[keep]) == nb(c[keep]))
+
+
+def test_noninteracting_closed_form():
+    K, N = 6, 6
+    h, _ = make_integrals(K, seed=5)
+    eps = np.linalg.eigvalsh(h)
+    for twosz in (0, 2):
+        na, nb = (N + twosz) // 2, (N - twosz) // 2
+        e = fock.fci_energy(h, np.zeros((K,) * 4), N, twosz)
+        assert abs(e - (eps[:na].sum() + eps[:nb].sum())) < 1e-11
+
+
+def test_single_orbital_doubly_occupied():
+    h = np.array([[-0.7]])
+    g = np.full((1, 1, 1, 1), 0.45)
+    assert abs(fock.fci_energy(h, g, 2, 0) - (2 * -0.7 + 0.45)) < 1e-14
+
+
+@pytest.mark.parametrize("t,U", [(1.0, 4.0), (0.5, 1.0), (1.0, 0.0)])
+def test_hubbard_dimer_closed_form(t, U):
+    h, g = hubbard_integrals(2, t, U)
+    e = fock.fci_energy(h, g, 2, 0)
+    assert abs(e - (U / 2 - np.sqrt(U * U / 4 + 4 * t * t))) < 1e-12
+
+
+def test_listing1_hubbard_holstein_printed_energy():
+    ref = json.load(open(os.path.join(GOLDEN, "listing1_hubbard_holstein.json")))
+    e, dim = holstein.ground_energy(n_sites=ref["n_sites_elec"], n_ph=ref["n_ph"], U=ref["U"],
+                                    omega=ref["omega"], g=ref["g"], n_elec=ref["n_elec"],
+                                    twosz=ref["twosz"])
+    assert dim == 36 * 11 ** 4
+    assert abs(e - ref["energy"]) < 0.5 * 10 ** (-ref["printed_digits"])
+
+
+# ---------------------------------------------------------------- MPS / P^T H P
+
+def _embedding(K, M, i, seed=0):
+    h, g = make_integrals(K, seed=seed)
+    bonds = bond_sector_tables(K, K, 0, M)
+    left = random_left_canonical_mps(bonds, seed + 1)
+    right = random_right_canonical_mps(bonds, seed + 2)
+    emb = mps.Embedding(h, g, K, 0, left[:i], right[i + 2:], bonds, i)
+    return h, g, bonds, emb
+
+
+def test_embedding_is_isometry_and_hermitian():
+    K, M, i = 6, 8, 2
+    _, _, bonds, emb = _embedding(K, M, i)
+    keys = two_site_blocks(bonds[i], bonds[i + 2])
+    P = emb.embedding_matrix(keys)
+    np.testing.assert_allclose(P.T @ P, np.eye(P.shape[1]), atol=1e-13)
+    Hm = emb.heff_matrix(keys)
+    np.testing.assert_allclose(Hm, Hm.T, atol=1e-12)
+
+
+def test_embedding_apply_matches_matrix():
+    K, M, i = 6, 8, 1
+    _, _, bonds, emb = _embedding(K, M, i)
+    keys = two_site_blocks(bonds[i], bonds[i + 2])
+    rng = np.random.default_rng(0)
+    psi = random_psi(bonds[i], bonds[i + 2], rng)
+    dense = mps.dense_two_site(psi, bonds[i], bonds[i + 2])
+    sig = mps.two_site_blocks_from_dense(emb.apply(dense), bonds[i], bonds[i + 2], keys)
+    vec = np.concatenate([psi[k].ravel() for k in keys])
+    ref = emb.heff_matrix(keys) @ vec
+    got = np.concatenate([sig[k].ravel() for k in keys])
+    np.testing.assert_allclose(got, ref, atol=1e-12)
+
+
+def test_complete_basis_two_site_space_gives_fci():
+    """K=6 with M=16: bonds 2 and 4 hold complete bases (4^2 = 16 states), so the
+    middle two-site space is the whole sector and H_eff's lowest eigenvalue is E_FCI."""
+    K, M, i = 6, 16, 2
+    h, g, bonds, emb = _embedding(K, M, i)
+    assert sum(m for _, m in bonds[i]) == 16 and sum(m for _, m in bonds[i + 2]) == 16
+    keys = two_site_blocks(bonds[i], bonds[i + 2])
+    w = np.linalg.eigvalsh(emb.heff_matrix(keys))
+    assert abs(w[0] - fock.fci_energy(h, g, K, 0)) < 1e-11
+
+
+@pytest.mark.slow
+def test_config1_middle_step_dimension_and_fci():
+    """8 orbitals, 8 electrons, M=64: bonds 3 and 5 are complete (64 = 4^3 states),
+    the middle two-site space has the FCI dimension 4900, and E0(H_eff) = E_FCI."""
+    from math import comb
+    K, M, i = 8, 64, 3
+    h, g, bonds, emb = _embedding(K, M, i)
+    for b in (bonds[3], bonds[5]):
+        assert sum(m for _, m in b) == 64
+    for q, m in bonds[3]:
+        na, nb = (q[0] + q[1]) // 2, (q[0] - q[1]) // 2
+        assert m == comb(3, na) * comb(3, nb)
+    keys = two_site_blocks(bonds[i], bonds[i + 2])
+    assert len(keys) == 196
+    assert sum(bonds[i][k[0]][1] * bonds[i + 2][k[3]][1] for k in keys) == 4900 == comb(8, 4) ** 2
+    w = np.linalg.eigvalsh(emb.heff_matrix(keys))
+    assert abs(w[0] - fock.fci_energy(h, g, K, 0)) < 1e-10
+
+
+# ---------------------------------------------------------------- contractions
+
+def _tiny_operands(seed=0):
+    rng = np.random.default_rng(seed)
+    lb = [((0, 0), 1), ((1, -1), 2), ((1, 1), 2), ((2, 0), 3)]
+    rb = [((1, 1), 2), ((2, 0), 2), ((3, 1), 1), ((3, -1), 2)]
+    dqs = [(0, 0), (1, 1), (-1, -1), (1, -1), (0, 2), (-1, 1)]
+    L = random_env(lb, dqs, rng)
+    mid = [(0, 0), (1, 1), (-1, 1), (0, 0), (2, 0), (0, -2)]
+    R = random_env(rb, dqs, rng)
+    W1 = random_site_ops(dqs, mid, rng)
+    W2 = random_site_ops(mid, dqs, rng)
+    psi = random_psi(lb, rb, rng)
+    return lb, rb, L, R, W1, W2, psi, len(dqs), len(mid)
+
+
+def test_sigma_einsum_matches_kron_bruteforce():
+    lb, rb, L, R, W1e, W2e, psi, D, Dm = _tiny_operands()
+    Ld, Rd = contract.dense_env(L, lb), contract.dense_env(R, rb)
+    W1, W2 = contract.dense_mpo(W1e, D, Dm), contract.dense_mpo(W2e, Dm, D)
+    P = mps.dense_two_site(psi, lb, rb)
+    s = contract.heff_apply(Ld, W1, W2, Rd, P)
+    H = contract.heff_matrix_kron(Ld, W1, W2, Rd)
+    np.testing.assert_allclose(s.ravel(), H @ P.ravel(), atol=1e-12)
+    d = contract.heff_diag(Ld, W1, W2, Rd)
+    np.testing.assert_allclose(d.ravel(), np.diag(H), atol=1e-12)
+
+
+def test_sigma_identity_mpo_reduces_to_matrix_products():
+    rng = np.random.default_rng(4)
+    lb = [((0, 0), 3), ((1, 1), 2)]
+    rb = [((1, 1), 2), ((2, 0), 4), ((2, 2), 1)]
+    L = random_env(lb, [(0, 0)], rng)
+    R = random_env(rb, [(0, 0)], rng)
+    W = [(0, 0, np.eye(4))]
+    psi = random_psi(lb, rb, rng)
+    s = contract.heff_apply(contract.dense_env(L, lb), contract.dense_mpo(W, 1, 1),
+                            contract.dense_mpo(W, 1, 1), contract.dense_env(R, rb),
+                            mps.dense_two_site(psi, lb, rb))
+    lo, _ = mps.bond_offsets(lb)
+    ro, _ = mps.bond_offsets(rb)
+    for (il, s1, s2, ir), blk in psi.items():
+        ref = L[0]["blocks"][il] @ blk @ R[0]["blocks"][ir].T
+        got = s[lo[il]:lo[il] + blk.shape[0], s1, s2, ro[ir]:ro[ir] + blk.shape[1]]
+        np.testing.assert_allclose(got, ref, atol=1e-13)
+
+
+def test_env_updates_match_kron_bruteforce():
+    rng = np.random.default_rng(7)
+    lb = [((0, 0), 2), ((1, 1), 2), ((1, -1), 1)]
+    nb = [((1, 1), 2), ((2, 0), 3), ((1, -1), 2), ((2, 2), 1)]
+    dqs = [(0, 0), (1, 1), (-1, 1)]
+    mid = [(0, 0), (1, -1), (0, 2)]
+    L = contract.dense_env(random_env(lb, dqs, rng), lb)
+    W = contract.dense_mpo(random_site_ops(dqs, mid, rng), len(dqs), len(mid))
+    A = mps.dense_site_tensor(random_site_tensor(lb, nb, rng), lb, nb)
+    Lp = contract.env_update_left(L, W, A)
+    Am = A.reshape(-1, A.shape[2])
+    for b in range(len(mid)):
+        ref = sum(Am.T @ np.kron(L[a], W[a, b]) @ Am for a in range(len(dqs)))
+        np.testing.assert_allclose(Lp[b], ref, atol=1e-12)
+    R = contract.dense_env(random_env(nb, mid, rng), nb)
+    Bt = mps.dense_site_tensor(random_site_tensor(lb, nb, rng), lb, nb)
+    Rp = contract.env_update_right(R, W, Bt)
+    Bm = Bt.reshape(Bt.shape[0], -1)
+    for a in range(len(dqs)):
+        ref = sum(Bm @ np.kron(W[a, b], R[b]) @ Bm.T for b in range(len(mid)))
+        np.testing.assert_allclose(Rp[a], ref, atol=1e-12)
+
+
+def test_sigma_rows_match_dense_definition():
+    lb, rb, L, R, W1e, W2e, psi, D, Dm = _tiny_operands(seed=2)
+    s = contract.heff_apply(contract.dense_env(L, lb), contract.dense_mpo(W1e, D, Dm),
+                            contract.dense_mpo(W2e, Dm, D), contract.dense_env(R, rb),
+                            mps.dense_two_site(psi, lb, rb))
+    lo, _ = mps.bond_offsets(lb)
+    ro, _ = mps.bond_offsets(rb)
+    rows = [(il, s1, x) for il, (_, m) in enumerate(lb) for s1 in range(4) for x in range(m)]
+    got = contract.sigma_rows(lb, rb, L, W1e, W2e, R, psi, rows)
+    for (il, s1, x), acc in got.items():
+        full = np.zeros((4, s.shape[3]))
+        for (s2, ir), vec in acc.items():
+            full[s2, ro[ir]:ro[ir] + len(vec)] += vec
+        np.testing.assert_allclose(full, s[lo[il] + x, s1], atol=1e-12)
+
+
+# ---------------------------------------------------------------- Davidson
+
+def test_davidson_step_invariants_and_solve():
+    rng = np.random.default_rng(1)
+    n = 60
+    A = rng.standard_normal((n, n))
+    H = 0.5 * (A + A.T) + np.diag(np.arange(n, dtype=float))
+    d = np.diag(H).copy()
+    V, _ = np.linalg.qr(rng.standard_normal((n, 4)))
+    V = V.T
+    theta, rnorm, x, hx, t, tnorm = davidson.step(V, V @ H, d)
+    assert abs(theta - x @ H @ x) < 1e-12 and abs(np.linalg.norm(x) - 1) < 1e-13
+    np.testing.assert_allclose(V @ t, 0, atol=1e-13)
+    assert abs(np.linalg.norm(t) - 1) < 1e-13
+    assert abs(rnorm - np.linalg.norm(H @ x - theta * x)) < 1e-12
+    e, xs, nmv, rn = davidson.solve(lambda v: H @ v, rng.standard_normal(n), d, tol=1e-10, kmax=8)
+    assert rn < 1e-10
+    assert abs(e - np.linalg.eigvalsh(H)[0]) < 1e-12
