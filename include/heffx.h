@@ -1,0 +1,200 @@
+/*
+ * heffx -- MI355X (gfx950) library for the two-site DMRG sigma-vector path of an
+ * ab initio Hamiltonian with U(1) x U(1) (particle number N, 2*Sz) symmetry.
+ *
+ * The operation (Sec. II.A.2 two-site sweep; Sec. II.C.1 NC-partition MPO whose
+ * bond operators are the normal / complementary renormalised operators):
+ *
+ *   sigma[l',s1',s2',r'] = sum_{a,b,c} sum_{l,s1,s2,r}
+ *       L_a[l',l] W1_ab[s1',s1] W2_bc[s2',s2] R_c[r',r] psi[l,s1,s2,r]
+ *
+ * with L_a / R_c the left / right environment operators (block-sparse by
+ * symmetry sector, Sec. II.A.1), W1 / W2 the MPO tensors of the two sites whose
+ * 4x4 site matrices already carry the Jordan-Wigner parity strings, so every
+ * product is a plain Kronecker product.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Site basis: [empty, alpha, beta, alpha-beta], (N, 2Sz) = (0,0),(1,1),(1,-1),(2,0)
+ * (Listing 1).  A bond is labelled by the quantum number of its LEFT block.
+ * A bond table lists sectors sorted lexicographically by (N, 2Sz).
+ * An operator set lists, per operator, the shift dq = (dN, d2Sz) it applies to
+ * the left-block label of the sectors it acts on (for a right-environment
+ * operator this is the shift on the same left-block labels of its bond).
+ *
+ * Payload layouts (FP64, all blocks row-major, no padding):
+ *  - environment: operators in order; operator a holds one block per source
+ *    sector q (ascending) whose destination q+dq_a exists; block (dst x src).
+ *  - two-site wavefunction between bond i and bond i+2: blocks for
+ *    (il, s1, s2) ascending lexicographic whose right sector
+ *    q(il)+q(s1)+q(s2) exists; block (dim il x dim ir).
+ *  - site tensor between bond k and k+1: blocks for (il, s) ascending whose right
+ *    sector q(il)+q(s) exists; block (dim il x dim ir).
+ * The hx_*_layout functions return these offsets.
+ *
+ * Memory: the library never allocates device memory.  Plans are built on the
+ * host (no HIP call); the caller allocates the device table buffer and the
+ * workspace with the sizes reported by hx_plan_get_info and passes them in.  All
+ * device calls are asynchronous on the caller's stream.
+ *
+ * Errors: every int-returning call returns 0 on success, HX_EINVAL for a
+ * malformed table or argument, HX_EHIP for a HIP failure, HX_EUNSUP for an
+ * unsupported request; hx_last_error() returns a thread-local message.
+ */
+#ifndef HEFFX_H
+#define HEFFX_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HX_OK 0
+#define HX_EINVAL (-1)
+#define HX_EHIP (-2)
+#define HX_EUNSUP (-3)
+
+typedef struct hx_plan hx_plan;
+typedef void* hx_stream; /* hipStream_t of the caller (0 = null stream) */
+
+/* Sector table of one bond: nsec sectors; qn[2*i] = N, qn[2*i+1] = 2Sz; dim[i] > 0. */
+typedef struct {
+    int32_t nsec;
+    const int32_t* qn;
+    const int32_t* dim;
+} hx_bond;
+
+/* Operator set: nop operators, dq[2*a] = dN, dq[2*a+1] = d2Sz. */
+typedef struct {
+    int32_t nop;
+    const int32_t* dq;
+} hx_opset;
+
+/* MPO tensor of one site in coordinate form: entry e couples operator row[e] of
+ * the cut on its left to operator col[e] of the cut on its right with the 4x4
+ * site matrix val[16*e + 4*s_out + s_in].  Entries need not be sorted; repeated
+ * (row, col) pairs are summed.  Each site matrix must shift the site quantum
+ * number by exactly dq(col) - dq(row); other elements must be zero. */
+typedef struct {
+    int64_t nnz;
+    const int32_t* row;
+    const int32_t* col;
+    const double* val;
+} hx_mpo_site;
+
+typedef struct {
+    int64_t t_budget_bytes;  /* cap on the intermediate (T) workspace; 0 = default 2 GiB */
+    int32_t reserved[8];
+} hx_plan_opts;
+
+typedef struct {
+    int64_t psi_nnz;        /* wavefunction / sigma length (doubles) */
+    int64_t in_nnz;         /* heff: left-env payload length; env: input env payload */
+    int64_t in2_nnz;        /* heff: right-env payload length; env: site tensor payload */
+    int64_t out_nnz;        /* env: output env payload length; heff: 0 */
+    int64_t table_bytes;    /* device table buffer the caller provides to hx_plan_upload */
+    int64_t ws_bytes;       /* workspace the caller provides to prepare/apply/update */
+    double flops_apply;     /* algorithmic FLOP of one hx_heff_apply or hx_env_update */
+    double flops_prepare;   /* algorithmic FLOP of operator mixing (hx_heff_prepare) */
+    double bytes_apply;     /* algorithmic operand bytes of one apply (each operand block once) */
+    int64_t n_tasks;        /* GEMM tasks of one apply */
+    int64_t n_tiles;        /* output tiles of one apply */
+    int32_t n_chunks;       /* number of intermediate chunks */
+    int32_t n_mixed;        /* number of materialised mixed operators */
+} hx_plan_info;
+
+/* ---- layouts (host only) ---------------------------------------------------- */
+
+/* Environment payload offsets: op_off[nop+1] (op a occupies [op_off[a], op_off[a+1]));
+ * blk_off[nop*nsec] = offset of the block with source sector q, or -1. */
+int hx_env_layout(const hx_bond* bond, const hx_opset* ops, int64_t* op_off, int64_t* blk_off);
+
+/* Two-site wavefunction layout: writes up to max_blocks keys (il,s1,s2,ir as 4
+ * int32 each) and offsets (max_blocks+1 entries incl. the total); returns the
+ * number of blocks or a negative error. keys/off may be NULL to query the count. */
+int64_t hx_psi_layout(const hx_bond* lbond, const hx_bond* rbond, int64_t max_blocks,
+                      int32_t* keys, int64_t* off);
+
+/* Site tensor layout: keys (il, s, ir) as 3 int32 each; same rules as hx_psi_layout. */
+int64_t hx_site_layout(const hx_bond* lbond, const hx_bond* rbond, int64_t max_blocks,
+                       int32_t* keys, int64_t* off);
+
+/* ---- sigma-vector plan ------------------------------------------------------ */
+
+/* Build (host only) the plan of sigma = H_eff psi for the two-site step between
+ * bond lbond (left environment Lops acting on it) and bond rbond (right
+ * environment Rops), with W1 coupling Lops -> mid and W2 coupling mid -> Rops.
+ * Validates every table; rejects shifts that break quantum-number conservation. */
+int hx_heff_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops,
+                        const hx_opset* mid, const hx_opset* Rops, const hx_mpo_site* W1,
+                        const hx_mpo_site* W2, const hx_plan_opts* opts, hx_plan** out);
+
+/* Build (host only) the plan of an environment update (Sec. II.A.2 sweep):
+ *  direction 0 (left, L -> R):  L'_b = sum_{a,s,t} A[.,s,.]^T (L_a W_ab[s,t]) A[.,t,.]
+ *     bond_in = bond k, bond_out = bond k+1, ops_in at cut k, ops_out at cut k+1,
+ *     W = MPO of site k (rows ops_in, cols ops_out), site tensor A between bond_in and bond_out.
+ *  direction 1 (right, R -> L): R'_a = sum_{b,s,t} B[.,s,.] (W_ab[s,t] R_b) B[.,t,.]^T
+ *     bond_in = bond k+1, bond_out = bond k, ops_in at cut k+1, ops_out at cut k,
+ *     W = MPO of site k (rows ops_out, cols ops_in), site tensor B between bond_out and bond_in. */
+int hx_env_plan_create(int direction, const hx_bond* bond_in, const hx_bond* bond_out,
+                       const hx_opset* ops_in, const hx_opset* ops_out, const hx_mpo_site* W,
+                       const hx_plan_opts* opts, hx_plan** out);
+
+int hx_plan_get_info(const hx_plan* plan, hx_plan_info* info);
+
+/* Copy the plan's tables to caller memory `dev_tables` (table_bytes, 256-byte
+ * aligned device memory).  Must precede every device call with this plan. */
+int hx_plan_upload(hx_plan* plan, void* dev_tables, hx_stream stream);
+
+void hx_plan_destroy(hx_plan* plan);
+
+/* Mixed operators sum_a W1_ab[s1',s1] L_a and sum_c W2_bc[s2',s2] R_c into ws
+ * (Sec. II.C.1 integral-weighted sums building the complementary operators).
+ * Needed once per (L, R) before hx_heff_apply / hx_heff_diag. */
+int hx_heff_prepare(const hx_plan* plan, const double* L, const double* R, void* ws,
+                    hx_stream stream);
+
+/* sigma = H_eff psi (sigma overwritten).  ws must hold the result of
+ * hx_heff_prepare for the same L and R.  psi and sigma must not overlap. */
+int hx_heff_apply(const hx_plan* plan, const double* L, const double* R, void* ws,
+                  const double* psi, double* sigma, hx_stream stream);
+
+/* diag = diagonal of H_eff in the wavefunction layout (ws prepared as above). */
+int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws,
+                 double* diag, hx_stream stream);
+
+/* env_out = updated environment (overwritten); see hx_env_plan_create. */
+int hx_env_update(const hx_plan* plan, const double* env_in, const double* site, void* ws,
+                  double* env_out, hx_stream stream);
+
+/* ---- Davidson (Davidson 1975; the eigensolver of the sweep) ----------------- */
+
+/* Workspace (bytes) of hx_davidson_step for vectors of length n and basis size <= kmax. */
+int64_t hx_davidson_ws_bytes(int64_t n, int32_t kmax);
+
+/* One Davidson step on an orthonormal basis V (k rows of length n, stride ldv)
+ * with S = H V (stride lds):
+ *   G_ij = v_i . s_j (row/column k-1 computed here; rows < k-1 kept in ws from
+ *   earlier calls with the same ws), symmetrised; lowest eigenpair (theta, y) of
+ *   G[:k,:k] by Jacobi rotations (largest |y_j| made positive); x = V^T y,
+ *   hx = S^T y, r = hx - theta x; t = r / (theta - diag) with |theta - diag|
+ *   raised to `guard` (sign kept, + for 0); t orthogonalised against V twice
+ *   (classical Gram-Schmidt) and normalised.
+ * Outputs (device): x, hx, t (length n) and scal[0] = theta, scal[1] = ||r||,
+ * scal[2] = ||t|| before normalisation.  1 <= k <= kmax <= 32. */
+int hx_davidson_step(int64_t n, int32_t k, int32_t kmax, const double* V, int64_t ldv,
+                     const double* S, int64_t lds, const double* diag, double guard, void* ws,
+                     double* x, double* hx, double* t, double* scal, hx_stream stream);
+
+/* Deterministic FP64 dot products out[j] = a_j . b for j < k (a_j = a + j*lda). */
+int hx_dots(int64_t n, int32_t k, const double* a, int64_t lda, const double* b, void* ws,
+            double* out, hx_stream stream);
+
+const char* hx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HEFFX_H */

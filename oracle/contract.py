@@ -13,8 +13,9 @@ DMRG equations" (Sec. II.C.1) becomes:
 
   diag(H_eff)[l, s1, s2, r] = sum_{a,b,c} L_a[l,l] W1_ab[s1,s1] W2_bc[s2,s2] R_c[r,r]
 
-Each is one einsum over dense zero-padded arrays (the library primitive decides
-the pairwise order; no blocking is done here).  `sigma_rows` evaluates selected
+Each is evaluated on dense zero-padded arrays as a chain of pairwise einsum
+contractions, one summed index group at a time (psi with L, then W1, W2, R);
+this only uses associativity of the single sum above, with no blocking.  `sigma_rows` evaluates selected
 output rows of the first formula at full size, summing over b in order.
 """
 
@@ -59,11 +60,20 @@ def dense_mpo(entries, nrow, ncol):
 
 def heff_apply(Ld, W1, W2, Rd, psi):
     """sigma for dense L[a,l',l], W1[a,b,s',s], W2[b,c,t',t], R[c,r',r], psi[l,s,t,r]."""
-    return np.einsum("axy,abst,bcuv,czw,ytvw->xsuz", Ld, W1, W2, Rd, psi, optimize=True)
+    x = np.einsum("axy,ytvw->axtvw", Ld, psi, optimize=True)
+    y = np.einsum("abst,axtvw->bxsvw", W1, x, optimize=True)
+    z = np.einsum("bcuv,bxsvw->cxsuw", W2, y, optimize=True)
+    return np.einsum("czw,cxsuw->xsuz", Rd, z, optimize=True)
 
 
 def heff_diag(Ld, W1, W2, Rd):
-    return np.einsum("axx,abss,bcuu,czz->xsuz", Ld, W1, W2, Rd, optimize=True)
+    dl = np.einsum("axx->ax", Ld)
+    dw1 = np.einsum("abss->abs", W1)
+    dw2 = np.einsum("bcuu->bcu", W2)
+    dr = np.einsum("czz->cz", Rd)
+    left = np.einsum("ax,abs->bxs", dl, dw1, optimize=True)
+    right = np.einsum("bcu,cz->buz", dw2, dr, optimize=True)
+    return np.einsum("bxs,buz->xsuz", left, right, optimize=True)
 
 
 def heff_matrix_kron(Ld, W1, W2, Rd):
@@ -83,12 +93,16 @@ def heff_matrix_kron(Ld, W1, W2, Rd):
 
 def env_update_left(Ld, W, A):
     """L'_b = sum A^T (L_a (x) W_ab) A with A[l, s, m] (dense)."""
-    return np.einsum("xsm,axy,abst,ytn->bmn", A, Ld, W, A, optimize=True)
+    t = np.einsum("axy,ytn->axtn", Ld, A, optimize=True)
+    u = np.einsum("abst,axtn->bxsn", W, t, optimize=True)
+    return np.einsum("xsm,bxsn->bmn", A, u, optimize=True)
 
 
 def env_update_right(Rd, W, B):
     """R'_a = sum B (W_ab (x) R_b) B^T with B[m, s, x] (dense)."""
-    return np.einsum("msx,abst,bxy,nty->amn", B, W, Rd, B, optimize=True)
+    t = np.einsum("bxy,nty->bxnt", Rd, B, optimize=True)
+    u = np.einsum("abst,bxnt->axsn", W, t, optimize=True)
+    return np.einsum("msx,axsn->amn", B, u, optimize=True)
 
 
 def sigma_rows(lbond, rbond, L, W1e, W2e, R, psi, rows):

@@ -1,0 +1,357 @@
+"""ctypes binding of libheffx.so (argument marshalling only).
+
+Every computation runs in the HIP library; this module converts numpy tables to
+the C structs of include/heffx.h, hands over device pointers of torch tensors
+and the current HIP stream, and checks return codes.  If the library is missing
+the import of any entry point raises: there is no fallback path.
+"""
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libheffx.so")
+
+HX_OK, HX_EINVAL, HX_EHIP, HX_EUNSUP = 0, -1, -2, -3
+
+EXPORTED = (
+    "hx_env_layout", "hx_psi_layout", "hx_site_layout", "hx_heff_plan_create", "hx_env_plan_create",
+    "hx_plan_get_info", "hx_plan_upload", "hx_plan_destroy", "hx_heff_prepare", "hx_heff_apply",
+    "hx_heff_diag", "hx_env_update", "hx_davidson_ws_bytes", "hx_davidson_step", "hx_dots",
+    "hx_last_error",
+)
+
+
+class HxBond(ctypes.Structure):
+    _fields_ = [("nsec", c_int32), ("qn", POINTER(c_int32)), ("dim", POINTER(c_int32))]
+
+
+class HxOpset(ctypes.Structure):
+    _fields_ = [("nop", c_int32), ("dq", POINTER(c_int32))]
+
+
+class HxMpoSite(ctypes.Structure):
+    _fields_ = [("nnz", c_int64), ("row", POINTER(c_int32)), ("col", POINTER(c_int32)),
+                ("val", POINTER(c_double))]
+
+
+class HxPlanOpts(ctypes.Structure):
+    _fields_ = [("t_budget_bytes", c_int64), ("reserved", c_int32 * 8)]
+
+
+class HxPlanInfo(ctypes.Structure):
+    _fields_ = [("psi_nnz", c_int64), ("in_nnz", c_int64), ("in2_nnz", c_int64), ("out_nnz", c_int64),
+                ("table_bytes", c_int64), ("ws_bytes", c_int64), ("flops_apply", c_double),
+                ("flops_prepare", c_double), ("bytes_apply", c_double), ("n_tasks", c_int64),
+                ("n_tiles", c_int64), ("n_chunks", c_int32), ("n_mixed", c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libheffx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"heffx HIP library not built: {LIB_PATH} missing "
+                           "(run __graft_entry__.build() or python paper_2310_03920_amd/build.py)")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    L.hx_last_error.restype = ctypes.c_char_p
+    L.hx_env_layout.argtypes = [P(HxBond), P(HxOpset), P(c_int64), P(c_int64)]
+    L.hx_psi_layout.argtypes = [P(HxBond), P(HxBond), c_int64, P(c_int32), P(c_int64)]
+    L.hx_psi_layout.restype = c_int64
+    L.hx_site_layout.argtypes = [P(HxBond), P(HxBond), c_int64, P(c_int32), P(c_int64)]
+    L.hx_site_layout.restype = c_int64
+    L.hx_heff_plan_create.argtypes = [P(HxBond), P(HxBond), P(HxOpset), P(HxOpset), P(HxOpset),
+                                      P(HxMpoSite), P(HxMpoSite), P(HxPlanOpts), P(c_void_p)]
+    L.hx_env_plan_create.argtypes = [c_int, P(HxBond), P(HxBond), P(HxOpset), P(HxOpset), P(HxMpoSite),
+                                     P(HxPlanOpts), P(c_void_p)]
+    L.hx_plan_get_info.argtypes = [c_void_p, P(HxPlanInfo)]
+    L.hx_plan_upload.argtypes = [c_void_p, c_void_p, c_void_p]
+    L.hx_plan_destroy.argtypes = [c_void_p]
+    L.hx_plan_destroy.restype = None
+    L.hx_heff_prepare.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hx_heff_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hx_heff_diag.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hx_env_update.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hx_davidson_ws_bytes.argtypes = [c_int64, c_int32]
+    L.hx_davidson_ws_bytes.restype = c_int64
+    L.hx_davidson_step.argtypes = [c_int64, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                   c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hx_dots.argtypes = [c_int64, c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    _lib = L
+    return L
+
+
+def check(rc, what):
+    if rc != HX_OK:
+        msg = lib().hx_last_error().decode(errors="replace")
+        raise RuntimeError(f"{what} failed (code {rc}): {msg}")
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class Bond:
+    """Sector table of one bond (list of ((N, 2Sz), dim), sorted)."""
+
+    def __init__(self, sectors):
+        self.sectors = [(tuple(q), int(m)) for q, m in sectors]
+        self.qn = _i32([q for q, _ in self.sectors]).reshape(-1, 2)
+        self.dim = _i32([m for _, m in self.sectors])
+        self.c = HxBond(len(self.sectors), self.qn.ctypes.data_as(POINTER(c_int32)),
+                        self.dim.ctypes.data_as(POINTER(c_int32)))
+        self.index = {q: i for i, (q, _) in enumerate(self.sectors)}
+
+    @property
+    def nsec(self):
+        return len(self.sectors)
+
+
+class OpSet:
+    def __init__(self, dq):
+        self.dq = _i32(dq).reshape(-1, 2)
+        self.c = HxOpset(self.dq.shape[0], self.dq.ctypes.data_as(POINTER(c_int32)))
+
+    @property
+    def nop(self):
+        return self.dq.shape[0]
+
+
+class MpoSite:
+    def __init__(self, rows, cols, mats):
+        self.rows = _i32(rows)
+        self.cols = _i32(cols)
+        self.vals = np.ascontiguousarray(np.asarray(mats, dtype=np.float64).reshape(-1, 16))
+        self.c = HxMpoSite(len(self.rows), self.rows.ctypes.data_as(POINTER(c_int32)),
+                           self.cols.ctypes.data_as(POINTER(c_int32)),
+                           self.vals.ctypes.data_as(POINTER(c_double)))
+
+    @classmethod
+    def from_entries(cls, entries):
+        if not entries:
+            return cls(np.zeros(0), np.zeros(0), np.zeros((0, 16)))
+        return cls([e[0] for e in entries], [e[1] for e in entries], [e[2] for e in entries])
+
+
+def env_layout(bond, ops):
+    op_off = np.zeros(ops.nop + 1, np.int64)
+    blk_off = np.zeros(max(ops.nop * bond.nsec, 1), np.int64)
+    check(lib().hx_env_layout(ctypes.byref(bond.c), ctypes.byref(ops.c),
+                              op_off.ctypes.data_as(POINTER(c_int64)), blk_off.ctypes.data_as(POINTER(c_int64))),
+          "env_layout")
+    return op_off, blk_off[:ops.nop * bond.nsec].reshape(ops.nop, bond.nsec)
+
+
+def psi_layout(lbond, rbond):
+    n = lib().hx_psi_layout(ctypes.byref(lbond.c), ctypes.byref(rbond.c), 0, None, None)
+    if n < 0:
+        check(int(n), "psi_layout")
+    keys = np.zeros((max(n, 1), 4), np.int32)
+    off = np.zeros(n + 1, np.int64)
+    n2 = lib().hx_psi_layout(ctypes.byref(lbond.c), ctypes.byref(rbond.c), n,
+                             keys.ctypes.data_as(POINTER(c_int32)), off.ctypes.data_as(POINTER(c_int64)))
+    if n2 < 0:
+        check(int(n2), "psi_layout")
+    return [tuple(int(x) for x in k) for k in keys[:n]], off
+
+
+def site_layout(lbond, rbond):
+    n = lib().hx_site_layout(ctypes.byref(lbond.c), ctypes.byref(rbond.c), 0, None, None)
+    if n < 0:
+        check(int(n), "site_layout")
+    keys = np.zeros((max(n, 1), 3), np.int32)
+    off = np.zeros(n + 1, np.int64)
+    n2 = lib().hx_site_layout(ctypes.byref(lbond.c), ctypes.byref(rbond.c), n,
+                              keys.ctypes.data_as(POINTER(c_int32)), off.ctypes.data_as(POINTER(c_int64)))
+    if n2 < 0:
+        check(int(n2), "site_layout")
+    return [tuple(int(x) for x in k) for k in keys[:n]], off
+
+
+# ------------------------------------------------------------------ packing (host data marshalling)
+
+def pack_env(bond, ops_dq, env):
+    """Environment in block-dict form -> flat payload in the library layout."""
+    ops = OpSet(ops_dq)
+    op_off, blk_off = env_layout(bond, ops)
+    out = np.zeros(int(op_off[-1]))
+    for a, op in enumerate(env):
+        for isrc, blk in op["blocks"].items():
+            o = blk_off[a, isrc]
+            if o < 0:
+                raise ValueError("block outside the operator's shift")
+            out[o:o + blk.size] = blk.ravel()
+    return out
+
+
+def unpack_env(bond, ops_dq, flat):
+    ops = OpSet(ops_dq)
+    op_off, blk_off = env_layout(bond, ops)
+    res = []
+    for a in range(ops.nop):
+        dq = tuple(int(x) for x in ops.dq[a])
+        blocks = {}
+        for isrc in range(bond.nsec):
+            o = blk_off[a, isrc]
+            if o < 0:
+                continue
+            q = bond.sectors[isrc][0]
+            idst = bond.index[(q[0] + dq[0], q[1] + dq[1])]
+            m, n = bond.sectors[idst][1], bond.sectors[isrc][1]
+            blocks[isrc] = np.asarray(flat[o:o + m * n]).reshape(m, n).copy()
+        res.append({"dq": dq, "blocks": blocks})
+    return res
+
+
+def pack_psi(lbond, rbond, psi):
+    keys, off = psi_layout(lbond, rbond)
+    out = np.zeros(int(off[-1]))
+    for i, k in enumerate(keys):
+        if k in psi:
+            out[off[i]:off[i + 1]] = psi[k].ravel()
+    return out
+
+
+def unpack_psi(lbond, rbond, flat):
+    keys, off = psi_layout(lbond, rbond)
+    res = {}
+    for i, (il, s1, s2, ir) in enumerate(keys):
+        res[(il, s1, s2, ir)] = np.asarray(flat[off[i]:off[i + 1]]).reshape(lbond.sectors[il][1],
+                                                                          rbond.sectors[ir][1]).copy()
+    return res
+
+
+def pack_site(lbond, rbond, t):
+    keys, off = site_layout(lbond, rbond)
+    out = np.zeros(int(off[-1]))
+    for i, k in enumerate(keys):
+        if k in t:
+            out[off[i]:off[i + 1]] = t[k].ravel()
+    return out
+
+
+def unpack_site(lbond, rbond, flat):
+    keys, off = site_layout(lbond, rbond)
+    res = {}
+    for i, (il, s, ir) in enumerate(keys):
+        res[(il, s, ir)] = np.asarray(flat[off[i]:off[i + 1]]).reshape(lbond.sectors[il][1],
+                                                                      rbond.sectors[ir][1]).copy()
+    return res
+
+
+# ------------------------------------------------------------------ plans
+
+def _ptr(t):
+    return c_void_p(0) if t is None else c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """A host plan; `upload(device)` places its tables and a workspace on the GPU."""
+
+    def __init__(self, handle, keep):
+        self.h = handle
+        self._keep = keep
+        info = HxPlanInfo()
+        check(lib().hx_plan_get_info(self.h, ctypes.byref(info)), "plan_get_info")
+        self.info = info
+        self.tables = None
+        self.ws = None
+
+    def upload(self, device="cuda"):
+        import torch
+        nb = int(self.info.table_bytes) + 256
+        buf = torch.empty(nb, dtype=torch.uint8, device=device)
+        shift = (-buf.data_ptr()) % 256
+        self.tables = buf
+        self._tab_ptr = buf.data_ptr() + shift
+        check(lib().hx_plan_upload(self.h, c_void_p(self._tab_ptr), _stream()), "plan_upload")
+        nws = max(int(self.info.ws_bytes) // 8, 1)
+        self.ws = torch.empty(nws, dtype=torch.float64, device=device)
+        return self
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().hx_plan_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def _opts(t_budget_bytes=0):
+    o = HxPlanOpts()
+    o.t_budget_bytes = int(t_budget_bytes)
+    return o
+
+
+class HeffPlan(Plan):
+    def __init__(self, lbond, rbond, Ldq, mid_dq, Rdq, W1, W2, t_budget_bytes=0):
+        lb, rb = (b if isinstance(b, Bond) else Bond(b) for b in (lbond, rbond))
+        Lo, Mo, Ro = OpSet(Ldq), OpSet(mid_dq), OpSet(Rdq)
+        w1 = W1 if isinstance(W1, MpoSite) else MpoSite.from_entries(W1)
+        w2 = W2 if isinstance(W2, MpoSite) else MpoSite.from_entries(W2)
+        opts = _opts(t_budget_bytes)
+        h = c_void_p()
+        check(lib().hx_heff_plan_create(ctypes.byref(lb.c), ctypes.byref(rb.c), ctypes.byref(Lo.c),
+                                        ctypes.byref(Mo.c), ctypes.byref(Ro.c), ctypes.byref(w1.c),
+                                        ctypes.byref(w2.c), ctypes.byref(opts), ctypes.byref(h)),
+              "heff_plan_create")
+        super().__init__(h, (lb, rb, Lo, Mo, Ro, w1, w2))
+        self.lbond, self.rbond = lb, rb
+
+    def prepare(self, L, R):
+        check(lib().hx_heff_prepare(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _stream()), "heff_prepare")
+
+    def apply(self, L, R, psi, sigma):
+        check(lib().hx_heff_apply(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(psi), _ptr(sigma), _stream()),
+              "heff_apply")
+
+    def diag(self, L, R, out):
+        check(lib().hx_heff_diag(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(out), _stream()), "heff_diag")
+
+
+class EnvPlan(Plan):
+    def __init__(self, direction, bond_in, bond_out, dq_in, dq_out, W, t_budget_bytes=0):
+        bi, bo = (b if isinstance(b, Bond) else Bond(b) for b in (bond_in, bond_out))
+        oi, oo = OpSet(dq_in), OpSet(dq_out)
+        w = W if isinstance(W, MpoSite) else MpoSite.from_entries(W)
+        opts = _opts(t_budget_bytes)
+        h = c_void_p()
+        check(lib().hx_env_plan_create(int(direction), ctypes.byref(bi.c), ctypes.byref(bo.c), ctypes.byref(oi.c),
+                                       ctypes.byref(oo.c), ctypes.byref(w.c), ctypes.byref(opts), ctypes.byref(h)),
+              "env_plan_create")
+        super().__init__(h, (bi, bo, oi, oo, w))
+
+    def update(self, env_in, site, env_out):
+        check(lib().hx_env_update(self.h, _ptr(env_in), _ptr(site), _ptr(self.ws), _ptr(env_out), _stream()),
+              "env_update")
+
+
+def davidson_ws_bytes(n, kmax):
+    return int(lib().hx_davidson_ws_bytes(int(n), int(kmax)))
+
+
+def davidson_step(n, k, kmax, V, S, diag, guard, ws, x, hx, t, scal):
+    """Tensors: V, S (kmax, n) row-major float64; diag, x, hx, t (n,); ws bytes; scal (>=3,)."""
+    check(lib().hx_davidson_step(int(n), int(k), int(kmax), _ptr(V), V.stride(0), _ptr(S), S.stride(0), _ptr(diag),
+                                 float(guard), _ptr(ws), _ptr(x), _ptr(hx), _ptr(t), _ptr(scal), _stream()),
+          "davidson_step")
+
+
+def dots(a, b, ws, out):
+    """out[j] = a[j] . b for a (k, n) float64 rows."""
+    k, n = a.shape
+    check(lib().hx_dots(int(n), int(k), _ptr(a), a.stride(0), _ptr(b), _ptr(ws), _ptr(out), _stream()), "dots")

@@ -1,0 +1,118 @@
+// Internal tables shared by the host plan builder and the gfx950 kernels.
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace hx {
+
+// Operand spaces: a task names its operands as (space, element offset); the
+// launcher passes one base pointer per space, so a plan is independent of the
+// buffers it is applied to.
+enum Space : int8_t {
+    SP_PSI = 0,   // input vector (psi) / input environment for env updates
+    SP_OUT = 1,   // output (sigma / updated environment / diag)
+    SP_L = 2,     // left environment payload
+    SP_R = 3,     // right environment payload (env update: site tensor)
+    SP_WS = 4,    // caller workspace (mixed operators, intermediates)
+    SP_TAB = 5,   // plan tables on the device (mixing coefficients)
+    SP_N = 6
+};
+
+// One contribution alpha * op(A) * op(B) to an output tile.  A is (rows x k),
+// B is (k x cols); with TRANS the stored matrix is the transpose.  For a tile
+// at (r0, c0) inside its block the kernel offsets A by r0 rows and B by c0 cols.
+struct Task {
+    int64_t aoff;
+    int64_t boff;
+    int32_t lda;
+    int32_t ldb;
+    int32_t k;
+    int8_t aspace;
+    int8_t bspace;
+    int16_t pad;
+    double alpha;
+};
+static_assert(sizeof(Task) == 40, "Task layout");
+
+// One output tile (at most TM x TN) of one output block.
+struct Tile {
+    int64_t coff;     // element offset of the tile's first element in cspace
+    int32_t ldc;
+    int32_t m, n;     // tile extent
+    int32_t r0, c0;   // tile origin inside its block
+    int32_t tbeg;     // task range [tbeg, tend)
+    int32_t tend;
+    int32_t ktot;     // sum of k over the task range
+    int8_t cspace;
+    int8_t beta;      // 0: overwrite, 1: accumulate
+    int16_t pad;
+};
+static_assert(sizeof(Tile) == 48, "Tile layout");
+
+// Strided copy with scale: dst[d + x*ds] = alpha * src[s + x*ss], x < count.
+struct Gather {
+    int64_t soff;
+    int64_t doff;
+    int32_t sstride;
+    int32_t dstride;
+    int32_t count;
+    int8_t sspace;
+    int8_t dspace;
+    int16_t pad;
+    double alpha;
+};
+static_assert(sizeof(Gather) == 40, "Gather layout");
+
+constexpr int TM = 64;
+constexpr int TN = 64;
+
+enum TransKind : int { NN = 0, NT = 1, TN_ = 2 };
+
+// A GEMM launch: tiles [tile0, tile0+ntile) and their tasks in the device table.
+struct Launch {
+    int kind;          // TransKind
+    int64_t tile0;     // index into the plan's tile array
+    int64_t ntile;
+    double flops;      // algorithmic 2 m n k of the blocks it covers
+};
+
+struct GatherLaunch {
+    int64_t g0, ng;
+};
+
+struct FillLaunch {
+    int8_t space;
+    int64_t off, count;
+};
+
+enum PlanKind : int { PK_HEFF = 0, PK_ENV_LEFT = 1, PK_ENV_RIGHT = 2 };
+
+struct Plan {
+    int kind = PK_HEFF;
+    // host tables (uploaded into one device buffer)
+    std::vector<Tile> tiles;
+    std::vector<Task> tasks;
+    std::vector<Gather> gathers;
+    std::vector<double> coef;     // mixing coefficient matrices (space SP_TAB)
+    // sequences of launches
+    std::vector<Launch> prep;     // mixing (heff_prepare / first part of env update)
+    std::vector<Launch> apply;    // sigma (heff) or E1/E2 chunks (env)
+    std::vector<FillLaunch> diag_fill;
+    std::vector<GatherLaunch> diag_gather;
+    std::vector<Launch> diag_gemm;
+    // sizes
+    int64_t psi_nnz = 0, in_nnz = 0, in2_nnz = 0, out_nnz = 0;
+    int64_t ws_doubles = 0;
+    double flops_apply = 0, flops_prepare = 0, bytes_apply = 0;
+    int64_t n_tasks_apply = 0, n_tiles_apply = 0;
+    int n_chunks = 0, n_mixed = 0;
+    // device table layout (byte offsets inside the uploaded buffer)
+    int64_t off_tiles = 0, off_tasks = 0, off_gathers = 0, off_coef = 0, table_bytes = 0;
+    void* dev = nullptr;          // caller-provided device table buffer (after upload)
+};
+
+void set_error(const std::string& msg);
+
+}  // namespace hx

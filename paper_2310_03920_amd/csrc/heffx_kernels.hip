@@ -1,0 +1,661 @@
+// gfx950 kernels and device entry points of the heffx library.
+//
+// bsgemm_f64: every GEMM of the sigma-vector path (operator mixing, the two
+// rounds of block products, diag(H_eff), environment updates) is one launch of
+// this kernel over a list of output tiles.  A tile (<= 64 x 64 of one output
+// block) is owned by one workgroup, which sums alpha_j op(A_j) op(B_j) over its
+// task list with the K dimensions of all tasks concatenated (no per-task
+// padding) and writes the tile once: no atomics, fixed summation order, so FP64
+// results are bitwise reproducible.  The inner product runs on the FP64 matrix
+// cores (v_mfma_f64_16x16x4_f64); each of the 4 waves owns a 32 x 32 quadrant
+// (2 x 2 MFMA tiles); 16-deep K stages are staged through LDS with a register
+// prefetch of the next stage.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <string>
+
+#include "heffx.h"
+#include "heffx_internal.h"
+
+using namespace hx;
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+struct Bases {
+    double* p[SP_N];
+};
+
+__device__ __forceinline__ double* space_ptr(const Bases& B, int sp) {
+    double* r = B.p[0];
+    r = sp == 1 ? B.p[1] : r;
+    r = sp == 2 ? B.p[2] : r;
+    r = sp == 3 ? B.p[3] : r;
+    r = sp == 4 ? B.p[4] : r;
+    r = sp == 5 ? B.p[5] : r;
+    return r;
+}
+
+// Walks the concatenated K range of a tile's tasks for one fixed k-lane.
+struct Cursor {
+    int j;          // current task
+    int kbeg;       // first global k of task j
+    int kend;       // one past its last global k
+    const double* ptr;
+    int ld;
+    double alpha;
+};
+
+template <bool IS_A, bool TRANS>
+__device__ __forceinline__ void cursor_load(Cursor& c, const Task* __restrict__ tasks, const Bases& B, int r0,
+                                            int c0) {
+    const Task& t = tasks[c.j];
+    if (IS_A) {
+        c.ld = t.lda;
+        c.alpha = t.alpha;
+        c.ptr = space_ptr(B, t.aspace) + t.aoff + (TRANS ? (int64_t)r0 : (int64_t)r0 * t.lda);
+    } else {
+        c.ld = t.ldb;
+        c.alpha = 1.0;
+        c.ptr = space_ptr(B, t.bspace) + t.boff + (TRANS ? (int64_t)c0 * t.ldb : (int64_t)c0);
+    }
+    c.kend = c.kbeg + t.k;
+}
+
+// Advance to the task containing global k index g; returns false past the end.
+template <bool IS_A, bool TRANS>
+__device__ __forceinline__ bool cursor_seek(Cursor& c, int g, int tend, const Task* __restrict__ tasks,
+                                            const Bases& B, int r0, int c0) {
+    while (g >= c.kend) {
+        c.j++;
+        if (c.j >= tend) return false;
+        c.kbeg = c.kend;
+        cursor_load<IS_A, TRANS>(c, tasks, B, r0, c0);
+    }
+    return true;
+}
+
+constexpr int LDS_PAD = 1;
+constexpr int LDW = TM + LDS_PAD;
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(256) void bsgemm_f64(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
+                                                  Bases B) {
+    __shared__ double As[2][16][LDW];
+    __shared__ double Bs[2][16][LDW];
+    const Tile tl = tiles[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
+    const int wr0 = (wave & 1) * 32;
+    const int wc0 = (wave >> 1) * 32;
+    const int m = tl.m, n = tl.n;
+
+    // load lane assignments
+    //  A !TA: kk = tid & 15, rows (tid >> 4) + 16 i         (one k-lane)
+    //  A  TA: rows tid & 63, kk = (tid >> 6) + 4 i          (four k-lanes)
+    //  B !TB: cols tid & 63, kk = (tid >> 6) + 4 i          (four k-lanes)
+    //  B  TB: kk = tid & 15, cols (tid >> 4) + 16 i         (one k-lane)
+    constexpr int NA = TA ? 4 : 1;
+    constexpr int NB = TB ? 1 : 4;
+    Cursor ca[NA], cb[NB];
+    int kka[NA], kkb[NB];
+    for (int i = 0; i < NA; ++i) {
+        kka[i] = TA ? ((tid >> 6) + 4 * i) : (tid & 15);
+        ca[i].j = tl.tbeg;
+        ca[i].kbeg = 0;
+        ca[i].kend = 0;
+        if (tl.tbeg < tl.tend) cursor_load<true, TA>(ca[i], tasks, B, tl.r0, tl.c0);
+    }
+    for (int i = 0; i < NB; ++i) {
+        kkb[i] = TB ? (tid & 15) : ((tid >> 6) + 4 * i);
+        cb[i].j = tl.tbeg;
+        cb[i].kbeg = 0;
+        cb[i].kend = 0;
+        if (tl.tbeg < tl.tend) cursor_load<false, TB>(cb[i], tasks, B, tl.r0, tl.c0);
+    }
+
+    dbl4 acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
+    double ra[4], rb[4];
+    const int nst = (tl.ktot + 15) >> 4;
+
+    auto load_stage = [&](int s) {
+        // A tile: 64 rows x 16 k
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ci = TA ? i : 0;
+            const int kk = kka[ci];
+            const int r = TA ? (tid & 63) : ((tid >> 4) + 16 * i);
+            double v = 0.0;
+            const int g = s * 16 + kk;
+            if (g < tl.ktot && r < m) {
+                if (cursor_seek<true, TA>(ca[ci], g, tl.tend, tasks, B, tl.r0, tl.c0)) {
+                    const int kl = g - ca[ci].kbeg;
+                    v = ca[ci].alpha * (TA ? ca[ci].ptr[(int64_t)kl * ca[ci].ld + r]
+                                           : ca[ci].ptr[(int64_t)r * ca[ci].ld + kl]);
+                }
+            }
+            ra[i] = v;
+        }
+        // B tile: 16 k x 64 cols
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int ci = TB ? 0 : i;
+            const int kk = kkb[ci];
+            const int c = TB ? ((tid >> 4) + 16 * i) : (tid & 63);
+            double v = 0.0;
+            const int g = s * 16 + kk;
+            if (g < tl.ktot && c < n) {
+                if (cursor_seek<false, TB>(cb[ci], g, tl.tend, tasks, B, tl.r0, tl.c0)) {
+                    const int kl = g - cb[ci].kbeg;
+                    v = TB ? cb[ci].ptr[(int64_t)c * cb[ci].ld + kl] : cb[ci].ptr[(int64_t)kl * cb[ci].ld + c];
+                }
+            }
+            rb[i] = v;
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kk = TA ? kka[i] : kka[0];
+            const int r = TA ? (tid & 63) : ((tid >> 4) + 16 * i);
+            As[buf][kk][r] = ra[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int kk = TB ? kkb[0] : kkb[i];
+            const int c = TB ? ((tid >> 4) + 16 * i) : (tid & 63);
+            Bs[buf][kk][c] = rb[i];
+        }
+    };
+
+    if (nst > 0) {
+        load_stage(0);
+        store_stage(0);
+        __syncthreads();
+        for (int s = 0; s < nst; ++s) {
+            const int buf = s & 1;
+            if (s + 1 < nst) load_stage(s + 1);
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const int kr = ks * 4 + (lane >> 4);
+                const double a0 = As[buf][kr][wr0 + (lane & 15)];
+                const double a1 = As[buf][kr][wr0 + 16 + (lane & 15)];
+                const double b0 = Bs[buf][kr][wc0 + (lane & 15)];
+                const double b1 = Bs[buf][kr][wc0 + 16 + (lane & 15)];
+                acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+                acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+                acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+                acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+            }
+            if (s + 1 < nst) store_stage(buf ^ 1);
+            __syncthreads();
+        }
+    }
+    // epilogue: for v_mfma_f64_16x16x4_f64 lane l holds rows l/16 + 4v (v = 0..3),
+    // column l%16 of each 16x16 tile
+    double* C = space_ptr(B, tl.cspace) + tl.coff;
+    const int ldc = tl.ldc;
+    const bool beta = tl.beta != 0;
+    auto put = [&](const dbl4& a, int rb0, int cb0) {
+        const int col = cb0 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = rb0 + (lane >> 4) + 4 * v;
+            if (row < m && col < n) {
+                double* p = C + (int64_t)row * ldc + col;
+                *p = beta ? (*p + a[v]) : a[v];
+            }
+        }
+    };
+    put(acc00, wr0, wc0);
+    put(acc01, wr0, wc0 + 16);
+    put(acc10, wr0 + 16, wc0);
+    put(acc11, wr0 + 16, wc0 + 16);
+}
+
+__global__ void gather_scale(const Gather* __restrict__ g, Bases B) {
+    const Gather gg = g[blockIdx.x];
+    const double* s = space_ptr(B, gg.sspace) + gg.soff;
+    double* d = space_ptr(B, gg.dspace) + gg.doff;
+    for (int x = threadIdx.x; x < gg.count; x += blockDim.x)
+        d[(int64_t)x * gg.dstride] = gg.alpha * s[(int64_t)x * gg.sstride];
+}
+
+__global__ void fill_zero(double* p, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0;
+}
+
+// ---------------------------------------------------------------- Davidson
+
+constexpr int DOT_BLOCKS = 256;
+constexpr int DOT_THREADS = 256;
+constexpr int KMAX = 32;
+
+// Deterministic dots: pass 1 writes per-block partial sums, pass 2 sums them in
+// a fixed tree order.  part[blk * KMAX + j].
+__global__ __launch_bounds__(DOT_THREADS) void dots_pass1(int64_t n, int k, const double* __restrict__ a,
+                                                          int64_t lda, const double* __restrict__ b,
+                                                          double* __restrict__ part) {
+    __shared__ double red[DOT_THREADS];
+    for (int j = 0; j < k; ++j) {
+        const double* aj = a + (int64_t)j * lda;
+        double s = 0.0;
+        for (int64_t e = (int64_t)blockIdx.x * DOT_THREADS + threadIdx.x; e < n; e += (int64_t)DOT_BLOCKS * DOT_THREADS)
+            s += aj[e] * b[e];
+        red[threadIdx.x] = s;
+        __syncthreads();
+        for (int w = DOT_THREADS / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[blockIdx.x * KMAX + j] = red[0];
+        __syncthreads();
+    }
+}
+
+// out[j * ostride] = sum over blocks (fixed tree); if `scale` != 0 multiply by it.
+__global__ __launch_bounds__(DOT_BLOCKS) void dots_pass2(int k, const double* __restrict__ part, double* out,
+                                                         int ostride) {
+    __shared__ double red[DOT_BLOCKS];
+    for (int j = 0; j < k; ++j) {
+        red[threadIdx.x] = part[threadIdx.x * KMAX + j];
+        __syncthreads();
+        for (int w = DOT_BLOCKS / 2; w > 0; w >>= 1) {
+            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) out[(int64_t)j * ostride] = red[0];
+        __syncthreads();
+    }
+}
+
+// Davidson workspace (doubles):
+//   [0, 1024)         G (KMAX x KMAX, row-major; G[i][j] = v_i . s_j)
+//   [1024, 1056)      y
+//   [1056, 1088)      c (Gram-Schmidt coefficients)
+//   [1088, 1096)      scalars: theta, |r|^2, |t|^2, ...
+//   [1096, ...)       partial sums (DOT_BLOCKS x KMAX)
+constexpr int64_t DW_G = 0, DW_Y = 1024, DW_C = 1056, DW_S = 1088, DW_P = 1096;
+constexpr int64_t DW_TOTAL = DW_P + (int64_t)DOT_BLOCKS * KMAX;
+
+// Lowest eigenpair of the symmetrised k x k projected matrix by cyclic Jacobi
+// rotations (one wavefront).  theta -> ws[DW_S], y -> ws[DW_Y..].
+__global__ __launch_bounds__(64) void dav_eig(int k, double* ws, double* scal) {
+    __shared__ double A[KMAX][KMAX + 1];
+    __shared__ double V[KMAX][KMAX + 1];
+    __shared__ double cs[3];
+    __shared__ int flag;
+    const int t = threadIdx.x;
+    const double* G = ws + DW_G;
+    for (int idx = t; idx < k * k; idx += 64) {
+        int i = idx / k, j = idx % k;
+        A[i][j] = 0.5 * (G[i * KMAX + j] + G[j * KMAX + i]);
+        V[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (t == 0) {
+            double off = 0.0, dia = 0.0;
+            for (int i = 0; i < k; ++i)
+                for (int j = 0; j < k; ++j) {
+                    if (i == j)
+                        dia = fmax(dia, fabs(A[i][i]));
+                    else
+                        off = fmax(off, fabs(A[i][j]));
+                }
+            flag = (off <= 1e-16 * fmax(dia, 1e-300)) ? 1 : 0;
+        }
+        __syncthreads();
+        if (flag) break;
+        for (int p = 0; p < k - 1; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                if (t == 0) {
+                    double apq = A[p][q];
+                    if (fabs(apq) < 1e-300) {
+                        cs[0] = 1.0;
+                        cs[1] = 0.0;
+                        cs[2] = 0.0;
+                    } else {
+                        double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+                        double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        double c = 1.0 / sqrt(tt * tt + 1.0);
+                        cs[0] = c;
+                        cs[1] = tt * c;
+                        cs[2] = tt;
+                    }
+                }
+                __syncthreads();
+                const double c = cs[0], s = cs[1], tt = cs[2];
+                if (s != 0.0) {
+                    if (t < k && t != p && t != q) {
+                        double arp = A[t][p], arq = A[t][q];
+                        double np = c * arp - s * arq, nq = s * arp + c * arq;
+                        A[t][p] = np;
+                        A[p][t] = np;
+                        A[t][q] = nq;
+                        A[q][t] = nq;
+                    }
+                    if (t < k) {
+                        double vp = V[t][p], vq = V[t][q];
+                        V[t][p] = c * vp - s * vq;
+                        V[t][q] = s * vp + c * vq;
+                    }
+                    if (t == 0) {
+                        double apq = A[p][q];
+                        A[p][p] -= tt * apq;
+                        A[q][q] += tt * apq;
+                        A[p][q] = 0.0;
+                        A[q][p] = 0.0;
+                    }
+                }
+                __syncthreads();
+            }
+    }
+    if (t == 0) {
+        int best = 0;
+        for (int i = 1; i < k; ++i)
+            if (A[i][i] < A[best][best]) best = i;
+        int big = 0;
+        for (int i = 1; i < k; ++i)
+            if (fabs(V[i][best]) > fabs(V[big][best])) big = i;
+        double sg = V[big][best] < 0 ? -1.0 : 1.0;
+        double nrm = 0.0;
+        for (int i = 0; i < k; ++i) nrm += V[i][best] * V[i][best];
+        nrm = sqrt(nrm);
+        for (int i = 0; i < k; ++i) ws[DW_Y + i] = sg * V[i][best] / nrm;
+        ws[DW_S + 0] = A[best][best];
+        scal[0] = A[best][best];
+    }
+}
+
+// x = V^T y, hx = S^T y, t = hx - theta x
+__global__ void dav_combine(int64_t n, int k, const double* __restrict__ V, int64_t ldv, const double* __restrict__ S,
+                            int64_t lds, const double* __restrict__ ws, double* __restrict__ x, double* __restrict__ hx,
+                            double* __restrict__ t) {
+    __shared__ double y[KMAX];
+    __shared__ double theta;
+    if (threadIdx.x < k) y[threadIdx.x] = ws[DW_Y + threadIdx.x];
+    if (threadIdx.x == 0) theta = ws[DW_S + 0];
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double xv = 0.0, hv = 0.0;
+        for (int j = 0; j < k; ++j) {
+            xv += y[j] * V[(int64_t)j * ldv + e];
+            hv += y[j] * S[(int64_t)j * lds + e];
+        }
+        x[e] = xv;
+        hx[e] = hv;
+        t[e] = hv - theta * xv;
+    }
+}
+
+// t = t / guard(theta - diag)
+__global__ void dav_precond(int64_t n, const double* __restrict__ diag, double guard, const double* __restrict__ ws,
+                            double* __restrict__ t) {
+    const double theta = ws[DW_S + 0];
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double den = theta - diag[e];
+        if (fabs(den) < guard) den = den < 0 ? -guard : guard;
+        t[e] = t[e] / den;
+    }
+}
+
+// t -= sum_j c_j v_j
+__global__ void dav_project(int64_t n, int k, const double* __restrict__ V, int64_t ldv, const double* __restrict__ ws,
+                            double* __restrict__ t) {
+    __shared__ double c[KMAX];
+    if (threadIdx.x < k) c[threadIdx.x] = ws[DW_C + threadIdx.x];
+    __syncthreads();
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        double acc = t[e];
+        for (int j = 0; j < k; ++j) acc -= c[j] * V[(int64_t)j * ldv + e];
+        t[e] = acc;
+    }
+}
+
+// t /= sqrt(ws[DW_S+2]) (if > 0); scal[1] = sqrt(|r|^2), scal[2] = |t|
+__global__ void dav_finish(int64_t n, double* ws, double* __restrict__ t, double* scal) {
+    const double tn = sqrt(ws[DW_S + 2]);
+    const double inv = tn > 0 ? 1.0 / tn : 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        t[e] *= inv;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        scal[1] = sqrt(ws[DW_S + 1]);
+        scal[2] = tn;
+    }
+}
+
+// ---------------------------------------------------------------- host side
+
+static int hip_check(hipError_t e, const char* what) {
+    if (e != hipSuccess) {
+        set_error(std::string(what) + ": " + hipGetErrorString(e));
+        return HX_EHIP;
+    }
+    return HX_OK;
+}
+
+static Bases make_bases(const Plan* P, const double* psi, double* out, const double* L, const double* R, void* ws) {
+    Bases b;
+    b.p[SP_PSI] = const_cast<double*>(psi);
+    b.p[SP_OUT] = out;
+    b.p[SP_L] = const_cast<double*>(L);
+    b.p[SP_R] = const_cast<double*>(R);
+    b.p[SP_WS] = static_cast<double*>(ws);
+    b.p[SP_TAB] = reinterpret_cast<double*>(static_cast<char*>(P->dev) + P->off_coef);
+    return b;
+}
+
+static int launch_gemm(const Plan* P, const Launch& L, const Bases& B, hipStream_t s) {
+    if (L.ntile <= 0) return HX_OK;
+    const Tile* tiles = reinterpret_cast<const Tile*>(static_cast<const char*>(P->dev) + P->off_tiles) + L.tile0;
+    const Task* tasks = reinterpret_cast<const Task*>(static_cast<const char*>(P->dev) + P->off_tasks);
+    dim3 grid((unsigned)L.ntile), block(256);
+    switch (L.kind) {
+        case NN:
+            hipLaunchKernelGGL((bsgemm_f64<false, false>), grid, block, 0, s, tiles, tasks, B);
+            break;
+        case NT:
+            hipLaunchKernelGGL((bsgemm_f64<false, true>), grid, block, 0, s, tiles, tasks, B);
+            break;
+        case TN_:
+            hipLaunchKernelGGL((bsgemm_f64<true, false>), grid, block, 0, s, tiles, tasks, B);
+            break;
+        default:
+            set_error("internal: bad GEMM kind");
+            return HX_EINVAL;
+    }
+    return hip_check(hipGetLastError(), "bsgemm launch");
+}
+
+static int check_ready(const hx_plan* plan, int kind) {
+    if (!plan) {
+        set_error("null plan");
+        return HX_EINVAL;
+    }
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (!P->dev) {
+        set_error("plan not uploaded (call hx_plan_upload first)");
+        return HX_EINVAL;
+    }
+    if (kind >= 0 && P->kind != kind && !(kind == PK_ENV_LEFT && P->kind == PK_ENV_RIGHT)) {
+        set_error("plan kind does not match this entry point");
+        return HX_EINVAL;
+    }
+    return HX_OK;
+}
+
+extern "C" {
+
+int hx_plan_upload(hx_plan* plan, void* dev_tables, hx_stream stream) {
+    if (!plan || !dev_tables) {
+        set_error("plan_upload: null argument");
+        return HX_EINVAL;
+    }
+    if ((reinterpret_cast<uintptr_t>(dev_tables) & 255) != 0) {
+        set_error("plan_upload: table buffer must be 256-byte aligned");
+        return HX_EINVAL;
+    }
+    Plan* P = reinterpret_cast<Plan*>(plan);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    char* d = static_cast<char*>(dev_tables);
+    int rc;
+    if (!P->tiles.empty() &&
+        (rc = hip_check(hipMemcpyAsync(d + P->off_tiles, P->tiles.data(), P->tiles.size() * sizeof(Tile),
+                                       hipMemcpyHostToDevice, s), "upload tiles")))
+        return rc;
+    if (!P->tasks.empty() &&
+        (rc = hip_check(hipMemcpyAsync(d + P->off_tasks, P->tasks.data(), P->tasks.size() * sizeof(Task),
+                                       hipMemcpyHostToDevice, s), "upload tasks")))
+        return rc;
+    if (!P->gathers.empty() &&
+        (rc = hip_check(hipMemcpyAsync(d + P->off_gathers, P->gathers.data(), P->gathers.size() * sizeof(Gather),
+                                       hipMemcpyHostToDevice, s), "upload gathers")))
+        return rc;
+    if (!P->coef.empty() &&
+        (rc = hip_check(hipMemcpyAsync(d + P->off_coef, P->coef.data(), P->coef.size() * sizeof(double),
+                                       hipMemcpyHostToDevice, s), "upload coefficients")))
+        return rc;
+    if ((rc = hip_check(hipStreamSynchronize(s), "upload sync"))) return rc;
+    P->dev = dev_tables;
+    return HX_OK;
+}
+
+int hx_heff_prepare(const hx_plan* plan, const double* L, const double* R, void* ws, hx_stream stream) {
+    int rc = check_ready(plan, PK_HEFF);
+    if (rc) return rc;
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if ((P->in_nnz && !L) || (P->in2_nnz && !R) || (P->ws_doubles && !ws)) {
+        set_error("heff_prepare: null operand");
+        return HX_EINVAL;
+    }
+    Bases B = make_bases(P, nullptr, nullptr, L, R, ws);
+    for (const Launch& l : P->prep)
+        if ((rc = launch_gemm(P, l, B, static_cast<hipStream_t>(stream)))) return rc;
+    return HX_OK;
+}
+
+int hx_heff_apply(const hx_plan* plan, const double* L, const double* R, void* ws, const double* psi, double* sigma,
+                  hx_stream stream) {
+    int rc = check_ready(plan, PK_HEFF);
+    if (rc) return rc;
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (!psi || !sigma || (P->in_nnz && !L) || (P->in2_nnz && !R) || (P->ws_doubles && !ws)) {
+        set_error("heff_apply: null operand");
+        return HX_EINVAL;
+    }
+    if (psi == sigma) {
+        set_error("heff_apply: psi and sigma must not alias");
+        return HX_EINVAL;
+    }
+    Bases B = make_bases(P, psi, sigma, L, R, ws);
+    for (const Launch& l : P->apply)
+        if ((rc = launch_gemm(P, l, B, static_cast<hipStream_t>(stream)))) return rc;
+    return HX_OK;
+}
+
+int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws, double* diag, hx_stream stream) {
+    int rc = check_ready(plan, PK_HEFF);
+    if (rc) return rc;
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (!diag || (P->ws_doubles && !ws)) {
+        set_error("heff_diag: null operand");
+        return HX_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Bases B = make_bases(P, nullptr, diag, L, R, ws);
+    for (const FillLaunch& f : P->diag_fill) {
+        if (f.count <= 0) continue;
+        int nb = (int)std::min<int64_t>(4096, (f.count + 255) / 256);
+        hipLaunchKernelGGL(fill_zero, dim3(nb), dim3(256), 0, s, B.p[f.space] + f.off, f.count);
+        if ((rc = hip_check(hipGetLastError(), "diag fill"))) return rc;
+    }
+    const Gather* g = reinterpret_cast<const Gather*>(static_cast<const char*>(P->dev) + P->off_gathers);
+    for (const GatherLaunch& gl : P->diag_gather) {
+        hipLaunchKernelGGL(gather_scale, dim3((unsigned)gl.ng), dim3(128), 0, s, g + gl.g0, B);
+        if ((rc = hip_check(hipGetLastError(), "diag gather"))) return rc;
+    }
+    for (const Launch& l : P->diag_gemm)
+        if ((rc = launch_gemm(P, l, B, s))) return rc;
+    return HX_OK;
+}
+
+int hx_env_update(const hx_plan* plan, const double* env_in, const double* site, void* ws, double* env_out,
+                  hx_stream stream) {
+    int rc = check_ready(plan, PK_ENV_LEFT);
+    if (rc) return rc;
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (P->kind == PK_HEFF) {
+        set_error("env_update: plan is a sigma-vector plan");
+        return HX_EINVAL;
+    }
+    if (!env_out || (P->in_nnz && !env_in) || (P->in2_nnz && !site) || (P->ws_doubles && !ws)) {
+        set_error("env_update: null operand");
+        return HX_EINVAL;
+    }
+    Bases B = make_bases(P, env_in, env_out, nullptr, site, ws);
+    for (const Launch& l : P->apply)
+        if ((rc = launch_gemm(P, l, B, static_cast<hipStream_t>(stream)))) return rc;
+    return HX_OK;
+}
+
+int64_t hx_davidson_ws_bytes(int64_t n, int32_t kmax) {
+    (void)n;
+    (void)kmax;
+    return DW_TOTAL * 8;
+}
+
+static int dots_into(int64_t n, int k, const double* a, int64_t lda, const double* b, double* ws, double* out,
+                     int ostride, hipStream_t s) {
+    hipLaunchKernelGGL(dots_pass1, dim3(DOT_BLOCKS), dim3(DOT_THREADS), 0, s, n, k, a, lda, b, ws + DW_P);
+    hipLaunchKernelGGL(dots_pass2, dim3(1), dim3(DOT_BLOCKS), 0, s, k, ws + DW_P, out, ostride);
+    return hip_check(hipGetLastError(), "dots");
+}
+
+int hx_dots(int64_t n, int32_t k, const double* a, int64_t lda, const double* b, void* ws, double* out,
+            hx_stream stream) {
+    if (k < 1 || k > KMAX || n < 0 || !a || !b || !ws || !out) {
+        set_error("dots: bad arguments (1 <= k <= 32)");
+        return HX_EINVAL;
+    }
+    return dots_into(n, k, a, lda, b, static_cast<double*>(ws), out, 1, static_cast<hipStream_t>(stream));
+}
+
+int hx_davidson_step(int64_t n, int32_t k, int32_t kmax, const double* V, int64_t ldv, const double* S, int64_t lds,
+                     const double* diag, double guard, void* wsv, double* x, double* hx, double* t, double* scal,
+                     hx_stream stream) {
+    if (k < 1 || kmax > KMAX || k > kmax || n <= 0 || !V || !S || !diag || !wsv || !x || !hx || !t || !scal ||
+        ldv < n || lds < n || !(guard > 0)) {
+        set_error("davidson_step: bad arguments (1 <= k <= kmax <= 32, ld >= n, guard > 0)");
+        return HX_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* ws = static_cast<double*>(wsv);
+    int rc;
+    const int kk = k - 1;
+    // new column and row of G: G[i][kk] = v_i . s_kk, G[kk][i] = v_kk . s_i
+    if ((rc = dots_into(n, k, V, ldv, S + (int64_t)kk * lds, ws, ws + DW_G + kk, KMAX, s))) return rc;
+    if ((rc = dots_into(n, k, S, lds, V + (int64_t)kk * ldv, ws, ws + DW_G + (int64_t)kk * KMAX, 1, s))) return rc;
+    hipLaunchKernelGGL(dav_eig, dim3(1), dim3(64), 0, s, k, ws, scal);
+    if ((rc = hip_check(hipGetLastError(), "dav_eig"))) return rc;
+    const int nb = (int)std::min<int64_t>(2048, (n + 255) / 256);
+    hipLaunchKernelGGL(dav_combine, dim3(nb), dim3(256), 0, s, n, k, V, ldv, S, lds, ws, x, hx, t);
+    if ((rc = hip_check(hipGetLastError(), "dav_combine"))) return rc;
+    if ((rc = dots_into(n, 1, t, n, t, ws, ws + DW_S + 1, 1, s))) return rc;  // |r|^2
+    hipLaunchKernelGGL(dav_precond, dim3(nb), dim3(256), 0, s, n, diag, guard, ws, t);
+    if ((rc = hip_check(hipGetLastError(), "dav_precond"))) return rc;
+    for (int pass = 0; pass < 2; ++pass) {
+        if ((rc = dots_into(n, k, V, ldv, t, ws, ws + DW_C, 1, s))) return rc;
+        hipLaunchKernelGGL(dav_project, dim3(nb), dim3(256), 0, s, n, k, V, ldv, ws, t);
+        if ((rc = hip_check(hipGetLastError(), "dav_project"))) return rc;
+    }
+    if ((rc = dots_into(n, 1, t, n, t, ws, ws + DW_S + 2, 1, s))) return rc;  // |t|^2
+    hipLaunchKernelGGL(dav_finish, dim3(nb), dim3(256), 0, s, n, ws, t, scal);
+    return hip_check(hipGetLastError(), "dav_finish");
+}
+
+}  // extern "C"

@@ -1,0 +1,1137 @@
+// Host-side plan builder: symmetry-sector bookkeeping, MPO operator mixing and
+// the owner-computes GEMM task lists of the two-site sigma-vector path and the
+// environment updates.  No HIP call is made here, so every function in this file
+// runs (and is tested) on a machine without a GPU.
+//
+// Method (Sec. II.A.1-2, II.C.1): sigma = sum_b Lhat_b psi Rhat_b^T with the
+// enlarged-block operators Lhat_b = sum_a L_a (x) W1_ab and Rhat_b = sum_c W2_bc (x) R_c.
+// For a fixed middle operator b and a fixed site transition (s' <- s) every
+// contributing environment operator has the same quantum-number shift, so the
+// sum over a (resp. c) is a plain linear combination of equally shaped
+// block-sparse matrices ("mixed operator"; these are the integral-weighted
+// complementary-operator sums).  The sigma-vector is then two rounds of block
+// GEMMs:  T_b = psi Rhat_b^T  and  sigma += Lhat_b T_b.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "heffx.h"
+#include "heffx_internal.h"
+
+namespace hx {
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+
+static const int SITE_Q[4][2] = {{0, 0}, {1, 1}, {1, -1}, {2, 0}};
+
+struct Bond {
+    std::vector<std::array<int, 2>> qn;
+    std::vector<int> dim;
+    std::unordered_map<int64_t, int> idx;
+    static int64_t key(int n, int s) { return (int64_t)(n + (1 << 20)) * (1 << 21) + (s + (1 << 20)); }
+    int find(int n, int s) const {
+        auto it = idx.find(key(n, s));
+        return it == idx.end() ? -1 : it->second;
+    }
+    int nsec() const { return (int)dim.size(); }
+};
+
+static bool parse_bond(const hx_bond* b, Bond& out, const char* what) {
+    if (!b || b->nsec <= 0 || !b->qn || !b->dim) {
+        set_error(std::string(what) + ": empty or null bond table");
+        return false;
+    }
+    out.qn.resize(b->nsec);
+    out.dim.resize(b->nsec);
+    for (int i = 0; i < b->nsec; ++i) {
+        out.qn[i] = {b->qn[2 * i], b->qn[2 * i + 1]};
+        out.dim[i] = b->dim[i];
+        if (b->dim[i] <= 0) {
+            set_error(std::string(what) + ": sector dimension must be positive");
+            return false;
+        }
+        if (i > 0 && !(out.qn[i - 1] < out.qn[i])) {
+            set_error(std::string(what) + ": sectors must be strictly increasing in (N, 2Sz)");
+            return false;
+        }
+        if (((out.qn[i][0] - out.qn[i][1]) & 1) != 0) {
+            set_error(std::string(what) + ": N and 2Sz must have equal parity");
+            return false;
+        }
+        out.idx[Bond::key(out.qn[i][0], out.qn[i][1])] = i;
+    }
+    return true;
+}
+
+struct OpSet {
+    std::vector<std::array<int, 2>> dq;
+};
+
+static bool parse_ops(const hx_opset* o, OpSet& out, const char* what) {
+    if (!o || o->nop < 0 || (o->nop > 0 && !o->dq)) {
+        set_error(std::string(what) + ": null operator set");
+        return false;
+    }
+    out.dq.resize(o->nop);
+    for (int a = 0; a < o->nop; ++a) out.dq[a] = {o->dq[2 * a], o->dq[2 * a + 1]};
+    return true;
+}
+
+// Layout of an environment payload (see heffx.h).
+struct EnvLayout {
+    std::vector<int64_t> op_off;   // nop + 1
+    std::vector<int64_t> blk_off;  // nop * nsec, -1 = absent
+    int nsec = 0;
+    int64_t blk(int a, int isrc) const { return blk_off[(size_t)a * nsec + isrc]; }
+};
+
+static EnvLayout env_layout(const Bond& b, const OpSet& ops) {
+    EnvLayout L;
+    L.nsec = b.nsec();
+    int nop = (int)ops.dq.size();
+    L.op_off.assign(nop + 1, 0);
+    L.blk_off.assign((size_t)nop * L.nsec, -1);
+    int64_t o = 0;
+    for (int a = 0; a < nop; ++a) {
+        L.op_off[a] = o;
+        for (int i = 0; i < L.nsec; ++i) {
+            int j = b.find(b.qn[i][0] + ops.dq[a][0], b.qn[i][1] + ops.dq[a][1]);
+            if (j < 0) continue;
+            L.blk_off[(size_t)a * L.nsec + i] = o;
+            o += (int64_t)b.dim[j] * b.dim[i];
+        }
+    }
+    L.op_off[nop] = o;
+    return L;
+}
+
+// Relative block offsets of an operator with shift dq on bond b.
+struct ShiftLayout {
+    std::vector<int64_t> rel;  // nsec, -1 absent
+    int64_t size = 0;
+};
+
+static ShiftLayout shift_layout(const Bond& b, int dn, int ds) {
+    ShiftLayout s;
+    s.rel.assign(b.nsec(), -1);
+    for (int i = 0; i < b.nsec(); ++i) {
+        int j = b.find(b.qn[i][0] + dn, b.qn[i][1] + ds);
+        if (j < 0) continue;
+        s.rel[i] = s.size;
+        s.size += (int64_t)b.dim[j] * b.dim[i];
+    }
+    return s;
+}
+
+struct PsiBlock {
+    int il, s1, s2, ir;
+    int64_t off;
+};
+
+struct PsiLayout {
+    std::vector<PsiBlock> blocks;
+    std::unordered_map<int64_t, int> by_key;  // (il, s1, s2) -> block
+    int64_t nnz = 0;
+    static int64_t key(int il, int s1, int s2) { return ((int64_t)il * 4 + s1) * 4 + s2; }
+    int find(int il, int s1, int s2) const {
+        auto it = by_key.find(key(il, s1, s2));
+        return it == by_key.end() ? -1 : it->second;
+    }
+};
+
+static PsiLayout psi_layout(const Bond& lb, const Bond& rb) {
+    PsiLayout P;
+    for (int il = 0; il < lb.nsec(); ++il)
+        for (int s1 = 0; s1 < 4; ++s1)
+            for (int s2 = 0; s2 < 4; ++s2) {
+                int ir = rb.find(lb.qn[il][0] + SITE_Q[s1][0] + SITE_Q[s2][0],
+                                 lb.qn[il][1] + SITE_Q[s1][1] + SITE_Q[s2][1]);
+                if (ir < 0) continue;
+                P.by_key[PsiLayout::key(il, s1, s2)] = (int)P.blocks.size();
+                P.blocks.push_back({il, s1, s2, ir, P.nnz});
+                P.nnz += (int64_t)lb.dim[il] * rb.dim[ir];
+            }
+    return P;
+}
+
+struct SiteBlock {
+    int il, s, ir;
+    int64_t off;
+};
+
+struct SiteLayout {
+    std::vector<SiteBlock> blocks;
+    std::vector<int> by_key;  // il*4+s -> block or -1
+    int64_t nnz = 0;
+    int find(int il, int s) const { return by_key[(size_t)il * 4 + s]; }
+};
+
+static SiteLayout site_layout(const Bond& lb, const Bond& rb) {
+    SiteLayout S;
+    S.by_key.assign((size_t)lb.nsec() * 4, -1);
+    for (int il = 0; il < lb.nsec(); ++il)
+        for (int s = 0; s < 4; ++s) {
+            int ir = rb.find(lb.qn[il][0] + SITE_Q[s][0], lb.qn[il][1] + SITE_Q[s][1]);
+            if (ir < 0) continue;
+            S.by_key[(size_t)il * 4 + s] = (int)S.blocks.size();
+            S.blocks.push_back({il, s, ir, S.nnz});
+            S.nnz += (int64_t)lb.dim[il] * rb.dim[ir];
+        }
+    return S;
+}
+
+// ---------------------------------------------------------------- MPO entries
+
+struct Entry {
+    int src, tgt;
+    double v[16];
+};
+
+// Parse MPO entries; `src_is_row` picks which side is the summed environment index.
+static bool parse_mpo(const hx_mpo_site* W, const OpSet& rows, const OpSet& cols, bool src_is_row,
+                      std::vector<Entry>& out, const char* what) {
+    if (!W || W->nnz < 0 || (W->nnz > 0 && (!W->row || !W->col || !W->val))) {
+        set_error(std::string(what) + ": null MPO table");
+        return false;
+    }
+    out.clear();
+    out.reserve(W->nnz);
+    for (int64_t e = 0; e < W->nnz; ++e) {
+        int r = W->row[e], c = W->col[e];
+        if (r < 0 || r >= (int)rows.dq.size() || c < 0 || c >= (int)cols.dq.size()) {
+            set_error(std::string(what) + ": operator index out of range");
+            return false;
+        }
+        int dn = cols.dq[c][0] - rows.dq[r][0], ds = cols.dq[c][1] - rows.dq[r][1];
+        Entry en;
+        en.src = src_is_row ? r : c;
+        en.tgt = src_is_row ? c : r;
+        for (int so = 0; so < 4; ++so)
+            for (int si = 0; si < 4; ++si) {
+                double v = W->val[16 * e + 4 * so + si];
+                en.v[4 * so + si] = v;
+                if (v != 0.0 && (SITE_Q[so][0] - SITE_Q[si][0] != dn || SITE_Q[so][1] - SITE_Q[si][1] != ds)) {
+                    set_error(std::string(what) + ": site matrix breaks (N, 2Sz) conservation");
+                    return false;
+                }
+            }
+        out.push_back(en);
+    }
+    return true;
+}
+
+// How a mixed operator (b, s'<-s) is referenced by the GEMM tasks.
+struct MixRef {
+    int8_t space;    // environment space (alias) or SP_WS (materialised)
+    int64_t base;    // element offset of the operator's payload
+    int dn, ds;      // shift
+    double alpha;
+};
+
+struct Trans {
+    int so, si;
+    MixRef m;
+};
+
+struct MixClass {
+    int dn, ds;
+    std::vector<int> cols;          // source operators with this shift (ascending)
+    std::unordered_map<int, int> col_of;
+    std::vector<std::vector<std::pair<int, double>>> rows;  // normalised term lists
+    int64_t size = 0;               // payload length of one operator
+    int64_t ws_base = 0;            // where its rows start in the workspace
+};
+
+struct Mixer {
+    // input
+    const Bond* bond;
+    const OpSet* ops;
+    const EnvLayout* lay;
+    int8_t env_space;
+    // output
+    std::vector<std::vector<Trans>> trans;  // per target operator
+    std::vector<MixClass> classes;
+    std::map<std::pair<int, int>, int> class_of;
+    double flops = 0;
+    int n_mixed = 0;
+};
+
+static void build_mixer(Mixer& M, const std::vector<Entry>& ents, int ntgt) {
+    M.trans.assign(ntgt, {});
+    // terms[tgt][(so,si)] -> (src -> coef)
+    std::vector<std::map<int, std::map<int, double>>> terms(ntgt);
+    for (const Entry& e : ents)
+        for (int t = 0; t < 16; ++t)
+            if (e.v[t] != 0.0) terms[e.tgt][t][e.src] += e.v[t];
+    std::map<std::vector<std::pair<int, uint64_t>>, std::pair<int, int>> seen;  // normalised -> (class,row)
+    for (int b = 0; b < ntgt; ++b) {
+        for (auto& kv : terms[b]) {
+            int t = kv.first;
+            std::vector<std::pair<int, double>> lst;
+            for (auto& sc : kv.second)
+                if (sc.second != 0.0) lst.push_back(sc);
+            if (lst.empty()) continue;
+            const auto& dq = M.ops->dq[lst[0].first];
+            Trans tr;
+            tr.so = t / 4;
+            tr.si = t % 4;
+            tr.m.dn = dq[0];
+            tr.m.ds = dq[1];
+            if (lst.size() == 1) {
+                tr.m.space = M.env_space;
+                tr.m.base = M.lay->op_off[lst[0].first];
+                tr.m.alpha = lst[0].second;
+            } else {
+                double c0 = lst[0].second;
+                std::vector<std::pair<int, uint64_t>> key;
+                std::vector<std::pair<int, double>> norm;
+                for (auto& sc : lst) {
+                    double v = sc.second / c0;
+                    uint64_t bits;
+                    std::memcpy(&bits, &v, 8);
+                    key.push_back({sc.first, bits});
+                    norm.push_back({sc.first, v});
+                }
+                auto ck = std::make_pair(dq[0], dq[1]);
+                int cls;
+                auto ci = M.class_of.find(ck);
+                if (ci == M.class_of.end()) {
+                    cls = (int)M.classes.size();
+                    M.class_of[ck] = cls;
+                    MixClass mc;
+                    mc.dn = dq[0];
+                    mc.ds = dq[1];
+                    for (int a = 0; a < (int)M.ops->dq.size(); ++a)
+                        if (M.ops->dq[a] == dq) {
+                            mc.col_of[a] = (int)mc.cols.size();
+                            mc.cols.push_back(a);
+                        }
+                    mc.size = M.lay->op_off[mc.cols[0] + 1] - M.lay->op_off[mc.cols[0]];
+                    M.classes.push_back(std::move(mc));
+                } else {
+                    cls = ci->second;
+                }
+                auto si = seen.find(key);
+                int row;
+                if (si != seen.end()) {
+                    row = si->second.second;
+                } else {
+                    row = (int)M.classes[cls].rows.size();
+                    M.classes[cls].rows.push_back(norm);
+                    seen[key] = {cls, row};
+                    M.flops += 2.0 * (double)norm.size() * (double)M.classes[cls].size;
+                    M.n_mixed++;
+                }
+                tr.m.space = SP_WS;
+                tr.m.base = -1 - ((int64_t)cls << 32 | row);  // resolved after ws placement
+                tr.m.alpha = c0;
+            }
+            M.trans[b].push_back(tr);
+        }
+    }
+}
+
+// Place materialised mixed operators in the workspace starting at ws0; return end.
+static int64_t place_mixer(Mixer& M, int64_t ws0) {
+    int64_t o = ws0;
+    for (auto& c : M.classes) {
+        c.ws_base = o;
+        o += c.size * (int64_t)c.rows.size();
+    }
+    for (auto& tv : M.trans)
+        for (auto& tr : tv)
+            if (tr.m.space == SP_WS && tr.m.base < 0) {
+                int64_t code = -1 - tr.m.base;
+                int cls = (int)(code >> 32), row = (int)(code & 0xffffffff);
+                tr.m.base = M.classes[cls].ws_base + (int64_t)row * M.classes[cls].size;
+            }
+    return o;
+}
+
+struct Builder {
+    Plan* P;
+    void add_block_tiles(int kind_unused, int64_t coff, int ldc, int m, int n, int8_t cspace, int8_t beta,
+                         int32_t tbeg, int32_t tend, int32_t ktot) {
+        (void)kind_unused;
+        for (int r0 = 0; r0 < m; r0 += TM)
+            for (int c0 = 0; c0 < n; c0 += TN) {
+                Tile t;
+                t.coff = coff + (int64_t)r0 * ldc + c0;
+                t.ldc = ldc;
+                t.m = std::min(TM, m - r0);
+                t.n = std::min(TN, n - c0);
+                t.r0 = r0;
+                t.c0 = c0;
+                t.tbeg = tbeg;
+                t.tend = tend;
+                t.ktot = ktot;
+                t.cspace = cspace;
+                t.beta = beta;
+                t.pad = 0;
+                P->tiles.push_back(t);
+            }
+    }
+};
+
+// Sort a launch's tiles by decreasing work (longest-processing-time first).
+static void sort_tiles(Plan& P, int64_t t0) {
+    std::stable_sort(P.tiles.begin() + t0, P.tiles.end(), [](const Tile& a, const Tile& b) {
+        return (int64_t)a.ktot * a.m * a.n > (int64_t)b.ktot * b.m * b.n;
+    });
+}
+
+// Emit the mixing GEMMs of a mixer: rows of a class in slabs of TM.
+static void emit_mixing(Plan& P, Mixer& M, std::vector<Launch>& seq) {
+    if (M.classes.empty()) return;
+    Launch L;
+    L.kind = NN;
+    L.tile0 = (int64_t)P.tiles.size();
+    L.flops = M.flops;
+    Builder B{&P};
+    for (auto& c : M.classes) {
+        int ncol = (int)c.cols.size();
+        int64_t coef0 = (int64_t)P.coef.size();
+        P.coef.resize(P.coef.size() + (size_t)ncol * c.rows.size(), 0.0);
+        for (size_t r = 0; r < c.rows.size(); ++r)
+            for (auto& sc : c.rows[r]) P.coef[coef0 + (int64_t)r * ncol + c.col_of.at(sc.first)] = sc.second;
+        int nrow = (int)c.rows.size();
+        for (int r0 = 0; r0 < nrow; r0 += TM) {
+            int mr = std::min(TM, nrow - r0);
+            // columns used by any row of the slab, merged into contiguous runs
+            std::vector<char> used(ncol, 0);
+            for (int r = r0; r < r0 + mr; ++r)
+                for (auto& sc : c.rows[r]) used[c.col_of.at(sc.first)] = 1;
+            int32_t tbeg = (int32_t)P.tasks.size();
+            int32_t ktot = 0;
+            int w = 0;
+            while (w < ncol) {
+                if (!used[w]) {
+                    ++w;
+                    continue;
+                }
+                int w1 = w + 1;
+                while (w1 < ncol && used[w1] &&
+                       M.lay->op_off[c.cols[w1]] == M.lay->op_off[c.cols[w1 - 1]] + c.size)
+                    ++w1;
+                Task t;
+                t.aoff = coef0 + (int64_t)r0 * ncol + w;
+                t.lda = ncol;
+                t.boff = M.lay->op_off[c.cols[w]];
+                t.ldb = (int32_t)c.size;
+                t.k = w1 - w;
+                t.aspace = SP_TAB;
+                t.bspace = M.env_space;
+                t.pad = 0;
+                t.alpha = 1.0;
+                P.tasks.push_back(t);
+                ktot += t.k;
+                w = w1;
+            }
+            int32_t tend = (int32_t)P.tasks.size();
+            // the mixed payload is written in chunks of TN elements; tile n <= TN
+            int64_t coff = c.ws_base + (int64_t)r0 * c.size;
+            for (int64_t c0 = 0; c0 < c.size; c0 += TN) {
+                Tile t;
+                t.coff = coff + c0;
+                t.ldc = (int32_t)c.size;
+                t.m = mr;
+                t.n = (int32_t)std::min<int64_t>(TN, c.size - c0);
+                t.r0 = 0;
+                t.c0 = (int32_t)c0;
+                t.tbeg = tbeg;
+                t.tend = tend;
+                t.ktot = ktot;
+                t.cspace = SP_WS;
+                t.beta = 0;
+                t.pad = 0;
+                P.tiles.push_back(t);
+            }
+            (void)B;
+        }
+    }
+    L.ntile = (int64_t)P.tiles.size() - L.tile0;
+    sort_tiles(P, L.tile0);
+    seq.push_back(L);
+}
+
+static int64_t default_budget(const hx_plan_opts* o) {
+    int64_t b = (o && o->t_budget_bytes > 0) ? o->t_budget_bytes : ((int64_t)2 << 30);
+    return b / 8;  // doubles
+}
+
+// ---------------------------------------------------------------- heff plan
+
+struct OutBlockTasks {
+    int64_t coff;
+    int ldc, m, n;
+    std::vector<Task> tasks;
+};
+
+static void flush_blocks(Plan& P, std::vector<OutBlockTasks>& blocks, int kind, int8_t cspace, int8_t beta,
+                         bool keep_empty, std::vector<Launch>& seq, double* flops_out, int64_t* ntask_out) {
+    Launch L;
+    L.kind = kind;
+    L.tile0 = (int64_t)P.tiles.size();
+    L.flops = 0;
+    Builder B{&P};
+    for (auto& ob : blocks) {
+        if (ob.tasks.empty() && !keep_empty) continue;
+        int32_t tbeg = (int32_t)P.tasks.size();
+        int32_t ktot = 0;
+        for (auto& t : ob.tasks) {
+            P.tasks.push_back(t);
+            ktot += t.k;
+            L.flops += 2.0 * ob.m * ob.n * (double)t.k;
+        }
+        int32_t tend = (int32_t)P.tasks.size();
+        if (ntask_out) *ntask_out += tend - tbeg;
+        B.add_block_tiles(kind, ob.coff, ob.ldc, ob.m, ob.n, cspace, beta, tbeg, tend, ktot);
+    }
+    L.ntile = (int64_t)P.tiles.size() - L.tile0;
+    sort_tiles(P, L.tile0);
+    if (flops_out) *flops_out += L.flops;
+    if (L.ntile > 0) seq.push_back(L);
+}
+
+static bool check_task_index_range(const Plan& P) {
+    if (P.tasks.size() > (size_t)INT32_MAX) {
+        set_error("plan too large: more than 2^31 GEMM tasks");
+        return false;
+    }
+    return true;
+}
+
+static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, const OpSet& Mo,
+                      const OpSet& Ro, const std::vector<Entry>& e1, const std::vector<Entry>& e2,
+                      const hx_plan_opts* opts) {
+    P.kind = PK_HEFF;
+    EnvLayout Ll = env_layout(lb, Lo), Rl = env_layout(rb, Ro);
+    PsiLayout psi = psi_layout(lb, rb);
+    P.psi_nnz = psi.nnz;
+    P.in_nnz = Ll.op_off.back();
+    P.in2_nnz = Rl.op_off.back();
+
+    Mixer ML{&lb, &Lo, &Ll, SP_L, {}, {}, {}, 0, 0};
+    Mixer MR{&rb, &Ro, &Rl, SP_R, {}, {}, {}, 0, 0};
+    build_mixer(ML, e1, (int)Mo.dq.size());
+    build_mixer(MR, e2, (int)Mo.dq.size());
+    int64_t ws = 0;
+    ws = place_mixer(ML, ws);
+    ws = place_mixer(MR, ws);
+    P.n_mixed = ML.n_mixed + MR.n_mixed;
+    P.flops_prepare = ML.flops + MR.flops;
+    emit_mixing(P, ML, P.prep);
+    emit_mixing(P, MR, P.prep);
+
+    // shift layouts of the mixed operators (block offsets relative to the payload)
+    std::map<std::pair<int, int>, ShiftLayout> lsh, rsh;
+    auto lshift = [&](int dn, int ds) -> const ShiftLayout& {
+        auto k = std::make_pair(dn, ds);
+        auto it = lsh.find(k);
+        if (it == lsh.end()) it = lsh.emplace(k, shift_layout(lb, dn, ds)).first;
+        return it->second;
+    };
+    auto rshift = [&](int dn, int ds) -> const ShiftLayout& {
+        auto k = std::make_pair(dn, ds);
+        auto it = rsh.find(k);
+        if (it == rsh.end()) it = rsh.emplace(k, shift_layout(rb, dn, ds)).first;
+        return it->second;
+    };
+
+    int nmid = (int)Mo.dq.size();
+    // psi blocks grouped by s2
+    std::vector<std::vector<int>> psi_by_s2(4);
+    for (int i = 0; i < (int)psi.blocks.size(); ++i) psi_by_s2[psi.blocks[i].s2].push_back(i);
+
+    // T sizes per b (for chunking)
+    std::vector<int64_t> tsize(nmid, 0);
+    std::vector<char> active(nmid, 0);
+    for (int b = 0; b < nmid; ++b) {
+        if (ML.trans[b].empty() || MR.trans[b].empty()) continue;
+        active[b] = 1;
+        std::unordered_map<int64_t, int64_t> seen;
+        for (auto& tr : MR.trans[b])
+            for (int pi : psi_by_s2[tr.si]) {
+                const PsiBlock& pb = psi.blocks[pi];
+                int irp = rb.find(rb.qn[pb.ir][0] + tr.m.dn, rb.qn[pb.ir][1] + tr.m.ds);
+                if (irp < 0) continue;
+                int64_t key = ((int64_t)pb.il * 4 + pb.s1) * 4 * 65536 + tr.so * 65536 + irp;
+                if (seen.emplace(key, 0).second) tsize[b] += (int64_t)lb.dim[pb.il] * rb.dim[irp];
+            }
+    }
+    int64_t budget = default_budget(opts);
+    std::vector<std::pair<int, int>> chunks;  // [b0, b1)
+    {
+        int b0 = 0;
+        int64_t acc = 0;
+        for (int b = 0; b < nmid; ++b) {
+            if (acc > 0 && acc + tsize[b] > budget) {
+                chunks.push_back({b0, b});
+                b0 = b;
+                acc = 0;
+            }
+            acc += tsize[b];
+        }
+        chunks.push_back({b0, nmid});
+    }
+    int64_t tmax = 0;
+    for (auto& ch : chunks) {
+        int64_t s = 0;
+        for (int b = ch.first; b < ch.second; ++b) s += tsize[b];
+        tmax = std::max(tmax, s);
+    }
+    int64_t t_ws = ws;
+    ws += tmax;
+    P.n_chunks = (int)chunks.size();
+
+    double fl = 0;
+    int64_t nt = 0;
+    double tbytes = 0;
+    for (size_t ci = 0; ci < chunks.size(); ++ci) {
+        // ---- stage 1: T_b[l, s1, s2', r'] = sum_{s2} psi[l,s1,s2,r] Rmix_{b,s2'<-s2}[r',r]^T
+        std::vector<OutBlockTasks> tblocks;
+        struct TInfo {
+            int b, il, s1, s2p, irp;
+            int64_t off;
+        };
+        std::vector<TInfo> tinfo;
+        std::unordered_map<int64_t, int> tidx;
+        int64_t toff = t_ws;
+        for (int b = chunks[ci].first; b < chunks[ci].second; ++b) {
+            if (!active[b]) continue;
+            tidx.clear();
+            std::vector<int> mine;
+            for (auto& tr : MR.trans[b]) {
+                const ShiftLayout& sl = rshift(tr.m.dn, tr.m.ds);
+                for (int pi : psi_by_s2[tr.si]) {
+                    const PsiBlock& pb = psi.blocks[pi];
+                    int irp = rb.find(rb.qn[pb.ir][0] + tr.m.dn, rb.qn[pb.ir][1] + tr.m.ds);
+                    if (irp < 0) continue;
+                    int64_t key = ((int64_t)pb.il * 4 + pb.s1) * 4 * 65536 + tr.so * 65536 + irp;
+                    auto it = tidx.find(key);
+                    int ti;
+                    if (it == tidx.end()) {
+                        ti = (int)tblocks.size();
+                        tidx[key] = ti;
+                        OutBlockTasks ob;
+                        ob.coff = toff;
+                        ob.ldc = rb.dim[irp];
+                        ob.m = lb.dim[pb.il];
+                        ob.n = rb.dim[irp];
+                        tblocks.push_back(std::move(ob));
+                        tinfo.push_back({b, pb.il, pb.s1, tr.so, irp, toff});
+                        toff += (int64_t)ob.m * ob.n;
+                        mine.push_back(ti);
+                    } else {
+                        ti = it->second;
+                    }
+                    Task t;
+                    t.aoff = pb.off;
+                    t.lda = rb.dim[pb.ir];
+                    t.aspace = SP_PSI;
+                    t.boff = tr.m.base + sl.rel[pb.ir];
+                    t.ldb = rb.dim[pb.ir];
+                    t.bspace = tr.m.space;
+                    t.k = rb.dim[pb.ir];
+                    t.pad = 0;
+                    t.alpha = tr.m.alpha;
+                    tblocks[ti].tasks.push_back(t);
+                }
+            }
+        }
+        for (auto& ob : tblocks) tbytes += 2.0 * 8.0 * ob.m * ob.n;
+        flush_blocks(P, tblocks, NT, SP_WS, 0, false, P.apply, &fl, &nt);
+
+        // ---- stage 2: sigma[l',s1',s2',r'] += sum Lmix_{b,s1'<-s1}[l',l] T_b[l,s1,s2',r']
+        std::vector<OutBlockTasks> sblocks(psi.blocks.size());
+        for (size_t i = 0; i < psi.blocks.size(); ++i) {
+            const PsiBlock& pb = psi.blocks[i];
+            sblocks[i].coff = pb.off;
+            sblocks[i].ldc = rb.dim[pb.ir];
+            sblocks[i].m = lb.dim[pb.il];
+            sblocks[i].n = rb.dim[pb.ir];
+        }
+        for (const TInfo& ti : tinfo) {
+            for (auto& tr : ML.trans[ti.b]) {
+                if (tr.si != ti.s1) continue;
+                int ilp = lb.find(lb.qn[ti.il][0] + tr.m.dn, lb.qn[ti.il][1] + tr.m.ds);
+                if (ilp < 0) continue;
+                int si = psi.find(ilp, tr.so, ti.s2p);
+                if (si < 0 || psi.blocks[si].ir != ti.irp) {
+                    set_error("internal: sigma block inconsistent with quantum numbers");
+                    return HX_EINVAL;
+                }
+                const ShiftLayout& sl = lshift(tr.m.dn, tr.m.ds);
+                Task t;
+                t.aoff = tr.m.base + sl.rel[ti.il];
+                t.lda = lb.dim[ti.il];
+                t.aspace = tr.m.space;
+                t.boff = ti.off;
+                t.ldb = rb.dim[ti.irp];
+                t.bspace = SP_WS;
+                t.k = lb.dim[ti.il];
+                t.pad = 0;
+                t.alpha = tr.m.alpha;
+                sblocks[si].tasks.push_back(t);
+            }
+        }
+        flush_blocks(P, sblocks, NN, SP_OUT, ci == 0 ? 0 : 1, ci == 0, P.apply, &fl, &nt);
+    }
+    P.flops_apply = fl;
+    P.n_tasks_apply = nt;
+    for (auto& L : P.apply) P.n_tiles_apply += L.ntile;
+
+    // algorithmic bytes of one apply: psi, sigma, T traffic and every referenced operator once
+    {
+        double ob = 0;
+        std::map<std::pair<int, int64_t>, int64_t> seen;
+        for (int b = 0; b < nmid; ++b) {
+            if (!active[b]) continue;
+            for (auto& tr : ML.trans[b]) seen[{tr.m.space, tr.m.base}] = lshift(tr.m.dn, tr.m.ds).size;
+            for (auto& tr : MR.trans[b]) seen[{tr.m.space, tr.m.base}] = rshift(tr.m.dn, tr.m.ds).size;
+        }
+        for (auto& kv : seen) ob += 8.0 * kv.second;
+        P.bytes_apply = ob + 16.0 * psi.nnz + tbytes;
+    }
+
+    // ---- diagonal: diag[l,s1,s2,r](x,y) = sum_b DL[(l,s1)][x,b] DR[(s2,r)][b,y]
+    std::vector<int> b0;
+    for (int b = 0; b < nmid; ++b) {
+        if (!active[b] || Mo.dq[b][0] != 0 || Mo.dq[b][1] != 0) continue;
+        bool l = false, r = false;
+        for (auto& tr : ML.trans[b]) l |= (tr.so == tr.si);
+        for (auto& tr : MR.trans[b]) r |= (tr.so == tr.si);
+        if (l && r) b0.push_back(b);
+    }
+    int nb0 = (int)b0.size();
+    int64_t dl_base = ws;
+    std::vector<int64_t> dl_off((size_t)lb.nsec() * 4), dr_off((size_t)rb.nsec() * 4);
+    int64_t o = dl_base;
+    for (int il = 0; il < lb.nsec(); ++il)
+        for (int s = 0; s < 4; ++s) {
+            dl_off[(size_t)il * 4 + s] = o;
+            o += (int64_t)lb.dim[il] * nb0;
+        }
+    for (int ir = 0; ir < rb.nsec(); ++ir)
+        for (int s = 0; s < 4; ++s) {
+            dr_off[(size_t)ir * 4 + s] = o;
+            o += (int64_t)rb.dim[ir] * nb0;
+        }
+    ws = o;
+    P.diag_fill.push_back({SP_WS, dl_base, o - dl_base});
+    GatherLaunch gl;
+    gl.g0 = (int64_t)P.gathers.size();
+    for (int j = 0; j < nb0; ++j) {
+        int b = b0[j];
+        for (auto& tr : ML.trans[b]) {
+            if (tr.so != tr.si || tr.m.dn != 0 || tr.m.ds != 0) continue;
+            const ShiftLayout& sl = lshift(0, 0);
+            for (int il = 0; il < lb.nsec(); ++il) {
+                Gather g;
+                g.soff = tr.m.base + sl.rel[il];
+                g.sstride = lb.dim[il] + 1;
+                g.sspace = tr.m.space;
+                g.doff = dl_off[(size_t)il * 4 + tr.so] + j;
+                g.dstride = nb0;
+                g.dspace = SP_WS;
+                g.count = lb.dim[il];
+                g.alpha = tr.m.alpha;
+                g.pad = 0;
+                P.gathers.push_back(g);
+            }
+        }
+        for (auto& tr : MR.trans[b]) {
+            if (tr.so != tr.si || tr.m.dn != 0 || tr.m.ds != 0) continue;
+            const ShiftLayout& sl = rshift(0, 0);
+            for (int ir = 0; ir < rb.nsec(); ++ir) {
+                Gather g;
+                g.soff = tr.m.base + sl.rel[ir];
+                g.sstride = rb.dim[ir] + 1;
+                g.sspace = tr.m.space;
+                g.doff = dr_off[(size_t)ir * 4 + tr.so] + (int64_t)j * rb.dim[ir];
+                g.dstride = 1;
+                g.dspace = SP_WS;
+                g.count = rb.dim[ir];
+                g.alpha = tr.m.alpha;
+                g.pad = 0;
+                P.gathers.push_back(g);
+            }
+        }
+    }
+    gl.ng = (int64_t)P.gathers.size() - gl.g0;
+    if (gl.ng) P.diag_gather.push_back(gl);
+    {
+        std::vector<OutBlockTasks> dblocks(psi.blocks.size());
+        for (size_t i = 0; i < psi.blocks.size(); ++i) {
+            const PsiBlock& pb = psi.blocks[i];
+            OutBlockTasks& ob = dblocks[i];
+            ob.coff = pb.off;
+            ob.ldc = rb.dim[pb.ir];
+            ob.m = lb.dim[pb.il];
+            ob.n = rb.dim[pb.ir];
+            if (nb0 > 0) {
+                Task t;
+                t.aoff = dl_off[(size_t)pb.il * 4 + pb.s1];
+                t.lda = nb0;
+                t.aspace = SP_WS;
+                t.boff = dr_off[(size_t)pb.ir * 4 + pb.s2];
+                t.ldb = rb.dim[pb.ir];
+                t.bspace = SP_WS;
+                t.k = nb0;
+                t.pad = 0;
+                t.alpha = 1.0;
+                ob.tasks.push_back(t);
+            }
+        }
+        flush_blocks(P, dblocks, NN, SP_OUT, 0, true, P.diag_gemm, nullptr, nullptr);
+    }
+    P.ws_doubles = ws;
+    if (!check_task_index_range(P)) return HX_EINVAL;
+    return HX_OK;
+}
+
+// ---------------------------------------------------------------- env plans
+
+static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const OpSet& oin, const OpSet& oout,
+                     const std::vector<Entry>& ents, const hx_plan_opts* opts) {
+    // dir 0: bin = bond k (lb), bout = bond k+1; site tensor between bin and bout.
+    // dir 1: bin = bond k+1 (rb), bout = bond k; site tensor between bout and bin.
+    P.kind = dir == 0 ? PK_ENV_LEFT : PK_ENV_RIGHT;
+    EnvLayout Lin = env_layout(bin, oin), Lout = env_layout(bout, oout);
+    SiteLayout S = dir == 0 ? site_layout(bin, bout) : site_layout(bout, bin);
+    P.in_nnz = Lin.op_off.back();
+    P.in2_nnz = S.nnz;
+    P.out_nnz = Lout.op_off.back();
+    Mixer M{&bin, &oin, &Lin, SP_PSI, {}, {}, {}, 0, 0};
+    build_mixer(M, ents, (int)oout.dq.size());
+    int64_t ws = place_mixer(M, 0);
+    P.n_mixed = M.n_mixed;
+    P.flops_prepare = M.flops;
+    emit_mixing(P, M, P.apply);  // env update = mixing + E1 + E2 in one call
+
+    std::map<std::pair<int, int>, ShiftLayout> shl;
+    auto shift = [&](int dn, int ds) -> const ShiftLayout& {
+        auto k = std::make_pair(dn, ds);
+        auto it = shl.find(k);
+        if (it == shl.end()) it = shl.emplace(k, shift_layout(bin, dn, ds)).first;
+        return it->second;
+    };
+    int nout = (int)oout.dq.size();
+    // site blocks grouped by site state
+    std::vector<std::vector<int>> by_s(4);
+    for (int i = 0; i < (int)S.blocks.size(); ++i) by_s[S.blocks[i].s].push_back(i);
+
+    // intermediate size per b
+    std::vector<int64_t> ysize(nout, 0);
+    for (int b = 0; b < nout; ++b) {
+        std::unordered_map<int64_t, char> seen;
+        for (auto& tr : M.trans[b])
+            for (int si : by_s[tr.si]) {
+                const SiteBlock& sb = S.blocks[si];
+                int x = dir == 0 ? sb.il : sb.ir;   // the index the mixed op acts on (in bin)
+                int xp = bin.find(bin.qn[x][0] + tr.m.dn, bin.qn[x][1] + tr.m.ds);
+                if (xp < 0) continue;
+                int y = dir == 0 ? sb.ir : sb.il;   // the free index (in bout)
+                int64_t key = ((int64_t)xp * 4 + tr.so) * 65536 + y;
+                if (seen.emplace(key, 1).second) ysize[b] += (int64_t)bin.dim[xp] * bout.dim[y];
+            }
+    }
+    int64_t budget = default_budget(opts);
+    std::vector<std::pair<int, int>> chunks;
+    {
+        int b0 = 0;
+        int64_t acc = 0;
+        for (int b = 0; b < nout; ++b) {
+            if (acc > 0 && acc + ysize[b] > budget) {
+                chunks.push_back({b0, b});
+                b0 = b;
+                acc = 0;
+            }
+            acc += ysize[b];
+        }
+        chunks.push_back({b0, nout});
+    }
+    int64_t ymax = 0;
+    for (auto& ch : chunks) {
+        int64_t s = 0;
+        for (int b = ch.first; b < ch.second; ++b) s += ysize[b];
+        ymax = std::max(ymax, s);
+    }
+    int64_t y_ws = ws;
+    ws += ymax;
+    P.n_chunks = (int)chunks.size();
+    double fl = 0;
+    int64_t nt = 0;
+    for (auto& ch : chunks) {
+        std::vector<OutBlockTasks> yblocks;
+        struct YInfo {
+            int b, xp, so, y;
+            int64_t off;
+        };
+        std::vector<YInfo> yinfo;
+        std::unordered_map<int64_t, int> yidx;
+        int64_t yoff = y_ws;
+        for (int b = ch.first; b < ch.second; ++b) {
+            yidx.clear();
+            for (auto& tr : M.trans[b]) {
+                const ShiftLayout& sl = shift(tr.m.dn, tr.m.ds);
+                for (int si : by_s[tr.si]) {
+                    const SiteBlock& sb = S.blocks[si];
+                    int x = dir == 0 ? sb.il : sb.ir;
+                    int y = dir == 0 ? sb.ir : sb.il;
+                    int xp = bin.find(bin.qn[x][0] + tr.m.dn, bin.qn[x][1] + tr.m.ds);
+                    if (xp < 0) continue;
+                    int64_t key = ((int64_t)xp * 4 + tr.so) * 65536 + y;
+                    auto it = yidx.find(key);
+                    int yi;
+                    if (it == yidx.end()) {
+                        yi = (int)yblocks.size();
+                        yidx[key] = yi;
+                        OutBlockTasks ob;
+                        ob.coff = yoff;
+                        ob.m = bin.dim[xp];
+                        ob.n = bout.dim[y];
+                        ob.ldc = ob.n;
+                        yblocks.push_back(std::move(ob));
+                        yinfo.push_back({b, xp, tr.so, y, yoff});
+                        yoff += (int64_t)bin.dim[xp] * bout.dim[y];
+                    } else {
+                        yi = it->second;
+                    }
+                    Task t;
+                    t.aoff = tr.m.base + sl.rel[x];   // mixed op block (xp <- x)
+                    t.lda = bin.dim[x];
+                    t.aspace = tr.m.space;
+                    t.boff = sb.off;                  // site block
+                    t.ldb = dir == 0 ? bout.dim[y] : bin.dim[x];
+                    t.bspace = SP_R;
+                    t.k = bin.dim[x];
+                    t.pad = 0;
+                    t.alpha = tr.m.alpha;
+                    yblocks[yi].tasks.push_back(t);
+                }
+            }
+        }
+        flush_blocks(P, yblocks, dir == 0 ? NN : NT, SP_WS, 0, false, P.apply, &fl, &nt);
+
+        // E2: out_b[y' <- y] = sum_{(xp, so)} op(site[(xp,so) -> y']) Y_b[xp, so, y]
+        std::vector<OutBlockTasks> oblocks;
+        std::unordered_map<int64_t, int> oidx;
+        for (int b = ch.first; b < ch.second; ++b)
+            for (int y = 0; y < bout.nsec(); ++y) {
+                int64_t off = Lout.blk(b, y);
+                if (off < 0) continue;
+                int yp = bout.find(bout.qn[y][0] + oout.dq[b][0], bout.qn[y][1] + oout.dq[b][1]);
+                OutBlockTasks ob;
+                ob.coff = off;
+                ob.m = bout.dim[yp];
+                ob.n = bout.dim[y];
+                ob.ldc = ob.n;
+                oidx[(int64_t)b * 65536 + y] = (int)oblocks.size();
+                oblocks.push_back(std::move(ob));
+            }
+        for (const YInfo& yi : yinfo) {
+            int yp = bout.find(bout.qn[yi.y][0] + oout.dq[yi.b][0], bout.qn[yi.y][1] + oout.dq[yi.b][1]);
+            if (yp < 0) continue;
+            int sbk;
+            if (dir == 0) {
+                sbk = S.find(yi.xp, yi.so);  // A block (xp, so) -> must land on yp
+                if (sbk < 0 || S.blocks[sbk].ir != yp) continue;
+            } else {
+                sbk = S.find(yp, yi.so);     // B block (yp, so) -> must land on xp
+                if (sbk < 0 || S.blocks[sbk].ir != yi.xp) continue;
+            }
+            auto it = oidx.find((int64_t)yi.b * 65536 + yi.y);
+            if (it == oidx.end()) {
+                set_error("internal: environment block missing");
+                return HX_EINVAL;
+            }
+            Task t;
+            t.aoff = S.blocks[sbk].off;
+            t.lda = dir == 0 ? bout.dim[yp] : bin.dim[yi.xp];
+            t.aspace = SP_R;
+            t.boff = yi.off;
+            t.ldb = bout.dim[yi.y];
+            t.bspace = SP_WS;
+            t.k = bin.dim[yi.xp];
+            t.pad = 0;
+            t.alpha = 1.0;
+            oblocks[it->second].tasks.push_back(t);
+        }
+        flush_blocks(P, oblocks, dir == 0 ? TN_ : NN, SP_OUT, 0, true, P.apply, &fl, &nt);
+    }
+    P.flops_apply = fl + M.flops;
+    P.n_tasks_apply = nt;
+    for (auto& L : P.apply) P.n_tiles_apply += L.ntile;
+    P.ws_doubles = ws;
+    P.bytes_apply = 8.0 * (P.in_nnz + P.in2_nnz + P.out_nnz);
+    if (!check_task_index_range(P)) return HX_EINVAL;
+    return HX_OK;
+}
+
+static void finalize_tables(Plan& P) {
+    auto al = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
+    int64_t o = 0;
+    P.off_tiles = o;
+    o = al(o + (int64_t)P.tiles.size() * sizeof(Tile));
+    P.off_tasks = o;
+    o = al(o + (int64_t)P.tasks.size() * sizeof(Task));
+    P.off_gathers = o;
+    o = al(o + (int64_t)P.gathers.size() * sizeof(Gather));
+    P.off_coef = o;
+    o = al(o + (int64_t)P.coef.size() * sizeof(double));
+    P.table_bytes = std::max<int64_t>(o, 256);
+}
+
+}  // namespace hx
+
+using namespace hx;
+
+extern "C" {
+
+const char* hx_last_error(void) { return g_err.c_str(); }
+
+int hx_env_layout(const hx_bond* bond, const hx_opset* ops, int64_t* op_off, int64_t* blk_off) {
+    Bond b;
+    OpSet o;
+    if (!parse_bond(bond, b, "env_layout") || !parse_ops(ops, o, "env_layout")) return HX_EINVAL;
+    EnvLayout L = env_layout(b, o);
+    if (op_off) std::copy(L.op_off.begin(), L.op_off.end(), op_off);
+    if (blk_off) std::copy(L.blk_off.begin(), L.blk_off.end(), blk_off);
+    return HX_OK;
+}
+
+int64_t hx_psi_layout(const hx_bond* lbond, const hx_bond* rbond, int64_t max_blocks, int32_t* keys,
+                      int64_t* off) {
+    Bond lb, rb;
+    if (!parse_bond(lbond, lb, "psi_layout left") || !parse_bond(rbond, rb, "psi_layout right")) return HX_EINVAL;
+    PsiLayout P = psi_layout(lb, rb);
+    int64_t n = (int64_t)P.blocks.size();
+    if (keys || off) {
+        if (max_blocks < n) {
+            set_error("psi_layout: max_blocks too small");
+            return HX_EINVAL;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (keys) {
+                keys[4 * i] = P.blocks[i].il;
+                keys[4 * i + 1] = P.blocks[i].s1;
+                keys[4 * i + 2] = P.blocks[i].s2;
+                keys[4 * i + 3] = P.blocks[i].ir;
+            }
+            if (off) off[i] = P.blocks[i].off;
+        }
+        if (off) off[n] = P.nnz;
+    }
+    return n;
+}
+
+int64_t hx_site_layout(const hx_bond* lbond, const hx_bond* rbond, int64_t max_blocks, int32_t* keys,
+                       int64_t* off) {
+    Bond lb, rb;
+    if (!parse_bond(lbond, lb, "site_layout left") || !parse_bond(rbond, rb, "site_layout right"))
+        return HX_EINVAL;
+    SiteLayout S = site_layout(lb, rb);
+    int64_t n = (int64_t)S.blocks.size();
+    if (keys || off) {
+        if (max_blocks < n) {
+            set_error("site_layout: max_blocks too small");
+            return HX_EINVAL;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            if (keys) {
+                keys[3 * i] = S.blocks[i].il;
+                keys[3 * i + 1] = S.blocks[i].s;
+                keys[3 * i + 2] = S.blocks[i].ir;
+            }
+            if (off) off[i] = S.blocks[i].off;
+        }
+        if (off) off[n] = S.nnz;
+    }
+    return n;
+}
+
+int hx_heff_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops, const hx_opset* mid,
+                        const hx_opset* Rops, const hx_mpo_site* W1, const hx_mpo_site* W2,
+                        const hx_plan_opts* opts, hx_plan** out) {
+    if (!out) {
+        set_error("heff_plan_create: null output");
+        return HX_EINVAL;
+    }
+    *out = nullptr;
+    Bond lb, rb;
+    OpSet Lo, Mo, Ro;
+    if (!parse_bond(lbond, lb, "heff left bond") || !parse_bond(rbond, rb, "heff right bond")) return HX_EINVAL;
+    if (!parse_ops(Lops, Lo, "heff Lops") || !parse_ops(mid, Mo, "heff mid") || !parse_ops(Rops, Ro, "heff Rops"))
+        return HX_EINVAL;
+    std::vector<Entry> e1, e2;
+    if (!parse_mpo(W1, Lo, Mo, true, e1, "heff W1") || !parse_mpo(W2, Mo, Ro, false, e2, "heff W2"))
+        return HX_EINVAL;
+    Plan* P = new Plan();
+    int rc = build_heff(*P, lb, rb, Lo, Mo, Ro, e1, e2, opts);
+    if (rc != HX_OK) {
+        delete P;
+        return rc;
+    }
+    finalize_tables(*P);
+    *out = reinterpret_cast<hx_plan*>(P);
+    return HX_OK;
+}
+
+int hx_env_plan_create(int direction, const hx_bond* bond_in, const hx_bond* bond_out, const hx_opset* ops_in,
+                       const hx_opset* ops_out, const hx_mpo_site* W, const hx_plan_opts* opts, hx_plan** out) {
+    if (!out || (direction != 0 && direction != 1)) {
+        set_error("env_plan_create: bad direction or null output");
+        return HX_EINVAL;
+    }
+    *out = nullptr;
+    Bond bi, bo;
+    OpSet oi, oo;
+    if (!parse_bond(bond_in, bi, "env bond_in") || !parse_bond(bond_out, bo, "env bond_out")) return HX_EINVAL;
+    if (!parse_ops(ops_in, oi, "env ops_in") || !parse_ops(ops_out, oo, "env ops_out")) return HX_EINVAL;
+    std::vector<Entry> ents;
+    bool ok = direction == 0 ? parse_mpo(W, oi, oo, true, ents, "env W") : parse_mpo(W, oo, oi, false, ents, "env W");
+    if (!ok) return HX_EINVAL;
+    Plan* P = new Plan();
+    int rc = build_env(*P, direction, bi, bo, oi, oo, ents, opts);
+    if (rc != HX_OK) {
+        delete P;
+        return rc;
+    }
+    finalize_tables(*P);
+    *out = reinterpret_cast<hx_plan*>(P);
+    return HX_OK;
+}
+
+int hx_plan_get_info(const hx_plan* plan, hx_plan_info* info) {
+    if (!plan || !info) {
+        set_error("plan_info: null argument");
+        return HX_EINVAL;
+    }
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    info->psi_nnz = P->psi_nnz;
+    info->in_nnz = P->in_nnz;
+    info->in2_nnz = P->in2_nnz;
+    info->out_nnz = P->out_nnz;
+    info->table_bytes = P->table_bytes;
+    info->ws_bytes = std::max<int64_t>(P->ws_doubles * 8, 256);
+    info->flops_apply = P->flops_apply;
+    info->flops_prepare = P->flops_prepare;
+    info->bytes_apply = P->bytes_apply;
+    info->n_tasks = P->n_tasks_apply;
+    info->n_tiles = P->n_tiles_apply;
+    info->n_chunks = P->n_chunks;
+    info->n_mixed = P->n_mixed;
+    return HX_OK;
+}
+
+void hx_plan_destroy(hx_plan* plan) { delete reinterpret_cast<Plan*>(plan); }
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+"""Device-side state of a two-site sweep: environments, plans and site tensors.
+
+Thin orchestration over the HIP library: plans are built on the host once per
+(site, bond tables) and cached; every contraction is a library call on the
+current HIP stream.  Environments live in HBM as flat payloads in the library's
+layout (include/heffx.h).
+"""
+
+import numpy as np
+
+from . import _lib as X
+from . import mpo as M
+
+
+class Engine:
+    """Environments of one MPO on the GPU.
+
+    left[k]  : payload of the left environment at cut k (ops mpo.cuts[k], bond k)
+    right[k] : payload of the right environment at cut k (ops mpo.cuts[k], bond k)
+    """
+
+    def __init__(self, mpo, device="cuda", t_budget_bytes=0):
+        import torch
+        self.torch = torch
+        self.mpo = mpo
+        self.K = mpo.K
+        self.device = device
+        self.t_budget = t_budget_bytes
+        self.left = {}
+        self.right = {}
+        self._env_plans = {}
+        self._heff_plans = {}
+        self._w = [X.MpoSite(s.rows, s.cols, s.mats) for s in mpo.sites]
+
+    # -- boundaries: the vacuum bond carries the identity, the full bond carries H
+    def init_boundaries(self):
+        t = self.torch
+        self.left[0] = t.ones(1, dtype=t.float64, device=self.device)
+        self.right[self.K] = t.ones(1, dtype=t.float64, device=self.device)
+
+    @staticmethod
+    def _bkey(bond):
+        return tuple((tuple(q), int(m)) for q, m in bond)
+
+    def env_plan(self, direction, k, bond_k, bond_k1):
+        key = (direction, k, self._bkey(bond_k), self._bkey(bond_k1))
+        p = self._env_plans.get(key)
+        if p is None:
+            if direction == 0:
+                p = X.EnvPlan(0, bond_k, bond_k1, self.mpo.dq[k], self.mpo.dq[k + 1], self._w[k],
+                              t_budget_bytes=self.t_budget).upload(self.device)
+            else:
+                p = X.EnvPlan(1, bond_k1, bond_k, self.mpo.dq[k + 1], self.mpo.dq[k], self._w[k],
+                              t_budget_bytes=self.t_budget).upload(self.device)
+            self._env_plans[key] = p
+        return p
+
+    def heff_plan(self, i, bond_i, bond_i2):
+        key = (i, self._bkey(bond_i), self._bkey(bond_i2))
+        p = self._heff_plans.get(key)
+        if p is None:
+            p = X.HeffPlan(bond_i, bond_i2, self.mpo.dq[i], self.mpo.dq[i + 1], self.mpo.dq[i + 2],
+                           self._w[i], self._w[i + 1], t_budget_bytes=self.t_budget).upload(self.device)
+            self._heff_plans[key] = p
+        return p
+
+    def drop_plans(self):
+        self._env_plans.clear()
+        self._heff_plans.clear()
+
+    def update_left(self, k, bond_k, bond_k1, A):
+        """left[k+1] from left[k] and the left-canonical tensor A (payload) of site k."""
+        p = self.env_plan(0, k, bond_k, bond_k1)
+        out = self.torch.empty(int(p.info.out_nnz), dtype=self.torch.float64, device=self.device)
+        p.update(self.left[k], A, out)
+        self.left[k + 1] = out
+        return out
+
+    def update_right(self, k, bond_k, bond_k1, B):
+        """right[k] from right[k+1] and the right-canonical tensor B (payload) of site k."""
+        p = self.env_plan(1, k, bond_k, bond_k1)
+        out = self.torch.empty(int(p.info.out_nnz), dtype=self.torch.float64, device=self.device)
+        p.update(self.right[k + 1], B, out)
+        self.right[k] = out
+        return out
+
+
+def site_payload(bond_l, bond_r, tensor, device="cuda"):
+    import torch
+    return torch.from_numpy(X.pack_site(X.Bond(bond_l), X.Bond(bond_r), tensor)).to(device)
+
+
+def mpo_from_integrals(h, g):
+    return M.build_nc_mpo(np.asarray(h), np.asarray(g))

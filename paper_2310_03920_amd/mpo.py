@@ -1,0 +1,374 @@
+"""Normal/complementary (NC) partition MPO for the ab initio Hamiltonian.
+
+Sec. II.C.1 builds the ab initio Hamiltonian as a symbolic MPO whose bond
+operators are the normal and complementary renormalised operators of
+traditional DMRG, in the NC partition.  This module builds that MPO explicitly:
+
+* Spin orbitals j = 2p + sigma, site-major (0a, 0b, 1a, 1b, ...).
+* Site basis [empty, alpha, beta, alpha-beta] and on-site matrices c, d, C, D as
+  printed in Listing 1; P = diag(1, -1, -1, 1) is the site parity.
+* Bond operators at cut k (left block = sites 0..k-1), in the NC partition:
+    I, H_L,
+    C_x = a+_x, D_x = a_x                 (x in the left block),
+    A_xy = a+_x a+_y, Ad_xy = a_y a_x     (x < y in the left block),
+    B_xy = a+_x a_y                       (x, y in the left block),
+    T_j, Td_j                             (j in the right block): the left-block
+        factors of all terms whose only right-block operator is a_j (resp. a+_j),
+        i.e. the left complementary operators of the single operators.
+  Their right-block partners (H_R, the three-operator S terms, the pair
+  operators P and Q, a_j / a+_j) are implied by the MPO recursion.
+* Jordan-Wigner strings are carried by the MPO: the bond operator of an odd
+  left-block operator X is X_JW times the left-block parity.  With this choice a
+  bond operator at cut k+1 built from a bond operator at cut k and an on-site
+  product x of ladder operators has site factor x . P^{parity of the new operator},
+  and H = W^(0) W^(1) ... W^(K-1) with every product a plain Kronecker product.
+
+Two-body coefficients: H2 = 1/2 sum V_ijkl a+_i a+_j a_k a_l with
+V_ijkl = g[p_i, p_l, p_j, p_k] delta(s_i, s_l) delta(s_j, s_k) (chemists'
+notation (pq|rs)); the one-body part is t_ij = h[p_i, p_j] delta(s_i, s_j).
+"""
+
+import itertools
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SITE_QN = ((0, 0), (1, 1), (1, -1), (2, 0))
+
+_c = np.array([[0, 0, 0, 0], [1, 0, 0, 0], [0, 0, 0, 0], [0, 0, 1, 0]], float)
+_d = _c.T.copy()
+_C = np.array([[0, 0, 0, 0], [0, 0, 0, 0], [1, 0, 0, 0], [0, -1, 0, 0]], float)
+_D = _C.T.copy()
+_P = np.diag([1.0, -1.0, -1.0, 1.0])
+_I = np.eye(4)
+CR = (_c, _C)  # a+_alpha, a+_beta
+AN = (_d, _D)  # a_alpha, a_beta
+
+
+def _spin_sign(j):
+    return 1 if j % 2 == 0 else -1
+
+
+def op_dq(key):
+    """(dN, d2Sz) of a bond operator (as an operator on the left block)."""
+    kind = key[0]
+    if kind in ("I", "H"):
+        return (0, 0)
+    if kind == "C":
+        return (1, _spin_sign(key[1]))
+    if kind == "D":
+        return (-1, -_spin_sign(key[1]))
+    if kind == "A":
+        return (2, _spin_sign(key[1]) + _spin_sign(key[2]))
+    if kind == "Ad":
+        return (-2, -_spin_sign(key[1]) - _spin_sign(key[2]))
+    if kind == "B":
+        return (0, _spin_sign(key[1]) - _spin_sign(key[2]))
+    if kind == "T":   # partner of a_j: left factor carries +dq(a+_j)
+        return (1, _spin_sign(key[1]))
+    if kind == "Td":
+        return (-1, -_spin_sign(key[1]))
+    raise KeyError(key)
+
+
+def op_parity(key):
+    return 1 if key[0] in ("C", "D", "T", "Td") else 0
+
+
+def cut_ops(K, k):
+    """Bond operators at cut k (before pruning), in a fixed order."""
+    ops = []
+    if k < K:
+        ops.append(("I",))
+    if k >= 1:
+        ops.append(("H",))
+    if 0 < k < K:
+        n = 2 * k
+        ops += [("C", x) for x in range(n)]
+        ops += [("D", x) for x in range(n)]
+        ops += [("A", x, y) for x in range(n) for y in range(x + 1, n)]
+        ops += [("Ad", x, y) for x in range(n) for y in range(x + 1, n)]
+        ops += [("B", x, y) for x in range(n) for y in range(n)]
+        ops += [("T", j) for j in range(n, 2 * K)]
+        ops += [("Td", j) for j in range(n, 2 * K)]
+    return ops
+
+
+class _Coef:
+    """Spin-orbital one- and two-body coefficients from spatial integrals."""
+
+    def __init__(self, h, g):
+        self.h, self.g = h, g
+
+    def t(self, i, j):
+        i, j = np.asarray(i), np.asarray(j)
+        return self.h[i // 2, j // 2] * ((i % 2) == (j % 2))
+
+    def v(self, i, j, k, l):
+        i, j, k, l = (np.asarray(x) for x in (i, j, k, l))
+        return (self.g[i // 2, l // 2, j // 2, k // 2]
+                * ((i % 2) == (l % 2)) * ((j % 2) == (k % 2)))
+
+
+def _inversions(regions):
+    inv = 0
+    for p in range(len(regions)):
+        for q in range(p + 1, len(regions)):
+            if regions[p] > regions[q]:
+                inv += 1
+    return inv
+
+
+@dataclass
+class SiteMPO:
+    """W^(k): entries (row op index at cut k, column op index at cut k+1, 4x4)."""
+    rows: np.ndarray
+    cols: np.ndarray
+    mats: np.ndarray
+
+
+@dataclass
+class MPO:
+    K: int
+    cuts: list            # cuts[k] = list of op keys at cut k (after pruning)
+    sites: list           # sites[k] = SiteMPO between cut k and cut k+1
+    dq: list = field(default_factory=list)      # dq[k] = (n_ops, 2) int array
+    parity: list = field(default_factory=list)  # parity[k] = (n_ops,) int array
+
+
+class _Acc:
+    def __init__(self):
+        self.a, self.b, self.m = [], [], []
+
+    def add(self, a, b, mat):
+        self.a.append(a)
+        self.b.append(b)
+        self.m.append(mat)
+
+
+def _site_entries(K, k, coef, ops_k, ops_k1):
+    """All W^(k) entries as (row key, col key, 4x4) accumulated per key pair."""
+    idx_k = {key: n for n, key in enumerate(ops_k)}
+    idx_k1 = {key: n for n, key in enumerate(ops_k1)}
+    acc = {}
+
+    def put(akey, bkey, mat):
+        if akey not in idx_k or bkey not in idx_k1:
+            return
+        kk = (idx_k[akey], idx_k1[bkey])
+        if kk in acc:
+            acc[kk] = acc[kk] + mat
+        else:
+            acc[kk] = mat.copy()
+
+    n = 2 * k
+    kap = (2 * k, 2 * k + 1)
+    # identity propagation and normal operators
+    put(("I",), ("I",), _I)
+    put(("H",), ("H",), _I)
+    for x in range(n):
+        put(("C", x), ("C", x), _P)
+        put(("D", x), ("D", x), _P)
+    for s in range(2):
+        put(("I",), ("C", kap[s]), CR[s] @ _P)
+        put(("I",), ("D", kap[s]), AN[s] @ _P)
+    for x in range(n):
+        for y in range(x + 1, n):
+            put(("A", x, y), ("A", x, y), _I)
+            put(("Ad", x, y), ("Ad", x, y), _I)
+    for x in range(n):
+        for y in range(n):
+            put(("B", x, y), ("B", x, y), _I)
+    for x in range(n):
+        for s in range(2):
+            put(("C", x), ("A", x, kap[s]), CR[s])
+            put(("D", x), ("Ad", x, kap[s]), -AN[s])
+            put(("C", x), ("B", x, kap[s]), AN[s])
+            put(("D", x), ("B", kap[s], x), -CR[s])
+    put(("I",), ("A", kap[0], kap[1]), CR[0] @ CR[1])
+    put(("I",), ("Ad", kap[0], kap[1]), AN[1] @ AN[0])
+    for s in range(2):
+        for t in range(2):
+            put(("I",), ("B", kap[s], kap[t]), CR[s] @ AN[t])
+    for j in range(2 * k + 2, 2 * K):
+        put(("T", j), ("T", j), _P)
+        put(("Td", j), ("Td", j), _P)
+    # H picks up the complementary operators of the new site's single operators
+    for s in range(2):
+        put(("T", kap[s]), ("H",), AN[s])
+        put(("Td", kap[s]), ("H",), CR[s])
+
+    # remaining H and T/Td contributions: enumerate operator-slot patterns
+    Lidx = np.arange(n)
+    outs = np.arange(2 * k + 2, 2 * K)
+    one = ((True, False), lambda a, b: coef.t(a, b))
+    two = ((True, True, False, False), lambda a, b, c, d: 0.5 * coef.v(a, b, c, d))
+
+    def slot_patterns(nslot, target):
+        # region per slot: 0 = left block, 1 = site k, 2 = outside operator
+        for regs in itertools.product((0, 1, 2), repeat=nslot):
+            nk = regs.count(1)
+            nout = regs.count(2)
+            if target == "H":
+                if nout or nk < 2:
+                    continue
+            else:
+                if nout != 1 or nk < 1:
+                    continue
+            yield regs
+
+    for daggers, cfn in (one, two):
+        ns = len(daggers)
+        for target in ("H", "T", "Td"):
+            for regs in slot_patterns(ns, target):
+                if target != "H":
+                    pos = regs.index(2)
+                    if target == "T" and daggers[pos]:
+                        continue
+                    if target == "Td" and not daggers[pos]:
+                        continue
+                lslots = [p for p in range(ns) if regs[p] == 0]
+                kslots = [p for p in range(ns) if regs[p] == 1]
+                if len(lslots) > 2 or (lslots and n == 0):
+                    continue
+                sign = -1.0 if _inversions(regs) % 2 else 1.0
+                par_b = 0 if target == "H" else 1
+                for spins in itertools.product(range(2), repeat=len(kslots)):
+                    site = _I
+                    for p, s in zip(kslots, spins):
+                        site = site @ (CR[s] if daggers[p] else AN[s])
+                    if not np.any(site):
+                        continue
+                    if par_b:
+                        site = site @ _P
+                    # coefficient array over (left slots..., outside)
+                    grids = []
+                    for p in range(ns):
+                        if regs[p] == 0:
+                            grids.append(Lidx)
+                        elif regs[p] == 1:
+                            grids.append(np.array([kap[spins[kslots.index(p)]]]))
+                        else:
+                            grids.append(outs if target != "H" else np.array([0]))
+                    mesh = np.meshgrid(*grids, indexing="ij")
+                    cval = sign * cfn(*mesh)
+                    # squeeze site-k axes; keep left slots and outside slot in slot order
+                    keep_axes = [p for p in range(ns) if regs[p] != 1]
+                    cval = cval.reshape([len(grids[p]) for p in range(ns)])
+                    cval = cval.reshape([len(grids[p]) for p in keep_axes])
+                    if target == "H":
+                        cval = cval[..., 0] if regs.count(2) else cval
+                    _emit(put, target, daggers, lslots, regs, cval, site, outs, n)
+
+    return [(a, b, m) for (a, b), m in acc.items()]
+
+
+def _emit(put, target, daggers, lslots, regs, cval, site, outs, n):
+    """Distribute a coefficient array onto canonical left operators."""
+    ld = [daggers[p] for p in lslots]
+    # axis order of cval: slots with region 0 or 2, in slot order
+    kept = [p for p in range(len(regs)) if regs[p] != 1]
+    if target == "H":
+        cols = [("H",)]
+        arrs = [cval]
+    else:
+        opos = regs.index(2)
+        oax = kept.index(opos)
+        cval = np.moveaxis(cval, oax, -1)  # outside index last
+        cols = [(target, int(j)) for j in outs]
+        arrs = [cval[..., m] for m in range(len(outs))]
+    for bkey, arr in zip(cols, arrs):
+        if len(lslots) == 0:
+            val = float(np.asarray(arr).reshape(()))
+            if val != 0.0:
+                put(("I",), bkey, val * site)
+        elif len(lslots) == 1:
+            kind = "C" if ld[0] else "D"
+            for x in np.nonzero(arr)[0]:
+                put((kind, int(x)), bkey, float(arr[x]) * site)
+        else:
+            if ld == [True, True]:      # a+_x a+_y = A_xy (x<y), -A_yx (x>y)
+                m = arr - arr.T
+                for x, y in zip(*np.nonzero(np.triu(m, 1))):
+                    put(("A", int(x), int(y)), bkey, float(m[x, y]) * site)
+            elif ld == [False, False]:  # a_x a_y = Ad_yx (y<x), -Ad_xy (x<y)
+                m = arr.T - arr        # m[j, l] = coefficient of Ad_jl = a_l a_j
+                for x, y in zip(*np.nonzero(np.triu(m, 1))):
+                    put(("Ad", int(x), int(y)), bkey, float(m[x, y]) * site)
+            elif ld == [True, False]:   # a+_x a_y = B_xy
+                for x, y in zip(*np.nonzero(arr)):
+                    put(("B", int(x), int(y)), bkey, float(arr[x, y]) * site)
+            else:
+                raise AssertionError("left factor not normal ordered")
+
+
+def build_nc_mpo(h, g, prune=True, tol=0.0):
+    """Return the NC-partition MPO of H(h, g) for K = h.shape[0] orbitals."""
+    K = h.shape[0]
+    coef = _Coef(np.asarray(h, float), np.asarray(g, float))
+    cuts = [cut_ops(K, k) for k in range(K + 1)]
+    raw = [_site_entries(K, k, coef, cuts[k], cuts[k + 1]) for k in range(K)]
+    # drop numerically empty entries
+    raw = [[(a, b, m) for a, b, m in ent if np.abs(m).max() > tol] for ent in raw]
+    alive = [np.ones(len(c), bool) for c in cuts]
+    if prune:
+        changed = True
+        while changed:
+            changed = False
+            for k in range(K):
+                used_in = np.zeros(len(cuts[k + 1]), bool)
+                used_out = np.zeros(len(cuts[k]), bool)
+                for a, b, _ in raw[k]:
+                    if alive[k][a] and alive[k + 1][b]:
+                        used_in[b] = True
+                        used_out[a] = True
+                new1 = alive[k + 1] & used_in
+                new0 = alive[k] & used_out
+                if (new1 != alive[k + 1]).any() or (new0 != alive[k]).any():
+                    changed = True
+                alive[k + 1], alive[k] = new1, new0
+    remap = []
+    new_cuts = []
+    for k in range(K + 1):
+        m = -np.ones(len(cuts[k]), int)
+        keep = np.nonzero(alive[k])[0]
+        m[keep] = np.arange(len(keep))
+        remap.append(m)
+        new_cuts.append([cuts[k][i] for i in keep])
+    sites = []
+    for k in range(K):
+        rows, cols, mats = [], [], []
+        for a, b, mat in raw[k]:
+            ra, rb = remap[k][a], remap[k + 1][b]
+            if ra >= 0 and rb >= 0:
+                rows.append(ra)
+                cols.append(rb)
+                mats.append(mat)
+        order = np.lexsort((np.array(rows), np.array(cols)))
+        sites.append(SiteMPO(np.array(rows, np.int32)[order], np.array(cols, np.int32)[order],
+                             np.array(mats)[order]))
+    mpo = MPO(K, new_cuts, sites)
+    mpo.dq = [np.array([op_dq(key) for key in c], np.int32).reshape(-1, 2) for c in new_cuts]
+    mpo.parity = [np.array([op_parity(key) for key in c], np.int32) for c in new_cuts]
+    return mpo
+
+
+def site_entries(mpo, k):
+    """W^(k) as a list of (row, col, 4x4) for the block formats used in tests."""
+    s = mpo.sites[k]
+    return [(int(a), int(b), m) for a, b, m in zip(s.rows, s.cols, s.mats)]
+
+
+def densify(mpo):
+    """Contract the whole MPO to a dense 4^K x 4^K matrix (small K only)."""
+    cur = np.ones((1, 1, 1))  # (op at cut 0, bra, ket)
+    for k in range(mpo.K):
+        s = mpo.sites[k]
+        D1 = len(mpo.cuts[k + 1])
+        n = cur.shape[1]
+        nxt = np.zeros((D1, n * 4, n * 4))
+        for a, b, m in zip(s.rows, s.cols, s.mats):
+            nxt[b] += np.kron(cur[a], m)
+        cur = nxt
+    assert cur.shape[0] == 1
+    return cur[0]

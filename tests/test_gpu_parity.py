@@ -1,0 +1,257 @@
+"""GPU parity of the HIP path against the FP64 oracle, element by element.
+
+Tolerance (FP64): every output is a sum of at most ~1e4 products formed and
+accumulated in IEEE double; the accumulated rounding is bounded by
+n * 2^-53 * sum|terms| <~ 1e-12 of the largest output here, so elements must
+agree to 1e-11 relative to the largest reference element.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import contract, davidson, mps
+from synth import bond_sector_tables, make_integrals, random_left_canonical_mps, random_right_canonical_mps
+from synth.blocks import random_env, random_psi, random_site_ops, random_site_tensor, two_site_blocks
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-11
+
+DQS = [(0, 0), (1, 1), (1, -1), (-1, 1), (-1, -1), (0, 2), (0, -2), (2, 0), (-2, 0)]
+
+
+def _bonds(seed, big):
+    rng = np.random.default_rng(seed)
+    lq = [(2, -2), (2, 0), (2, 2), (3, -1), (3, 1), (4, 0)]
+    rq = [(3, -1), (3, 1), (4, -2), (4, 0), (4, 2), (5, -1), (5, 1), (6, 0)]
+    dims = [1, 3, 17, 64, 65, 130] if big else [1, 2, 5, 9]
+    lb = [(q, int(rng.choice(dims))) for q in lq]
+    rb = [(q, int(rng.choice(dims))) for q in rq]
+    return lb, rb
+
+
+def _problem(seed, big=False, nL=7, nM=9, nR=7):
+    rng = np.random.default_rng(seed)
+    lb, rb = _bonds(seed, big)
+    Ldq = [DQS[i % len(DQS)] for i in range(nL)]
+    Mdq = [DQS[(i * 5) % len(DQS)] for i in range(nM)]
+    Rdq = [DQS[(i * 7 + 3) % len(DQS)] for i in range(nR)]
+    L = random_env(lb, Ldq, rng)
+    R = random_env(rb, Rdq, rng)
+    W1 = random_site_ops(Ldq, Mdq, rng, per_col=3)
+    W2 = random_site_ops(Mdq, Rdq, rng, per_col=3)
+    psi = random_psi(lb, rb, rng)
+    return lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi
+
+
+def _dense_sigma(lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi):
+    s = contract.heff_apply(contract.dense_env(L, lb), contract.dense_mpo(W1, len(Ldq), len(Mdq)),
+                            contract.dense_mpo(W2, len(Mdq), len(Rdq)), contract.dense_env(R, rb),
+                            mps.dense_two_site(psi, lb, rb))
+    return mps.two_site_blocks_from_dense(s, lb, rb, two_site_blocks(lb, rb))
+
+
+def _close(got, ref, rtol=RTOL):
+    scale = max(max(np.abs(v).max() for v in ref.values() if v.size), 1e-300)
+    for k in ref:
+        err = np.abs(got[k] - ref[k]).max() if ref[k].size else 0.0
+        assert err <= rtol * scale, (k, err, scale)
+
+
+def _run_heff(device, lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi, budget=0, diag=False):
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, t_budget_bytes=budget).upload(device)
+    Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
+    Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
+    pt = torch.from_numpy(X.pack_psi(lbB, rbB, psi)).to(device)
+    st = torch.full_like(pt, float("nan"))
+    plan.prepare(Lt, Rt)
+    plan.apply(Lt, Rt, pt, st)
+    out = {"sigma": X.unpack_psi(lbB, rbB, st.cpu().numpy()), "plan": plan}
+    if diag:
+        dt = torch.full_like(pt, float("nan"))
+        plan.diag(Lt, Rt, dt)
+        out["diag"] = X.unpack_psi(lbB, rbB, dt.cpu().numpy())
+    torch.cuda.synchronize()
+    return out
+
+
+@pytest.mark.parametrize("seed,big", [(0, False), (1, True), (2, True)])
+def test_heff_apply_random_operands(device, seed, big):
+    print(f"[heff_apply] seed={seed} big={big}", flush=True)
+    prob = _problem(seed, big)
+    got = _run_heff(device, *prob)["sigma"]
+    _close(got, _dense_sigma(*prob))
+
+
+def test_heff_apply_chunked_intermediates(device):
+    print("[heff_apply chunked]", flush=True)
+    prob = _problem(3, True)
+    res = _run_heff(device, *prob, budget=256 * 1024)
+    assert res["plan"].info.n_chunks > 2
+    _close(res["sigma"], _dense_sigma(*prob))
+
+
+def test_heff_diag_random_operands(device):
+    print("[heff_diag]", flush=True)
+    lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = _problem(4, True)
+    got = _run_heff(device, lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi, diag=True)["diag"]
+    d = contract.heff_diag(contract.dense_env(L, lb), contract.dense_mpo(W1, len(Ldq), len(Mdq)),
+                           contract.dense_mpo(W2, len(Mdq), len(Rdq)), contract.dense_env(R, rb))
+    _close(got, mps.two_site_blocks_from_dense(d, lb, rb, two_site_blocks(lb, rb)))
+
+
+def test_heff_apply_is_bitwise_repeatable(device):
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    print("[heff repeat]", flush=True)
+    lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = _problem(5, True)
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2).upload(device)
+    Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
+    Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
+    pt = torch.from_numpy(X.pack_psi(lbB, rbB, psi)).to(device)
+    plan.prepare(Lt, Rt)
+    s1, s2 = torch.empty_like(pt), torch.empty_like(pt)
+    plan.apply(Lt, Rt, pt, s1)
+    plan.apply(Lt, Rt, pt, s2)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2)
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_env_update_random_operands(device, direction):
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    print(f"[env_update] direction={direction}", flush=True)
+    rng = np.random.default_rng(10 + direction)
+    kb = sorted([((2, 0), 64), ((2, 2), 3), ((3, 1), 70), ((3, -1), 1), ((4, 0), 9)])
+    kb1 = sorted([((3, 1), 65), ((3, -1), 2), ((4, 0), 130), ((4, 2), 5), ((5, 1), 7), ((5, -1), 1)])
+    din = [DQS[i % 9] for i in range(6)]
+    dout = [DQS[(i * 4 + 1) % 9] for i in range(8)]
+    if direction == 0:
+        env = random_env(kb, din, rng)
+        W = random_site_ops(din, dout, rng, per_col=3)
+        A = random_site_tensor(kb, kb1, rng)
+        ref = contract.env_blocks_from_dense(
+            contract.env_update_left(contract.dense_env(env, kb), contract.dense_mpo(W, len(din), len(dout)),
+                                     mps.dense_site_tensor(A, kb, kb1)), kb1, dout)
+        bin_, bout = X.Bond(kb), X.Bond(kb1)
+        plan = X.EnvPlan(0, bin_, bout, din, dout, W).upload(device)
+        site = torch.from_numpy(X.pack_site(bin_, bout, A)).to(device)
+    else:
+        env = random_env(kb1, din, rng)
+        W = random_site_ops(dout, din, rng, per_col=3)  # rows: ops at cut k, cols: ops at cut k+1
+        B = random_site_tensor(kb, kb1, rng)
+        ref = contract.env_blocks_from_dense(
+            contract.env_update_right(contract.dense_env(env, kb1), contract.dense_mpo(W, len(dout), len(din)),
+                                      mps.dense_site_tensor(B, kb, kb1)), kb, dout)
+        bin_, bout = X.Bond(kb1), X.Bond(kb)
+        plan = X.EnvPlan(1, bin_, bout, din, dout, W).upload(device)
+        site = torch.from_numpy(X.pack_site(bout, bin_, B)).to(device)
+    et = torch.from_numpy(X.pack_env(bin_, din, env)).to(device)
+    out = torch.full((int(plan.info.out_nnz),), float("nan"), dtype=torch.float64, device=device)
+    plan.update(et, site, out)
+    got = X.unpack_env(bout, dout, out.cpu().numpy())
+    scale = max(np.abs(blk).max() for op in ref for blk in op["blocks"].values())
+    for a, op in enumerate(ref):
+        for isrc, blk in op["blocks"].items():
+            assert np.abs(got[a]["blocks"][isrc] - blk).max() <= RTOL * scale, (a, isrc)
+
+
+def test_dots_match_numpy(device):
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    print("[dots]", flush=True)
+    rng = np.random.default_rng(0)
+    for n in (1, 255, 70001):
+        a = rng.standard_normal((5, n))
+        b = rng.standard_normal(n)
+        ws = torch.empty(X.davidson_ws_bytes(n, 32) // 8, dtype=torch.float64, device=device)
+        out = torch.empty(5, dtype=torch.float64, device=device)
+        X.dots(torch.from_numpy(a).to(device), torch.from_numpy(b).to(device), ws, out)
+        ref = a @ b
+        np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=1e-13, atol=1e-13 * np.abs(a).sum())
+
+
+def test_davidson_step_matches_oracle(device):
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    print("[davidson_step]", flush=True)
+    rng = np.random.default_rng(3)
+    n, kmax = 3001, 8
+    H = np.diag(np.linspace(-3, 5, n))
+    Q, _ = np.linalg.qr(rng.standard_normal((n, 6)))
+    H += 0.05 * (Q @ np.diag(rng.standard_normal(6)) @ Q.T)
+    d = np.diag(H).copy()
+    V = np.zeros((kmax, n))
+    S = np.zeros((kmax, n))
+    ws = torch.zeros(X.davidson_ws_bytes(n, kmax) // 8, dtype=torch.float64, device=device)
+    dt = torch.from_numpy(d).to(device)
+    x = torch.empty(n, dtype=torch.float64, device=device)
+    hx, t = torch.empty_like(x), torch.empty_like(x)
+    scal = torch.zeros(4, dtype=torch.float64, device=device)
+    v = rng.standard_normal(n)
+    v /= np.linalg.norm(v)
+    V[0], S[0] = v, H @ v
+    Vt = torch.from_numpy(V).to(device)
+    St = torch.from_numpy(S).to(device)
+    for k in range(1, kmax + 1):
+        X.davidson_step(n, k, kmax, Vt, St, dt, 1e-8, ws, x, hx, t, scal)
+        theta, rn, xr, hxr, tr, tn = davidson.step(V[:k], S[:k], d, 1e-8)
+        sc = scal.cpu().numpy()
+        assert abs(sc[0] - theta) <= 1e-12 * max(1.0, abs(theta))
+        assert abs(sc[1] - rn) <= 1e-10 * max(1.0, rn)
+        np.testing.assert_allclose(x.cpu().numpy(), xr, atol=1e-10)
+        np.testing.assert_allclose(hx.cpu().numpy(), hxr, atol=1e-10)
+        np.testing.assert_allclose(t.cpu().numpy(), tr, atol=1e-9)
+        if k < kmax:
+            tv = t.cpu().numpy()
+            V[k], S[k] = tv, H @ tv
+            Vt[k] = torch.from_numpy(V[k]).to(device)
+            St[k] = torch.from_numpy(S[k]).to(device)
+
+
+@pytest.mark.parametrize("i", [1, 3, 5])
+def test_sigma_with_gpu_environments_equals_PtHP(device, i):
+    """Product MPO + GPU environment chain + GPU sigma == P^T H P psi (definition)."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.engine import Engine, site_payload
+    from paper_2310_03920_amd.mpo import build_nc_mpo
+    print(f"[sigma vs PtHP] i={i}", flush=True)
+    K, Mb = 8, 64
+    h, g = make_integrals(K, seed=0)
+    bonds = bond_sector_tables(K, K, 0, Mb)
+    left = random_left_canonical_mps(bonds, 1)
+    right = random_right_canonical_mps(bonds, 2)
+    eng = Engine(build_nc_mpo(h, g), device=device)
+    eng.init_boundaries()
+    for k in range(i):
+        eng.update_left(k, bonds[k], bonds[k + 1], site_payload(bonds[k], bonds[k + 1], left[k], device))
+    for k in range(K - 1, i + 1, -1):
+        eng.update_right(k, bonds[k], bonds[k + 1], site_payload(bonds[k], bonds[k + 1], right[k], device))
+    plan = eng.heff_plan(i, bonds[i], bonds[i + 2])
+    rng = np.random.default_rng(7)
+    psi = random_psi(bonds[i], bonds[i + 2], rng)
+    lb, rb = X.Bond(bonds[i]), X.Bond(bonds[i + 2])
+    pt = torch.from_numpy(X.pack_psi(lb, rb, psi)).to(device)
+    st = torch.empty_like(pt)
+    plan.prepare(eng.left[i], eng.right[i + 2])
+    plan.apply(eng.left[i], eng.right[i + 2], pt, st)
+    got = X.unpack_psi(lb, rb, st.cpu().numpy())
+    emb = mps.Embedding(h, g, K, 0, left[:i], right[i + 2:], bonds, i)
+    keys = two_site_blocks(bonds[i], bonds[i + 2])
+    ref = mps.two_site_blocks_from_dense(emb.apply(mps.dense_two_site(psi, bonds[i], bonds[i + 2])),
+                                         bonds[i], bonds[i + 2], keys)
+    _close(got, ref)
+    # Hermiticity of the GPU H_eff: <phi|H psi> = <H phi|psi>
+    phi = random_psi(bonds[i], bonds[i + 2], rng)
+    ft = torch.from_numpy(X.pack_psi(lb, rb, phi)).to(device)
+    hf = torch.empty_like(ft)
+    plan.apply(eng.left[i], eng.right[i + 2], ft, hf)
+    a = float(torch.dot(ft, st))
+    b = float(torch.dot(hf, pt))
+    assert abs(a - b) <= 1e-12 * (abs(a) + abs(b) + 1)

@@ -1,0 +1,153 @@
+"""Host-only checks of the C-ABI library and the product's host logic (no GPU)."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import fock
+from paper_2310_03920_amd import _lib as X
+from paper_2310_03920_amd import mpo as M
+from synth import bond_sector_tables, hubbard_integrals, make_integrals
+from synth.blocks import two_site_blocks
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "heffx.h")).read()
+    names = set(re.findall(r"^\s*(?:int|int64_t|void|const char\*)\s+(hx_\w+)\s*\(", hdr, re.M))
+    assert names, "no declarations parsed"
+    lib = ctypes.CDLL(X.LIB_PATH)
+    for n in sorted(names):
+        assert hasattr(lib, n), n
+    assert names == set(X.EXPORTED)
+
+
+@pytest.mark.parametrize("K", [2, 3, 4, 5])
+def test_nc_mpo_densifies_to_fock_hamiltonian(K):
+    h, g = make_integrals(K, seed=K + 20)
+    m = M.build_nc_mpo(h, g)
+    dets = fock.all_dets(K)
+    Hf = fock.hamiltonian(h, g, dets).toarray()
+    p = fock.product_index(dets, K)
+    Hp = np.zeros_like(Hf)
+    Hp[np.ix_(p, p)] = Hf
+    np.testing.assert_allclose(M.densify(m), Hp, atol=1e-12)
+
+
+def test_nc_mpo_sparse_hamiltonian_prunes_to_minimal_bond():
+    h, g = hubbard_integrals(5, 1.0, 3.0)
+    m = M.build_nc_mpo(h, g)
+    assert max(len(c) for c in m.cuts) == 6
+    dets = fock.all_dets(5)
+    Hf = fock.hamiltonian(h, g, dets).toarray()
+    p = fock.product_index(dets, 5)
+    Hp = np.zeros_like(Hf)
+    Hp[np.ix_(p, p)] = Hf
+    np.testing.assert_allclose(M.densify(m), Hp, atol=1e-13)
+
+
+def test_nc_mpo_bond_dimension_grows_quadratically():
+    """NC partition: normal pair operators on the left give D ~ 8 k^2."""
+    K = 12
+    m = M.build_nc_mpo(*make_integrals(K, seed=1))
+    D = [len(c) for c in m.cuts]
+    for k in (3, 4, 5, 6):
+        assert 6 * k * k < D[k] < 10 * k * k + 4 * K + 8
+
+
+def test_psi_layout_matches_block_enumeration():
+    b = bond_sector_tables(8, 8, 0, 64)
+    lb, rb = X.Bond(b[3]), X.Bond(b[5])
+    keys, off = X.psi_layout(lb, rb)
+    assert keys == two_site_blocks(b[3], b[5])
+    sizes = [b[3][k[0]][1] * b[5][k[3]][1] for k in keys]
+    np.testing.assert_array_equal(np.diff(off), sizes)
+    assert off[-1] == 4900
+
+
+def test_plan_rejects_site_matrix_breaking_conservation():
+    lb = X.Bond([((0, 0), 2), ((1, 1), 3)])
+    rb = X.Bond([((1, 1), 2), ((2, 0), 2)])
+    bad = np.zeros((4, 4))
+    bad[1, 0] = 1.0  # empty -> alpha: shift (1, 1)
+    with pytest.raises(RuntimeError, match="conservation"):
+        X.HeffPlan(lb, rb, [(0, 0)], [(0, 0)], [(0, 0)], [(0, 0, bad)], [(0, 0, np.eye(4))])
+
+
+def test_plan_rejects_unsorted_bond():
+    lb = X.Bond([((1, 1), 2), ((0, 0), 3)])
+    rb = X.Bond([((1, 1), 2)])
+    with pytest.raises(RuntimeError, match="increasing"):
+        X.HeffPlan(lb, rb, [(0, 0)], [(0, 0)], [(0, 0)], [(0, 0, np.eye(4))], [(0, 0, np.eye(4))])
+
+
+def _count_flops(lbond, rbond, Ldq, Rdq, W1, W2):
+    """Independent count of 2 m n k over the two block-GEMM rounds."""
+    lidx = {q: i for i, (q, _) in enumerate(lbond)}
+    ridx = {q: i for i, (q, _) in enumerate(rbond)}
+    SQ = M.SITE_QN
+    left, right = {}, {}
+    for a, b, op in W1:
+        for so in range(4):
+            for si in range(4):
+                if op[so, si] != 0:
+                    left.setdefault(b, {}).setdefault((so, si), set()).add(a)
+    for b, c, op in W2:
+        for so in range(4):
+            for si in range(4):
+                if op[so, si] != 0:
+                    right.setdefault(b, {}).setdefault((so, si), set()).add(c)
+    psi = two_site_blocks(lbond, rbond)
+    fl = 0.0
+    for b in set(left) & set(right):
+        tb = set()
+        for (so, si), cs in right[b].items():
+            dq = Rdq[next(iter(cs))]
+            for (il, s1, s2, ir) in psi:
+                if s2 != si:
+                    continue
+                q = rbond[ir][0]
+                irp = ridx.get((q[0] + dq[0], q[1] + dq[1]))
+                if irp is None:
+                    continue
+                fl += 2.0 * lbond[il][1] * rbond[ir][1] * rbond[irp][1]
+                tb.add((il, s1, so, irp))
+        for (il, s1, s2p, irp) in tb:
+            for (so, si), as_ in left[b].items():
+                if si != s1:
+                    continue
+                dq = Ldq[next(iter(as_))]
+                q = lbond[il][0]
+                ilp = lidx.get((q[0] + dq[0], q[1] + dq[1]))
+                if ilp is None:
+                    continue
+                fl += 2.0 * lbond[ilp][1] * lbond[il][1] * rbond[irp][1]
+    return fl
+
+
+def test_plan_flop_count_matches_independent_count():
+    K, M_ = 8, 64
+    h, g = make_integrals(K, seed=0)
+    m = M.build_nc_mpo(h, g)
+    b = bond_sector_tables(K, K, 0, M_)
+    for i in (1, 3, 5):
+        W1, W2 = M.site_entries(m, i), M.site_entries(m, i + 1)
+        p = X.HeffPlan(b[i], b[i + 2], m.dq[i], m.dq[i + 1], m.dq[i + 2], W1, W2)
+        ref = _count_flops(b[i], b[i + 2], [tuple(x) for x in m.dq[i]], [tuple(x) for x in m.dq[i + 2]], W1, W2)
+        assert p.info.flops_apply == pytest.approx(ref, rel=1e-12)
+        assert p.info.psi_nnz == sum(b[i][k[0]][1] * b[i + 2][k[3]][1] for k in two_site_blocks(b[i], b[i + 2]))
+
+
+def test_plan_chunking_keeps_flops():
+    K = 8
+    m = M.build_nc_mpo(*make_integrals(K, seed=0))
+    b = bond_sector_tables(K, K, 0, 64)
+    args = (b[3], b[5], m.dq[3], m.dq[4], m.dq[5], M.site_entries(m, 3), M.site_entries(m, 4))
+    p1 = X.HeffPlan(*args)
+    p2 = X.HeffPlan(*args, t_budget_bytes=64 * 1024)
+    assert p1.info.n_chunks == 1 and p2.info.n_chunks > 4
+    assert p2.info.flops_apply == pytest.approx(p1.info.flops_apply, rel=1e-12)
