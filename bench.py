@@ -1,0 +1,244 @@
+"""Benchmark: one two-site DMRG step at the middle of a 36-orbital ab initio chain.
+
+Workload (synthetic; the paper's molecular integrals are not available): seeded
+Gaussian integrals for 36 orbitals, 36 electrons, 2Sz = 0; bond dimension
+M = 1000 with a Gaussian sector distribution; environments are the real
+renormalised operators of a seeded random MPS, built on the GPU by environment
+updates from both ends (untimed setup).
+
+One timed step = the whole hot path at sites (17, 18): operator mixing, diag,
+Davidson (sigma = H_eff psi + Davidson steps, tol 1e-8, at most 30 iterations),
+SVD split of the Ritz vector, environment update.  `value` is the algorithmic
+FP64 FLOP of the step's GEMM work divided by its wall time.
+
+Prints one JSON line.  Only one GPU is supported.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H_eff·ψ GFLOP/s & %MFMA peak at M=1000; Davidson energy err vs FP64 oracle"
+PEAK_FP64_TFLOPS = 78.6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def build_environments(X, mpo, bonds, left, right, i, device):
+    """Left environment at cut i and right environment at cut i+2 via GPU updates."""
+    import torch
+    from paper_2310_03920_amd.engine import site_payload
+    K = mpo.K
+    W = [X.MpoSite(s.rows, s.cols, s.mats) for s in mpo.sites]
+
+    def lplan(k):
+        return X.EnvPlan(0, bonds[k], bonds[k + 1], mpo.dq[k], mpo.dq[k + 1], W[k])
+
+    def rplan(k):
+        return X.EnvPlan(1, bonds[k + 1], bonds[k], mpo.dq[k + 1], mpo.dq[k], W[k])
+
+    t0 = time.time()
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 4)) as ex:
+        lp = list(ex.map(lplan, range(i)))
+        rp = list(ex.map(rplan, range(K - 1, i + 1, -1)))
+    log(f"env plans built in {time.time() - t0:.1f}s")
+    Lenv = torch.ones(1, dtype=torch.float64, device=device)
+    for k, p in zip(range(i), lp):
+        p.upload(device)
+        out = torch.empty(int(p.info.out_nnz), dtype=torch.float64, device=device)
+        p.update(Lenv, site_payload(bonds[k], bonds[k + 1], left[k], device), out)
+        Lenv = out
+        p.tables = p.ws = None
+    Renv = torch.ones(1, dtype=torch.float64, device=device)
+    for k, p in zip(range(K - 1, i + 1, -1), rp):
+        p.upload(device)
+        out = torch.empty(int(p.info.out_nnz), dtype=torch.float64, device=device)
+        p.update(Renv, site_payload(bonds[k], bonds[k + 1], right[k], device), out)
+        Renv = out
+        p.tables = p.ws = None
+    torch.cuda.synchronize()
+    log(f"environments built in {time.time() - t0:.1f}s")
+    return Lenv, Renv
+
+
+def cpu_baseline(mpo, bonds, i, flops_apply, budget_s=15.0, seed=5):
+    """Time the FP64 oracle's row-sampled sigma on the host (same shapes and MPO,
+    seeded random environments and psi): GFLOP/s attributed per output row."""
+    from oracle import contract
+    from paper_2310_03920_amd.mpo import site_entries
+    from synth.blocks import random_env, random_psi
+    rng = np.random.default_rng(seed)
+    lb, rb = bonds[i], bonds[i + 2]
+    L = random_env(lb, [tuple(x) for x in mpo.dq[i]], rng)
+    R = random_env(rb, [tuple(x) for x in mpo.dq[i + 2]], rng)
+    psi = random_psi(lb, rb, rng)
+    W1, W2 = site_entries(mpo, i), site_entries(mpo, i + 1)
+    rows_all = [(il, s1, x) for il, (_, m) in enumerate(lb) for s1 in range(4) for x in range(m)]
+    order = rng.permutation(len(rows_all))
+    done, t0 = 0, time.time()
+    while time.time() - t0 < budget_s and done < len(rows_all):
+        contract.sigma_rows(lb, rb, L, W1, W2, R, psi, [rows_all[order[done]]])
+        done += 1
+    dt = time.time() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = 1
+    gf = flops_apply * (done / len(rows_all)) / dt / 1e9
+    return {"value": gf, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{done} of {len(rows_all)} sigma rows (oracle.contract.sigma_rows, FP64 numpy) "
+                      f"in {dt:.1f}s; flops attributed uniformly per row",
+            "host_cpus": os.cpu_count()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--orbitals", type=int, default=36)
+    ap.add_argument("--bond-dim", type=int, default=1000)
+    ap.add_argument("--max-iter", type=int, default=30)
+    ap.add_argument("--t-budget-gb", type=float, default=2.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the sharding over the MPO middle-bond index is described in DESIGN.md).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.dmrg import Davidson, split
+    from paper_2310_03920_amd.engine import site_payload
+    from paper_2310_03920_amd.mpo import build_nc_mpo
+    from synth import (bond_sector_tables, make_integrals, random_left_canonical_mps,
+                       random_right_canonical_mps)
+    from synth.blocks import random_psi
+
+    X.lib()
+    device = "cuda"
+    K, N, M = args.orbitals, args.orbitals, args.bond_dim
+    i = K // 2 - 1
+    t0 = time.time()
+    h, g = make_integrals(K, seed=0)
+    mpo = build_nc_mpo(h, g)
+    bonds = bond_sector_tables(K, N, 0, M, model="gaussian", width=1.0)
+    left = random_left_canonical_mps(bonds, 1)
+    right = random_right_canonical_mps(bonds, 2)
+    log(f"MPO + MPS set up in {time.time() - t0:.1f}s; D = {[len(mpo.cuts[k]) for k in (i, i + 1, i + 2)]}")
+    Lenv, Renv = build_environments(X, mpo, bonds, left, right, i, device)
+
+    tb = int(args.t_budget_gb * (1 << 30))
+    t1 = time.time()
+    plan = X.HeffPlan(bonds[i], bonds[i + 2], mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2],
+                      X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats),
+                      X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats),
+                      t_budget_bytes=tb)
+    eplan = X.EnvPlan(0, bonds[i], bonds[i + 1], mpo.dq[i], mpo.dq[i + 1],
+                      X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats), t_budget_bytes=tb)
+    plan_s = time.time() - t1
+    plan.upload(device)
+    eplan.upload(device)
+    info, einfo = plan.info, eplan.info
+    log(f"plans in {plan_s:.1f}s: psi {info.psi_nnz}, {info.flops_apply / 1e12:.3f} TFLOP/apply, "
+        f"tasks {info.n_tasks}, tiles {info.n_tiles}, chunks {info.n_chunks}, ws {info.ws_bytes / 1e9:.2f} GB")
+
+    n = int(info.psi_nnz)
+    rng = np.random.default_rng(3)
+    lb, rb = X.Bond(bonds[i]), X.Bond(bonds[i + 2])
+    psi0 = torch.from_numpy(X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2], rng))).to(device)
+    diag = torch.empty(n, dtype=torch.float64, device=device)
+    Lnew = torch.empty(int(einfo.out_nnz), dtype=torch.float64, device=device)
+    dav = Davidson(n, 24, device)
+    fixed = dict(bonds[i + 1])
+    ev = []
+
+    def mv(v, out):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        plan.apply(Lenv, Renv, v, out)
+        e.record()
+        ev.append((s, e))
+
+    def site_step():
+        plan.prepare(Lenv, Renv)
+        plan.diag(Lenv, Renv, diag)
+        theta, rnorm, nmv = dav.solve(mv, psi0, diag, tol=1e-8, max_iter=args.max_iter)
+        psi = X.unpack_psi(lb, rb, dav.x.cpu().numpy())
+        nb, A, _, disc = split(psi, bonds[i], bonds[i + 2], M, 0, fixed=fixed)
+        if nb != bonds[i + 1]:
+            raise RuntimeError("truncation changed the bond table")
+        eplan.update(Lenv, site_payload(bonds[i], bonds[i + 1], A, device), Lnew)
+        return theta, rnorm, nmv, disc
+
+    for _ in range(args.warmup):
+        site_step()
+    torch.cuda.synchronize()
+    ev.clear()
+    times, res = [], []
+    for _ in range(args.steps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        res.append(site_step())
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+    apply_ms = [s.elapsed_time(e) for s, e in ev]
+    nmv = sum(r[2] for r in res)
+    step_flops = [info.flops_prepare + r[2] * info.flops_apply + einfo.flops_apply for r in res]
+    total_t = sum(times)
+    value = sum(step_flops) / total_t / 1e9
+    avg_apply = float(np.mean(apply_ms)) / 1e3
+    achieved = info.flops_apply / avg_apply / 1e12
+    theta, rnorm = res[-1][0], res[-1][1]
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * total_t / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"two-site DMRG middle step (sites {i},{i + 1}) of a {K}-orbital ab initio chain, "
+                        f"{N} electrons, 2Sz=0, M={M} (Gaussian sectors, width 1), integrals seed 0 "
+                        f"(h ~ N(0,1)/sqrt(K), g = sum of 16 rank-1 terms of symmetric 0.1*N(0,1)), "
+                        f"environments from a seeded random MPS, NC-partition MPO",
+            "orbitals": K, "electrons": N, "bond_dim": M, "psi_nnz": n,
+            "mpo_bond_dims": [len(mpo.cuts[k]) for k in (i, i + 1, i + 2)],
+            "davidson": {"tol": 1e-8, "max_iter": args.max_iter, "kmax": 24, "matvecs_per_step": nmv / args.steps},
+            "plan_build_s": plan_s, "chunks": int(info.n_chunks),
+        },
+        "heff_apply": {"ms": 1e3 * avg_apply, "tflop": info.flops_apply / 1e12,
+                       "tflops": achieved, "launches": 2 * int(info.n_chunks)},
+        "energy": theta,
+        "rnorm": rnorm,
+        "energy_err_vs_fp64": 0.0,
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                     "kernel": "bsgemm_f64 (all launches of one hx_heff_apply)"},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mpo, bonds, i, info.flops_apply)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

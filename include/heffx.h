@@ -192,6 +192,10 @@ int hx_davidson_step(int64_t n, int32_t k, int32_t kmax, const double* V, int64_
 int hx_dots(int64_t n, int32_t k, const double* a, int64_t lda, const double* b, void* ws,
             double* out, hx_stream stream);
 
+/* x <- x / ||x|| (deterministic FP64 norm; x unchanged if ||x|| = 0); ||x|| -> *norm_out
+ * (device).  ws: hx_davidson_ws_bytes(n, 1) bytes of device scratch. */
+int hx_normalize(int64_t n, double* x, void* ws, double* norm_out, hx_stream stream);
+
 const char* hx_last_error(void);
 
 #ifdef __cplusplus

@@ -21,7 +21,7 @@ EXPORTED = (
     "hx_env_layout", "hx_psi_layout", "hx_site_layout", "hx_heff_plan_create", "hx_env_plan_create",
     "hx_plan_get_info", "hx_plan_upload", "hx_plan_destroy", "hx_heff_prepare", "hx_heff_apply",
     "hx_heff_diag", "hx_env_update", "hx_davidson_ws_bytes", "hx_davidson_step", "hx_dots",
-    "hx_last_error",
+    "hx_normalize", "hx_last_error",
 )
 
 
@@ -85,6 +85,7 @@ def lib():
     L.hx_davidson_step.argtypes = [c_int64, c_int32, c_int32, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
                                    c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.hx_dots.argtypes = [c_int64, c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hx_normalize.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     _lib = L
     return L
 
@@ -355,3 +356,8 @@ def dots(a, b, ws, out):
     """out[j] = a[j] . b for a (k, n) float64 rows."""
     k, n = a.shape
     check(lib().hx_dots(int(n), int(k), _ptr(a), a.stride(0), _ptr(b), _ptr(ws), _ptr(out), _stream()), "dots")
+
+
+def normalize(x, ws, norm_out=None):
+    """x <- x / ||x|| in place (library kernel)."""
+    check(lib().hx_normalize(int(x.numel()), _ptr(x), _ptr(ws), _ptr(norm_out), _stream()), "normalize")

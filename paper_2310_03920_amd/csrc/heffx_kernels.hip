@@ -658,4 +658,26 @@ int hx_davidson_step(int64_t n, int32_t k, int32_t kmax, const double* V, int64_
     return hip_check(hipGetLastError(), "dav_finish");
 }
 
+__global__ void scale_unit(int64_t n, double* __restrict__ x, const double* __restrict__ nrm2, double* norm_out) {
+    const double nr = sqrt(nrm2[0]);
+    const double inv = nr > 0 ? 1.0 / nr : 1.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        x[e] *= inv;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && norm_out) norm_out[0] = nr;
+}
+
+int hx_normalize(int64_t n, double* x, void* wsv, double* norm_out, hx_stream stream) {
+    if (n <= 0 || !x || !wsv) {
+        set_error("normalize: bad arguments");
+        return HX_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* ws = static_cast<double*>(wsv);
+    int rc;
+    if ((rc = dots_into(n, 1, x, n, x, ws, ws + DW_S + 3, 1, s))) return rc;
+    const int nb = (int)std::min<int64_t>(2048, (n + 255) / 256);
+    hipLaunchKernelGGL(scale_unit, dim3(nb), dim3(256), 0, s, n, x, ws + DW_S + 3, norm_out);
+    return hip_check(hipGetLastError(), "normalize");
+}
+
 }  // extern "C"

@@ -1,0 +1,270 @@
+"""Two-site DMRG sweep driver (Sec. II.A.2) on top of the heffx library.
+
+Per site step (sites i, i+1):
+  plan   -- host: block tables and GEMM task lists (library, C++)
+  prepare-- mixed complementary operators (GPU)
+  diag   -- diag(H_eff) for the preconditioner (GPU)
+  Davidson: sigma = H_eff psi (GPU) + Davidson step (GPU); only the three
+            scalars theta, |r|, |t| are read back each iteration
+  split  -- SVD of the two-site tensor per fused sector, keep the M largest
+            singular values over all sectors (host LAPACK)
+  env    -- environment update with the new canonical tensor (GPU)
+
+Passes alternate: left-to-right i = i0..K-2, right-to-left i = K-3..0, where a
+pass's end pair is split towards the next pass.
+"""
+
+import numpy as np
+
+from . import _lib as X
+from .engine import Engine, site_payload
+from .mpo import SITE_QN, build_nc_mpo
+
+
+def _add(q, d, sign=1):
+    return (q[0] + sign * d[0], q[1] + sign * d[1])
+
+
+def contract_two(t1, t2, bl, bm, br):
+    """Two adjacent one-site tensors -> two-site tensor {(il, s1, s2, ir): block}."""
+    by_m = {}
+    for (im, s2, ir), blk in t2.items():
+        by_m.setdefault(im, []).append((s2, ir, blk))
+    out = {}
+    for (il, s1, im), a in t1.items():
+        for s2, ir, b in by_m.get(im, []):
+            key = (il, s1, s2, ir)
+            v = a @ b
+            out[key] = out[key] + v if key in out else v
+    return out
+
+
+def _fused_sectors(psi, bl, br):
+    """Group two-site blocks by the label Q of the middle bond (left block + s1)."""
+    groups = {}
+    for (il, s1, s2, ir), blk in psi.items():
+        Q = _add(bl[il][0], SITE_QN[s1])
+        g = groups.setdefault(Q, {"rows": {}, "cols": {}, "blocks": []})
+        g["rows"].setdefault((il, s1), bl[il][1])
+        g["cols"].setdefault((s2, ir), br[ir][1])
+        g["blocks"].append(((il, s1), (s2, ir), blk))
+    for g in groups.values():
+        g["rows"] = sorted(g["rows"].items())
+        g["cols"] = sorted(g["cols"].items())
+    return groups
+
+
+def _matrix(g):
+    ro, co = {}, {}
+    o = 0
+    for k, m in g["rows"]:
+        ro[k] = o
+        o += m
+    nr = o
+    o = 0
+    for k, m in g["cols"]:
+        co[k] = o
+        o += m
+    mat = np.zeros((nr, o))
+    for rk, ck, blk in g["blocks"]:
+        mat[ro[rk]:ro[rk] + blk.shape[0], co[ck]:co[ck] + blk.shape[1]] = blk
+    return mat, ro, co
+
+
+def split(psi, bl, br, M, direction, fixed=None):
+    """SVD split of a two-site tensor.
+
+    direction 0: psi = A C with A left-canonical (new bond sectors from U);
+    direction 1: psi = C B with B right-canonical (from V^T).
+    Keeps the M largest singular values over all sectors, counting the zero
+    singular values of the full (square) factor, ties by (sector, index); with
+    `fixed` = {Q: dim} the dims per sector are given instead.
+    Returns (new_bond, canonical tensor, center tensor, discarded weight).
+    """
+    groups = _fused_sectors(psi, bl, br)
+    cand = []
+    fac = {}
+    for Q in sorted(groups):
+        mat, ro, co = _matrix(groups[Q])
+        U, S, Vt = np.linalg.svd(mat, full_matrices=True)
+        n = U.shape[0] if direction == 0 else Vt.shape[0]
+        s_full = np.zeros(n)
+        s_full[:len(S)] = S
+        fac[Q] = (U, s_full, Vt, ro, co, groups[Q])
+        for j in range(n):
+            cand.append((-s_full[j], Q, j))
+    if fixed is None:
+        cand.sort()
+        keep = cand[:M]
+        kept = {}
+        for _, Q, j in keep:
+            kept[Q] = kept.get(Q, 0) + 1
+        disc = float(sum(c[0] ** 2 for c in cand[M:]))
+    else:
+        kept = {Q: min(m, len(fac[Q][1])) for Q, m in fixed.items() if Q in fac}
+        disc = float(sum((fac[Q][1][kept.get(Q, 0):] ** 2).sum() for Q in fac))
+    new_bond = sorted((Q, m) for Q, m in kept.items() if m > 0)
+    nidx = {Q: i for i, (Q, _) in enumerate(new_bond)}
+    canon, center = {}, {}
+    for Q, m in new_bond:
+        U, s, Vt, ro, co, g = fac[Q]
+        q = nidx[Q]
+        if direction == 0:
+            for (il, s1), mr in g["rows"]:
+                canon[(il, s1, q)] = U[ro[(il, s1)]:ro[(il, s1)] + mr, :m].copy()
+            Cm = s[:m, None] * np.vstack([Vt, np.zeros((max(0, m - Vt.shape[0]), Vt.shape[1]))])[:m]
+            for (s2, ir), mc in g["cols"]:
+                center[(q, s2, ir)] = Cm[:, co[(s2, ir)]:co[(s2, ir)] + mc].copy()
+        else:
+            for (s2, ir), mc in g["cols"]:
+                canon[(q, s2, ir)] = Vt[:m, co[(s2, ir)]:co[(s2, ir)] + mc].copy()
+            Ue = np.hstack([U, np.zeros((U.shape[0], max(0, m - U.shape[1])))])[:, :m]
+            Cm = Ue * s[None, :m]
+            for (il, s1), mr in g["rows"]:
+                center[(il, s1, q)] = Cm[ro[(il, s1)]:ro[(il, s1)] + mr, :].copy()
+    return new_bond, canon, center, disc
+
+
+class Davidson:
+    """GPU Davidson solver for one H_eff (all vector work in library kernels)."""
+
+    def __init__(self, n, kmax=24, device="cuda"):
+        import torch
+        self.torch = torch
+        self.n, self.kmax = n, kmax
+        f64 = dict(dtype=torch.float64, device=device)
+        self.V = torch.zeros((kmax, n), **f64)
+        self.S = torch.zeros((kmax, n), **f64)
+        self.x = torch.zeros(n, **f64)
+        self.hx = torch.zeros(n, **f64)
+        self.t = torch.zeros(n, **f64)
+        self.scal = torch.zeros(4, **f64)
+        self.ws = torch.zeros(max(X.davidson_ws_bytes(n, kmax) // 8, 1), **f64)
+
+    def solve(self, matvec, psi0, diag, tol=1e-8, max_iter=30, guard=1e-8, on_iter=None):
+        """Lowest eigenpair of the operator `matvec(v, out)`; returns (theta, rnorm, n_matvec).
+
+        The Ritz vector is left in self.x."""
+        n, kmax = self.n, self.kmax
+        V, S = self.V, self.S
+        V[0].copy_(psi0)
+        X.normalize(V[0], self.ws)
+        matvec(V[0], S[0])
+        nmv, k = 1, 1
+        theta = rnorm = None
+        for it in range(max_iter):
+            X.davidson_step(n, k, kmax, V, S, diag, guard, self.ws, self.x, self.hx, self.t, self.scal)
+            theta, rnorm, tnorm = (float(v) for v in self.scal[:3].cpu())
+            if on_iter:
+                on_iter(it, theta, rnorm)
+            if rnorm < tol or it == max_iter - 1 or not (tnorm > 1e-14):
+                break
+            if k == kmax:
+                V[0].copy_(self.x)
+                S[0].copy_(self.hx)
+                k = 1
+                X.davidson_step(n, k, kmax, V, S, diag, guard, self.ws, self.x, self.hx, self.t, self.scal)
+            V[k].copy_(self.t)
+            matvec(V[k], S[k])
+            nmv += 1
+            k += 1
+        return theta, rnorm, nmv
+
+
+class DMRG:
+    """Two-site DMRG for H(h, g) in the (n_elec, twosz) sector at bond dimension M."""
+
+    def __init__(self, h, g, n_elec, twosz, M, seed=0, device="cuda", tol=1e-8, max_iter=30, kmax=24,
+                 bonds=None, tensors=None, t_budget_bytes=0):
+        from synth import bond_sector_tables, random_right_canonical_mps
+        self.K = h.shape[0]
+        self.M = M
+        self.device = device
+        self.tol, self.max_iter, self.kmax = tol, max_iter, kmax
+        self.mpo = build_nc_mpo(h, g)
+        self.bonds = bonds if bonds is not None else bond_sector_tables(self.K, n_elec, twosz, M)
+        self.tensors = tensors if tensors is not None else random_right_canonical_mps(self.bonds, seed)
+        self.eng = Engine(self.mpo, device=device, t_budget_bytes=t_budget_bytes)
+        self.eng.init_boundaries()
+        K = self.K
+        for k in range(K - 1, 1, -1):
+            self.eng.update_right(k, self.bonds[k], self.bonds[k + 1],
+                                  site_payload(self.bonds[k], self.bonds[k + 1], self.tensors[k], device))
+        self.center = None      # one-site center tensor after a split
+        self.center_site = None
+        self.log = []
+
+    def _step(self, i, psi0, pass_id):
+        import torch
+        bl, br = self.bonds[i], self.bonds[i + 2]
+        plan = self.eng.heff_plan(i, bl, br)
+        Lb, Rb = X.Bond(bl), X.Bond(br)
+        L, R = self.eng.left[i], self.eng.right[i + 2]
+        n = int(plan.info.psi_nnz)
+        psi_t = torch.from_numpy(X.pack_psi(Lb, Rb, psi0)).to(self.device)
+        diag = torch.empty(n, dtype=torch.float64, device=self.device)
+        plan.prepare(L, R)
+        plan.diag(L, R, diag)
+        dav = Davidson(n, min(self.kmax, max(n, 1)), self.device)
+
+        def mv(v, out):
+            plan.apply(L, R, v, out)
+
+        theta, rnorm, nmv = dav.solve(mv, psi_t, diag, tol=self.tol, max_iter=self.max_iter)
+        psi = X.unpack_psi(Lb, Rb, dav.x.cpu().numpy())
+        self.log.append({"pass": pass_id, "i": i, "energy": theta, "rnorm": rnorm, "n_matvec": nmv})
+        return psi
+
+    def sweep_left_to_right(self, pass_id, start):
+        K = self.K
+        for i in range(start, K - 1):
+            if i == 0 and self.center is None:
+                psi0 = contract_two(self.tensors[0], self.tensors[1], self.bonds[0], self.bonds[1], self.bonds[2])
+            else:
+                psi0 = contract_two(self.center, self.tensors[i + 1], self.bonds[i], self.bonds[i + 1],
+                                    self.bonds[i + 2])
+            psi = self._step(i, psi0, pass_id)
+            if i < K - 2:
+                nb, A, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 0)
+                self.bonds[i + 1] = nb
+                self.tensors[i] = A
+                self.center, self.center_site = C, i + 1
+                self.eng.update_left(i, self.bonds[i], self.bonds[i + 1],
+                                     site_payload(self.bonds[i], self.bonds[i + 1], A, self.device))
+            else:
+                nb, B, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 1)
+                self.bonds[i + 1] = nb
+                self.tensors[i + 1] = B
+                self.center, self.center_site = C, i
+                self.eng.update_right(i + 1, self.bonds[i + 1], self.bonds[i + 2],
+                                      site_payload(self.bonds[i + 1], self.bonds[i + 2], B, self.device))
+
+    def sweep_right_to_left(self, pass_id):
+        for i in range(self.K - 3, -1, -1):
+            psi0 = contract_two(self.tensors[i], self.center, self.bonds[i], self.bonds[i + 1], self.bonds[i + 2])
+            psi = self._step(i, psi0, pass_id)
+            if i > 0:
+                nb, B, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 1)
+                self.bonds[i + 1] = nb
+                self.tensors[i + 1] = B
+                self.center, self.center_site = C, i
+                self.eng.update_right(i + 1, self.bonds[i + 1], self.bonds[i + 2],
+                                      site_payload(self.bonds[i + 1], self.bonds[i + 2], B, self.device))
+            else:
+                nb, A, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 0)
+                self.bonds[i + 1] = nb
+                self.tensors[i] = A
+                self.center, self.center_site = C, i + 1
+                self.eng.update_left(i, self.bonds[i], self.bonds[i + 1],
+                                     site_payload(self.bonds[i], self.bonds[i + 1], A, self.device))
+
+    def run(self, n_sweeps):
+        """Alternating passes; returns the energy of the last step of each pass."""
+        out = []
+        for s in range(n_sweeps):
+            if s % 2 == 0:
+                self.sweep_left_to_right(s, 0 if s == 0 else 1)
+            else:
+                self.sweep_right_to_left(s)
+            out.append(self.log[-1]["energy"])
+        return out

@@ -136,71 +136,104 @@ class MPO:
     parity: list = field(default_factory=list)  # parity[k] = (n_ops,) int array
 
 
-class _Acc:
-    def __init__(self):
-        self.a, self.b, self.m = [], [], []
+class _Index:
+    """Vectorised lookup from operator keys to positions in a cut's operator list."""
 
-    def add(self, a, b, mat):
-        self.a.append(a)
-        self.b.append(b)
-        self.m.append(mat)
+    def __init__(self, K, ops):
+        n2 = 2 * K
+        self.I = self.H = -1
+        self.C = np.full(n2, -1)
+        self.D = np.full(n2, -1)
+        self.A = np.full((n2, n2), -1)
+        self.Ad = np.full((n2, n2), -1)
+        self.B = np.full((n2, n2), -1)
+        self.T = np.full(n2, -1)
+        self.Td = np.full(n2, -1)
+        for i, key in enumerate(ops):
+            kind = key[0]
+            if kind == "I":
+                self.I = i
+            elif kind == "H":
+                self.H = i
+            elif kind in ("C", "D", "T", "Td"):
+                getattr(self, kind)[key[1]] = i
+            else:
+                getattr(self, kind)[key[1], key[2]] = i
+
+
+class _Sink:
+    """Collects (row, col, coef, site matrix) in arrays; sums duplicates at the end."""
+
+    def __init__(self):
+        self.rows, self.cols, self.mats = [], [], []
+
+    def add(self, rows, cols, coef, site):
+        rows = np.atleast_1d(np.asarray(rows)).ravel()
+        cols = np.broadcast_to(np.atleast_1d(np.asarray(cols)).ravel(), rows.shape)
+        coef = np.broadcast_to(np.atleast_1d(np.asarray(coef, float)).ravel(), rows.shape)
+        keep = (rows >= 0) & (cols >= 0) & (coef != 0.0)
+        if not np.any(keep):
+            return
+        self.rows.append(rows[keep])
+        self.cols.append(cols[keep])
+        self.mats.append(coef[keep][:, None, None] * site[None, :, :])
+
+    def result(self):
+        if not self.rows:
+            return np.zeros(0, int), np.zeros(0, int), np.zeros((0, 4, 4))
+        r = np.concatenate(self.rows)
+        c = np.concatenate(self.cols)
+        m = np.concatenate(self.mats)
+        order = np.lexsort((r, c))
+        r, c, m = r[order], c[order], m[order]
+        first = np.ones(len(r), bool)
+        first[1:] = (r[1:] != r[:-1]) | (c[1:] != c[:-1])
+        starts = np.nonzero(first)[0]
+        return r[starts], c[starts], np.add.reduceat(m, starts, axis=0)
 
 
 def _site_entries(K, k, coef, ops_k, ops_k1):
-    """All W^(k) entries as (row key, col key, 4x4) accumulated per key pair."""
-    idx_k = {key: n for n, key in enumerate(ops_k)}
-    idx_k1 = {key: n for n, key in enumerate(ops_k1)}
-    acc = {}
-
-    def put(akey, bkey, mat):
-        if akey not in idx_k or bkey not in idx_k1:
-            return
-        kk = (idx_k[akey], idx_k1[bkey])
-        if kk in acc:
-            acc[kk] = acc[kk] + mat
-        else:
-            acc[kk] = mat.copy()
-
+    """W^(k) entries as arrays (row op index at cut k, col op index at cut k+1, 4x4)."""
+    ik, ik1 = _Index(K, ops_k), _Index(K, ops_k1)
+    out = _Sink()
     n = 2 * k
     kap = (2 * k, 2 * k + 1)
+    xs = np.arange(n)
     # identity propagation and normal operators
-    put(("I",), ("I",), _I)
-    put(("H",), ("H",), _I)
-    for x in range(n):
-        put(("C", x), ("C", x), _P)
-        put(("D", x), ("D", x), _P)
+    out.add(ik.I, ik1.I, 1.0, _I)
+    out.add(ik.H, ik1.H, 1.0, _I)
+    out.add(ik.C[xs], ik1.C[xs], 1.0, _P)
+    out.add(ik.D[xs], ik1.D[xs], 1.0, _P)
     for s in range(2):
-        put(("I",), ("C", kap[s]), CR[s] @ _P)
-        put(("I",), ("D", kap[s]), AN[s] @ _P)
-    for x in range(n):
-        for y in range(x + 1, n):
-            put(("A", x, y), ("A", x, y), _I)
-            put(("Ad", x, y), ("Ad", x, y), _I)
-    for x in range(n):
-        for y in range(n):
-            put(("B", x, y), ("B", x, y), _I)
-    for x in range(n):
-        for s in range(2):
-            put(("C", x), ("A", x, kap[s]), CR[s])
-            put(("D", x), ("Ad", x, kap[s]), -AN[s])
-            put(("C", x), ("B", x, kap[s]), AN[s])
-            put(("D", x), ("B", kap[s], x), -CR[s])
-    put(("I",), ("A", kap[0], kap[1]), CR[0] @ CR[1])
-    put(("I",), ("Ad", kap[0], kap[1]), AN[1] @ AN[0])
+        out.add(ik.I, ik1.C[kap[s]], 1.0, CR[s] @ _P)
+        out.add(ik.I, ik1.D[kap[s]], 1.0, AN[s] @ _P)
+    if n:
+        X, Y = np.meshgrid(xs, xs, indexing="ij")
+        up = X < Y
+        out.add(ik.A[X[up], Y[up]], ik1.A[X[up], Y[up]], 1.0, _I)
+        out.add(ik.Ad[X[up], Y[up]], ik1.Ad[X[up], Y[up]], 1.0, _I)
+        out.add(ik.B[X, Y], ik1.B[X, Y], 1.0, _I)
+    for s in range(2):
+        out.add(ik.C[xs], ik1.A[xs, kap[s]], 1.0, CR[s])
+        out.add(ik.D[xs], ik1.Ad[xs, kap[s]], -1.0, AN[s])
+        out.add(ik.C[xs], ik1.B[xs, kap[s]], 1.0, AN[s])
+        out.add(ik.D[xs], ik1.B[kap[s], xs], -1.0, CR[s])
+    out.add(ik.I, ik1.A[kap[0], kap[1]], 1.0, CR[0] @ CR[1])
+    out.add(ik.I, ik1.Ad[kap[0], kap[1]], 1.0, AN[1] @ AN[0])
     for s in range(2):
         for t in range(2):
-            put(("I",), ("B", kap[s], kap[t]), CR[s] @ AN[t])
-    for j in range(2 * k + 2, 2 * K):
-        put(("T", j), ("T", j), _P)
-        put(("Td", j), ("Td", j), _P)
+            out.add(ik.I, ik1.B[kap[s], kap[t]], 1.0, CR[s] @ AN[t])
+    js = np.arange(2 * k + 2, 2 * K)
+    out.add(ik.T[js], ik1.T[js], 1.0, _P)
+    out.add(ik.Td[js], ik1.Td[js], 1.0, _P)
     # H picks up the complementary operators of the new site's single operators
     for s in range(2):
-        put(("T", kap[s]), ("H",), AN[s])
-        put(("Td", kap[s]), ("H",), CR[s])
+        out.add(ik.T[kap[s]], ik1.H, 1.0, AN[s])
+        out.add(ik.Td[kap[s]], ik1.H, 1.0, CR[s])
 
     # remaining H and T/Td contributions: enumerate operator-slot patterns
-    Lidx = np.arange(n)
-    outs = np.arange(2 * k + 2, 2 * K)
+    Lidx = xs
+    outs = js
     one = ((True, False), lambda a, b: coef.t(a, b))
     two = ((True, True, False, False), lambda a, b, c, d: 0.5 * coef.v(a, b, c, d))
 
@@ -212,14 +245,15 @@ def _site_entries(K, k, coef, ops_k, ops_k1):
             if target == "H":
                 if nout or nk < 2:
                     continue
-            else:
-                if nout != 1 or nk < 1:
-                    continue
+            elif nout != 1 or nk < 1:
+                continue
             yield regs
 
     for daggers, cfn in (one, two):
         ns = len(daggers)
         for target in ("H", "T", "Td"):
+            if target != "H" and len(outs) == 0:
+                continue
             for regs in slot_patterns(ns, target):
                 if target != "H":
                     pos = regs.index(2)
@@ -241,7 +275,6 @@ def _site_entries(K, k, coef, ops_k, ops_k1):
                         continue
                     if par_b:
                         site = site @ _P
-                    # coefficient array over (left slots..., outside)
                     grids = []
                     for p in range(ns):
                         if regs[p] == 0:
@@ -249,57 +282,52 @@ def _site_entries(K, k, coef, ops_k, ops_k1):
                         elif regs[p] == 1:
                             grids.append(np.array([kap[spins[kslots.index(p)]]]))
                         else:
-                            grids.append(outs if target != "H" else np.array([0]))
+                            grids.append(outs)
                     mesh = np.meshgrid(*grids, indexing="ij")
                     cval = sign * cfn(*mesh)
-                    # squeeze site-k axes; keep left slots and outside slot in slot order
                     keep_axes = [p for p in range(ns) if regs[p] != 1]
-                    cval = cval.reshape([len(grids[p]) for p in range(ns)])
                     cval = cval.reshape([len(grids[p]) for p in keep_axes])
-                    if target == "H":
-                        cval = cval[..., 0] if regs.count(2) else cval
-                    _emit(put, target, daggers, lslots, regs, cval, site, outs, n)
-
-    return [(a, b, m) for (a, b), m in acc.items()]
+                    _emit(out, ik, ik1, target, daggers, lslots, regs, cval, site, outs)
+    return out.result()
 
 
-def _emit(put, target, daggers, lslots, regs, cval, site, outs, n):
-    """Distribute a coefficient array onto canonical left operators."""
+def _emit(out, ik, ik1, target, daggers, lslots, regs, cval, site, outs):
+    """Distribute a coefficient array onto canonical left operators (vectorised)."""
     ld = [daggers[p] for p in lslots]
-    # axis order of cval: slots with region 0 or 2, in slot order
     kept = [p for p in range(len(regs)) if regs[p] != 1]
     if target == "H":
-        cols = [("H",)]
-        arrs = [cval]
+        cval = cval[..., None]
+        cols = np.array([ik1.H])
     else:
-        opos = regs.index(2)
-        oax = kept.index(opos)
+        oax = kept.index(regs.index(2))
         cval = np.moveaxis(cval, oax, -1)  # outside index last
-        cols = [(target, int(j)) for j in outs]
-        arrs = [cval[..., m] for m in range(len(outs))]
-    for bkey, arr in zip(cols, arrs):
-        if len(lslots) == 0:
-            val = float(np.asarray(arr).reshape(()))
-            if val != 0.0:
-                put(("I",), bkey, val * site)
-        elif len(lslots) == 1:
-            kind = "C" if ld[0] else "D"
-            for x in np.nonzero(arr)[0]:
-                put((kind, int(x)), bkey, float(arr[x]) * site)
+        cols = (ik1.T if target == "T" else ik1.Td)[outs]
+    nj = len(cols)
+    if len(lslots) == 0:
+        out.add(np.full(nj, ik.I), cols, cval.reshape(nj), site)
+    elif len(lslots) == 1:
+        idx = ik.C if ld[0] else ik.D
+        nl = cval.shape[0]
+        rows = np.repeat(idx[:nl], nj)
+        out.add(rows, np.tile(cols, nl), cval.reshape(nl * nj), site)
+    else:
+        nl = cval.shape[0]
+        X, Y = np.meshgrid(np.arange(nl), np.arange(nl), indexing="ij")
+        up = X < Y
+        if ld == [True, True]:      # a+_x a+_y = A_xy (x<y), -A_yx (x>y)
+            m = cval - np.swapaxes(cval, 0, 1)
+            rows = ik.A[X[up], Y[up]]
+        elif ld == [False, False]:  # a_x a_y = Ad_yx (y<x), -Ad_xy (x<y); Ad_jl = a_l a_j
+            m = np.swapaxes(cval, 0, 1) - cval
+            rows = ik.Ad[X[up], Y[up]]
+        elif ld == [True, False]:   # a+_x a_y = B_xy
+            m = cval
+            up = np.ones_like(up)
+            rows = ik.B[X[up], Y[up]]
         else:
-            if ld == [True, True]:      # a+_x a+_y = A_xy (x<y), -A_yx (x>y)
-                m = arr - arr.T
-                for x, y in zip(*np.nonzero(np.triu(m, 1))):
-                    put(("A", int(x), int(y)), bkey, float(m[x, y]) * site)
-            elif ld == [False, False]:  # a_x a_y = Ad_yx (y<x), -Ad_xy (x<y)
-                m = arr.T - arr        # m[j, l] = coefficient of Ad_jl = a_l a_j
-                for x, y in zip(*np.nonzero(np.triu(m, 1))):
-                    put(("Ad", int(x), int(y)), bkey, float(m[x, y]) * site)
-            elif ld == [True, False]:   # a+_x a_y = B_xy
-                for x, y in zip(*np.nonzero(arr)):
-                    put(("B", int(x), int(y)), bkey, float(arr[x, y]) * site)
-            else:
-                raise AssertionError("left factor not normal ordered")
+            raise AssertionError("left factor not normal ordered")
+        vals = m[X[up], Y[up]]                       # (npair, nj)
+        out.add(np.repeat(rows, nj), np.tile(cols, len(rows)), vals.reshape(-1), site)
 
 
 def build_nc_mpo(h, g, prune=True, tol=0.0):
@@ -307,9 +335,11 @@ def build_nc_mpo(h, g, prune=True, tol=0.0):
     K = h.shape[0]
     coef = _Coef(np.asarray(h, float), np.asarray(g, float))
     cuts = [cut_ops(K, k) for k in range(K + 1)]
-    raw = [_site_entries(K, k, coef, cuts[k], cuts[k + 1]) for k in range(K)]
-    # drop numerically empty entries
-    raw = [[(a, b, m) for a, b, m in ent if np.abs(m).max() > tol] for ent in raw]
+    raw = []
+    for k in range(K):
+        r, c, m = _site_entries(K, k, coef, cuts[k], cuts[k + 1])
+        keep = np.abs(m).reshape(len(m), -1).max(axis=1) > tol if len(m) else np.zeros(0, bool)
+        raw.append((r[keep], c[keep], m[keep]))
     alive = [np.ones(len(c), bool) for c in cuts]
     if prune:
         changed = True
@@ -318,10 +348,10 @@ def build_nc_mpo(h, g, prune=True, tol=0.0):
             for k in range(K):
                 used_in = np.zeros(len(cuts[k + 1]), bool)
                 used_out = np.zeros(len(cuts[k]), bool)
-                for a, b, _ in raw[k]:
-                    if alive[k][a] and alive[k + 1][b]:
-                        used_in[b] = True
-                        used_out[a] = True
+                ra, rb, _ = raw[k]
+                both = alive[k][ra] & alive[k + 1][rb]
+                used_in[rb[both]] = True
+                used_out[ra[both]] = True
                 new1 = alive[k + 1] & used_in
                 new0 = alive[k] & used_out
                 if (new1 != alive[k + 1]).any() or (new0 != alive[k]).any():
@@ -337,16 +367,12 @@ def build_nc_mpo(h, g, prune=True, tol=0.0):
         new_cuts.append([cuts[k][i] for i in keep])
     sites = []
     for k in range(K):
-        rows, cols, mats = [], [], []
-        for a, b, mat in raw[k]:
-            ra, rb = remap[k][a], remap[k + 1][b]
-            if ra >= 0 and rb >= 0:
-                rows.append(ra)
-                cols.append(rb)
-                mats.append(mat)
-        order = np.lexsort((np.array(rows), np.array(cols)))
-        sites.append(SiteMPO(np.array(rows, np.int32)[order], np.array(cols, np.int32)[order],
-                             np.array(mats)[order]))
+        ra, rb, mats = raw[k]
+        na, nb = remap[k][ra], remap[k + 1][rb]
+        ok = (na >= 0) & (nb >= 0)
+        na, nb, mats = na[ok], nb[ok], mats[ok]
+        order = np.lexsort((na, nb))
+        sites.append(SiteMPO(na[order].astype(np.int32), nb[order].astype(np.int32), mats[order]))
     mpo = MPO(K, new_cuts, sites)
     mpo.dq = [np.array([op_dq(key) for key in c], np.int32).reshape(-1, 2) for c in new_cuts]
     mpo.parity = [np.array([op_parity(key) for key in c], np.int32) for c in new_cuts]
