@@ -25,9 +25,10 @@
  * Payload layouts (FP64, all blocks row-major, no padding):
  *  - environment: operators in order; operator a holds one block per source
  *    sector q (ascending) whose destination q+dq_a exists; block (dst x src).
- *  - two-site wavefunction between bond i and bond i+2: blocks for
- *    (il, s1, s2) ascending lexicographic whose right sector
- *    q(il)+q(s1)+q(s2) exists; block (dim il x dim ir).
+ *  - two-site wavefunction between bond i and bond i+2: column blocks
+ *    (s2, ir) ascending; inside one, the row blocks (il, s1) ascending with
+ *    q(il)+q(s1)+q(s2) = q(ir); block (dim il x dim ir).  A column block is
+ *    thus one dense row-major matrix (sum of dim il) x dim ir.
  *  - site tensor between bond k and k+1: blocks for (il, s) ascending whose right
  *    sector q(il)+q(s) exists; block (dim il x dim ir).
  * The hx_*_layout functions return these offsets.
@@ -86,7 +87,8 @@ typedef struct {
 
 typedef struct {
     int64_t t_budget_bytes;  /* cap on the intermediate (T) workspace; 0 = default 2 GiB */
-    int32_t reserved[8];
+    int32_t split_kseg_min;  /* minimum K of a split-K segment; 0 = default 2048 */
+    int32_t reserved[7];
 } hx_plan_opts;
 
 typedef struct {

@@ -17,7 +17,8 @@ enum Space : int8_t {
     SP_R = 3,     // right environment payload (env update: site tensor)
     SP_WS = 4,    // caller workspace (mixed operators, intermediates)
     SP_TAB = 5,   // plan tables on the device (mixing coefficients)
-    SP_N = 6
+    SP_PART = 6,  // split-K partial tiles (a region of the workspace)
+    SP_N = 7
 };
 
 // One contribution alpha * op(A) * op(B) to an output tile.  A is (rows x k),
@@ -65,6 +66,20 @@ struct Gather {
 };
 static_assert(sizeof(Gather) == 40, "Gather layout");
 
+// Fixed-order sum of a split tile's partials: out = beta*out + sum_j part[j].
+struct Reduce {
+    int64_t coff;     // output tile (cspace)
+    int64_t pbase;    // first partial (SP_PART), partial j at pbase + j*TM*TN, ld TN
+    int32_t ldc;
+    int32_t m, n;
+    int32_t np;
+    int8_t cspace;
+    int8_t beta;
+    int16_t pad;
+    int32_t pad2;
+};
+static_assert(sizeof(Reduce) == 40, "Reduce layout");
+
 constexpr int TM = 64;
 constexpr int TN = 64;
 
@@ -76,6 +91,8 @@ struct Launch {
     int64_t tile0;     // index into the plan's tile array
     int64_t ntile;
     double flops;      // algorithmic 2 m n k of the blocks it covers
+    int64_t red0 = 0;  // split-K reductions run after the GEMM: [red0, red0+nred)
+    int64_t nred = 0;
 };
 
 struct GatherLaunch {
@@ -95,6 +112,7 @@ struct Plan {
     std::vector<Tile> tiles;
     std::vector<Task> tasks;
     std::vector<Gather> gathers;
+    std::vector<Reduce> reduces;
     std::vector<double> coef;     // mixing coefficient matrices (space SP_TAB)
     // sequences of launches
     std::vector<Launch> prep;     // mixing (heff_prepare / first part of env update)
@@ -105,11 +123,14 @@ struct Plan {
     // sizes
     int64_t psi_nnz = 0, in_nnz = 0, in2_nnz = 0, out_nnz = 0;
     int64_t ws_doubles = 0;
+    int64_t part_base = 0;      // workspace offset (doubles) of the split-K partial region
+    int64_t part_tiles = 0;     // partial tiles needed by the largest launch
+    int64_t split_kseg_min = 2048;
     double flops_apply = 0, flops_prepare = 0, bytes_apply = 0;
     int64_t n_tasks_apply = 0, n_tiles_apply = 0;
     int n_chunks = 0, n_mixed = 0;
     // device table layout (byte offsets inside the uploaded buffer)
-    int64_t off_tiles = 0, off_tasks = 0, off_gathers = 0, off_coef = 0, table_bytes = 0;
+    int64_t off_tiles = 0, off_tasks = 0, off_gathers = 0, off_coef = 0, off_reduces = 0, table_bytes = 0;
     void* dev = nullptr;          // caller-provided device table buffer (after upload)
 };
 

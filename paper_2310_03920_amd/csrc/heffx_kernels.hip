@@ -35,6 +35,7 @@ __device__ __forceinline__ double* space_ptr(const Bases& B, int sp) {
     r = sp == 3 ? B.p[3] : r;
     r = sp == 4 ? B.p[4] : r;
     r = sp == 5 ? B.p[5] : r;
+    r = sp == 6 ? B.p[6] : r;
     return r;
 }
 
@@ -214,6 +215,20 @@ __global__ __launch_bounds__(256) void bsgemm_f64(const Tile* __restrict__ tiles
     put(acc01, wr0, wc0 + 16);
     put(acc10, wr0 + 16, wc0);
     put(acc11, wr0 + 16, wc0 + 16);
+}
+
+// Fixed-order sum of split-K partial tiles into the owning output tile.
+__global__ __launch_bounds__(256) void reduce_partials(const Reduce* __restrict__ red, Bases B) {
+    const Reduce r = red[blockIdx.x];
+    const double* P = space_ptr(B, SP_PART) + r.pbase;
+    double* C = space_ptr(B, r.cspace) + r.coff;
+    for (int e = threadIdx.x; e < r.m * r.n; e += blockDim.x) {
+        const int row = e / r.n, col = e % r.n;
+        double acc = 0.0;
+        for (int j = 0; j < r.np; ++j) acc += P[(int64_t)j * TM * TN + row * TN + col];
+        double* p = C + (int64_t)row * r.ldc + col;
+        *p = r.beta ? (*p + acc) : acc;
+    }
 }
 
 __global__ void gather_scale(const Gather* __restrict__ g, Bases B) {
@@ -447,6 +462,7 @@ static Bases make_bases(const Plan* P, const double* psi, double* out, const dou
     b.p[SP_R] = const_cast<double*>(R);
     b.p[SP_WS] = static_cast<double*>(ws);
     b.p[SP_TAB] = reinterpret_cast<double*>(static_cast<char*>(P->dev) + P->off_coef);
+    b.p[SP_PART] = ws ? static_cast<double*>(ws) + P->part_base : nullptr;
     return b;
 }
 
@@ -469,7 +485,11 @@ static int launch_gemm(const Plan* P, const Launch& L, const Bases& B, hipStream
             set_error("internal: bad GEMM kind");
             return HX_EINVAL;
     }
-    return hip_check(hipGetLastError(), "bsgemm launch");
+    int rc = hip_check(hipGetLastError(), "bsgemm launch");
+    if (rc || L.nred <= 0) return rc;
+    const Reduce* red = reinterpret_cast<const Reduce*>(static_cast<const char*>(P->dev) + P->off_reduces) + L.red0;
+    hipLaunchKernelGGL(reduce_partials, dim3((unsigned)L.nred), dim3(256), 0, s, red, B);
+    return hip_check(hipGetLastError(), "reduce launch");
 }
 
 static int check_ready(const hx_plan* plan, int kind) {
@@ -519,6 +539,10 @@ int hx_plan_upload(hx_plan* plan, void* dev_tables, hx_stream stream) {
     if (!P->coef.empty() &&
         (rc = hip_check(hipMemcpyAsync(d + P->off_coef, P->coef.data(), P->coef.size() * sizeof(double),
                                        hipMemcpyHostToDevice, s), "upload coefficients")))
+        return rc;
+    if (!P->reduces.empty() &&
+        (rc = hip_check(hipMemcpyAsync(d + P->off_reduces, P->reduces.data(), P->reduces.size() * sizeof(Reduce),
+                                       hipMemcpyHostToDevice, s), "upload reductions")))
         return rc;
     if ((rc = hip_check(hipStreamSynchronize(s), "upload sync"))) return rc;
     P->dev = dev_tables;

@@ -135,8 +135,19 @@ struct PsiBlock {
     int64_t off;
 };
 
+// Column block of the two-site tensor: all row blocks (il, s1) of the fused
+// left sector Q = q(ir) - q(s2), stacked, times the right index of sector ir.
+// Stored as one dense (rows x dim(ir)) row-major matrix.
+struct PsiCol {
+    int s2, ir;
+    int rows;                                  // sum of dim(il) over the stacked row blocks
+    int64_t off;                               // offset of the column block
+    std::vector<std::array<int, 3>> rowblk;    // (il, s1, row offset)
+};
+
 struct PsiLayout {
     std::vector<PsiBlock> blocks;
+    std::vector<PsiCol> cols;
     std::unordered_map<int64_t, int> by_key;  // (il, s1, s2) -> block
     int64_t nnz = 0;
     static int64_t key(int il, int s1, int s2) { return ((int64_t)il * 4 + s1) * 4 + s2; }
@@ -146,18 +157,30 @@ struct PsiLayout {
     }
 };
 
+// Blocks ordered by column block (s2, ir), then by (il, s1): each column block is a
+// contiguous dense matrix and each block a contiguous row range of it.
 static PsiLayout psi_layout(const Bond& lb, const Bond& rb) {
     PsiLayout P;
-    for (int il = 0; il < lb.nsec(); ++il)
-        for (int s1 = 0; s1 < 4; ++s1)
-            for (int s2 = 0; s2 < 4; ++s2) {
-                int ir = rb.find(lb.qn[il][0] + SITE_Q[s1][0] + SITE_Q[s2][0],
-                                 lb.qn[il][1] + SITE_Q[s1][1] + SITE_Q[s2][1]);
-                if (ir < 0) continue;
-                P.by_key[PsiLayout::key(il, s1, s2)] = (int)P.blocks.size();
-                P.blocks.push_back({il, s1, s2, ir, P.nnz});
-                P.nnz += (int64_t)lb.dim[il] * rb.dim[ir];
-            }
+    for (int s2 = 0; s2 < 4; ++s2)
+        for (int ir = 0; ir < rb.nsec(); ++ir) {
+            PsiCol c;
+            c.s2 = s2;
+            c.ir = ir;
+            c.rows = 0;
+            c.off = P.nnz;
+            for (int il = 0; il < lb.nsec(); ++il)
+                for (int s1 = 0; s1 < 4; ++s1) {
+                    if (lb.qn[il][0] + SITE_Q[s1][0] + SITE_Q[s2][0] != rb.qn[ir][0] ||
+                        lb.qn[il][1] + SITE_Q[s1][1] + SITE_Q[s2][1] != rb.qn[ir][1])
+                        continue;
+                    P.by_key[PsiLayout::key(il, s1, s2)] = (int)P.blocks.size();
+                    P.blocks.push_back({il, s1, s2, ir, P.nnz});
+                    c.rowblk.push_back({il, s1, c.rows});
+                    c.rows += lb.dim[il];
+                    P.nnz += (int64_t)lb.dim[il] * rb.dim[ir];
+                }
+            if (c.rows > 0) P.cols.push_back(std::move(c));
+        }
     return P;
 }
 
@@ -380,6 +403,62 @@ struct Builder {
     }
 };
 
+// Split-K: when a launch has too few tiles to fill the GPU, cut long task lists
+// at task boundaries into segments that write partial tiles; a reduction then
+// sums the partials of each tile in a fixed order (deterministic).
+static void split_launch(Plan& P, Launch& L) {
+    const int64_t want = 2048;
+    if (L.ntile >= want) return;
+    int64_t total = 0;
+    for (int64_t t = L.tile0; t < L.tile0 + L.ntile; ++t) total += P.tiles[t].ktot;
+    const int64_t kseg = std::max<int64_t>(P.split_kseg_min, total / want);
+    std::vector<Tile> out;
+    int64_t pidx = 0;
+    L.red0 = (int64_t)P.reduces.size();
+    for (int64_t t = L.tile0; t < L.tile0 + L.ntile; ++t) {
+        const Tile tl = P.tiles[t];
+        if (tl.ktot <= 2 * kseg) {
+            out.push_back(tl);
+            continue;
+        }
+        Reduce r;
+        r.coff = tl.coff;
+        r.ldc = tl.ldc;
+        r.m = tl.m;
+        r.n = tl.n;
+        r.cspace = tl.cspace;
+        r.beta = tl.beta;
+        r.pad = 0;
+        r.pad2 = 0;
+        r.pbase = pidx * TM * TN;
+        r.np = 0;
+        int32_t a = tl.tbeg;
+        while (a < tl.tend) {
+            int32_t b = a;
+            int64_t ks = 0;
+            while (b < tl.tend && (ks < kseg || b == a)) ks += P.tasks[b++].k;
+            Tile p = tl;
+            p.tbeg = a;
+            p.tend = b;
+            p.ktot = (int32_t)ks;
+            p.cspace = SP_PART;
+            p.coff = pidx * TM * TN;
+            p.ldc = TN;
+            p.beta = 0;
+            out.push_back(p);
+            ++pidx;
+            ++r.np;
+            a = b;
+        }
+        P.reduces.push_back(r);
+    }
+    L.nred = (int64_t)P.reduces.size() - L.red0;
+    P.tiles.resize(L.tile0);
+    P.tiles.insert(P.tiles.end(), out.begin(), out.end());
+    L.ntile = (int64_t)out.size();
+    P.part_tiles = std::max(P.part_tiles, pidx);
+}
+
 // Sort a launch's tiles by decreasing work (longest-processing-time first).
 static void sort_tiles(Plan& P, int64_t t0) {
     std::stable_sort(P.tiles.begin() + t0, P.tiles.end(), [](const Tile& a, const Tile& b) {
@@ -495,6 +574,7 @@ static void flush_blocks(Plan& P, std::vector<OutBlockTasks>& blocks, int kind, 
         B.add_block_tiles(kind, ob.coff, ob.ldc, ob.m, ob.n, cspace, beta, tbeg, tend, ktot);
     }
     L.ntile = (int64_t)P.tiles.size() - L.tile0;
+    split_launch(P, L);
     sort_tiles(P, L.tile0);
     if (flops_out) *flops_out += L.flops;
     if (L.ntile > 0) seq.push_back(L);
@@ -512,6 +592,7 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                       const OpSet& Ro, const std::vector<Entry>& e1, const std::vector<Entry>& e2,
                       const hx_plan_opts* opts) {
     P.kind = PK_HEFF;
+    if (opts && opts->split_kseg_min > 0) P.split_kseg_min = opts->split_kseg_min;
     EnvLayout Ll = env_layout(lb, Lo), Rl = env_layout(rb, Ro);
     PsiLayout psi = psi_layout(lb, rb);
     P.psi_nnz = psi.nnz;
@@ -546,24 +627,24 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
     };
 
     int nmid = (int)Mo.dq.size();
-    // psi blocks grouped by s2
-    std::vector<std::vector<int>> psi_by_s2(4);
-    for (int i = 0; i < (int)psi.blocks.size(); ++i) psi_by_s2[psi.blocks[i].s2].push_back(i);
 
-    // T sizes per b (for chunking)
+    // psi column blocks grouped by s2
+    std::vector<std::vector<int>> col_by_s2(4);
+    for (int c = 0; c < (int)psi.cols.size(); ++c) col_by_s2[psi.cols[c].s2].push_back(c);
+
+    // T sizes per b (for chunking): one stacked column block per (s2', r')
     std::vector<int64_t> tsize(nmid, 0);
     std::vector<char> active(nmid, 0);
     for (int b = 0; b < nmid; ++b) {
         if (ML.trans[b].empty() || MR.trans[b].empty()) continue;
         active[b] = 1;
-        std::unordered_map<int64_t, int64_t> seen;
+        std::unordered_map<int64_t, char> seen;
         for (auto& tr : MR.trans[b])
-            for (int pi : psi_by_s2[tr.si]) {
-                const PsiBlock& pb = psi.blocks[pi];
-                int irp = rb.find(rb.qn[pb.ir][0] + tr.m.dn, rb.qn[pb.ir][1] + tr.m.ds);
+            for (int ci : col_by_s2[tr.si]) {
+                const PsiCol& pc = psi.cols[ci];
+                int irp = rb.find(rb.qn[pc.ir][0] + tr.m.dn, rb.qn[pc.ir][1] + tr.m.ds);
                 if (irp < 0) continue;
-                int64_t key = ((int64_t)pb.il * 4 + pb.s1) * 4 * 65536 + tr.so * 65536 + irp;
-                if (seen.emplace(key, 0).second) tsize[b] += (int64_t)lb.dim[pb.il] * rb.dim[irp];
+                if (seen.emplace((int64_t)tr.so * 65536 + irp, 1).second) tsize[b] += (int64_t)pc.rows * rb.dim[irp];
             }
     }
     int64_t budget = default_budget(opts);
@@ -595,10 +676,11 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
     int64_t nt = 0;
     double tbytes = 0;
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
-        // ---- stage 1: T_b[l, s1, s2', r'] = sum_{s2} psi[l,s1,s2,r] Rmix_{b,s2'<-s2}[r',r]^T
+        // ---- stage 1: T_b[:, (s2', r')] = sum_{s2} psi[:, (s2, r)] Rmix_{b,s2'<-s2}[r', r]^T
+        //      on stacked column blocks (all row blocks of one fused sector at once)
         std::vector<OutBlockTasks> tblocks;
         struct TInfo {
-            int b, il, s1, s2p, irp;
+            int b, col, s2p, irp;  // col: the psi column block whose row structure T shares
             int64_t off;
         };
         std::vector<TInfo> tinfo;
@@ -607,14 +689,13 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
         for (int b = chunks[ci].first; b < chunks[ci].second; ++b) {
             if (!active[b]) continue;
             tidx.clear();
-            std::vector<int> mine;
             for (auto& tr : MR.trans[b]) {
                 const ShiftLayout& sl = rshift(tr.m.dn, tr.m.ds);
-                for (int pi : psi_by_s2[tr.si]) {
-                    const PsiBlock& pb = psi.blocks[pi];
-                    int irp = rb.find(rb.qn[pb.ir][0] + tr.m.dn, rb.qn[pb.ir][1] + tr.m.ds);
+                for (int cj : col_by_s2[tr.si]) {
+                    const PsiCol& pc = psi.cols[cj];
+                    int irp = rb.find(rb.qn[pc.ir][0] + tr.m.dn, rb.qn[pc.ir][1] + tr.m.ds);
                     if (irp < 0) continue;
-                    int64_t key = ((int64_t)pb.il * 4 + pb.s1) * 4 * 65536 + tr.so * 65536 + irp;
+                    int64_t key = (int64_t)tr.so * 65536 + irp;
                     auto it = tidx.find(key);
                     int ti;
                     if (it == tidx.end()) {
@@ -623,23 +704,26 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                         OutBlockTasks ob;
                         ob.coff = toff;
                         ob.ldc = rb.dim[irp];
-                        ob.m = lb.dim[pb.il];
+                        ob.m = pc.rows;
                         ob.n = rb.dim[irp];
                         tblocks.push_back(std::move(ob));
-                        tinfo.push_back({b, pb.il, pb.s1, tr.so, irp, toff});
-                        toff += (int64_t)ob.m * ob.n;
-                        mine.push_back(ti);
+                        tinfo.push_back({b, cj, tr.so, irp, toff});
+                        toff += (int64_t)pc.rows * rb.dim[irp];
                     } else {
                         ti = it->second;
+                        if (tblocks[ti].m != pc.rows) {
+                            set_error("internal: stacked intermediate rows inconsistent");
+                            return HX_EINVAL;
+                        }
                     }
                     Task t;
-                    t.aoff = pb.off;
-                    t.lda = rb.dim[pb.ir];
+                    t.aoff = pc.off;
+                    t.lda = rb.dim[pc.ir];
                     t.aspace = SP_PSI;
-                    t.boff = tr.m.base + sl.rel[pb.ir];
-                    t.ldb = rb.dim[pb.ir];
+                    t.boff = tr.m.base + sl.rel[pc.ir];
+                    t.ldb = rb.dim[pc.ir];
                     t.bspace = tr.m.space;
-                    t.k = rb.dim[pb.ir];
+                    t.k = rb.dim[pc.ir];
                     t.pad = 0;
                     t.alpha = tr.m.alpha;
                     tblocks[ti].tasks.push_back(t);
@@ -649,7 +733,7 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
         for (auto& ob : tblocks) tbytes += 2.0 * 8.0 * ob.m * ob.n;
         flush_blocks(P, tblocks, NT, SP_WS, 0, false, P.apply, &fl, &nt);
 
-        // ---- stage 2: sigma[l',s1',s2',r'] += sum Lmix_{b,s1'<-s1}[l',l] T_b[l,s1,s2',r']
+        // ---- stage 2: sigma[l',s1',s2',r'] += sum Lmix_{b,s1'<-s1}[l',l] T_b[(l,s1), (s2',r')]
         std::vector<OutBlockTasks> sblocks(psi.blocks.size());
         for (size_t i = 0; i < psi.blocks.size(); ++i) {
             const PsiBlock& pb = psi.blocks[i];
@@ -659,27 +743,31 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
             sblocks[i].n = rb.dim[pb.ir];
         }
         for (const TInfo& ti : tinfo) {
-            for (auto& tr : ML.trans[ti.b]) {
-                if (tr.si != ti.s1) continue;
-                int ilp = lb.find(lb.qn[ti.il][0] + tr.m.dn, lb.qn[ti.il][1] + tr.m.ds);
-                if (ilp < 0) continue;
-                int si = psi.find(ilp, tr.so, ti.s2p);
-                if (si < 0 || psi.blocks[si].ir != ti.irp) {
-                    set_error("internal: sigma block inconsistent with quantum numbers");
-                    return HX_EINVAL;
+            const PsiCol& pc = psi.cols[ti.col];
+            for (const auto& rbk : pc.rowblk) {
+                const int il = rbk[0], s1 = rbk[1], roff = rbk[2];
+                for (auto& tr : ML.trans[ti.b]) {
+                    if (tr.si != s1) continue;
+                    int ilp = lb.find(lb.qn[il][0] + tr.m.dn, lb.qn[il][1] + tr.m.ds);
+                    if (ilp < 0) continue;
+                    int si = psi.find(ilp, tr.so, ti.s2p);
+                    if (si < 0 || psi.blocks[si].ir != ti.irp) {
+                        set_error("internal: sigma block inconsistent with quantum numbers");
+                        return HX_EINVAL;
+                    }
+                    const ShiftLayout& sl = lshift(tr.m.dn, tr.m.ds);
+                    Task t;
+                    t.aoff = tr.m.base + sl.rel[il];
+                    t.lda = lb.dim[il];
+                    t.aspace = tr.m.space;
+                    t.boff = ti.off + (int64_t)roff * rb.dim[ti.irp];
+                    t.ldb = rb.dim[ti.irp];
+                    t.bspace = SP_WS;
+                    t.k = lb.dim[il];
+                    t.pad = 0;
+                    t.alpha = tr.m.alpha;
+                    sblocks[si].tasks.push_back(t);
                 }
-                const ShiftLayout& sl = lshift(tr.m.dn, tr.m.ds);
-                Task t;
-                t.aoff = tr.m.base + sl.rel[ti.il];
-                t.lda = lb.dim[ti.il];
-                t.aspace = tr.m.space;
-                t.boff = ti.off;
-                t.ldb = rb.dim[ti.irp];
-                t.bspace = SP_WS;
-                t.k = lb.dim[ti.il];
-                t.pad = 0;
-                t.alpha = tr.m.alpha;
-                sblocks[si].tasks.push_back(t);
             }
         }
         flush_blocks(P, sblocks, NN, SP_OUT, ci == 0 ? 0 : 1, ci == 0, P.apply, &fl, &nt);
@@ -792,6 +880,8 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
         }
         flush_blocks(P, dblocks, NN, SP_OUT, 0, true, P.diag_gemm, nullptr, nullptr);
     }
+    P.part_base = ws;
+    ws += P.part_tiles * TM * TN;
     P.ws_doubles = ws;
     if (!check_task_index_range(P)) return HX_EINVAL;
     return HX_OK;
@@ -804,6 +894,7 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
     // dir 0: bin = bond k (lb), bout = bond k+1; site tensor between bin and bout.
     // dir 1: bin = bond k+1 (rb), bout = bond k; site tensor between bout and bin.
     P.kind = dir == 0 ? PK_ENV_LEFT : PK_ENV_RIGHT;
+    if (opts && opts->split_kseg_min > 0) P.split_kseg_min = opts->split_kseg_min;
     EnvLayout Lin = env_layout(bin, oin), Lout = env_layout(bout, oout);
     SiteLayout S = dir == 0 ? site_layout(bin, bout) : site_layout(bout, bin);
     P.in_nnz = Lin.op_off.back();
@@ -970,6 +1061,8 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
     P.flops_apply = fl + M.flops;
     P.n_tasks_apply = nt;
     for (auto& L : P.apply) P.n_tiles_apply += L.ntile;
+    P.part_base = ws;
+    ws += P.part_tiles * TM * TN;
     P.ws_doubles = ws;
     P.bytes_apply = 8.0 * (P.in_nnz + P.in2_nnz + P.out_nnz);
     if (!check_task_index_range(P)) return HX_EINVAL;
@@ -987,6 +1080,8 @@ static void finalize_tables(Plan& P) {
     o = al(o + (int64_t)P.gathers.size() * sizeof(Gather));
     P.off_coef = o;
     o = al(o + (int64_t)P.coef.size() * sizeof(double));
+    P.off_reduces = o;
+    o = al(o + (int64_t)P.reduces.size() * sizeof(Reduce));
     P.table_bytes = std::max<int64_t>(o, 256);
 }
 

@@ -58,11 +58,12 @@ def _close(got, ref, rtol=RTOL):
         assert err <= rtol * scale, (k, err, scale)
 
 
-def _run_heff(device, lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi, budget=0, diag=False):
+def _run_heff(device, lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi, budget=0, diag=False, kseg=0):
     import torch
     from paper_2310_03920_amd import _lib as X
     lbB, rbB = X.Bond(lb), X.Bond(rb)
-    plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, t_budget_bytes=budget).upload(device)
+    plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, t_budget_bytes=budget,
+                      split_kseg_min=kseg).upload(device)
     Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
     Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
     pt = torch.from_numpy(X.pack_psi(lbB, rbB, psi)).to(device)
@@ -91,6 +92,15 @@ def test_heff_apply_chunked_intermediates(device):
     prob = _problem(3, True)
     res = _run_heff(device, *prob, budget=256 * 1024)
     assert res["plan"].info.n_chunks > 2
+    _close(res["sigma"], _dense_sigma(*prob))
+
+
+@pytest.mark.parametrize("kseg", [8, 33])
+def test_heff_apply_split_k(device, kseg):
+    """Long task lists cut into split-K segments summed by the fixed-order reduction."""
+    print(f"[heff_apply split-K] kseg={kseg}", flush=True)
+    prob = _problem(6, True)
+    res = _run_heff(device, *prob, kseg=kseg, budget=512 * 1024)
     _close(res["sigma"], _dense_sigma(*prob))
 
 

@@ -60,10 +60,13 @@ def test_nc_mpo_bond_dimension_grows_quadratically():
 
 
 def test_psi_layout_matches_block_enumeration():
+    """Blocks are ordered by column block (s2, ir) and then (il, s1), so every
+    column block is one contiguous dense matrix."""
     b = bond_sector_tables(8, 8, 0, 64)
     lb, rb = X.Bond(b[3]), X.Bond(b[5])
     keys, off = X.psi_layout(lb, rb)
-    assert keys == two_site_blocks(b[3], b[5])
+    assert sorted(keys) == sorted(two_site_blocks(b[3], b[5]))
+    assert keys == sorted(keys, key=lambda k: (k[2], k[3], k[0], k[1]))
     sizes = [b[3][k[0]][1] * b[5][k[3]][1] for k in keys]
     np.testing.assert_array_equal(np.diff(off), sizes)
     assert off[-1] == 4900
@@ -140,6 +143,17 @@ def test_plan_flop_count_matches_independent_count():
         ref = _count_flops(b[i], b[i + 2], [tuple(x) for x in m.dq[i]], [tuple(x) for x in m.dq[i + 2]], W1, W2)
         assert p.info.flops_apply == pytest.approx(ref, rel=1e-12)
         assert p.info.psi_nnz == sum(b[i][k[0]][1] * b[i + 2][k[3]][1] for k in two_site_blocks(b[i], b[i + 2]))
+
+
+def test_plan_split_k_keeps_flops():
+    K = 8
+    m = M.build_nc_mpo(*make_integrals(K, seed=0))
+    b = bond_sector_tables(K, K, 0, 64)
+    args = (b[3], b[5], m.dq[3], m.dq[4], m.dq[5], M.site_entries(m, 3), M.site_entries(m, 4))
+    p1 = X.HeffPlan(*args)
+    p2 = X.HeffPlan(*args, split_kseg_min=8)
+    assert p2.info.n_tiles > p1.info.n_tiles
+    assert p2.info.flops_apply == pytest.approx(p1.info.flops_apply, rel=1e-12)
 
 
 def test_plan_chunking_keeps_flops():
