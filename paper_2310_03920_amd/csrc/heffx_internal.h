@@ -30,10 +30,11 @@ struct Task {
     int32_t lda;
     int32_t ldb;
     int32_t k;
-    int8_t aspace;
-    int8_t bspace;
-    int16_t pad;
+    int32_t spaces;   // aspace | bspace << 8 (one dword: read with scalar loads)
     double alpha;
+    int aspace() const { return spaces & 0xff; }
+    int bspace() const { return (spaces >> 8) & 0xff; }
+    void set_spaces(int a, int b) { spaces = (a & 0xff) | ((b & 0xff) << 8); }
 };
 static_assert(sizeof(Task) == 40, "Task layout");
 
@@ -45,10 +46,11 @@ struct Tile {
     int32_t r0, c0;   // tile origin inside its block
     int32_t tbeg;     // task range [tbeg, tend)
     int32_t tend;
-    int32_t ktot;     // sum of k over the task range
-    int8_t cspace;
-    int8_t beta;      // 0: overwrite, 1: accumulate
-    int16_t pad;
+    int32_t ktot;     // sum over the task range of k rounded up to a multiple of 16
+    int32_t flags;    // cspace | beta << 8
+    int cspace() const { return flags & 0xff; }
+    int beta() const { return (flags >> 8) & 0xff; }
+    void set_out(int space, int b) { flags = (space & 0xff) | ((b & 0xff) << 8); }
 };
 static_assert(sizeof(Tile) == 48, "Tile layout");
 

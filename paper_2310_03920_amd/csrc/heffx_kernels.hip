@@ -39,43 +39,44 @@ __device__ __forceinline__ double* space_ptr(const Bases& B, int sp) {
     return r;
 }
 
-// Walks the concatenated K range of a tile's tasks for one fixed k-lane.
-struct Cursor {
-    int j;          // current task
-    int kbeg;       // first global k of task j
-    int kend;       // one past its last global k
-    const double* ptr;
-    int ld;
+// The K range of a tile is walked in 16-deep stages; every task's K is padded to
+// a multiple of 16 with zeros, so a stage belongs to exactly one task and the
+// walk is uniform across the workgroup (scalar registers, one lookup per stage).
+constexpr int KS = 16;
+
+struct Stage {
+    const double* a;   // A at the tile origin and the stage's first k
+    const double* b;
+    int lda, ldb;
+    int krem;          // valid k in this stage (0..16)
     double alpha;
 };
 
-template <bool IS_A, bool TRANS>
-__device__ __forceinline__ void cursor_load(Cursor& c, const Task* __restrict__ tasks, const Bases& B, int r0,
-                                            int c0) {
-    const Task& t = tasks[c.j];
-    if (IS_A) {
-        c.ld = t.lda;
-        c.alpha = t.alpha;
-        c.ptr = space_ptr(B, t.aspace) + t.aoff + (TRANS ? (int64_t)r0 : (int64_t)r0 * t.lda);
-    } else {
-        c.ld = t.ldb;
-        c.alpha = 1.0;
-        c.ptr = space_ptr(B, t.bspace) + t.boff + (TRANS ? (int64_t)c0 * t.ldb : (int64_t)c0);
-    }
-    c.kend = c.kbeg + t.k;
-}
-
-// Advance to the task containing global k index g; returns false past the end.
-template <bool IS_A, bool TRANS>
-__device__ __forceinline__ bool cursor_seek(Cursor& c, int g, int tend, const Task* __restrict__ tasks,
+template <bool TA, bool TB>
+__device__ __forceinline__ Stage next_stage(int& j, int& kl, int tend, const Task* __restrict__ tasks,
                                             const Bases& B, int r0, int c0) {
-    while (g >= c.kend) {
-        c.j++;
-        if (c.j >= tend) return false;
-        c.kbeg = c.kend;
-        cursor_load<IS_A, TRANS>(c, tasks, B, r0, c0);
+    Stage q;
+    while (j < tend && kl >= tasks[j].k) {
+        ++j;
+        kl = 0;
     }
-    return true;
+    if (j >= tend) {
+        q.a = q.b = nullptr;
+        q.lda = q.ldb = 0;
+        q.krem = 0;
+        q.alpha = 0.0;
+        return q;
+    }
+    const Task& t = tasks[j];
+    q.lda = t.lda;
+    q.ldb = t.ldb;
+    q.alpha = t.alpha;
+    q.krem = min(KS, t.k - kl);
+    const int sp = t.spaces;
+    q.a = space_ptr(B, sp & 0xff) + t.aoff + (TA ? (int64_t)kl * t.lda + r0 : (int64_t)r0 * t.lda + kl);
+    q.b = space_ptr(B, (sp >> 8) & 0xff) + t.boff + (TB ? (int64_t)c0 * t.ldb + kl : (int64_t)kl * t.ldb + c0);
+    kl += KS;
+    return q;
 }
 
 constexpr int LDS_PAD = 1;
@@ -84,8 +85,8 @@ constexpr int LDW = TM + LDS_PAD;
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void bsgemm_f64(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
                                                   Bases B) {
-    __shared__ double As[2][16][LDW];
-    __shared__ double Bs[2][16][LDW];
+    __shared__ double As[2][KS][LDW];
+    __shared__ double Bs[2][KS][LDW];
     const Tile tl = tiles[blockIdx.x];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -93,94 +94,57 @@ __global__ __launch_bounds__(256) void bsgemm_f64(const Tile* __restrict__ tiles
     const int wr0 = (wave & 1) * 32;
     const int wc0 = (wave >> 1) * 32;
     const int m = tl.m, n = tl.n;
-
-    // load lane assignments
-    //  A !TA: kk = tid & 15, rows (tid >> 4) + 16 i         (one k-lane)
-    //  A  TA: rows tid & 63, kk = (tid >> 6) + 4 i          (four k-lanes)
-    //  B !TB: cols tid & 63, kk = (tid >> 6) + 4 i          (four k-lanes)
-    //  B  TB: kk = tid & 15, cols (tid >> 4) + 16 i         (one k-lane)
-    constexpr int NA = TA ? 4 : 1;
-    constexpr int NB = TB ? 1 : 4;
-    Cursor ca[NA], cb[NB];
-    int kka[NA], kkb[NB];
-    for (int i = 0; i < NA; ++i) {
-        kka[i] = TA ? ((tid >> 6) + 4 * i) : (tid & 15);
-        ca[i].j = tl.tbeg;
-        ca[i].kbeg = 0;
-        ca[i].kend = 0;
-        if (tl.tbeg < tl.tend) cursor_load<true, TA>(ca[i], tasks, B, tl.r0, tl.c0);
-    }
-    for (int i = 0; i < NB; ++i) {
-        kkb[i] = TB ? (tid & 15) : ((tid >> 6) + 4 * i);
-        cb[i].j = tl.tbeg;
-        cb[i].kbeg = 0;
-        cb[i].kend = 0;
-        if (tl.tbeg < tl.tend) cursor_load<false, TB>(cb[i], tasks, B, tl.r0, tl.c0);
-    }
+    // load lanes (element e of a thread: idx = tid + 256 e):
+    //  A !TA: k = idx % 16, row = idx / 16 (16 contiguous k per row)
+    //  A  TA: row = idx % 64, k = idx / 64 (64 contiguous rows per k)
+    //  B !TB: col = idx % 64, k = idx / 64
+    //  B  TB: k = idx % 16, col = idx / 16
+    const int a_r = TA ? (tid & 63) : (tid >> 4);
+    const int a_k = TA ? (tid >> 6) : (tid & 15);
+    const int b_c = TB ? (tid >> 4) : (tid & 63);
+    const int b_k = TB ? (tid & 15) : (tid >> 6);
+    constexpr int a_dr = TA ? 0 : 16, a_dk = TA ? 4 : 0;  // step per element e
+    constexpr int b_dc = TB ? 16 : 0, b_dk = TB ? 0 : 4;
+    int cj = tl.tbeg, ckl = 0;  // uniform cursor
 
     dbl4 acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
     double ra[4], rb[4];
-    const int nst = (tl.ktot + 15) >> 4;
+    double alpha = 0.0;
+    const int nst = tl.ktot / KS;
 
-    auto load_stage = [&](int s) {
-        // A tile: 64 rows x 16 k
+    // raw loads; alpha is applied at the LDS store so the loads stay in flight
+    // across the MFMA work of the current stage
+    auto load_stage = [&]() {
+        const Stage q = next_stage<TA, TB>(cj, ckl, tl.tend, tasks, B, tl.r0, tl.c0);
+        alpha = q.alpha;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ci = TA ? i : 0;
-            const int kk = kka[ci];
-            const int r = TA ? (tid & 63) : ((tid >> 4) + 16 * i);
-            double v = 0.0;
-            const int g = s * 16 + kk;
-            if (g < tl.ktot && r < m) {
-                if (cursor_seek<true, TA>(ca[ci], g, tl.tend, tasks, B, tl.r0, tl.c0)) {
-                    const int kl = g - ca[ci].kbeg;
-                    v = ca[ci].alpha * (TA ? ca[ci].ptr[(int64_t)kl * ca[ci].ld + r]
-                                           : ca[ci].ptr[(int64_t)r * ca[ci].ld + kl]);
-                }
-            }
-            ra[i] = v;
-        }
-        // B tile: 16 k x 64 cols
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int ci = TB ? 0 : i;
-            const int kk = kkb[ci];
-            const int c = TB ? ((tid >> 4) + 16 * i) : (tid & 63);
-            double v = 0.0;
-            const int g = s * 16 + kk;
-            if (g < tl.ktot && c < n) {
-                if (cursor_seek<false, TB>(cb[ci], g, tl.tend, tasks, B, tl.r0, tl.c0)) {
-                    const int kl = g - cb[ci].kbeg;
-                    v = TB ? cb[ci].ptr[(int64_t)c * cb[ci].ld + kl] : cb[ci].ptr[(int64_t)kl * cb[ci].ld + c];
-                }
-            }
-            rb[i] = v;
+        for (int e = 0; e < 4; ++e) {
+            const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
+            const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
+            double va = 0.0, vb = 0.0;
+            if (ka < q.krem && r < m) va = TA ? q.a[(int64_t)ka * q.lda + r] : q.a[(int64_t)r * q.lda + ka];
+            if (kb < q.krem && c < n) vb = TB ? q.b[(int64_t)c * q.ldb + kb] : q.b[(int64_t)kb * q.ldb + c];
+            ra[e] = va;
+            rb[e] = vb;
         }
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int kk = TA ? kka[i] : kka[0];
-            const int r = TA ? (tid & 63) : ((tid >> 4) + 16 * i);
-            As[buf][kk][r] = ra[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int kk = TB ? kkb[0] : kkb[i];
-            const int c = TB ? ((tid >> 4) + 16 * i) : (tid & 63);
-            Bs[buf][kk][c] = rb[i];
+        for (int e = 0; e < 4; ++e) {
+            As[buf][a_k + a_dk * e][a_r + a_dr * e] = alpha * ra[e];
+            Bs[buf][b_k + b_dk * e][b_c + b_dc * e] = rb[e];
         }
     };
 
     if (nst > 0) {
-        load_stage(0);
+        load_stage();
         store_stage(0);
         __syncthreads();
         for (int s = 0; s < nst; ++s) {
             const int buf = s & 1;
-            if (s + 1 < nst) load_stage(s + 1);
+            if (s + 1 < nst) load_stage();
 #pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
+            for (int ks = 0; ks < KS / 4; ++ks) {
                 const int kr = ks * 4 + (lane >> 4);
                 const double a0 = As[buf][kr][wr0 + (lane & 15)];
                 const double a1 = As[buf][kr][wr0 + 16 + (lane & 15)];
@@ -197,14 +161,14 @@ __global__ __launch_bounds__(256) void bsgemm_f64(const Tile* __restrict__ tiles
     }
     // epilogue: for v_mfma_f64_16x16x4_f64 lane l holds rows l/16 + 4v (v = 0..3),
     // column l%16 of each 16x16 tile
-    double* C = space_ptr(B, tl.cspace) + tl.coff;
+    double* C = space_ptr(B, tl.flags & 0xff) + tl.coff;
     const int ldc = tl.ldc;
-    const bool beta = tl.beta != 0;
-    auto put = [&](const dbl4& a, int rb0, int cb0) {
+    const bool beta = ((tl.flags >> 8) & 0xff) != 0;
+    auto put = [&](const dbl4& a, int rb0_, int cb0) {
         const int col = cb0 + (lane & 15);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = rb0 + (lane >> 4) + 4 * v;
+            const int row = rb0_ + (lane >> 4) + 4 * v;
             if (row < m && col < n) {
                 double* p = C + (int64_t)row * ldc + col;
                 *p = beta ? (*p + a[v]) : a[v];

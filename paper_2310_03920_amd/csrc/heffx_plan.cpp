@@ -395,13 +395,14 @@ struct Builder {
                 t.tbeg = tbeg;
                 t.tend = tend;
                 t.ktot = ktot;
-                t.cspace = cspace;
-                t.beta = beta;
-                t.pad = 0;
+                t.set_out(cspace, beta);
                 P->tiles.push_back(t);
             }
     }
 };
+
+// K of a task as walked by the kernel: padded to the 16-deep LDS stage with zeros.
+static inline int32_t kpad(int32_t k) { return (k + 15) & ~15; }
 
 // Split-K: when a launch has too few tiles to fill the GPU, cut long task lists
 // at task boundaries into segments that write partial tiles; a reduction then
@@ -426,8 +427,8 @@ static void split_launch(Plan& P, Launch& L) {
         r.ldc = tl.ldc;
         r.m = tl.m;
         r.n = tl.n;
-        r.cspace = tl.cspace;
-        r.beta = tl.beta;
+        r.cspace = (int8_t)tl.cspace();
+        r.beta = (int8_t)tl.beta();
         r.pad = 0;
         r.pad2 = 0;
         r.pbase = pidx * TM * TN;
@@ -436,15 +437,14 @@ static void split_launch(Plan& P, Launch& L) {
         while (a < tl.tend) {
             int32_t b = a;
             int64_t ks = 0;
-            while (b < tl.tend && (ks < kseg || b == a)) ks += P.tasks[b++].k;
+            while (b < tl.tend && (ks < kseg || b == a)) ks += kpad(P.tasks[b++].k);
             Tile p = tl;
             p.tbeg = a;
             p.tend = b;
             p.ktot = (int32_t)ks;
-            p.cspace = SP_PART;
+            p.set_out(SP_PART, 0);
             p.coff = pidx * TM * TN;
             p.ldc = TN;
-            p.beta = 0;
             out.push_back(p);
             ++pidx;
             ++r.np;
@@ -505,12 +505,11 @@ static void emit_mixing(Plan& P, Mixer& M, std::vector<Launch>& seq) {
                 t.boff = M.lay->op_off[c.cols[w]];
                 t.ldb = (int32_t)c.size;
                 t.k = w1 - w;
-                t.aspace = SP_TAB;
-                t.bspace = M.env_space;
-                t.pad = 0;
+                const int ta_ = SP_TAB;
+                t.set_spaces(ta_, M.env_space);
                 t.alpha = 1.0;
                 P.tasks.push_back(t);
-                ktot += t.k;
+                ktot += kpad(t.k);
                 w = w1;
             }
             int32_t tend = (int32_t)P.tasks.size();
@@ -527,9 +526,7 @@ static void emit_mixing(Plan& P, Mixer& M, std::vector<Launch>& seq) {
                 t.tbeg = tbeg;
                 t.tend = tend;
                 t.ktot = ktot;
-                t.cspace = SP_WS;
-                t.beta = 0;
-                t.pad = 0;
+                t.set_out(SP_WS, 0);
                 P.tiles.push_back(t);
             }
             (void)B;
@@ -566,7 +563,7 @@ static void flush_blocks(Plan& P, std::vector<OutBlockTasks>& blocks, int kind, 
         int32_t ktot = 0;
         for (auto& t : ob.tasks) {
             P.tasks.push_back(t);
-            ktot += t.k;
+            ktot += kpad(t.k);
             L.flops += 2.0 * ob.m * ob.n * (double)t.k;
         }
         int32_t tend = (int32_t)P.tasks.size();
@@ -719,13 +716,12 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                     Task t;
                     t.aoff = pc.off;
                     t.lda = rb.dim[pc.ir];
-                    t.aspace = SP_PSI;
+                    const int ta_ = SP_PSI;
                     t.boff = tr.m.base + sl.rel[pc.ir];
                     t.ldb = rb.dim[pc.ir];
-                    t.bspace = tr.m.space;
+                    t.set_spaces(ta_, tr.m.space);
                     t.k = rb.dim[pc.ir];
-                    t.pad = 0;
-                    t.alpha = tr.m.alpha;
+                        t.alpha = tr.m.alpha;
                     tblocks[ti].tasks.push_back(t);
                 }
             }
@@ -759,13 +755,12 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                     Task t;
                     t.aoff = tr.m.base + sl.rel[il];
                     t.lda = lb.dim[il];
-                    t.aspace = tr.m.space;
+                    const int ta_ = tr.m.space;
                     t.boff = ti.off + (int64_t)roff * rb.dim[ti.irp];
                     t.ldb = rb.dim[ti.irp];
-                    t.bspace = SP_WS;
+                    t.set_spaces(ta_, SP_WS);
                     t.k = lb.dim[il];
-                    t.pad = 0;
-                    t.alpha = tr.m.alpha;
+                        t.alpha = tr.m.alpha;
                     sblocks[si].tasks.push_back(t);
                 }
             }
@@ -868,12 +863,11 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                 Task t;
                 t.aoff = dl_off[(size_t)pb.il * 4 + pb.s1];
                 t.lda = nb0;
-                t.aspace = SP_WS;
+                const int ta_ = SP_WS;
                 t.boff = dr_off[(size_t)pb.ir * 4 + pb.s2];
                 t.ldb = rb.dim[pb.ir];
-                t.bspace = SP_WS;
+                t.set_spaces(ta_, SP_WS);
                 t.k = nb0;
-                t.pad = 0;
                 t.alpha = 1.0;
                 ob.tasks.push_back(t);
             }
@@ -999,13 +993,12 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
                     Task t;
                     t.aoff = tr.m.base + sl.rel[x];   // mixed op block (xp <- x)
                     t.lda = bin.dim[x];
-                    t.aspace = tr.m.space;
+                    const int ta_ = tr.m.space;
                     t.boff = sb.off;                  // site block
                     t.ldb = dir == 0 ? bout.dim[y] : bin.dim[x];
-                    t.bspace = SP_R;
+                    t.set_spaces(ta_, SP_R);
                     t.k = bin.dim[x];
-                    t.pad = 0;
-                    t.alpha = tr.m.alpha;
+                        t.alpha = tr.m.alpha;
                     yblocks[yi].tasks.push_back(t);
                 }
             }
@@ -1047,12 +1040,11 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
             Task t;
             t.aoff = S.blocks[sbk].off;
             t.lda = dir == 0 ? bout.dim[yp] : bin.dim[yi.xp];
-            t.aspace = SP_R;
+            const int ta_ = SP_R;
             t.boff = yi.off;
             t.ldb = bout.dim[yi.y];
-            t.bspace = SP_WS;
+            t.set_spaces(ta_, SP_WS);
             t.k = bin.dim[yi.xp];
-            t.pad = 0;
             t.alpha = 1.0;
             oblocks[it->second].tasks.push_back(t);
         }
