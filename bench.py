@@ -7,9 +7,14 @@ renormalised operators of a seeded random MPS, built on the GPU by environment
 updates from both ends (untimed setup).
 
 One timed step = the whole hot path at sites (17, 18): operator mixing, diag,
-Davidson (sigma = H_eff psi + Davidson steps, tol 1e-8, at most 30 iterations),
-SVD split of the Ritz vector, environment update.  `value` is the algorithmic
-FP64 FLOP of the step's GEMM work divided by its wall time.
+Davidson (sigma = H_eff psi + Davidson steps) to |r| <= 1e-7, SVD split of the
+Ritz vector, environment update.  The Davidson start vector is warm, as in a
+step after the first sweep: the Ritz vector of an untimed 100-iteration FP64
+solve from a seeded random vector.  The FP64 reference energy comes from an
+untimed FP64 solve to |r| <= 1e-9.  `value` is the algorithmic FLOP of the
+step's GEMM work divided by its wall time.  --mode f32 runs the block
+contractions in FP32 (FP32 MFMA accumulation) until |r| <= 1e-5, then refines
+with FP64 sigma-vectors; the Davidson vector work is FP64 in both modes.
 
 Prints one JSON line.  Only one GPU is supported.
 """
@@ -28,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "H_eff·ψ GFLOP/s & %MFMA peak at M=1000; Davidson energy err vs FP64 oracle"
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 
 
 def log(*a):
@@ -109,9 +115,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--orbitals", type=int, default=36)
     ap.add_argument("--bond-dim", type=int, default=1000)
-    ap.add_argument("--max-iter", type=int, default=30)
-    ap.add_argument("--t-budget-gb", type=float, default=2.0)
+    ap.add_argument("--max-iter", type=int, default=200)
+    ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--pre-iter", type=int, default=100)
+    ap.add_argument("--t-budget-gb", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=["f64", "f32"], default="f64",
+                    help="precision of the block contractions; Davidson is FP64 in both")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -166,6 +176,10 @@ def main():
     fixed = dict(bonds[i + 1])
     ev = []
 
+    ev32 = []
+    v32 = torch.empty(n, dtype=torch.float32, device=device)
+    s32 = torch.empty(n, dtype=torch.float32, device=device)
+
     def mv(v, out):
         s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         s.record()
@@ -173,10 +187,29 @@ def main():
         e.record()
         ev.append((s, e))
 
+    def mv32(v, out):
+        X.convert_f64_f32(v, v32)
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        plan.apply_f32(v32, s32)
+        e.record()
+        ev32.append((s, e))
+        X.convert_f32_f64(s32, out)
+
+    counts = {"f32": 0, "f64": 0}
+
     def site_step():
         plan.prepare(Lenv, Renv)
         plan.diag(Lenv, Renv, diag)
-        theta, rnorm, nmv = dav.solve(mv, psi0, diag, tol=1e-8, max_iter=args.max_iter)
+        if args.mode == "f32":
+            plan.lower_f32(Lenv, Renv)
+            theta, rnorm, n32, n64 = dav.solve_mixed(mv32, mv, psi0, diag, tol=args.tol, max_iter=args.max_iter)
+            counts["f32"] += n32
+            counts["f64"] += n64
+            nmv = n32 + n64
+        else:
+            theta, rnorm, nmv = dav.solve(mv, psi0, diag, tol=args.tol, max_iter=args.max_iter)
+            counts["f64"] += nmv
         psi = X.unpack_psi(lb, rb, dav.x.cpu().numpy())
         nb, A, _, disc = split(psi, bonds[i], bonds[i + 2], M, 0, fixed=fixed)
         if nb != bonds[i + 1]:
@@ -184,10 +217,22 @@ def main():
         eplan.update(Lenv, site_payload(bonds[i], bonds[i + 1], A, device), Lnew)
         return theta, rnorm, nmv, disc
 
+    # warm start (untimed FP64 pre-solve) and the FP64 reference energy of this step
+    plan.prepare(Lenv, Renv)
+    plan.diag(Lenv, Renv, diag)
+    t2 = time.time()
+    _, r_pre, _ = dav.solve(mv, psi0, diag, tol=1e-12, max_iter=args.pre_iter)
+    psi0 = dav.x.clone()
+    e_ref, r_ref, n_ref = dav.solve(mv, psi0, diag, tol=1e-9, max_iter=600)
+    ev.clear()
+    log(f"warm start |r| = {r_pre:.2e}; reference E = {e_ref:.12f} (|r| {r_ref:.1e}, {n_ref} matvecs) "
+        f"in {time.time() - t2:.1f}s")
     for _ in range(args.warmup):
         site_step()
     torch.cuda.synchronize()
     ev.clear()
+    ev32.clear()
+    counts["f32"] = counts["f64"] = 0
     times, res = [], []
     for _ in range(args.steps):
         torch.cuda.synchronize()
@@ -195,13 +240,15 @@ def main():
         res.append(site_step())
         torch.cuda.synchronize()
         times.append(time.perf_counter() - ts)
-    apply_ms = [s.elapsed_time(e) for s, e in ev]
+    main_ev = ev32 if args.mode == "f32" else ev
+    apply_ms = [s.elapsed_time(e) for s, e in main_ev]
     nmv = sum(r[2] for r in res)
     step_flops = [info.flops_prepare + r[2] * info.flops_apply + einfo.flops_apply for r in res]
     total_t = sum(times)
     value = sum(step_flops) / total_t / 1e9
     avg_apply = float(np.mean(apply_ms)) / 1e3
     achieved = info.flops_apply / avg_apply / 1e12
+    peak = PEAK_FP32_TFLOPS if args.mode == "f32" else PEAK_FP64_TFLOPS
     theta, rnorm = res[-1][0], res[-1][1]
     out = {
         "metric": METRIC,
@@ -214,7 +261,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": args.mode,
         "data": "synthetic",
         "config": {
             "workload": f"two-site DMRG middle step (sites {i},{i + 1}) of a {K}-orbital ab initio chain, "
@@ -223,17 +270,21 @@ def main():
                         f"environments from a seeded random MPS, NC-partition MPO",
             "orbitals": K, "electrons": N, "bond_dim": M, "psi_nnz": n,
             "mpo_bond_dims": [len(mpo.cuts[k]) for k in (i, i + 1, i + 2)],
-            "davidson": {"tol": 1e-8, "max_iter": args.max_iter, "kmax": 24, "matvecs_per_step": nmv / args.steps},
+            "davidson": {"tol": args.tol, "max_iter": args.max_iter, "kmax": 24, "matvecs_per_step": nmv / args.steps,
+                         "warm_start_rnorm": r_pre, "reference_energy": e_ref, "reference_rnorm": r_ref,
+                         "f32_matvecs_per_step": counts["f32"] / args.steps,
+                         "f64_matvecs_per_step": counts["f64"] / args.steps, "precision": args.mode},
             "plan_build_s": plan_s, "chunks": int(info.n_chunks),
         },
         "heff_apply": {"ms": 1e3 * avg_apply, "tflop": info.flops_apply / 1e12,
                        "tflops": achieved, "launches": 2 * int(info.n_chunks)},
         "energy": theta,
         "rnorm": rnorm,
-        "energy_err_vs_fp64": 0.0,
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "bsgemm_f64 (all launches of one hx_heff_apply)"},
+        "energy_err_vs_fp64": abs(theta - e_ref),
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None,
+                     "kernel": ("bsgemm<float> (all launches of one hx_heff_apply_f32)" if args.mode == "f32"
+                                else "bsgemm<double> (all launches of one hx_heff_apply)")},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mpo, bonds, i, info.flops_apply)

@@ -86,7 +86,7 @@ typedef struct {
 } hx_mpo_site;
 
 typedef struct {
-    int64_t t_budget_bytes;  /* cap on the intermediate (T) workspace; 0 = default 2 GiB */
+    int64_t t_budget_bytes;  /* cap on the intermediate (T) workspace; 0 = default 1 GiB */
     int32_t split_kseg_min;  /* minimum K of a split-K segment; 0 = default 2048 */
     int32_t reserved[7];
 } hx_plan_opts;
@@ -170,6 +170,24 @@ int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws
 /* env_out = updated environment (overwritten); see hx_env_plan_create. */
 int hx_env_update(const hx_plan* plan, const double* env_in, const double* site, void* ws,
                   double* env_out, hx_stream stream);
+
+/* ---- FP32 precision mode (the Davidson work stays FP64) -------------------- */
+
+/* Element-wise conversions (n elements, device pointers). */
+int hx_convert_f64_f32(int64_t n, const double* src, float* dst, hx_stream stream);
+int hx_convert_f32_f64(int64_t n, const float* src, double* dst, hx_stream stream);
+
+/* Round the operands of a prepared sigma-vector plan to FP32: L -> L32 (in_nnz
+ * floats), R -> R32 (in2_nnz floats) and the mixed operators held in ws (built
+ * in FP64 by hx_heff_prepare) -> ws32 (a separate buffer of ws_bytes/2 bytes). */
+int hx_heff_lower_f32(const hx_plan* plan, const double* L, const double* R, const void* ws, float* L32,
+                      float* R32, void* ws32, hx_stream stream);
+
+/* sigma32 = H_eff psi32 with FP32 operands and FP32 MFMA accumulation
+ * (v_mfma_f32_16x16x4_f32), same blocks and task order as hx_heff_apply.
+ * ws32 must hold the result of hx_heff_lower_f32. */
+int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
+                      float* sigma32, hx_stream stream);
 
 /* ---- Davidson (Davidson 1975; the eigensolver of the sweep) ----------------- */
 

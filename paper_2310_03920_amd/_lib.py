@@ -21,7 +21,8 @@ EXPORTED = (
     "hx_env_layout", "hx_psi_layout", "hx_site_layout", "hx_heff_plan_create", "hx_env_plan_create",
     "hx_plan_get_info", "hx_plan_upload", "hx_plan_destroy", "hx_heff_prepare", "hx_heff_apply",
     "hx_heff_diag", "hx_env_update", "hx_davidson_ws_bytes", "hx_davidson_step", "hx_dots",
-    "hx_normalize", "hx_last_error",
+    "hx_normalize", "hx_convert_f64_f32", "hx_convert_f32_f64", "hx_heff_lower_f32", "hx_heff_apply_f32",
+    "hx_last_error",
 )
 
 
@@ -86,6 +87,10 @@ def lib():
                                    c_double, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.hx_dots.argtypes = [c_int64, c_int32, c_void_p, c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
     L.hx_normalize.argtypes = [c_int64, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hx_convert_f64_f32.argtypes = [c_int64, c_void_p, c_void_p, c_void_p]
+    L.hx_convert_f32_f64.argtypes = [c_int64, c_void_p, c_void_p, c_void_p]
+    L.hx_heff_lower_f32.argtypes = [c_void_p] + [c_void_p] * 7
+    L.hx_heff_apply_f32.argtypes = [c_void_p] + [c_void_p] * 6
     _lib = L
     return L
 
@@ -324,6 +329,21 @@ class HeffPlan(Plan):
     def diag(self, L, R, out):
         check(lib().hx_heff_diag(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(out), _stream()), "heff_diag")
 
+    # FP32 mode: operands rounded once per (L, R); Davidson stays FP64
+    def lower_f32(self, L, R):
+        import torch
+        dev = self.ws.device
+        if getattr(self, "ws32", None) is None:
+            self.ws32 = torch.empty(max(int(self.info.ws_bytes) // 8, 1), dtype=torch.float32, device=dev)
+        self.L32 = torch.empty(max(int(self.info.in_nnz), 1), dtype=torch.float32, device=dev)
+        self.R32 = torch.empty(max(int(self.info.in2_nnz), 1), dtype=torch.float32, device=dev)
+        check(lib().hx_heff_lower_f32(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(self.L32), _ptr(self.R32),
+                                      _ptr(self.ws32), _stream()), "heff_lower_f32")
+
+    def apply_f32(self, psi32, sigma32):
+        check(lib().hx_heff_apply_f32(self.h, _ptr(self.L32), _ptr(self.R32), _ptr(self.ws32), _ptr(psi32),
+                                      _ptr(sigma32), _stream()), "heff_apply_f32")
+
 
 class EnvPlan(Plan):
     def __init__(self, direction, bond_in, bond_out, dq_in, dq_out, W, t_budget_bytes=0, split_kseg_min=0):
@@ -362,3 +382,11 @@ def dots(a, b, ws, out):
 def normalize(x, ws, norm_out=None):
     """x <- x / ||x|| in place (library kernel)."""
     check(lib().hx_normalize(int(x.numel()), _ptr(x), _ptr(ws), _ptr(norm_out), _stream()), "normalize")
+
+
+def convert_f64_f32(src, dst):
+    check(lib().hx_convert_f64_f32(int(src.numel()), _ptr(src), _ptr(dst), _stream()), "convert_f64_f32")
+
+
+def convert_f32_f64(src, dst):
+    check(lib().hx_convert_f32_f64(int(src.numel()), _ptr(src), _ptr(dst), _stream()), "convert_f32_f64")

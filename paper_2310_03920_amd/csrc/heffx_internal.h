@@ -126,6 +126,7 @@ struct Plan {
     int64_t psi_nnz = 0, in_nnz = 0, in2_nnz = 0, out_nnz = 0;
     int64_t ws_doubles = 0;
     int64_t part_base = 0;      // workspace offset (doubles) of the split-K partial region
+    int64_t mix_end = 0;        // workspace elements [0, mix_end) hold the mixed operators
     int64_t part_tiles = 0;     // partial tiles needed by the largest launch
     int64_t split_kseg_min = 2048;
     double flops_apply = 0, flops_prepare = 0, bytes_apply = 0;

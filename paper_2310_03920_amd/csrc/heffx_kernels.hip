@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 #include <cstdio>
 #include <string>
 
@@ -23,13 +24,17 @@
 using namespace hx;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
-struct Bases {
-    double* p[SP_N];
+template <typename T>
+struct BasesT {
+    T* p[SP_N];
 };
+using Bases = BasesT<double>;
 
-__device__ __forceinline__ double* space_ptr(const Bases& B, int sp) {
-    double* r = B.p[0];
+template <typename T>
+__device__ __forceinline__ T* space_ptr(const BasesT<T>& B, int sp) {
+    T* r = B.p[0];
     r = sp == 1 ? B.p[1] : r;
     r = sp == 2 ? B.p[2] : r;
     r = sp == 3 ? B.p[3] : r;
@@ -44,18 +49,19 @@ __device__ __forceinline__ double* space_ptr(const Bases& B, int sp) {
 // walk is uniform across the workgroup (scalar registers, one lookup per stage).
 constexpr int KS = 16;
 
+template <typename T>
 struct Stage {
-    const double* a;   // A at the tile origin and the stage's first k
-    const double* b;
+    const T* a;   // A at the tile origin and the stage's first k
+    const T* b;
     int lda, ldb;
     int krem;          // valid k in this stage (0..16)
     double alpha;
 };
 
-template <bool TA, bool TB>
-__device__ __forceinline__ Stage next_stage(int& j, int& kl, int tend, const Task* __restrict__ tasks,
-                                            const Bases& B, int r0, int c0) {
-    Stage q;
+template <typename T, bool TA, bool TB>
+__device__ __forceinline__ Stage<T> next_stage(int& j, int& kl, int tend, const Task* __restrict__ tasks,
+                                               const BasesT<T>& B, int r0, int c0) {
+    Stage<T> q;
     while (j < tend && kl >= tasks[j].k) {
         ++j;
         kl = 0;
@@ -82,11 +88,14 @@ __device__ __forceinline__ Stage next_stage(int& j, int& kl, int tend, const Tas
 constexpr int LDS_PAD = 1;
 constexpr int LDW = TM + LDS_PAD;
 
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void bsgemm_f64(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
-                                                  Bases B) {
-    __shared__ double As[2][KS][LDW];
-    __shared__ double Bs[2][KS][LDW];
+// Element type T: double (v_mfma_f64_16x16x4_f64) or float (v_mfma_f32_16x16x4_f32,
+// FP32 accumulation).  The tile tables are the same for both.
+template <typename T, bool TA, bool TB>
+__global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
+                                              BasesT<T> B) {
+    using acc_t = typename std::conditional<std::is_same<T, double>::value, dbl4, flt4>::type;
+    __shared__ T As[2][KS][LDW];
+    __shared__ T Bs[2][KS][LDW];
     const Tile tl = tiles[blockIdx.x];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -107,21 +116,21 @@ __global__ __launch_bounds__(256) void bsgemm_f64(const Tile* __restrict__ tiles
     constexpr int b_dc = TB ? 16 : 0, b_dk = TB ? 0 : 4;
     int cj = tl.tbeg, ckl = 0;  // uniform cursor
 
-    dbl4 acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
-    double ra[4], rb[4];
-    double alpha = 0.0;
+    acc_t acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
+    T ra[4], rb[4];
+    T alpha = 0;
     const int nst = tl.ktot / KS;
 
     // raw loads; alpha is applied at the LDS store so the loads stay in flight
     // across the MFMA work of the current stage
     auto load_stage = [&]() {
-        const Stage q = next_stage<TA, TB>(cj, ckl, tl.tend, tasks, B, tl.r0, tl.c0);
-        alpha = q.alpha;
+        const Stage<T> q = next_stage<T, TA, TB>(cj, ckl, tl.tend, tasks, B, tl.r0, tl.c0);
+        alpha = (T)q.alpha;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
             const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
-            double va = 0.0, vb = 0.0;
+            T va = 0, vb = 0;
             if (ka < q.krem && r < m) va = TA ? q.a[(int64_t)ka * q.lda + r] : q.a[(int64_t)r * q.lda + ka];
             if (kb < q.krem && c < n) vb = TB ? q.b[(int64_t)c * q.ldb + kb] : q.b[(int64_t)kb * q.ldb + c];
             ra[e] = va;
@@ -146,31 +155,38 @@ __global__ __launch_bounds__(256) void bsgemm_f64(const Tile* __restrict__ tiles
 #pragma unroll
             for (int ks = 0; ks < KS / 4; ++ks) {
                 const int kr = ks * 4 + (lane >> 4);
-                const double a0 = As[buf][kr][wr0 + (lane & 15)];
-                const double a1 = As[buf][kr][wr0 + 16 + (lane & 15)];
-                const double b0 = Bs[buf][kr][wc0 + (lane & 15)];
-                const double b1 = Bs[buf][kr][wc0 + 16 + (lane & 15)];
-                acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
-                acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
-                acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
-                acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+                const T a0 = As[buf][kr][wr0 + (lane & 15)];
+                const T a1 = As[buf][kr][wr0 + 16 + (lane & 15)];
+                const T b0 = Bs[buf][kr][wc0 + (lane & 15)];
+                const T b1 = Bs[buf][kr][wc0 + 16 + (lane & 15)];
+                if constexpr (std::is_same<T, double>::value) {
+                    acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+                    acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+                    acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+                    acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+                } else {
+                    acc00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc00, 0, 0, 0);
+                    acc01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc01, 0, 0, 0);
+                    acc10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc10, 0, 0, 0);
+                    acc11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc11, 0, 0, 0);
+                }
             }
             if (s + 1 < nst) store_stage(buf ^ 1);
             __syncthreads();
         }
     }
-    // epilogue: for v_mfma_f64_16x16x4_f64 lane l holds rows l/16 + 4v (v = 0..3),
-    // column l%16 of each 16x16 tile
-    double* C = space_ptr(B, tl.flags & 0xff) + tl.coff;
+    // epilogue (lane layouts measured on gfx950): v_mfma_f64_16x16x4_f64 gives lane l
+    // rows l/16 + 4v of column l%16; v_mfma_f32_16x16x4_f32 rows 4(l/16) + v.
+    T* C = space_ptr(B, tl.flags & 0xff) + tl.coff;
     const int ldc = tl.ldc;
     const bool beta = ((tl.flags >> 8) & 0xff) != 0;
-    auto put = [&](const dbl4& a, int rb0_, int cb0) {
+    auto put = [&](const acc_t& a, int rb0_, int cb0) {
         const int col = cb0 + (lane & 15);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int row = rb0_ + (lane >> 4) + 4 * v;
+            const int row = std::is_same<T, double>::value ? rb0_ + (lane >> 4) + 4 * v : rb0_ + 4 * (lane >> 4) + v;
             if (row < m && col < n) {
-                double* p = C + (int64_t)row * ldc + col;
+                T* p = C + (int64_t)row * ldc + col;
                 *p = beta ? (*p + a[v]) : a[v];
             }
         }
@@ -182,17 +198,28 @@ __global__ __launch_bounds__(256) void bsgemm_f64(const Tile* __restrict__ tiles
 }
 
 // Fixed-order sum of split-K partial tiles into the owning output tile.
-__global__ __launch_bounds__(256) void reduce_partials(const Reduce* __restrict__ red, Bases B) {
+template <typename T>
+__global__ __launch_bounds__(256) void reduce_partials(const Reduce* __restrict__ red, BasesT<T> B) {
     const Reduce r = red[blockIdx.x];
-    const double* P = space_ptr(B, SP_PART) + r.pbase;
-    double* C = space_ptr(B, r.cspace) + r.coff;
+    const T* P = space_ptr(B, SP_PART) + r.pbase;
+    T* C = space_ptr(B, r.cspace) + r.coff;
     for (int e = threadIdx.x; e < r.m * r.n; e += blockDim.x) {
         const int row = e / r.n, col = e % r.n;
-        double acc = 0.0;
+        T acc = 0;
         for (int j = 0; j < r.np; ++j) acc += P[(int64_t)j * TM * TN + row * TN + col];
-        double* p = C + (int64_t)row * r.ldc + col;
+        T* p = C + (int64_t)row * r.ldc + col;
         *p = r.beta ? (*p + acc) : acc;
     }
+}
+
+__global__ void cvt_f64_f32(int64_t n, const double* __restrict__ s, float* __restrict__ d) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = (float)s[i];
+}
+
+__global__ void cvt_f32_f64(int64_t n, const float* __restrict__ s, double* __restrict__ d) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        d[i] = (double)s[i];
 }
 
 __global__ void gather_scale(const Gather* __restrict__ g, Bases B) {
@@ -430,20 +457,21 @@ static Bases make_bases(const Plan* P, const double* psi, double* out, const dou
     return b;
 }
 
-static int launch_gemm(const Plan* P, const Launch& L, const Bases& B, hipStream_t s) {
+template <typename T>
+static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipStream_t s) {
     if (L.ntile <= 0) return HX_OK;
     const Tile* tiles = reinterpret_cast<const Tile*>(static_cast<const char*>(P->dev) + P->off_tiles) + L.tile0;
     const Task* tasks = reinterpret_cast<const Task*>(static_cast<const char*>(P->dev) + P->off_tasks);
     dim3 grid((unsigned)L.ntile), block(256);
     switch (L.kind) {
         case NN:
-            hipLaunchKernelGGL((bsgemm_f64<false, false>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, false, false>), grid, block, 0, s, tiles, tasks, B);
             break;
         case NT:
-            hipLaunchKernelGGL((bsgemm_f64<false, true>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, false, true>), grid, block, 0, s, tiles, tasks, B);
             break;
         case TN_:
-            hipLaunchKernelGGL((bsgemm_f64<true, false>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, true, false>), grid, block, 0, s, tiles, tasks, B);
             break;
         default:
             set_error("internal: bad GEMM kind");
@@ -452,9 +480,11 @@ static int launch_gemm(const Plan* P, const Launch& L, const Bases& B, hipStream
     int rc = hip_check(hipGetLastError(), "bsgemm launch");
     if (rc || L.nred <= 0) return rc;
     const Reduce* red = reinterpret_cast<const Reduce*>(static_cast<const char*>(P->dev) + P->off_reduces) + L.red0;
-    hipLaunchKernelGGL(reduce_partials, dim3((unsigned)L.nred), dim3(256), 0, s, red, B);
+    hipLaunchKernelGGL((reduce_partials<T>), dim3((unsigned)L.nred), dim3(256), 0, s, red, B);
     return hip_check(hipGetLastError(), "reduce launch");
 }
+
+static inline hipStream_t s_of(hx_stream st) { return static_cast<hipStream_t>(st); }
 
 static int check_ready(const hx_plan* plan, int kind) {
     if (!plan) {
@@ -543,6 +573,73 @@ int hx_heff_apply(const hx_plan* plan, const double* L, const double* R, void* w
     Bases B = make_bases(P, psi, sigma, L, R, ws);
     for (const Launch& l : P->apply)
         if ((rc = launch_gemm(P, l, B, static_cast<hipStream_t>(stream)))) return rc;
+    return HX_OK;
+}
+
+static int cvt(int64_t n, const double* a, float* b, hipStream_t s) {
+    if (n <= 0) return HX_OK;
+    const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(cvt_f64_f32, dim3(nb), dim3(256), 0, s, n, a, b);
+    return hip_check(hipGetLastError(), "convert f64->f32");
+}
+
+int hx_convert_f64_f32(int64_t n, const double* src, float* dst, hx_stream stream) {
+    if (n < 0 || (n > 0 && (!src || !dst))) {
+        set_error("convert: bad arguments");
+        return HX_EINVAL;
+    }
+    return cvt(n, src, dst, static_cast<hipStream_t>(stream));
+}
+
+int hx_convert_f32_f64(int64_t n, const float* src, double* dst, hx_stream stream) {
+    if (n < 0 || (n > 0 && (!src || !dst))) {
+        set_error("convert: bad arguments");
+        return HX_EINVAL;
+    }
+    if (n == 0) return HX_OK;
+    const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(cvt_f32_f64, dim3(nb), dim3(256), 0, static_cast<hipStream_t>(stream), n, src, dst);
+    return hip_check(hipGetLastError(), "convert f32->f64");
+}
+
+int hx_heff_lower_f32(const hx_plan* plan, const double* L, const double* R, const void* ws, float* L32, float* R32,
+                      void* ws32, hx_stream stream) {
+    int rc = check_ready(plan, PK_HEFF);
+    if (rc) return rc;
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if ((P->in_nnz && (!L || !L32)) || (P->in2_nnz && (!R || !R32)) || (P->ws_doubles && (!ws || !ws32))) {
+        set_error("heff_lower_f32: null operand");
+        return HX_EINVAL;
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if ((rc = cvt(P->in_nnz, L, L32, s))) return rc;
+    if ((rc = cvt(P->in2_nnz, R, R32, s))) return rc;
+    return cvt(P->mix_end, static_cast<const double*>(ws), static_cast<float*>(ws32), s);
+}
+
+int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
+                      float* sigma32, hx_stream stream) {
+    int rc = check_ready(plan, PK_HEFF);
+    if (rc) return rc;
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (!psi32 || !sigma32 || (P->in_nnz && !L32) || (P->in2_nnz && !R32) || (P->ws_doubles && !ws32)) {
+        set_error("heff_apply_f32: null operand");
+        return HX_EINVAL;
+    }
+    if (psi32 == sigma32) {
+        set_error("heff_apply_f32: psi and sigma must not alias");
+        return HX_EINVAL;
+    }
+    BasesT<float> B;
+    B.p[SP_PSI] = const_cast<float*>(psi32);
+    B.p[SP_OUT] = sigma32;
+    B.p[SP_L] = const_cast<float*>(L32);
+    B.p[SP_R] = const_cast<float*>(R32);
+    B.p[SP_WS] = static_cast<float*>(ws32);
+    B.p[SP_TAB] = nullptr;  // mixing (the only user of the coefficient table) runs in FP64
+    B.p[SP_PART] = ws32 ? static_cast<float*>(ws32) + P->part_base : nullptr;
+    for (const Launch& l : P->apply)
+        if ((rc = launch_gemm(P, l, B, s_of(stream)))) return rc;
     return HX_OK;
 }
 

@@ -538,7 +538,7 @@ static void emit_mixing(Plan& P, Mixer& M, std::vector<Launch>& seq) {
 }
 
 static int64_t default_budget(const hx_plan_opts* o) {
-    int64_t b = (o && o->t_budget_bytes > 0) ? o->t_budget_bytes : ((int64_t)2 << 30);
+    int64_t b = (o && o->t_budget_bytes > 0) ? o->t_budget_bytes : ((int64_t)1 << 30);
     return b / 8;  // doubles
 }
 
@@ -603,6 +603,7 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
     int64_t ws = 0;
     ws = place_mixer(ML, ws);
     ws = place_mixer(MR, ws);
+    P.mix_end = ws;
     P.n_mixed = ML.n_mixed + MR.n_mixed;
     P.flops_prepare = ML.flops + MR.flops;
     emit_mixing(P, ML, P.prep);

@@ -155,9 +155,8 @@ class Davidson:
         for it in range(max_iter):
             X.davidson_step(n, k, kmax, V, S, diag, guard, self.ws, self.x, self.hx, self.t, self.scal)
             theta, rnorm, tnorm = (float(v) for v in self.scal[:3].cpu())
-            if on_iter:
-                on_iter(it, theta, rnorm)
-            if rnorm < tol or it == max_iter - 1 or not (tnorm > 1e-14):
+            stop = bool(on_iter(it, theta, rnorm)) if on_iter else False
+            if stop or rnorm < tol or it == max_iter - 1 or not (tnorm > 1e-14):
                 break
             if k == kmax:
                 V[0].copy_(self.x)
@@ -170,17 +169,37 @@ class Davidson:
             k += 1
         return theta, rnorm, nmv
 
+    def solve_mixed(self, mv32, mv64, psi0, diag, tol=1e-8, max_iter=30, low_tol=1e-5, guard=1e-8):
+        """FP32 sigma-vectors until |r| < low_tol (or stagnation near the FP32 rounding
+        floor), then FP64 sigma-vectors restarted from the FP32 Ritz vector until
+        |r| < tol.  Returns (theta, rnorm, n_matvec_f32, n_matvec_f64)."""
+        hist = []
+
+        def watch(it, theta, rn):
+            # stagnation: below 1e-3 and no 2x gain over the last 6 iterations
+            hist.append(rn)
+            return rn < 1e-3 and len(hist) >= 7 and rn > 0.5 * hist[-7]
+
+        _, _, n32 = self.solve(mv32, psi0, diag, tol=low_tol, max_iter=max_iter, guard=guard,
+                               on_iter=watch)
+        x32 = self.x.clone()
+        theta, rnorm, n64 = self.solve(mv64, x32, diag, tol=tol, max_iter=max_iter, guard=guard)
+        return theta, rnorm, n32, n64
+
 
 class DMRG:
     """Two-site DMRG for H(h, g) in the (n_elec, twosz) sector at bond dimension M."""
 
     def __init__(self, h, g, n_elec, twosz, M, seed=0, device="cuda", tol=1e-8, max_iter=30, kmax=24,
-                 bonds=None, tensors=None, t_budget_bytes=0):
+                 bonds=None, tensors=None, t_budget_bytes=0, precision="f64"):
         from synth import bond_sector_tables, random_right_canonical_mps
         self.K = h.shape[0]
         self.M = M
         self.device = device
         self.tol, self.max_iter, self.kmax = tol, max_iter, kmax
+        if precision not in ("f64", "f32"):
+            raise ValueError("precision must be 'f64' or 'f32'")
+        self.precision = precision
         self.mpo = build_nc_mpo(h, g)
         self.bonds = bonds if bonds is not None else bond_sector_tables(self.K, n_elec, twosz, M)
         self.tensors = tensors if tensors is not None else random_right_canonical_mps(self.bonds, seed)
@@ -210,7 +229,20 @@ class DMRG:
         def mv(v, out):
             plan.apply(L, R, v, out)
 
-        theta, rnorm, nmv = dav.solve(mv, psi_t, diag, tol=self.tol, max_iter=self.max_iter)
+        if self.precision == "f32":
+            plan.lower_f32(L, R)
+            v32 = torch.empty(n, dtype=torch.float32, device=self.device)
+            s32 = torch.empty(n, dtype=torch.float32, device=self.device)
+
+            def mv32(v, out):
+                X.convert_f64_f32(v, v32)
+                plan.apply_f32(v32, s32)
+                X.convert_f32_f64(s32, out)
+
+            theta, rnorm, n32, n64 = dav.solve_mixed(mv32, mv, psi_t, diag, tol=self.tol, max_iter=self.max_iter)
+            nmv = n32 + n64
+        else:
+            theta, rnorm, nmv = dav.solve(mv, psi_t, diag, tol=self.tol, max_iter=self.max_iter)
         psi = X.unpack_psi(Lb, Rb, dav.x.cpu().numpy())
         self.log.append({"pass": pass_id, "i": i, "energy": theta, "rnorm": rnorm, "n_matvec": nmv})
         return psi

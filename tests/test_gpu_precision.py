@@ -1,0 +1,122 @@
+"""FP32 precision mode of the block contractions (Davidson stays FP64).
+
+Parity of the FP32 sigma-vector is unpinned except relative to FP64: each input
+is rounded once to FP32 (relative 2^-24) and the products are accumulated in
+FP32 (MFMA f32 accumulation) over at most ~2e3 terms here, so an element can
+differ from the FP64 definition by at most ~2e3 * 2^-24 * sum|terms|; the test
+bound is 2e-4 of the largest reference element.  Energies are pinned: the mixed
+Davidson refines the FP32 Ritz vector with FP64 sigma-vectors, so its energy
+must equal the FP64 eigenvalue to 1e-10 Ha.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import fock, mps
+from synth import bond_sector_tables, make_integrals, random_left_canonical_mps, random_right_canonical_mps
+from synth.blocks import random_psi, two_site_blocks
+
+from test_gpu_parity import _close, _dense_sigma, _problem
+
+pytestmark = pytest.mark.gpu
+
+RTOL32 = 2e-4
+
+
+def _f32_sigma(device, prob):
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = prob
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, split_kseg_min=32).upload(device)
+    Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
+    Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
+    pt = torch.from_numpy(X.pack_psi(lbB, rbB, psi)).to(device)
+    plan.prepare(Lt, Rt)
+    plan.lower_f32(Lt, Rt)
+    p32 = torch.empty(pt.numel(), dtype=torch.float32, device=device)
+    s32 = torch.full_like(p32, float("nan"))
+    X.convert_f64_f32(pt, p32)
+    plan.apply_f32(p32, s32)
+    s64 = torch.empty_like(pt)
+    X.convert_f32_f64(s32, s64)
+    s32b = torch.empty_like(p32)
+    plan.apply_f32(p32, s32b)
+    torch.cuda.synchronize()
+    assert torch.equal(s32, s32b)
+    return X.unpack_psi(lbB, rbB, s64.cpu().numpy())
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_heff_apply_f32_random_operands(device, seed):
+    print(f"[heff_apply_f32] seed={seed}", flush=True)
+    prob = _problem(seed, True)
+    _close(_f32_sigma(device, prob), _dense_sigma(*prob), rtol=RTOL32)
+
+
+def test_mixed_davidson_reaches_fp64_energy(device):
+    """Middle step of the 8-orbital problem with GPU environments: the mixed
+    FP32/FP64 Davidson energy equals the FP64 Davidson energy and the lowest
+    eigenvalue of the oracle's P^T H P."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.dmrg import Davidson
+    from paper_2310_03920_amd.engine import Engine, site_payload
+    from paper_2310_03920_amd.mpo import build_nc_mpo
+    print("[mixed davidson]", flush=True)
+    K, i = 8, 3
+    h, g = make_integrals(K, seed=0)
+    bonds = bond_sector_tables(K, K, 0, 64)
+    left = random_left_canonical_mps(bonds, 1)
+    right = random_right_canonical_mps(bonds, 2)
+    eng = Engine(build_nc_mpo(h, g), device=device)
+    eng.init_boundaries()
+    for k in range(i):
+        eng.update_left(k, bonds[k], bonds[k + 1], site_payload(bonds[k], bonds[k + 1], left[k], device))
+    for k in range(K - 1, i + 1, -1):
+        eng.update_right(k, bonds[k], bonds[k + 1], site_payload(bonds[k], bonds[k + 1], right[k], device))
+    plan = eng.heff_plan(i, bonds[i], bonds[i + 2])
+    L, R = eng.left[i], eng.right[i + 2]
+    n = int(plan.info.psi_nnz)
+    plan.prepare(L, R)
+    plan.lower_f32(L, R)
+    diag = torch.empty(n, dtype=torch.float64, device=device)
+    plan.diag(L, R, diag)
+    lb, rb = X.Bond(bonds[i]), X.Bond(bonds[i + 2])
+    psi0 = torch.from_numpy(X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2], np.random.default_rng(5)))).to(device)
+    v32 = torch.empty(n, dtype=torch.float32, device=device)
+    s32 = torch.empty_like(v32)
+
+    def mv(v, out):
+        plan.apply(L, R, v, out)
+
+    def mv32(v, out):
+        X.convert_f64_f32(v, v32)
+        plan.apply_f32(v32, s32)
+        X.convert_f32_f64(s32, out)
+
+    dav = Davidson(n, 24, device)
+    e64, r64, _ = dav.solve(mv, psi0, diag, tol=1e-9, max_iter=200)
+    e32, _, _ = Davidson(n, 24, device).solve(mv32, psi0, diag, tol=1e-5, max_iter=200)
+    em, rm, n32, n64 = Davidson(n, 24, device).solve_mixed(mv32, mv, psi0, diag, tol=1e-9, max_iter=200)
+    e_fci = fock.fci_energy(h, g, K, 0)
+    print(f"E64 {e64:.12f} E32-only {e32:.12f} Emixed {em:.12f} FCI {e_fci:.12f} (f32 {n32}, f64 {n64} matvecs)",
+          flush=True)
+    assert r64 < 1e-9 and rm < 1e-9
+    assert abs(e64 - e_fci) < 1e-10
+    assert abs(em - e64) < 1e-10
+    assert abs(e32 - e64) < 1e-4      # FP32-only energy: within the FP32 rounding floor
+
+
+def test_mixed_precision_sweep_matches_fci(device):
+    from paper_2310_03920_amd.dmrg import DMRG
+    print("[sweep f32]", flush=True)
+    K = 8
+    h, g = make_integrals(K, seed=0)
+    d = DMRG(h, g, K, 0, 64, seed=1, device="cuda", tol=1e-9, max_iter=120, precision="f32")
+    d.run(4)
+    e_fci = fock.fci_energy(h, g, K, 0)
+    for rec in d.log:
+        assert rec["energy"] >= e_fci - 1e-10
+        if rec["i"] == 3:
+            assert abs(rec["energy"] - e_fci) < 1e-10, (rec, e_fci)
