@@ -171,6 +171,50 @@ int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws
 int hx_env_update(const hx_plan* plan, const double* env_in, const double* site, void* ws,
                   double* env_out, hx_stream stream);
 
+/* ---- batching: many independent sigma-vector problems per launch ----------- */
+
+/* Merge n single-chunk sigma-vector plans (each built by hx_heff_plan_create
+ * with an intermediate budget large enough for one chunk; HX_EUNSUP otherwise)
+ * into one plan whose prepare, apply and diag stages each issue the same
+ * number of launches as ONE instance, every launch covering all instances.
+ * This is the data parallelism across independent two-site problems (several
+ * states, sites or molecules) that the sweep of Sec. II.A.2 does not expose
+ * within one step.  Instance i's operands are placed in concatenated buffers:
+ * psi/sigma/diag at psi_off(i), L at L_off(i), R at R_off(i) (elements, from
+ * hx_batch_offsets); the workspace and tables are the merged plan's own.  The
+ * merged plan is used with the ordinary entry points (prepare, apply, diag,
+ * lower_f32, apply_f32); each instance's sigma equals, bit for bit, what its
+ * own plan produces.  The input plans are not modified and may be destroyed. */
+int hx_heff_plan_batch(const hx_plan* const* plans, int32_t n, hx_plan** out);
+
+/* Element offsets of instance i inside the concatenated psi/sigma, L and R
+ * buffers of a batched plan (any pointer may be NULL).  HX_EINVAL if the plan
+ * is not batched or i is out of range. */
+int hx_batch_offsets(const hx_plan* plan, int32_t i, int64_t* psi_off, int64_t* L_off, int64_t* R_off);
+
+/* ---- HIP graphs ------------------------------------------------------------ */
+
+typedef struct hx_graph hx_graph;
+
+#define HX_GRAPH_APPLY 1          /* hx_heff_apply (FP64 pointers) */
+#define HX_GRAPH_PREPARE_APPLY 2  /* hx_heff_prepare then hx_heff_apply (FP64 pointers) */
+#define HX_GRAPH_APPLY_F32 3      /* hx_heff_apply_f32 (L32, R32, ws32, psi32, sigma32) */
+
+/* Capture the launch sequence `what` of an uploaded sigma-vector plan (single
+ * or batched) with these operand pointers into an executable HIP graph, so one
+ * hx_graph_launch replays every launch of the step.  The pointers are baked into
+ * the graph: they must stay valid, and their contents are read / written at
+ * each launch.  The sequences contain kernel launches only (no memset or copy
+ * nodes).  Capture uses a private stream and runs nothing; HIP allocates the
+ * graph's own host/device bookkeeping, released by hx_graph_destroy. */
+int hx_heff_graph_create(const hx_plan* plan, int32_t what, const void* L, const void* R, void* ws,
+                         const void* psi, void* sigma, hx_graph** out);
+
+/* Enqueue one replay of the graph on `stream` (asynchronous). */
+int hx_graph_launch(hx_graph* graph, hx_stream stream);
+
+void hx_graph_destroy(hx_graph* graph);
+
 /* ---- FP32 precision mode (the Davidson work stays FP64) -------------------- */
 
 /* Element-wise conversions (n elements, device pointers). */

@@ -22,6 +22,7 @@ EXPORTED = (
     "hx_plan_get_info", "hx_plan_upload", "hx_plan_destroy", "hx_heff_prepare", "hx_heff_apply",
     "hx_heff_diag", "hx_env_update", "hx_davidson_ws_bytes", "hx_davidson_step", "hx_dots",
     "hx_normalize", "hx_convert_f64_f32", "hx_convert_f32_f64", "hx_heff_lower_f32", "hx_heff_apply_f32",
+    "hx_heff_plan_batch", "hx_batch_offsets", "hx_heff_graph_create", "hx_graph_launch", "hx_graph_destroy",
     "hx_last_error",
 )
 
@@ -91,6 +92,12 @@ def lib():
     L.hx_convert_f32_f64.argtypes = [c_int64, c_void_p, c_void_p, c_void_p]
     L.hx_heff_lower_f32.argtypes = [c_void_p] + [c_void_p] * 7
     L.hx_heff_apply_f32.argtypes = [c_void_p] + [c_void_p] * 6
+    L.hx_heff_plan_batch.argtypes = [P(c_void_p), c_int32, P(c_void_p)]
+    L.hx_batch_offsets.argtypes = [c_void_p, c_int32, P(c_int64), P(c_int64), P(c_int64)]
+    L.hx_heff_graph_create.argtypes = [c_void_p, c_int32] + [c_void_p] * 5 + [P(c_void_p)]
+    L.hx_graph_launch.argtypes = [c_void_p, c_void_p]
+    L.hx_graph_destroy.argtypes = [c_void_p]
+    L.hx_graph_destroy.restype = None
     _lib = L
     return L
 
@@ -343,6 +350,50 @@ class HeffPlan(Plan):
     def apply_f32(self, psi32, sigma32):
         check(lib().hx_heff_apply_f32(self.h, _ptr(self.L32), _ptr(self.R32), _ptr(self.ws32), _ptr(psi32),
                                       _ptr(sigma32), _stream()), "heff_apply_f32")
+
+
+GRAPH_APPLY, GRAPH_PREPARE_APPLY, GRAPH_APPLY_F32 = 1, 2, 3
+
+
+class Graph:
+    """An executable HIP graph of a plan's launch sequence with fixed operand
+    tensors (kept alive here)."""
+
+    def __init__(self, plan, what, L, R, ws, psi, sigma):
+        h = c_void_p()
+        check(lib().hx_heff_graph_create(plan.h, int(what), _ptr(L), _ptr(R), _ptr(ws), _ptr(psi), _ptr(sigma),
+                                         ctypes.byref(h)), "heff_graph_create")
+        self.h = h
+        self._keep = (plan, L, R, ws, psi, sigma)
+
+    def launch(self):
+        check(lib().hx_graph_launch(self.h, _stream()), "graph_launch")
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().hx_graph_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class BatchPlan(HeffPlan):
+    """Several sigma-vector plans merged into one launch sequence.  Operands of
+    instance i live at `offsets[i] = (psi_off, L_off, R_off)` of the concatenated
+    buffers."""
+
+    def __init__(self, plans):
+        arr = (c_void_p * len(plans))(*[p.h for p in plans])
+        h = c_void_p()
+        check(lib().hx_heff_plan_batch(arr, len(plans), ctypes.byref(h)), "heff_plan_batch")
+        Plan.__init__(self, h, tuple(plans))
+        self.offsets = []
+        for i in range(len(plans)):
+            o = [c_int64(), c_int64(), c_int64()]
+            check(lib().hx_batch_offsets(self.h, i, *[ctypes.byref(x) for x in o]), "batch_offsets")
+            self.offsets.append(tuple(int(x.value) for x in o))
+        self.sizes = [(int(p.info.psi_nnz), int(p.info.in_nnz), int(p.info.in2_nnz)) for p in plans]
 
 
 class EnvPlan(Plan):

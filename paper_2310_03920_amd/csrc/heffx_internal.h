@@ -3,6 +3,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace hx {
@@ -127,6 +128,9 @@ struct Plan {
     int64_t ws_doubles = 0;
     int64_t part_base = 0;      // workspace offset (doubles) of the split-K partial region
     int64_t mix_end = 0;        // workspace elements [0, mix_end) hold the mixed operators
+    std::vector<std::pair<int64_t, int64_t>> mix_ranges;  // batched plans: per-instance mixed ranges
+    // batched plans: per-instance element offsets of psi/sigma, L, R in the concatenated buffers
+    std::vector<int64_t> inst_psi, inst_L, inst_R;
     int64_t part_tiles = 0;     // partial tiles needed by the largest launch
     int64_t split_kseg_min = 2048;
     double flops_apply = 0, flops_prepare = 0, bytes_apply = 0;

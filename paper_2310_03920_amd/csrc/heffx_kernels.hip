@@ -614,7 +614,11 @@ int hx_heff_lower_f32(const hx_plan* plan, const double* L, const double* R, con
     hipStream_t s = static_cast<hipStream_t>(stream);
     if ((rc = cvt(P->in_nnz, L, L32, s))) return rc;
     if ((rc = cvt(P->in2_nnz, R, R32, s))) return rc;
-    return cvt(P->mix_end, static_cast<const double*>(ws), static_cast<float*>(ws32), s);
+    for (const auto& r : P->mix_ranges)
+        if ((rc = cvt(r.second - r.first, static_cast<const double*>(ws) + r.first, static_cast<float*>(ws32) + r.first,
+                      s)))
+            return rc;
+    return HX_OK;
 }
 
 int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
@@ -763,6 +767,77 @@ int hx_normalize(int64_t n, double* x, void* wsv, double* norm_out, hx_stream st
     const int nb = (int)std::min<int64_t>(2048, (n + 255) / 256);
     hipLaunchKernelGGL(scale_unit, dim3(nb), dim3(256), 0, s, n, x, ws + DW_S + 3, norm_out);
     return hip_check(hipGetLastError(), "normalize");
+}
+
+
+// ---- HIP graphs of the sigma-vector launch sequence
+
+struct hx_graph {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+};
+
+int hx_heff_graph_create(const hx_plan* plan, int32_t what, const void* L, const void* R, void* ws, const void* psi,
+                         void* sigma, hx_graph** out) {
+    if (!out) {
+        set_error("graph_create: null output");
+        return HX_EINVAL;
+    }
+    *out = nullptr;
+    if (what != HX_GRAPH_APPLY && what != HX_GRAPH_PREPARE_APPLY && what != HX_GRAPH_APPLY_F32) {
+        set_error("graph_create: unknown sequence");
+        return HX_EINVAL;
+    }
+    int rc = check_ready(plan, PK_HEFF);
+    if (rc) return rc;
+    hipStream_t cs;
+    if ((rc = hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "graph_create: stream"))) return rc;
+    if ((rc = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "graph_create: begin capture"))) {
+        (void)hipStreamDestroy(cs);
+        return rc;
+    }
+    hx_stream hs = static_cast<hx_stream>(cs);
+    if (what == HX_GRAPH_PREPARE_APPLY)
+        rc = hx_heff_prepare(plan, static_cast<const double*>(L), static_cast<const double*>(R), ws, hs);
+    if (rc == HX_OK && what == HX_GRAPH_APPLY_F32)
+        rc = hx_heff_apply_f32(plan, static_cast<const float*>(L), static_cast<const float*>(R), ws,
+                               static_cast<const float*>(psi), static_cast<float*>(sigma), hs);
+    else if (rc == HX_OK)
+        rc = hx_heff_apply(plan, static_cast<const double*>(L), static_cast<const double*>(R), ws,
+                           static_cast<const double*>(psi), static_cast<double*>(sigma), hs);
+    std::string saved = rc ? hx_last_error() : std::string();
+    hipGraph_t g = nullptr;
+    int rc2 = hip_check(hipStreamEndCapture(cs, &g), "graph_create: end capture");
+    (void)hipStreamDestroy(cs);
+    if (rc || rc2) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc) set_error(saved);
+        return rc ? rc : rc2;
+    }
+    hx_graph* G = new hx_graph();
+    G->g = g;
+    if ((rc = hip_check(hipGraphInstantiate(&G->e, g, nullptr, nullptr, 0), "graph_create: instantiate"))) {
+        (void)hipGraphDestroy(g);
+        delete G;
+        return rc;
+    }
+    *out = G;
+    return HX_OK;
+}
+
+int hx_graph_launch(hx_graph* graph, hx_stream stream) {
+    if (!graph || !graph->e) {
+        set_error("graph_launch: null graph");
+        return HX_EINVAL;
+    }
+    return hip_check(hipGraphLaunch(graph->e, s_of(stream)), "graph_launch");
+}
+
+void hx_graph_destroy(hx_graph* graph) {
+    if (!graph) return;
+    if (graph->e) (void)hipGraphExecDestroy(graph->e);
+    if (graph->g) (void)hipGraphDestroy(graph->g);
+    delete graph;
 }
 
 }  // extern "C"

@@ -604,6 +604,7 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
     ws = place_mixer(ML, ws);
     ws = place_mixer(MR, ws);
     P.mix_end = ws;
+    P.mix_ranges.push_back({0, ws});
     P.n_mixed = ML.n_mixed + MR.n_mixed;
     P.flops_prepare = ML.flops + MR.flops;
     emit_mixing(P, ML, P.prep);
@@ -1062,6 +1063,7 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
     return HX_OK;
 }
 
+static void finalize_tables(Plan& P);
 static void finalize_tables(Plan& P) {
     auto al = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
     int64_t o = 0;
@@ -1076,6 +1078,149 @@ static void finalize_tables(Plan& P) {
     P.off_reduces = o;
     o = al(o + (int64_t)P.reduces.size() * sizeof(Reduce));
     P.table_bytes = std::max<int64_t>(o, 256);
+}
+
+
+// ---------------------------------------------------------------- batching
+
+// Merge independent sigma-vector plans into one plan whose every stage is a
+// single launch over all instances.  Instance i's operands live at its offsets
+// in concatenated buffers (psi/sigma, L, R, workspace, coefficient table).
+static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
+    M.kind = PK_HEFF;
+    M.n_chunks = 1;
+    std::vector<std::array<int64_t, SP_N>> off(in.size());
+    int64_t o_psi = 0, o_L = 0, o_R = 0, o_ws = 0, o_tab = 0;
+    for (size_t i = 0; i < in.size(); ++i) {
+        const Plan& P = *in[i];
+        if (P.kind != PK_HEFF || P.n_chunks != 1) {
+            set_error("plan_batch: every instance must be a single-chunk sigma-vector plan "
+                      "(raise t_budget_bytes)");
+            return HX_EUNSUP;
+        }
+        off[i].fill(0);
+        off[i][SP_PSI] = off[i][SP_OUT] = o_psi;
+        off[i][SP_L] = o_L;
+        off[i][SP_R] = o_R;
+        off[i][SP_WS] = o_ws;
+        off[i][SP_TAB] = o_tab;
+        off[i][SP_PART] = o_ws + P.part_base;  // partials become workspace offsets
+        M.inst_psi.push_back(o_psi);
+        M.inst_L.push_back(o_L);
+        M.inst_R.push_back(o_R);
+        M.mix_ranges.push_back({o_ws, o_ws + P.mix_end});
+        o_psi += P.psi_nnz;
+        o_L += P.in_nnz;
+        o_R += P.in2_nnz;
+        o_ws += P.ws_doubles;
+        o_tab += (int64_t)P.coef.size();
+        M.flops_apply += P.flops_apply;
+        M.flops_prepare += P.flops_prepare;
+        M.bytes_apply += P.bytes_apply;
+        M.n_tasks_apply += P.n_tasks_apply;
+        M.n_mixed += P.n_mixed;
+    }
+    M.psi_nnz = o_psi;
+    M.in_nnz = o_L;
+    M.in2_nnz = o_R;
+    M.ws_doubles = o_ws;
+    M.part_base = 0;
+    M.mix_end = 0;
+    for (size_t i = 0; i < in.size(); ++i) M.coef.insert(M.coef.end(), in[i]->coef.begin(), in[i]->coef.end());
+
+    auto remap_space = [&](size_t i, int sp, int64_t off_in, int& sp_out) -> int64_t {
+        sp_out = sp == SP_PART ? SP_WS : sp;
+        return off_in + off[i][sp];
+    };
+    // merge the k-th launches of each instance's sequence into one launch
+    auto merge_seq = [&](std::vector<Launch> Plan::*seq, std::vector<Launch>& out) -> int {
+        size_t len = 0;
+        for (auto* P : in) len = std::max(len, (P->*seq).size());
+        for (size_t k = 0; k < len; ++k) {
+            Launch L;
+            L.kind = -1;
+            L.tile0 = (int64_t)M.tiles.size();
+            L.flops = 0;
+            std::vector<Reduce> reds;
+            for (size_t i = 0; i < in.size(); ++i) {
+                const Plan& P = *in[i];
+                if (k >= (P.*seq).size()) continue;
+                const Launch& S = (P.*seq)[k];
+                if (L.kind >= 0 && L.kind != S.kind) {
+                    set_error("plan_batch: instances have different launch sequences");
+                    return HX_EUNSUP;
+                }
+                L.kind = S.kind;
+                L.flops += S.flops;
+                const int32_t tbase = (int32_t)M.tasks.size();
+                int32_t tmin = INT32_MAX, tmax = 0;
+                for (int64_t t = S.tile0; t < S.tile0 + S.ntile; ++t) {
+                    tmin = std::min(tmin, P.tiles[t].tbeg);
+                    tmax = std::max(tmax, P.tiles[t].tend);
+                }
+                if (tmin > tmax) tmin = tmax = 0;
+                for (int32_t j = tmin; j < tmax; ++j) {
+                    Task t = P.tasks[j];
+                    int a, b;
+                    t.aoff = remap_space(i, t.spaces & 0xff, t.aoff, a);
+                    t.boff = remap_space(i, (t.spaces >> 8) & 0xff, t.boff, b);
+                    t.set_spaces(a, b);
+                    M.tasks.push_back(t);
+                }
+                for (int64_t t = S.tile0; t < S.tile0 + S.ntile; ++t) {
+                    Tile tl = P.tiles[t];
+                    int c;
+                    tl.coff = remap_space(i, tl.cspace(), tl.coff, c);
+                    tl.set_out(c, tl.beta());
+                    tl.tbeg = tl.tbeg - tmin + tbase;
+                    tl.tend = tl.tend - tmin + tbase;
+                    M.tiles.push_back(tl);
+                }
+                for (int64_t r = S.red0; r < S.red0 + S.nred; ++r) {
+                    Reduce rd = P.reduces[r];
+                    int c;
+                    rd.coff = remap_space(i, rd.cspace, rd.coff, c);
+                    rd.cspace = (int8_t)c;
+                    rd.pbase += off[i][SP_PART];
+                    reds.push_back(rd);
+                }
+            }
+            L.ntile = (int64_t)M.tiles.size() - L.tile0;
+            sort_tiles(M, L.tile0);
+            L.red0 = (int64_t)M.reduces.size();
+            L.nred = (int64_t)reds.size();
+            M.reduces.insert(M.reduces.end(), reds.begin(), reds.end());
+            if (L.ntile > 0) out.push_back(L);
+        }
+        return HX_OK;
+    };
+    int rc;
+    if ((rc = merge_seq(&Plan::prep, M.prep))) return rc;
+    if ((rc = merge_seq(&Plan::apply, M.apply))) return rc;
+    if ((rc = merge_seq(&Plan::diag_gemm, M.diag_gemm))) return rc;
+    for (size_t i = 0; i < in.size(); ++i) {
+        for (const FillLaunch& f : in[i]->diag_fill) {
+            FillLaunch g = f;
+            g.off += off[i][f.space];
+            M.diag_fill.push_back(g);
+        }
+        GatherLaunch gl;
+        gl.g0 = (int64_t)M.gathers.size();
+        for (const Gather& g0 : in[i]->gathers) {
+            Gather g = g0;
+            int a, b;
+            g.soff = remap_space(i, g.sspace, g.soff, a);
+            g.doff = remap_space(i, g.dspace, g.doff, b);
+            g.sspace = (int8_t)a;
+            g.dspace = (int8_t)b;
+            M.gathers.push_back(g);
+        }
+        gl.ng = (int64_t)M.gathers.size() - gl.g0;
+        if (gl.ng) M.diag_gather.push_back(gl);
+    }
+    for (auto& L : M.apply) M.n_tiles_apply += L.ntile;
+    if (!check_task_index_range(M)) return HX_EINVAL;
+    return HX_OK;
 }
 
 }  // namespace hx
@@ -1195,6 +1340,43 @@ int hx_env_plan_create(int direction, const hx_bond* bond_in, const hx_bond* bon
     }
     finalize_tables(*P);
     *out = reinterpret_cast<hx_plan*>(P);
+    return HX_OK;
+}
+
+int hx_heff_plan_batch(const hx_plan* const* plans, int32_t n, hx_plan** out) {
+    if (!out || !plans || n < 1) {
+        set_error("plan_batch: bad arguments");
+        return HX_EINVAL;
+    }
+    *out = nullptr;
+    std::vector<const Plan*> in;
+    for (int i = 0; i < n; ++i) {
+        if (!plans[i]) {
+            set_error("plan_batch: null instance plan");
+            return HX_EINVAL;
+        }
+        in.push_back(reinterpret_cast<const Plan*>(plans[i]));
+    }
+    Plan* M = new Plan();
+    int rc = merge_plans(in, *M);
+    if (rc != HX_OK) {
+        delete M;
+        return rc;
+    }
+    finalize_tables(*M);
+    *out = reinterpret_cast<hx_plan*>(M);
+    return HX_OK;
+}
+
+int hx_batch_offsets(const hx_plan* plan, int32_t i, int64_t* psi_off, int64_t* L_off, int64_t* R_off) {
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (!P || i < 0 || (size_t)i >= P->inst_psi.size()) {
+        set_error("batch_offsets: not a batched plan or instance out of range");
+        return HX_EINVAL;
+    }
+    if (psi_off) *psi_off = P->inst_psi[i];
+    if (L_off) *L_off = P->inst_L[i];
+    if (R_off) *R_off = P->inst_R[i];
     return HX_OK;
 }
 

@@ -165,3 +165,35 @@ def test_plan_chunking_keeps_flops():
     p2 = X.HeffPlan(*args, t_budget_bytes=64 * 1024)
     assert p1.info.n_chunks == 1 and p2.info.n_chunks > 4
     assert p2.info.flops_apply == pytest.approx(p1.info.flops_apply, rel=1e-12)
+
+
+def _small_plans():
+    K = 8
+    m = M.build_nc_mpo(*make_integrals(K, seed=0))
+    b = bond_sector_tables(K, K, 0, 32)
+    return [X.HeffPlan(b[i], b[i + 2], m.dq[i], m.dq[i + 1], m.dq[i + 2], M.site_entries(m, i),
+                       M.site_entries(m, i + 1)) for i in (1, 3, 4)]
+
+
+def test_batch_plan_concatenates_instances():
+    ps = _small_plans()
+    B = X.BatchPlan(ps)
+    assert B.info.flops_apply == pytest.approx(sum(p.info.flops_apply for p in ps), rel=1e-12)
+    assert B.info.n_tiles == sum(p.info.n_tiles for p in ps)
+    assert B.info.psi_nnz == sum(p.info.psi_nnz for p in ps)
+    assert B.info.ws_bytes == sum(p.info.ws_bytes for p in ps)
+    po = np.cumsum([0] + [p.info.psi_nnz for p in ps])[:-1]
+    lo = np.cumsum([0] + [p.info.in_nnz for p in ps])[:-1]
+    ro = np.cumsum([0] + [p.info.in2_nnz for p in ps])[:-1]
+    assert B.offsets == [(int(a), int(b), int(c)) for a, b, c in zip(po, lo, ro)]
+
+
+def test_batch_plan_rejects_chunked_instance():
+    K = 8
+    m = M.build_nc_mpo(*make_integrals(K, seed=0))
+    b = bond_sector_tables(K, K, 0, 64)
+    p = X.HeffPlan(b[3], b[5], m.dq[3], m.dq[4], m.dq[5], M.site_entries(m, 3), M.site_entries(m, 4),
+                   t_budget_bytes=64 * 1024)
+    assert p.info.n_chunks > 1
+    with pytest.raises(RuntimeError, match="single-chunk"):
+        X.BatchPlan([p])
