@@ -99,10 +99,14 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     const Tile tl = tiles[blockIdx.x];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    const int wave = tid >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr0 = (wave & 1) * 32;
     const int wc0 = (wave >> 1) * 32;
     const int m = tl.m, n = tl.n;
+    // 16 x 16 MFMA blocks wholly outside the tile's extent are skipped (wave-uniform
+    // branches), so matrix-core work follows the block shape at 16 x 16 granularity
+    const bool r0 = wr0 < m, r1 = wr0 + 16 < m, c0 = wc0 < n, c1 = wc0 + 16 < n;
+    const bool any = r0 && c0;
     // load lanes (element e of a thread: idx = tid + 256 e):
     //  A !TA: k = idx % 16, row = idx / 16 (16 contiguous k per row)
     //  A  TA: row = idx % 64, k = idx / 64 (64 contiguous rows per k)
@@ -152,23 +156,25 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         for (int s = 0; s < nst; ++s) {
             const int buf = s & 1;
             if (s + 1 < nst) load_stage();
+            if (any) {
 #pragma unroll
-            for (int ks = 0; ks < KS / 4; ++ks) {
-                const int kr = ks * 4 + (lane >> 4);
-                const T a0 = As[buf][kr][wr0 + (lane & 15)];
-                const T a1 = As[buf][kr][wr0 + 16 + (lane & 15)];
-                const T b0 = Bs[buf][kr][wc0 + (lane & 15)];
-                const T b1 = Bs[buf][kr][wc0 + 16 + (lane & 15)];
-                if constexpr (std::is_same<T, double>::value) {
-                    acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
-                    acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
-                    acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
-                    acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
-                } else {
-                    acc00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc00, 0, 0, 0);
-                    acc01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc01, 0, 0, 0);
-                    acc10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc10, 0, 0, 0);
-                    acc11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc11, 0, 0, 0);
+                for (int ks = 0; ks < KS / 4; ++ks) {
+                    const int kr = ks * 4 + (lane >> 4);
+                    const T a0 = As[buf][kr][wr0 + (lane & 15)];
+                    const T a1 = As[buf][kr][wr0 + 16 + (lane & 15)];
+                    const T b0 = Bs[buf][kr][wc0 + (lane & 15)];
+                    const T b1 = Bs[buf][kr][wc0 + 16 + (lane & 15)];
+                    if constexpr (std::is_same<T, double>::value) {
+                        acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+                        if (c1) acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+                        if (r1) acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+                        if (r1 && c1) acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+                    } else {
+                        acc00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc00, 0, 0, 0);
+                        if (c1) acc01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc01, 0, 0, 0);
+                        if (r1) acc10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc10, 0, 0, 0);
+                        if (r1 && c1) acc11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc11, 0, 0, 0);
+                    }
                 }
             }
             if (s + 1 < nst) store_stage(buf ^ 1);
