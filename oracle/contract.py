@@ -66,6 +66,34 @@ def heff_apply(Ld, W1, W2, Rd, psi):
     return np.einsum("czw,cxsuw->xsuz", Rd, z, optimize=True)
 
 
+def heff_vjp(Ld, W1, W2, Rd, psi, g):
+    """Vector-Jacobian products of sigma = heff_apply(L, W1, W2, R, psi) with the
+    cotangent g[x,s,u,z]: the derivatives of <g, sigma> with respect to each
+    operand, from the same single sum differentiated term by term:
+
+      d/dpsi[y,t,v,w] = sum g[x,s,u,z] L[a,x,y] W1[a,b,s,t] W2[b,c,u,v] R[c,z,w]
+      d/dL[a,x,y]     = sum g[x,s,u,z] W1[a,b,s,t] W2[b,c,u,v] R[c,z,w] psi[y,t,v,w]
+      d/dW1[a,b,s,t]  = sum g[x,s,u,z] L[a,x,y] W2[b,c,u,v] R[c,z,w] psi[y,t,v,w]
+      d/dW2[b,c,u,v]  = sum g[x,s,u,z] L[a,x,y] W1[a,b,s,t] R[c,z,w] psi[y,t,v,w]
+      d/dR[c,z,w]     = sum g[x,s,u,z] L[a,x,y] W1[a,b,s,t] W2[b,c,u,v] psi[y,t,v,w]
+
+    Returns (g_L, g_W1, g_W2, g_R, g_psi) as dense arrays."""
+    # cotangent carried through L, W1, W2 (the left part of each product)
+    p = np.einsum("axy,xsuz->aysuz", Ld, g, optimize=True)
+    q = np.einsum("abst,aysuz->bytuz", W1, p, optimize=True)
+    r = np.einsum("bcuv,bytuz->cytvz", W2, q, optimize=True)
+    g_psi = np.einsum("czw,cytvz->ytvw", Rd, r, optimize=True)
+    g_R = np.einsum("cytvz,ytvw->czw", r, psi, optimize=True)
+    # psi carried through R, W2 (the right part of each product)
+    m1 = np.einsum("czw,ytvw->cytvz", Rd, psi, optimize=True)
+    m2 = np.einsum("bcuv,cytvz->bytuz", W2, m1, optimize=True)
+    g_W2 = np.einsum("bytuz,cytvz->bcuv", q, m1, optimize=True)
+    g_W1 = np.einsum("aysuz,bytuz->abst", p, m2, optimize=True)
+    m3 = np.einsum("abst,bytuz->aysuz", W1, m2, optimize=True)
+    g_L = np.einsum("xsuz,aysuz->axy", g, m3, optimize=True)
+    return g_L, g_W1, g_W2, g_R, g_psi
+
+
 def heff_diag(Ld, W1, W2, Rd):
     dl = np.einsum("axx->ax", Ld)
     dw1 = np.einsum("abss->abs", W1)

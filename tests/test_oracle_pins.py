@@ -254,6 +254,74 @@ def test_sigma_rows_match_dense_definition():
         np.testing.assert_allclose(full, s[lo[il] + x, s1], atol=1e-12)
 
 
+def _dense_random_operands(seed):
+    """Dense random operands (no symmetry) of a tiny two-site problem."""
+    rng = np.random.default_rng(seed)
+    A, Bm, Dl, Dr = 3, 4, 5, 6  # left ops, mid ops, left dim, right dim
+    return (rng.standard_normal((A, Dl, Dl)), rng.standard_normal((A, Bm, 4, 4)),
+            rng.standard_normal((Bm, 2, 4, 4)), rng.standard_normal((2, Dr, Dr)),
+            rng.standard_normal((Dl, 4, 4, Dr)), rng.standard_normal((Dl, 4, 4, Dr)))
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_vjp_is_adjoint_of_each_linear_slot(seed):
+    """sigma is linear in each operand X, so <dX, V> must equal <g, sigma(X -> V)>
+    for any V: pins every index and term of the VJP against heff_apply."""
+    L, W1, W2, R, psi, g = _dense_random_operands(seed)
+    gL, gW1, gW2, gR, gpsi = contract.heff_vjp(L, W1, W2, R, psi, g)
+    rng = np.random.default_rng(100 + seed)
+    args = [L, W1, W2, R, psi]
+    for slot, grad in zip(range(5), (gL, gW1, gW2, gR, gpsi)):
+        V = rng.standard_normal(args[slot].shape)
+        a2 = list(args)
+        a2[slot] = V
+        lhs = np.sum(grad * V)
+        rhs = np.sum(g * contract.heff_apply(*a2))
+        assert lhs == pytest.approx(rhs, rel=1e-12, abs=1e-10), slot
+
+
+def test_vjp_psi_is_transpose_of_kron_matrix():
+    lb, rb, L, R, W1e, W2e, psi, D, Dm = _tiny_operands(seed=3)
+    Ld, Rd = contract.dense_env(L, lb), contract.dense_env(R, rb)
+    W1, W2 = contract.dense_mpo(W1e, D, Dm), contract.dense_mpo(W2e, Dm, D)
+    P = mps.dense_two_site(psi, lb, rb)
+    g = np.random.default_rng(9).standard_normal(P.shape)
+    gpsi = contract.heff_vjp(Ld, W1, W2, Rd, P, g)[4]
+    H = contract.heff_matrix_kron(Ld, W1, W2, Rd)
+    np.testing.assert_allclose(gpsi.ravel(), H.T @ g.ravel(), atol=1e-12)
+
+
+def test_energy_gradient_matches_central_differences():
+    """E = <psi|H_eff|psi>: dE/dX from the VJP with g = psi (plus H psi for psi
+    itself) against central differences, step 1e-5, along random directions."""
+    L, W1, W2, R, psi, _ = _dense_random_operands(5)
+    args = [L, W1, W2, R, psi]
+    sigma = contract.heff_apply(*args)
+    grads = list(contract.heff_vjp(*args, psi))
+    grads[4] = grads[4] + sigma
+
+    def energy(a):
+        return float(np.sum(a[4] * contract.heff_apply(*a)))
+
+    rng = np.random.default_rng(6)
+    h = 1e-5
+    for slot in range(5):
+        V = rng.standard_normal(args[slot].shape)
+        ap, am = list(args), list(args)
+        ap[slot] = args[slot] + h * V
+        am[slot] = args[slot] - h * V
+        fd = (energy(ap) - energy(am)) / (2 * h)
+        assert np.sum(grads[slot] * V) == pytest.approx(fd, rel=1e-6), slot
+
+
+def test_vjp_euler_identity():
+    """Degree-1 homogeneity in each operand: <dX, X> = <g, sigma> for all five."""
+    L, W1, W2, R, psi, g = _dense_random_operands(2)
+    ref = np.sum(g * contract.heff_apply(L, W1, W2, R, psi))
+    for grad, x in zip(contract.heff_vjp(L, W1, W2, R, psi, g), (L, W1, W2, R, psi)):
+        assert np.sum(grad * x) == pytest.approx(ref, rel=1e-12)
+
+
 # ---------------------------------------------------------------- Davidson
 
 def test_davidson_step_invariants_and_solve():
