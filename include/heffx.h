@@ -171,6 +171,36 @@ int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws
 int hx_env_update(const hx_plan* plan, const double* env_in, const double* site, void* ws,
                   double* env_out, hx_stream stream);
 
+/* ---- adjoint (vector-Jacobian products of the sigma-vector) ----------------- */
+
+/* Build (host only) the plan of the VJP of sigma = H_eff(L, W1, W2, R) psi, same
+ * arguments as hx_heff_plan_create.  Given a cotangent g (the gradient of a
+ * scalar f with respect to sigma, wavefunction layout) it yields df/dpsi, df/dL,
+ * df/dR and df/dW1, df/dW2.  With g = psi these are the derivatives of
+ * <psi|H_eff|psi> with respect to L, W and R (the quantities from which reduced
+ * density matrices and integral gradients follow, Sec. II.E.1 and the
+ * DMRG-CASSCF use of Sec. II.A), and df/dpsi + H_eff psi is its psi gradient.
+ * The plan's hx_plan_get_info reports the backward FLOP as flops_apply. */
+int hx_heff_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops,
+                            const hx_opset* mid, const hx_opset* Rops, const hx_mpo_site* W1,
+                            const hx_mpo_site* W2, const hx_plan_opts* opts, hx_plan** out);
+
+/* Backward of hx_heff_apply with an uploaded VJP plan whose workspace holds
+ * hx_heff_prepare(plan, L, R, ws) for the same L and R.  Outputs (overwritten,
+ * device, FP64):
+ *   g_psi  (psi_nnz)   = H_eff^T g                       (wavefunction layout)
+ *   g_L    (in_nnz)    = df/dL, left-environment payload layout
+ *   g_R    (in2_nnz)   = df/dR, right-environment payload layout
+ *   g_W1   (16 x W1->nnz), g_W2 (16 x W2->nnz): df/dval for every NONZERO site-
+ *          matrix value of the MPO tables passed at plan creation, in their
+ *          val[] layout; entries whose value is zero are written as 0.
+ * The operation is the exact transpose of the forward contraction in the
+ * forward's block structure (Sec. II.C.1 operator mixing, both GEMM rounds).
+ * g_psi must not alias psi or g.  Deterministic: no atomics, fixed order. */
+int hx_heff_apply_backward(const hx_plan* plan, const double* L, const double* R, void* ws,
+                           const double* psi, const double* g, double* g_psi, double* g_L,
+                           double* g_R, double* g_W1, double* g_W2, hx_stream stream);
+
 /* ---- batching: many independent sigma-vector problems per launch ----------- */
 
 /* Merge n single-chunk sigma-vector plans (each built by hx_heff_plan_create

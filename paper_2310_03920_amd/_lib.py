@@ -23,7 +23,7 @@ EXPORTED = (
     "hx_heff_diag", "hx_env_update", "hx_davidson_ws_bytes", "hx_davidson_step", "hx_dots",
     "hx_normalize", "hx_convert_f64_f32", "hx_convert_f32_f64", "hx_heff_lower_f32", "hx_heff_apply_f32",
     "hx_heff_plan_batch", "hx_batch_offsets", "hx_heff_graph_create", "hx_graph_launch", "hx_graph_destroy",
-    "hx_last_error",
+    "hx_heff_vjp_plan_create", "hx_heff_apply_backward", "hx_last_error",
 )
 
 
@@ -94,6 +94,8 @@ def lib():
     L.hx_heff_apply_f32.argtypes = [c_void_p] + [c_void_p] * 6
     L.hx_heff_plan_batch.argtypes = [P(c_void_p), c_int32, P(c_void_p)]
     L.hx_batch_offsets.argtypes = [c_void_p, c_int32, P(c_int64), P(c_int64), P(c_int64)]
+    L.hx_heff_vjp_plan_create.argtypes = L.hx_heff_plan_create.argtypes
+    L.hx_heff_apply_backward.argtypes = [c_void_p] * 11 + [c_void_p]
     L.hx_heff_graph_create.argtypes = [c_void_p, c_int32] + [c_void_p] * 5 + [P(c_void_p)]
     L.hx_graph_launch.argtypes = [c_void_p, c_void_p]
     L.hx_graph_destroy.argtypes = [c_void_p]
@@ -350,6 +352,33 @@ class HeffPlan(Plan):
     def apply_f32(self, psi32, sigma32):
         check(lib().hx_heff_apply_f32(self.h, _ptr(self.L32), _ptr(self.R32), _ptr(self.ws32), _ptr(psi32),
                                       _ptr(sigma32), _stream()), "heff_apply_f32")
+
+
+class HeffVjpPlan(Plan):
+    """Plan of the vector-Jacobian products of sigma = H_eff psi."""
+
+    def __init__(self, lbond, rbond, Ldq, mid_dq, Rdq, W1, W2, t_budget_bytes=0, split_kseg_min=0):
+        lb, rb = (b if isinstance(b, Bond) else Bond(b) for b in (lbond, rbond))
+        Lo, Mo, Ro = OpSet(Ldq), OpSet(mid_dq), OpSet(Rdq)
+        w1 = W1 if isinstance(W1, MpoSite) else MpoSite.from_entries(W1)
+        w2 = W2 if isinstance(W2, MpoSite) else MpoSite.from_entries(W2)
+        opts = _opts(t_budget_bytes, split_kseg_min)
+        h = c_void_p()
+        check(lib().hx_heff_vjp_plan_create(ctypes.byref(lb.c), ctypes.byref(rb.c), ctypes.byref(Lo.c),
+                                            ctypes.byref(Mo.c), ctypes.byref(Ro.c), ctypes.byref(w1.c),
+                                            ctypes.byref(w2.c), ctypes.byref(opts), ctypes.byref(h)),
+              "heff_vjp_plan_create")
+        super().__init__(h, (lb, rb, Lo, Mo, Ro, w1, w2))
+        self.lbond, self.rbond = lb, rb
+        self.nnz1, self.nnz2 = len(w1.rows), len(w2.rows)
+
+    def prepare(self, L, R):
+        check(lib().hx_heff_prepare(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _stream()), "heff_prepare")
+
+    def backward(self, L, R, psi, g, g_psi, g_L, g_R, g_W1, g_W2):
+        check(lib().hx_heff_apply_backward(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(psi), _ptr(g), _ptr(g_psi),
+                                           _ptr(g_L), _ptr(g_R), _ptr(g_W1), _ptr(g_W2), _stream()),
+              "heff_apply_backward")
 
 
 GRAPH_APPLY, GRAPH_PREPARE_APPLY, GRAPH_APPLY_F32 = 1, 2, 3

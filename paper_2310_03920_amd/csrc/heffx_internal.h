@@ -19,7 +19,12 @@ enum Space : int8_t {
     SP_WS = 4,    // caller workspace (mixed operators, intermediates)
     SP_TAB = 5,   // plan tables on the device (mixing coefficients)
     SP_PART = 6,  // split-K partial tiles (a region of the workspace)
-    SP_N = 7
+    SP_G = 7,     // adjoint: cotangent of sigma (wavefunction layout)
+    SP_GL = 8,    // adjoint: gradient of the left environment payload
+    SP_GR = 9,    // adjoint: gradient of the right environment payload
+    SP_GW1 = 10,  // adjoint: gradient of the values of W1 (16 per MPO entry)
+    SP_GW2 = 11,  // adjoint: gradient of the values of W2
+    SP_N = 12
 };
 
 // One contribution alpha * op(A) * op(B) to an output tile.  A is (rows x k),
@@ -107,7 +112,7 @@ struct FillLaunch {
     int64_t off, count;
 };
 
-enum PlanKind : int { PK_HEFF = 0, PK_ENV_LEFT = 1, PK_ENV_RIGHT = 2 };
+enum PlanKind : int { PK_HEFF = 0, PK_ENV_LEFT = 1, PK_ENV_RIGHT = 2, PK_HEFF_VJP = 3 };
 
 struct Plan {
     int kind = PK_HEFF;
@@ -123,6 +128,10 @@ struct Plan {
     std::vector<FillLaunch> diag_fill;
     std::vector<GatherLaunch> diag_gather;
     std::vector<Launch> diag_gemm;
+    // adjoint plans: zero fills before, coefficient-gradient gathers after the GEMM launches
+    std::vector<FillLaunch> bw_fill;
+    std::vector<GatherLaunch> bw_gather;
+    int64_t w1_nnz = 0, w2_nnz = 0;  // MPO entries of the two sites (gradient lengths / 16)
     // sizes
     int64_t psi_nnz = 0, in_nnz = 0, in2_nnz = 0, out_nnz = 0;
     int64_t ws_doubles = 0;

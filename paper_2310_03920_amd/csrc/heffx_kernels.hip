@@ -32,17 +32,18 @@ struct BasesT {
 };
 using Bases = BasesT<double>;
 
-template <typename T>
+// Select a space's base pointer without indexing the argument array dynamically
+// (which would move it to scratch).  NSP: number of spaces the launch can name
+// (the sigma-vector and environment paths use the first 7, the adjoint all).
+template <typename T, int NSP = SP_N>
 __device__ __forceinline__ T* space_ptr(const BasesT<T>& B, int sp) {
     T* r = B.p[0];
-    r = sp == 1 ? B.p[1] : r;
-    r = sp == 2 ? B.p[2] : r;
-    r = sp == 3 ? B.p[3] : r;
-    r = sp == 4 ? B.p[4] : r;
-    r = sp == 5 ? B.p[5] : r;
-    r = sp == 6 ? B.p[6] : r;
+#pragma unroll
+    for (int i = 1; i < NSP; ++i) r = sp == i ? B.p[i] : r;
     return r;
 }
+
+constexpr int NSP_FWD = SP_PART + 1;
 
 // The K range of a tile is walked in 16-deep stages; every task's K is padded to
 // a multiple of 16 with zeros, so a stage belongs to exactly one task and the
@@ -58,7 +59,7 @@ struct Stage {
     double alpha;
 };
 
-template <typename T, bool TA, bool TB>
+template <typename T, bool TA, bool TB, int NSP>
 __device__ __forceinline__ Stage<T> next_stage(int& j, int& kl, int tend, const Task* __restrict__ tasks,
                                                const BasesT<T>& B, int r0, int c0) {
     Stage<T> q;
@@ -79,8 +80,8 @@ __device__ __forceinline__ Stage<T> next_stage(int& j, int& kl, int tend, const 
     q.alpha = t.alpha;
     q.krem = min(KS, t.k - kl);
     const int sp = t.spaces;
-    q.a = space_ptr(B, sp & 0xff) + t.aoff + (TA ? (int64_t)kl * t.lda + r0 : (int64_t)r0 * t.lda + kl);
-    q.b = space_ptr(B, (sp >> 8) & 0xff) + t.boff + (TB ? (int64_t)c0 * t.ldb + kl : (int64_t)kl * t.ldb + c0);
+    q.a = space_ptr<T, NSP>(B, sp & 0xff) + t.aoff + (TA ? (int64_t)kl * t.lda + r0 : (int64_t)r0 * t.lda + kl);
+    q.b = space_ptr<T, NSP>(B, (sp >> 8) & 0xff) + t.boff + (TB ? (int64_t)c0 * t.ldb + kl : (int64_t)kl * t.ldb + c0);
     kl += KS;
     return q;
 }
@@ -90,7 +91,7 @@ constexpr int LDW = TM + LDS_PAD;
 
 // Element type T: double (v_mfma_f64_16x16x4_f64) or float (v_mfma_f32_16x16x4_f32,
 // FP32 accumulation).  The tile tables are the same for both.
-template <typename T, bool TA, bool TB>
+template <typename T, bool TA, bool TB, int NSP>
 __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
                                               BasesT<T> B) {
     using acc_t = typename std::conditional<std::is_same<T, double>::value, dbl4, flt4>::type;
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     // raw loads; alpha is applied at the LDS store so the loads stay in flight
     // across the MFMA work of the current stage
     auto load_stage = [&]() {
-        const Stage<T> q = next_stage<T, TA, TB>(cj, ckl, tl.tend, tasks, B, tl.r0, tl.c0);
+        const Stage<T> q = next_stage<T, TA, TB, NSP>(cj, ckl, tl.tend, tasks, B, tl.r0, tl.c0);
         alpha = (T)q.alpha;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     }
     // epilogue (lane layouts measured on gfx950): v_mfma_f64_16x16x4_f64 gives lane l
     // rows l/16 + 4v of column l%16; v_mfma_f32_16x16x4_f32 rows 4(l/16) + v.
-    T* C = space_ptr(B, tl.flags & 0xff) + tl.coff;
+    T* C = space_ptr<T, NSP>(B, tl.flags & 0xff) + tl.coff;
     const int ldc = tl.ldc;
     const bool beta = ((tl.flags >> 8) & 0xff) != 0;
     auto put = [&](const acc_t& a, int rb0_, int cb0) {
@@ -207,7 +208,7 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
 template <typename T>
 __global__ __launch_bounds__(256) void reduce_partials(const Reduce* __restrict__ red, BasesT<T> B) {
     const Reduce r = red[blockIdx.x];
-    const T* P = space_ptr(B, SP_PART) + r.pbase;
+    const T* P = B.p[SP_PART] + r.pbase;
     T* C = space_ptr(B, r.cspace) + r.coff;
     for (int e = threadIdx.x; e < r.m * r.n; e += blockDim.x) {
         const int row = e / r.n, col = e % r.n;
@@ -452,7 +453,7 @@ static int hip_check(hipError_t e, const char* what) {
 }
 
 static Bases make_bases(const Plan* P, const double* psi, double* out, const double* L, const double* R, void* ws) {
-    Bases b;
+    Bases b{};
     b.p[SP_PSI] = const_cast<double*>(psi);
     b.p[SP_OUT] = out;
     b.p[SP_L] = const_cast<double*>(L);
@@ -463,7 +464,7 @@ static Bases make_bases(const Plan* P, const double* psi, double* out, const dou
     return b;
 }
 
-template <typename T>
+template <typename T, int NSP = NSP_FWD>
 static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipStream_t s) {
     if (L.ntile <= 0) return HX_OK;
     const Tile* tiles = reinterpret_cast<const Tile*>(static_cast<const char*>(P->dev) + P->off_tiles) + L.tile0;
@@ -471,13 +472,13 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
     dim3 grid((unsigned)L.ntile), block(256);
     switch (L.kind) {
         case NN:
-            hipLaunchKernelGGL((bsgemm<T, false, false>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, false, false, NSP>), grid, block, 0, s, tiles, tasks, B);
             break;
         case NT:
-            hipLaunchKernelGGL((bsgemm<T, false, true>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, false, true, NSP>), grid, block, 0, s, tiles, tasks, B);
             break;
         case TN_:
-            hipLaunchKernelGGL((bsgemm<T, true, false>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, true, false, NSP>), grid, block, 0, s, tiles, tasks, B);
             break;
         default:
             set_error("internal: bad GEMM kind");
@@ -492,7 +493,7 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
 
 static inline hipStream_t s_of(hx_stream st) { return static_cast<hipStream_t>(st); }
 
-static int check_ready(const hx_plan* plan, int kind) {
+static int check_ready(const hx_plan* plan, int kind, int kind2 = -1) {
     if (!plan) {
         set_error("null plan");
         return HX_EINVAL;
@@ -502,7 +503,7 @@ static int check_ready(const hx_plan* plan, int kind) {
         set_error("plan not uploaded (call hx_plan_upload first)");
         return HX_EINVAL;
     }
-    if (kind >= 0 && P->kind != kind && !(kind == PK_ENV_LEFT && P->kind == PK_ENV_RIGHT)) {
+    if (kind >= 0 && P->kind != kind && P->kind != kind2 && !(kind == PK_ENV_LEFT && P->kind == PK_ENV_RIGHT)) {
         set_error("plan kind does not match this entry point");
         return HX_EINVAL;
     }
@@ -550,7 +551,7 @@ int hx_plan_upload(hx_plan* plan, void* dev_tables, hx_stream stream) {
 }
 
 int hx_heff_prepare(const hx_plan* plan, const double* L, const double* R, void* ws, hx_stream stream) {
-    int rc = check_ready(plan, PK_HEFF);
+    int rc = check_ready(plan, PK_HEFF, PK_HEFF_VJP);
     if (rc) return rc;
     const Plan* P = reinterpret_cast<const Plan*>(plan);
     if ((P->in_nnz && !L) || (P->in2_nnz && !R) || (P->ws_doubles && !ws)) {
@@ -640,7 +641,7 @@ int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, v
         set_error("heff_apply_f32: psi and sigma must not alias");
         return HX_EINVAL;
     }
-    BasesT<float> B;
+    BasesT<float> B{};
     B.p[SP_PSI] = const_cast<float*>(psi32);
     B.p[SP_OUT] = sigma32;
     B.p[SP_L] = const_cast<float*>(L32);
@@ -676,6 +677,44 @@ int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws
     }
     for (const Launch& l : P->diag_gemm)
         if ((rc = launch_gemm(P, l, B, s))) return rc;
+    return HX_OK;
+}
+
+int hx_heff_apply_backward(const hx_plan* plan, const double* L, const double* R, void* ws, const double* psi,
+                           const double* g, double* g_psi, double* g_L, double* g_R, double* g_W1, double* g_W2,
+                           hx_stream stream) {
+    int rc = check_ready(plan, PK_HEFF_VJP);
+    if (rc) return rc;
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (!psi || !g || !g_psi || (P->in_nnz && (!L || !g_L)) || (P->in2_nnz && (!R || !g_R)) ||
+        (P->w1_nnz && !g_W1) || (P->w2_nnz && !g_W2) || (P->ws_doubles && !ws)) {
+        set_error("heff_apply_backward: null operand");
+        return HX_EINVAL;
+    }
+    if (g_psi == psi || g_psi == g) {
+        set_error("heff_apply_backward: g_psi must not alias psi or g");
+        return HX_EINVAL;
+    }
+    hipStream_t s = s_of(stream);
+    Bases B = make_bases(P, psi, g_psi, L, R, ws);
+    B.p[SP_G] = const_cast<double*>(g);
+    B.p[SP_GL] = g_L;
+    B.p[SP_GR] = g_R;
+    B.p[SP_GW1] = g_W1;
+    B.p[SP_GW2] = g_W2;
+    for (const FillLaunch& f : P->bw_fill) {
+        if (f.count <= 0) continue;
+        int nb = (int)std::min<int64_t>(4096, (f.count + 255) / 256);
+        hipLaunchKernelGGL(fill_zero, dim3(nb), dim3(256), 0, s, B.p[f.space] + f.off, f.count);
+        if ((rc = hip_check(hipGetLastError(), "backward fill"))) return rc;
+    }
+    for (const Launch& l : P->apply)
+        if ((rc = launch_gemm<double, SP_N>(P, l, B, s))) return rc;
+    const Gather* gt = reinterpret_cast<const Gather*>(static_cast<const char*>(P->dev) + P->off_gathers);
+    for (const GatherLaunch& gl : P->bw_gather) {
+        hipLaunchKernelGGL(gather_scale, dim3((unsigned)gl.ng), dim3(64), 0, s, gt + gl.g0, B);
+        if ((rc = hip_check(hipGetLastError(), "backward gather"))) return rc;
+    }
     return HX_OK;
 }
 

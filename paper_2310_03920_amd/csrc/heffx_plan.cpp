@@ -883,6 +883,562 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
     return HX_OK;
 }
 
+
+// ---------------------------------------------------------------- adjoint plan
+//
+// Vector-Jacobian products of sigma = H_eff(L, W1, W2, R) psi with a cotangent g
+// (the derivative of a scalar with respect to sigma).  sigma is linear in each
+// operand, so with the intermediates of the forward pass,
+//   T_b   = psi Rhat_b^T                (recomputed, as in the forward pass)
+//   gT_b  = Lhat_b^T g                  (cotangent of T_b)
+//   G_t   = g T_b^T   restricted to the (s1' <- s1) rows/cols of transition t = (b, s1', s1)
+//   H_t   = gT_b^T psi restricted likewise on the right
+//   g_psi = sum_b gT_b Rhat_b
+//   g_L_a = sum_t W1_ab[t] G_t,      g_W1_ab[s1', s1] = <L_a, G_(b, s1', s1)>
+//   g_R_c = sum_t W2_bc[t] H_t,      g_W2_bc[s2', s2] = <R_c, H_(b, s2', s2)>
+// Transitions of one side with equal operator shift form a class: the last two
+// lines are then GEMMs with the (transitions x operators) coefficient matrix.
+
+struct GradClass {
+    int dn = 0, ds = 0;
+    std::vector<int> cols;                       // environment operators with this shift
+    std::unordered_map<int, int> col_of;
+    std::vector<std::array<int, 3>> trans;       // (b, so, si)
+    std::map<std::array<int, 3>, int> t_of;
+    std::map<std::pair<int, int>, double> coef;  // (t, col) -> summed site-matrix value
+    int64_t size = 0;
+    int64_t g_base = 0, gc_base = 0, coef0 = 0;
+};
+
+struct GradSide {
+    std::vector<GradClass> classes;
+    std::map<std::pair<int, int>, int> class_of;
+    std::vector<std::vector<std::pair<int, int>>> by_b;  // b -> (class, t)
+};
+
+static void build_grad_side(GradSide& G, const std::vector<Entry>& ents, const OpSet& ops, const EnvLayout& lay,
+                            int nmid) {
+    G.by_b.assign(nmid, {});
+    for (const Entry& e : ents)
+        for (int t = 0; t < 16; ++t) {
+            if (e.v[t] == 0.0) continue;
+            const auto& dq = ops.dq[e.src];
+            auto ck = std::make_pair(dq[0], dq[1]);
+            auto ci = G.class_of.find(ck);
+            int c;
+            if (ci == G.class_of.end()) {
+                c = (int)G.classes.size();
+                G.class_of[ck] = c;
+                GradClass gc;
+                gc.dn = dq[0];
+                gc.ds = dq[1];
+                for (int a = 0; a < (int)ops.dq.size(); ++a)
+                    if (ops.dq[a] == dq) {
+                        gc.col_of[a] = (int)gc.cols.size();
+                        gc.cols.push_back(a);
+                    }
+                gc.size = lay.op_off[gc.cols[0] + 1] - lay.op_off[gc.cols[0]];
+                G.classes.push_back(std::move(gc));
+            } else {
+                c = ci->second;
+            }
+            GradClass& gc = G.classes[c];
+            std::array<int, 3> key = {e.tgt, t / 4, t % 4};
+            auto ti = gc.t_of.find(key);
+            int tix;
+            if (ti == gc.t_of.end()) {
+                tix = (int)gc.trans.size();
+                gc.t_of[key] = tix;
+                gc.trans.push_back(key);
+                G.by_b[e.tgt].push_back({c, tix});
+            } else {
+                tix = ti->second;
+            }
+            gc.coef[{tix, gc.col_of.at(e.src)}] += e.v[t];
+        }
+}
+
+// Coefficient matrices into the table, transition-gradient and coefficient-gradient
+// regions into the workspace.
+static int64_t place_grad_side(Plan& P, GradSide& G, int64_t ws) {
+    for (auto& gc : G.classes) {
+        const int64_t nt = (int64_t)gc.trans.size(), nc = (int64_t)gc.cols.size();
+        gc.coef0 = (int64_t)P.coef.size();
+        P.coef.resize(P.coef.size() + (size_t)(nt * nc), 0.0);
+        for (auto& kv : gc.coef) P.coef[gc.coef0 + kv.first.first * nc + kv.first.second] = kv.second;
+        gc.g_base = ws;
+        ws += nt * gc.size;
+        gc.gc_base = ws;
+        ws += nt * nc;
+    }
+    return ws;
+}
+
+// Class GEMMs of one side: g_env (TN, into genv_space) and the coefficient gradient (NT).
+static void grad_class_blocks(const GradSide& G, const EnvLayout& lay, int8_t env_space, int8_t genv_space,
+                              std::vector<OutBlockTasks>& tn, std::vector<OutBlockTasks>& nt) {
+    for (const auto& gc : G.classes) {
+        const int ncol = (int)gc.cols.size(), ntr = (int)gc.trans.size();
+        int w = 0;
+        while (w < ncol) {
+            int w1 = w + 1;
+            while (w1 < ncol && lay.op_off[gc.cols[w1]] == lay.op_off[gc.cols[w1 - 1]] + gc.size) ++w1;
+            const int64_t eoff = lay.op_off[gc.cols[w]];
+            if (gc.size > 0) {
+                // g_env[run] = C[:, run]^T G_class
+                OutBlockTasks ob;
+                ob.coff = eoff;
+                ob.ldc = (int)gc.size;
+                ob.m = w1 - w;
+                ob.n = (int)gc.size;
+                Task t;
+                t.aoff = gc.coef0 + w;
+                t.lda = ncol;
+                t.boff = gc.g_base;
+                t.ldb = (int32_t)gc.size;
+                t.k = ntr;
+                t.alpha = 1.0;
+                t.set_spaces(SP_TAB, SP_WS);
+                ob.tasks.push_back(t);
+                tn.push_back(std::move(ob));
+                // gC[:, run] = G_class env[run]^T
+                OutBlockTasks oc;
+                oc.coff = gc.gc_base + w;
+                oc.ldc = ncol;
+                oc.m = ntr;
+                oc.n = w1 - w;
+                Task u;
+                u.aoff = gc.g_base;
+                u.lda = (int32_t)gc.size;
+                u.boff = eoff;
+                u.ldb = (int32_t)gc.size;
+                u.k = (int32_t)gc.size;
+                u.alpha = 1.0;
+                u.set_spaces(SP_WS, env_space);
+                oc.tasks.push_back(u);
+                nt.push_back(std::move(oc));
+            }
+            w = w1;
+        }
+    }
+    (void)genv_space;
+}
+
+static int build_heff_vjp(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, const OpSet& Mo,
+                          const OpSet& Ro, const std::vector<Entry>& e1, const std::vector<Entry>& e2,
+                          const hx_plan_opts* opts) {
+    P.kind = PK_HEFF_VJP;
+    if (opts && opts->split_kseg_min > 0) P.split_kseg_min = opts->split_kseg_min;
+    EnvLayout Ll = env_layout(lb, Lo), Rl = env_layout(rb, Ro);
+    PsiLayout psi = psi_layout(lb, rb);
+    P.psi_nnz = psi.nnz;
+    P.in_nnz = Ll.op_off.back();
+    P.in2_nnz = Rl.op_off.back();
+    P.w1_nnz = (int64_t)e1.size();
+    P.w2_nnz = (int64_t)e2.size();
+    const int nmid = (int)Mo.dq.size();
+
+    // forward mixed operators (hx_heff_prepare on this plan builds them)
+    Mixer ML{&lb, &Lo, &Ll, SP_L, {}, {}, {}, 0, 0};
+    Mixer MR{&rb, &Ro, &Rl, SP_R, {}, {}, {}, 0, 0};
+    build_mixer(ML, e1, nmid);
+    build_mixer(MR, e2, nmid);
+    int64_t ws = 0;
+    ws = place_mixer(ML, ws);
+    ws = place_mixer(MR, ws);
+    P.mix_end = ws;
+    P.mix_ranges.push_back({0, ws});
+    P.n_mixed = ML.n_mixed + MR.n_mixed;
+    P.flops_prepare = ML.flops + MR.flops;
+    emit_mixing(P, ML, P.prep);
+    emit_mixing(P, MR, P.prep);
+
+    GradSide GL, GR;
+    build_grad_side(GL, e1, Lo, Ll, nmid);
+    build_grad_side(GR, e2, Ro, Rl, nmid);
+    ws = place_grad_side(P, GL, ws);
+    ws = place_grad_side(P, GR, ws);
+
+    std::map<std::pair<int, int>, ShiftLayout> lsh, rsh;
+    auto lshift = [&](int dn, int ds) -> const ShiftLayout& {
+        auto k = std::make_pair(dn, ds);
+        auto it = lsh.find(k);
+        if (it == lsh.end()) it = lsh.emplace(k, shift_layout(lb, dn, ds)).first;
+        return it->second;
+    };
+    auto rshift = [&](int dn, int ds) -> const ShiftLayout& {
+        auto k = std::make_pair(dn, ds);
+        auto it = rsh.find(k);
+        if (it == rsh.end()) it = rsh.emplace(k, shift_layout(rb, dn, ds)).first;
+        return it->second;
+    };
+
+    // wavefunction column block (s2, ir) -> index; row block (il, s1) -> row offset per column
+    std::vector<int> col_at((size_t)4 * rb.nsec(), -1);
+    std::vector<std::unordered_map<int, int>> roff_of(psi.cols.size());
+    for (int c = 0; c < (int)psi.cols.size(); ++c) {
+        col_at[(size_t)psi.cols[c].s2 * rb.nsec() + psi.cols[c].ir] = c;
+        for (const auto& rbk : psi.cols[c].rowblk) roff_of[c][rbk[0] * 4 + rbk[1]] = rbk[2];
+    }
+    std::vector<std::vector<int>> col_by_s2(4);
+    for (int c = 0; c < (int)psi.cols.size(); ++c) col_by_s2[psi.cols[c].s2].push_back(c);
+    // an intermediate column block (T_b or gT_b) is keyed by k = so * nsec + irp; its rows
+    // are those of the fused left sector of the wavefunction columns it comes from
+    const int nsr = rb.nsec();
+    auto target_key = [&](int ir, int so, int dn, int ds) -> int {
+        int irp = rb.find(rb.qn[ir][0] + dn, rb.qn[ir][1] + ds);
+        return irp < 0 ? -1 : so * nsr + irp;
+    };
+
+    // per b: the column blocks of T_b (from the forward right transitions) and of
+    // gT_b (also those the right gradient transitions read)
+    std::vector<std::vector<int>> tcols(nmid), gtcols(nmid);
+    std::vector<std::unordered_map<int, int>> rep(nmid);  // key -> wavefunction column with the same rows
+    std::vector<char> need_t(nmid, 0), need_gt(nmid, 0);
+    std::vector<int64_t> bsize(nmid, 0);
+    for (int b = 0; b < nmid; ++b) {
+        need_t[b] = !MR.trans[b].empty() && !GL.by_b[b].empty();
+        need_gt[b] = !ML.trans[b].empty() && (!MR.trans[b].empty() || !GR.by_b[b].empty());
+        std::vector<char> in_t((size_t)4 * nsr, 0), in_gt((size_t)4 * nsr, 0);
+        auto note = [&](int k, int cj) -> bool {
+            auto it = rep[b].find(k);
+            if (it == rep[b].end()) {
+                rep[b][k] = cj;
+                return true;
+            }
+            if (psi.cols[it->second].rows != psi.cols[cj].rows) {
+                set_error("internal: stacked intermediate rows inconsistent");
+                return false;
+            }
+            return true;
+        };
+        for (auto& tr : MR.trans[b])
+            for (int cj : col_by_s2[tr.si]) {
+                int k = target_key(psi.cols[cj].ir, tr.so, tr.m.dn, tr.m.ds);
+                if (k < 0) continue;
+                if (!note(k, cj)) return HX_EINVAL;
+                in_t[k] = in_gt[k] = 1;
+            }
+        for (auto& ct : GR.by_b[b]) {
+            const GradClass& gc = GR.classes[ct.first];
+            const auto& key = gc.trans[ct.second];
+            for (int cj : col_by_s2[key[2]]) {
+                int k = target_key(psi.cols[cj].ir, key[1], gc.dn, gc.ds);
+                if (k < 0) continue;
+                if (!note(k, cj)) return HX_EINVAL;
+                in_gt[k] = 1;
+            }
+        }
+        for (int k = 0; k < 4 * nsr; ++k) {
+            if (!in_t[k] && !in_gt[k]) continue;
+            const int64_t sz = (int64_t)psi.cols[rep[b].at(k)].rows * rb.dim[k % nsr];
+            if (need_t[b] && in_t[k]) {
+                tcols[b].push_back(k);
+                bsize[b] += sz;
+            }
+            if (need_gt[b] && in_gt[k]) {
+                gtcols[b].push_back(k);
+                bsize[b] += sz;
+            }
+        }
+    }
+    const int64_t budget = default_budget(opts);
+    std::vector<std::pair<int, int>> chunks;
+    {
+        int b0 = 0;
+        int64_t acc = 0;
+        for (int b = 0; b < nmid; ++b) {
+            if (acc > 0 && acc + bsize[b] > budget) {
+                chunks.push_back({b0, b});
+                b0 = b;
+                acc = 0;
+            }
+            acc += bsize[b];
+        }
+        chunks.push_back({b0, nmid});
+    }
+    int64_t cmax = 0;
+    for (auto& ch : chunks) {
+        int64_t sz = 0;
+        for (int b = ch.first; b < ch.second; ++b) sz += bsize[b];
+        cmax = std::max(cmax, sz);
+    }
+    const int64_t t_ws = ws;
+    ws += cmax;
+    P.n_chunks = (int)chunks.size();
+
+    P.bw_fill.push_back({SP_GL, 0, P.in_nnz});
+    P.bw_fill.push_back({SP_GR, 0, P.in2_nnz});
+    P.bw_fill.push_back({SP_GW1, 0, 16 * P.w1_nnz});
+    P.bw_fill.push_back({SP_GW2, 0, 16 * P.w2_nnz});
+
+    double fl = 0;
+    int64_t ntask = 0;
+    std::vector<int64_t> toff(psi.cols.size()), gtoff(psi.cols.size());
+    for (size_t ci = 0; ci < chunks.size(); ++ci) {
+        // intermediates of the chunk: T_b then gT_b column blocks per b
+        std::vector<std::unordered_map<int, int64_t>> T(nmid), GT(nmid);
+        int64_t o = t_ws;
+        for (int b = chunks[ci].first; b < chunks[ci].second; ++b) {
+            for (int k : tcols[b]) {
+                T[b][k] = o;
+                o += (int64_t)psi.cols[rep[b].at(k)].rows * rb.dim[k % nsr];
+            }
+            for (int k : gtcols[b]) {
+                GT[b][k] = o;
+                o += (int64_t)psi.cols[rep[b].at(k)].rows * rb.dim[k % nsr];
+            }
+        }
+        // ---- T_b = psi Rhat_b^T (NT), as in the forward pass
+        {
+            std::vector<OutBlockTasks> blocks;
+            for (int b = chunks[ci].first; b < chunks[ci].second; ++b) {
+                if (!need_t[b]) continue;
+                std::unordered_map<int, int> bi;
+                for (int k : tcols[b]) {
+                    bi[k] = (int)blocks.size();
+                    OutBlockTasks ob;
+                    ob.coff = T[b][k];
+                    ob.ldc = rb.dim[k % nsr];
+                    ob.m = psi.cols[rep[b].at(k)].rows;
+                    ob.n = rb.dim[k % nsr];
+                    blocks.push_back(std::move(ob));
+                }
+                for (auto& tr : MR.trans[b]) {
+                    const ShiftLayout& sl = rshift(tr.m.dn, tr.m.ds);
+                    for (int cj : col_by_s2[tr.si]) {
+                        const PsiCol& pc = psi.cols[cj];
+                        int c = target_key(pc.ir, tr.so, tr.m.dn, tr.m.ds);
+                        if (c < 0) continue;
+                        Task t;
+                        t.aoff = pc.off;
+                        t.lda = rb.dim[pc.ir];
+                        t.boff = tr.m.base + sl.rel[pc.ir];
+                        t.ldb = rb.dim[pc.ir];
+                        t.k = rb.dim[pc.ir];
+                        t.alpha = tr.m.alpha;
+                        t.set_spaces(SP_PSI, tr.m.space);
+                        blocks[bi.at(c)].tasks.push_back(t);
+                    }
+                }
+            }
+            flush_blocks(P, blocks, NT, SP_WS, 0, true, P.apply, &fl, &ntask);
+        }
+        // ---- gT_b = Lhat_b^T g (TN), one output block per (column, row block)
+        {
+            std::vector<OutBlockTasks> blocks;
+            for (int b = chunks[ci].first; b < chunks[ci].second; ++b) {
+                if (!need_gt[b]) continue;
+                for (int c : gtcols[b]) {
+                    const PsiCol& pc = psi.cols[rep[b].at(c)];
+                    const int n = rb.dim[c % nsr], s2p = c / nsr, irp = c % nsr;
+                    for (const auto& rbk : pc.rowblk) {
+                        const int il = rbk[0], s1 = rbk[1];
+                        OutBlockTasks ob;
+                        ob.coff = GT[b][c] + (int64_t)rbk[2] * n;
+                        ob.ldc = n;
+                        ob.m = lb.dim[il];
+                        ob.n = n;
+                        for (auto& tr : ML.trans[b]) {
+                            if (tr.si != s1) continue;
+                            int ilp = lb.find(lb.qn[il][0] + tr.m.dn, lb.qn[il][1] + tr.m.ds);
+                            if (ilp < 0) continue;
+                            int gi = psi.find(ilp, tr.so, s2p);
+                            if (gi < 0 || psi.blocks[gi].ir != irp) {
+                                set_error("internal: cotangent block inconsistent with quantum numbers");
+                                return HX_EINVAL;
+                            }
+                            const ShiftLayout& sl = lshift(tr.m.dn, tr.m.ds);
+                            Task t;
+                            t.aoff = tr.m.base + sl.rel[il];
+                            t.lda = lb.dim[il];
+                            t.boff = psi.blocks[gi].off;
+                            t.ldb = n;
+                            t.k = lb.dim[ilp];
+                            t.alpha = tr.m.alpha;
+                            t.set_spaces(tr.m.space, SP_G);
+                            ob.tasks.push_back(t);
+                        }
+                        blocks.push_back(std::move(ob));
+                    }
+                }
+            }
+            flush_blocks(P, blocks, TN_, SP_WS, 0, true, P.apply, &fl, &ntask);
+        }
+        // ---- G_t = g T_b^T on the rows/cols of t (NT)
+        {
+            std::vector<OutBlockTasks> blocks;
+            for (int b = chunks[ci].first; b < chunks[ci].second; ++b) {
+                // output blocks (t, il) of this b (zero when T_b vanishes)
+                std::map<std::pair<int, int>, int> out_of;  // ((class<<20)|t, il) -> block
+                for (auto& ct : GL.by_b[b]) {
+                    const GradClass& gc = GL.classes[ct.first];
+                    const ShiftLayout& sl = lshift(gc.dn, gc.ds);
+                    for (int il = 0; il < lb.nsec(); ++il) {
+                        if (sl.rel[il] < 0) continue;
+                        int ilp = lb.find(lb.qn[il][0] + gc.dn, lb.qn[il][1] + gc.ds);
+                        OutBlockTasks ob;
+                        ob.coff = gc.g_base + (int64_t)ct.second * gc.size + sl.rel[il];
+                        ob.ldc = lb.dim[il];
+                        ob.m = lb.dim[ilp];
+                        ob.n = lb.dim[il];
+                        out_of[{(ct.first << 20) | ct.second, il}] = (int)blocks.size();
+                        blocks.push_back(std::move(ob));
+                    }
+                }
+                if (!need_t[b]) continue;
+                for (int c : tcols[b]) {
+                    const PsiCol& pc = psi.cols[rep[b].at(c)];
+                    const int n = rb.dim[c % nsr], s2p = c / nsr, irp = c % nsr;
+                    for (const auto& rbk : pc.rowblk) {
+                        const int il = rbk[0], s1 = rbk[1];
+                        for (auto& ct : GL.by_b[b]) {
+                            const GradClass& gc = GL.classes[ct.first];
+                            const auto& key = gc.trans[ct.second];
+                            if (key[2] != s1) continue;
+                            int ilp = lb.find(lb.qn[il][0] + gc.dn, lb.qn[il][1] + gc.ds);
+                            if (ilp < 0) continue;
+                            int gi = psi.find(ilp, key[1], s2p);
+                            if (gi < 0 || psi.blocks[gi].ir != irp) continue;
+                            Task t;
+                            t.aoff = psi.blocks[gi].off;
+                            t.lda = n;
+                            t.boff = T[b][c] + (int64_t)rbk[2] * n;
+                            t.ldb = n;
+                            t.k = n;
+                            t.alpha = 1.0;
+                            t.set_spaces(SP_G, SP_WS);
+                            blocks[out_of.at({(ct.first << 20) | ct.second, il})].tasks.push_back(t);
+                        }
+                    }
+                }
+            }
+            flush_blocks(P, blocks, NT, SP_WS, 0, true, P.apply, &fl, &ntask);
+        }
+        // ---- g_psi += gT_b Rhat_b (NN), summed over the chunk's b
+        {
+            std::vector<OutBlockTasks> blocks(psi.cols.size());
+            for (size_t c = 0; c < psi.cols.size(); ++c) {
+                blocks[c].coff = psi.cols[c].off;
+                blocks[c].ldc = rb.dim[psi.cols[c].ir];
+                blocks[c].m = psi.cols[c].rows;
+                blocks[c].n = rb.dim[psi.cols[c].ir];
+            }
+            for (int b = chunks[ci].first; b < chunks[ci].second; ++b) {
+                if (!need_gt[b]) continue;
+                for (auto& tr : MR.trans[b]) {
+                    const ShiftLayout& sl = rshift(tr.m.dn, tr.m.ds);
+                    for (int cj : col_by_s2[tr.si]) {
+                        const PsiCol& pc = psi.cols[cj];
+                        int c = target_key(pc.ir, tr.so, tr.m.dn, tr.m.ds);
+                        if (c < 0) continue;
+                        const int np = rb.dim[c % nsr];
+                        Task t;
+                        t.aoff = GT[b].at(c);
+                        t.lda = np;
+                        t.boff = tr.m.base + sl.rel[pc.ir];
+                        t.ldb = rb.dim[pc.ir];
+                        t.k = np;
+                        t.alpha = tr.m.alpha;
+                        t.set_spaces(SP_WS, tr.m.space);
+                        blocks[cj].tasks.push_back(t);
+                    }
+                }
+            }
+            flush_blocks(P, blocks, NN, SP_OUT, ci == 0 ? 0 : 1, ci == 0, P.apply, &fl, &ntask);
+        }
+        // ---- H_t = gT_b^T psi on the rows/cols of t (TN)
+        {
+            std::vector<OutBlockTasks> blocks;
+            for (int b = chunks[ci].first; b < chunks[ci].second; ++b) {
+                for (auto& ct : GR.by_b[b]) {
+                    const GradClass& gc = GR.classes[ct.first];
+                    const auto& key = gc.trans[ct.second];
+                    const ShiftLayout& sl = rshift(gc.dn, gc.ds);
+                    for (int ir = 0; ir < rb.nsec(); ++ir) {
+                        if (sl.rel[ir] < 0) continue;
+                        int irp = rb.find(rb.qn[ir][0] + gc.dn, rb.qn[ir][1] + gc.ds);
+                        OutBlockTasks ob;
+                        ob.coff = gc.g_base + (int64_t)ct.second * gc.size + sl.rel[ir];
+                        ob.ldc = rb.dim[ir];
+                        ob.m = rb.dim[irp];
+                        ob.n = rb.dim[ir];
+                        int cj = col_at[(size_t)key[2] * rb.nsec() + ir];
+                        int c = key[1] * nsr + irp;
+                        if (need_gt[b] && cj >= 0 && c >= 0) {
+                            auto it = GT[b].find(c);
+                            if (it == GT[b].end()) {
+                                set_error("internal: missing cotangent intermediate");
+                                return HX_EINVAL;
+                            }
+                            Task t;
+                            t.aoff = it->second;
+                            t.lda = rb.dim[irp];
+                            t.boff = psi.cols[cj].off;
+                            t.ldb = rb.dim[ir];
+                            t.k = psi.cols[cj].rows;
+                            t.alpha = 1.0;
+                            t.set_spaces(SP_WS, SP_PSI);
+                            ob.tasks.push_back(t);
+                        }
+                        blocks.push_back(std::move(ob));
+                    }
+                }
+            }
+            flush_blocks(P, blocks, TN_, SP_WS, 0, true, P.apply, &fl, &ntask);
+        }
+    }
+    // ---- class GEMMs: environment gradients (TN) and coefficient gradients (NT)
+    {
+        std::vector<OutBlockTasks> tnL, ntL, tnR, ntR;
+        grad_class_blocks(GL, Ll, SP_L, SP_GL, tnL, ntL);
+        grad_class_blocks(GR, Rl, SP_R, SP_GR, tnR, ntR);
+        flush_blocks(P, tnL, TN_, SP_GL, 0, false, P.apply, &fl, &ntask);
+        flush_blocks(P, tnR, TN_, SP_GR, 0, false, P.apply, &fl, &ntask);
+        ntL.insert(ntL.end(), ntR.begin(), ntR.end());
+        flush_blocks(P, ntL, NT, SP_WS, 0, false, P.apply, &fl, &ntask);
+    }
+    // ---- scatter the coefficient gradients to the MPO value layout
+    {
+        GatherLaunch gl;
+        gl.g0 = (int64_t)P.gathers.size();
+        auto emit = [&](const GradSide& G, const std::vector<Entry>& ents, const OpSet& ops, int8_t dspace) {
+            for (size_t e = 0; e < ents.size(); ++e) {
+                const Entry& en = ents[e];
+                const auto& dq = ops.dq[en.src];
+                const GradClass& gc = G.classes[G.class_of.at({dq[0], dq[1]})];
+                for (int t = 0; t < 16; ++t) {
+                    if (en.v[t] == 0.0) continue;
+                    int tix = gc.t_of.at({en.tgt, t / 4, t % 4});
+                    Gather g;
+                    g.soff = gc.gc_base + (int64_t)tix * (int64_t)gc.cols.size() + gc.col_of.at(en.src);
+                    g.doff = (int64_t)e * 16 + t;
+                    g.sstride = 1;
+                    g.dstride = 1;
+                    g.count = 1;
+                    g.sspace = SP_WS;
+                    g.dspace = dspace;
+                    g.pad = 0;
+                    g.alpha = 1.0;
+                    P.gathers.push_back(g);
+                }
+            }
+        };
+        emit(GL, e1, Lo, SP_GW1);
+        emit(GR, e2, Ro, SP_GW2);
+        gl.ng = (int64_t)P.gathers.size() - gl.g0;
+        if (gl.ng) P.bw_gather.push_back(gl);
+    }
+    P.flops_apply = fl;
+    P.n_tasks_apply = ntask;
+    for (auto& L : P.apply) P.n_tiles_apply += L.ntile;
+    P.part_base = ws;
+    ws += P.part_tiles * TM * TN;
+    P.ws_doubles = ws;
+    if (!check_task_index_range(P)) return HX_EINVAL;
+    return HX_OK;
+}
+
 // ---------------------------------------------------------------- env plans
 
 static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const OpSet& oin, const OpSet& oout,
@@ -1309,6 +1865,32 @@ int hx_heff_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_ops
         return HX_EINVAL;
     Plan* P = new Plan();
     int rc = build_heff(*P, lb, rb, Lo, Mo, Ro, e1, e2, opts);
+    if (rc != HX_OK) {
+        delete P;
+        return rc;
+    }
+    finalize_tables(*P);
+    *out = reinterpret_cast<hx_plan*>(P);
+    return HX_OK;
+}
+
+int hx_heff_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops, const hx_opset* mid,
+                            const hx_opset* Rops, const hx_mpo_site* W1, const hx_mpo_site* W2,
+                            const hx_plan_opts* opts, hx_plan** out) {
+    if (!out) {
+        set_error("heff_vjp_plan_create: null output");
+        return HX_EINVAL;
+    }
+    *out = nullptr;
+    Bond lb, rb;
+    OpSet Lo, Mo, Ro;
+    if (!parse_bond(lbond, lb, "vjp left bond") || !parse_bond(rbond, rb, "vjp right bond")) return HX_EINVAL;
+    if (!parse_ops(Lops, Lo, "vjp Lops") || !parse_ops(mid, Mo, "vjp mid") || !parse_ops(Rops, Ro, "vjp Rops"))
+        return HX_EINVAL;
+    std::vector<Entry> e1, e2;
+    if (!parse_mpo(W1, Lo, Mo, true, e1, "vjp W1") || !parse_mpo(W2, Mo, Ro, false, e2, "vjp W2")) return HX_EINVAL;
+    Plan* P = new Plan();
+    int rc = build_heff_vjp(*P, lb, rb, Lo, Mo, Ro, e1, e2, opts);
     if (rc != HX_OK) {
         delete P;
         return rc;

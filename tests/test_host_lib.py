@@ -197,3 +197,17 @@ def test_batch_plan_rejects_chunked_instance():
     assert p.info.n_chunks > 1
     with pytest.raises(RuntimeError, match="single-chunk"):
         X.BatchPlan([p])
+
+
+def test_vjp_plan_builds_for_every_site_of_the_nc_mpo():
+    """The adjoint plan exists wherever the forward plan does; its work includes
+    the recomputed first round plus four more block-GEMM rounds."""
+    K = 8
+    m = M.build_nc_mpo(*make_integrals(K, seed=0))
+    b = bond_sector_tables(K, K, 0, 32)
+    for i in range(K - 1):
+        args = (b[i], b[i + 2], m.dq[i], m.dq[i + 1], m.dq[i + 2], M.site_entries(m, i), M.site_entries(m, i + 1))
+        f = X.HeffPlan(*args)
+        v = X.HeffVjpPlan(*args)
+        assert v.info.psi_nnz == f.info.psi_nnz and v.info.in_nnz == f.info.in_nnz
+        assert v.info.flops_apply > 2.0 * f.info.flops_apply
