@@ -135,17 +135,19 @@ def bench_batch(args):
     device = "cuda"
     t0 = time.time()
     insts = batch_instances(X, M=args.bond_dim, K=args.orbitals, count=args.instances)
-    plans = []
-    for d in insts:
-        m = d["mpo"]
-        i = d["i"]
-        plans.append(X.HeffPlan(d["lbond"], d["rbond"], m.dq[i], m.dq[i + 1], m.dq[i + 2], d["W1"], d["W2"],
-                                t_budget_bytes=1 << 40, split_kseg_min=args.kseg))
-    B = X.BatchPlan(plans).upload(device)
-    for p in plans:
-        p.upload(device)
-    log(f"{len(plans)} plans + batch in {time.time() - t0:.1f}s; batch {B.info.flops_apply / 1e9:.2f} GFLOP/apply, "
-        f"tiles {B.info.n_tiles}, ws {B.info.ws_bytes / 1e9:.2f} GB")
+
+    def make_plans(opts):
+        ps = []
+        for d in insts:
+            m = d["mpo"]
+            i = d["i"]
+            ps.append(X.HeffPlan(d["lbond"], d["rbond"], m.dq[i], m.dq[i + 1], m.dq[i + 2], d["W1"], d["W2"],
+                                 t_budget_bytes=1 << 40, **opts))
+        return ps
+
+    opts = {"split_kseg_min": args.kseg or 2048, "kernel_variant": 0 if args.variant is None else args.variant}
+    plans = make_plans(opts)
+    log(f"{len(plans)} plans in {time.time() - t0:.1f}s")
     gen = torch.Generator(device=device)
     gen.manual_seed(11)
 
@@ -160,6 +162,31 @@ def bench_batch(args):
     Rc = torch.cat([x[:int(p.info.in2_nnz)] for x, p in zip(Rs, plans)])
     Pc = torch.cat([x[:int(p.info.psi_nnz)] for x, p in zip(Ps, plans)])
     Sc = torch.empty_like(Pc)
+    tune_s = 0.0
+    if not args.no_autotune:
+        from paper_2310_03920_amd import autotune
+        axes = [a for a in autotune.AXES[:2] if not (a[0] == "kernel_variant" and args.variant is not None)
+                and not (a[0] == "split_kseg_min" and args.kseg)]
+
+        def build(o):
+            b = X.BatchPlan(make_plans(o)).upload(device)
+            b.prepare(Lc, Rc)
+            return b
+
+        def run(b):
+            b.apply(Lc, Rc, Pc, Sc)
+            return Sc
+
+        t1 = time.time()
+        opts, timings = autotune.tune(build, run, axes=axes, reps=3, start=opts)
+        tune_s = time.time() - t1
+        log(f"autotune in {tune_s:.1f}s: {opts} "
+            f"({', '.join(f'{k}: {1e3 * v:.2f} ms' for k, v in timings.items() if v is not None)})")
+        plans = make_plans(opts)
+    B = X.BatchPlan(plans).upload(device)
+    for p in plans:
+        p.upload(device)
+    log(f"batch {B.info.flops_apply / 1e9:.2f} GFLOP/apply, tiles {B.info.n_tiles}, ws {B.info.ws_bytes / 1e9:.2f} GB")
     f32 = args.mode == "f32"
     for p, L, R in zip(plans, Ls, Rs):
         p.prepare(L, R)
@@ -239,7 +266,8 @@ def bench_batch(args):
                         f"integral seeds 1..{len(plans)}, random N(0,1) environments; one step = one batched "
                         f"sigma-vector replayed from a HIP graph",
             "instances": len(plans), "bond_dim": args.bond_dim, "orbitals": args.orbitals,
-            "psi_nnz_total": int(B.info.psi_nnz), "tiles": int(B.info.n_tiles),
+            "psi_nnz_total": int(B.info.psi_nnz), "tiles": int(B.info.n_tiles), "plan_opts": opts,
+            "autotune_s": tune_s,
         },
         "batch": {"gflop": fl / 1e9, "one_by_one_ms": 1e3 * t_one, "batched_ms": 1e3 * t_bat,
                   "graph_ms": 1e3 * t_gr, "one_by_one_wall_ms": 1e3 * w_one, "batched_wall_ms": 1e3 * w_bat,
@@ -249,6 +277,96 @@ def bench_batch(args):
                      "kernel": "bsgemm (every launch of one batched sigma-vector, graph replay)"},
     }
     print(json.dumps(out), flush=True)
+
+
+def plan_options(args, X, mpo, bonds, i, Lenv, Renv, tb, device):
+    """Plan options of the middle step: tuned on the GPU (untimed setup) unless
+    --no-autotune; explicit --variant / --kseg pin those axes."""
+    import torch
+    from paper_2310_03920_amd import autotune
+    from synth.blocks import random_psi
+    opts = {"t_budget_bytes": tb, "split_kseg_min": args.kseg or 2048,
+            "kernel_variant": 0 if args.variant is None else args.variant}
+    if args.no_autotune:
+        return opts, 0.0
+    axes = [a for a in autotune.AXES if not (a[0] == "kernel_variant" and args.variant is not None)
+            and not (a[0] == "split_kseg_min" and args.kseg)]
+    lb, rb = X.Bond(bonds[i]), X.Bond(bonds[i + 2])
+    psi = torch.from_numpy(X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2], np.random.default_rng(9)))).to(device)
+    W1 = X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats)
+    W2 = X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats)
+    sig = torch.empty_like(psi)
+
+    def build(o):
+        p = X.HeffPlan(lb, rb, mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2], W1, W2, **o).upload(device)
+        p.prepare(Lenv, Renv)
+        return p
+
+    def run(p):
+        p.apply(Lenv, Renv, psi, sig)
+        return sig
+
+    t0 = time.time()
+    best, timings = autotune.tune(build, run, axes=axes, reps=2, start=opts)
+    log(f"autotune in {time.time() - t0:.1f}s: {best} "
+        f"({', '.join(f'{k}: {1e3 * v:.1f} ms' for k, v in timings.items() if v is not None)})")
+    torch.cuda.empty_cache()
+    return best, time.time() - t0
+
+
+def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
+    """Time bare sigma-vectors (FP64, or FP32 with --mode f32) at the middle step."""
+    import torch
+    from synth.blocks import random_psi
+    plan = X.HeffPlan(bonds[i], bonds[i + 2], mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2],
+                      X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats),
+                      X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats),
+                      **opts).upload(device)
+    lb, rb = X.Bond(bonds[i]), X.Bond(bonds[i + 2])
+    psi = torch.from_numpy(X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2], np.random.default_rng(3)))).to(device)
+    sig = torch.empty_like(psi)
+    plan.prepare(Lenv, Renv)
+    f32 = args.mode == "f32"
+    if f32:
+        plan.lower_f32(Lenv, Renv)
+        psi32, sig32 = psi.float(), torch.empty_like(psi, dtype=torch.float32)
+
+    def one():
+        if f32:
+            plan.apply_f32(psi32, sig32)
+        else:
+            plan.apply(Lenv, Renv, psi, sig)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(args.steps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        one()
+        e.record()
+        e.synchronize()
+        ms.append(s.elapsed_time(e))
+    info = plan.info
+    avg = float(np.mean(ms)) / 1e3
+    peak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
+    achieved = info.flops_apply / avg / 1e12
+    src = torch.ones(1 << 26, dtype=torch.float64, device=device)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({
+        "metric": METRIC, "value": info.flops_apply / avg / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * avg, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.mode, "data": "synthetic",
+        "config": {"workload": f"sigma-vectors only at sites ({i},{i + 1}) of the {mpo.K}-orbital chain, "
+                               f"M={args.bond_dim}", "chunks": int(info.n_chunks), "tiles": int(info.n_tiles),
+                   "apply_ms_each": ms, "plan_opts": opts, "autotune_s": tune_s},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak, "traffic": None},
+    }), flush=True)
 
 
 def main():
@@ -265,10 +383,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["f64", "f32"], default="f64",
                     help="precision of the block contractions; Davidson is FP64 in both")
-    ap.add_argument("--workload", choices=["middle", "batch"], default="middle",
-                    help="middle: one DMRG step at the chain's middle; batch: many small sigma-vectors")
+    ap.add_argument("--workload", choices=["middle", "batch", "apply"], default="middle",
+                    help="middle: one DMRG step at the chain's middle; batch: many small sigma-vectors; "
+                         "apply: sigma-vectors only at the middle step (profiling), ending with a 512 MiB "
+                         "device copy that calibrates HBM byte counters")
     ap.add_argument("--instances", type=int, default=16)
     ap.add_argument("--kseg", type=int, default=0, help="split-K minimum segment (0 = default)")
+    ap.add_argument("--variant", type=int, default=None,
+                    help="block-GEMM kernel variant (0, 1, 2); default: chosen by the autotuner")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library defaults (or the given --variant/--kseg) instead of tuning")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -305,13 +429,17 @@ def main():
     Lenv, Renv = build_environments(X, mpo, bonds, left, right, i, device)
 
     tb = int(args.t_budget_gb * (1 << 30))
+    opts, tune_s = plan_options(args, X, mpo, bonds, i, Lenv, Renv, tb, device)
+    if args.workload == "apply":
+        apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device)
+        return
     t1 = time.time()
     plan = X.HeffPlan(bonds[i], bonds[i + 2], mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2],
                       X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats),
-                      X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats),
-                      t_budget_bytes=tb)
+                      X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats), **opts)
     eplan = X.EnvPlan(0, bonds[i], bonds[i + 1], mpo.dq[i], mpo.dq[i + 1],
-                      X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats), t_budget_bytes=tb)
+                      X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats), t_budget_bytes=tb,
+                      kernel_variant=opts["kernel_variant"])
     plan_s = time.time() - t1
     plan.upload(device)
     eplan.upload(device)
@@ -427,7 +555,7 @@ def main():
                          "warm_start_rnorm": r_pre, "reference_energy": e_ref, "reference_rnorm": r_ref,
                          "f32_matvecs_per_step": counts["f32"] / args.steps,
                          "f64_matvecs_per_step": counts["f64"] / args.steps, "precision": args.mode},
-            "plan_build_s": plan_s, "chunks": int(info.n_chunks),
+            "plan_build_s": plan_s, "chunks": int(info.n_chunks), "plan_opts": opts, "autotune_s": tune_s,
         },
         "heff_apply": {"ms": 1e3 * avg_apply, "tflop": info.flops_apply / 1e12,
                        "tflops": achieved, "launches": 2 * int(info.n_chunks)},

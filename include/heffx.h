@@ -88,7 +88,11 @@ typedef struct {
 typedef struct {
     int64_t t_budget_bytes;  /* cap on the intermediate (T) workspace; 0 = default 1 GiB */
     int32_t split_kseg_min;  /* minimum K of a split-K segment; 0 = default 2048 */
-    int32_t reserved[7];
+    int32_t kernel_variant;  /* block-GEMM pipeline: 0 = two LDS buffers, 16-deep K stages (default);
+                                1 = one LDS buffer, 16-deep (more workgroups per CU);
+                                2 = two LDS buffers, 8-deep (less K padding, more workgroups per CU).
+                                Results are identical up to FP rounding order of the padding. */
+    int32_t reserved[6];
 } hx_plan_opts;
 
 typedef struct {

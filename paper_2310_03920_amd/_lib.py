@@ -41,7 +41,8 @@ class HxMpoSite(ctypes.Structure):
 
 
 class HxPlanOpts(ctypes.Structure):
-    _fields_ = [("t_budget_bytes", c_int64), ("split_kseg_min", c_int32), ("reserved", c_int32 * 7)]
+    _fields_ = [("t_budget_bytes", c_int64), ("split_kseg_min", c_int32), ("kernel_variant", c_int32),
+                ("reserved", c_int32 * 6)]
 
 
 class HxPlanInfo(ctypes.Structure):
@@ -306,20 +307,22 @@ class Plan:
             pass
 
 
-def _opts(t_budget_bytes=0, split_kseg_min=0):
+def _opts(t_budget_bytes=0, split_kseg_min=0, kernel_variant=0):
     o = HxPlanOpts()
     o.t_budget_bytes = int(t_budget_bytes)
     o.split_kseg_min = int(split_kseg_min)
+    o.kernel_variant = int(kernel_variant)
     return o
 
 
 class HeffPlan(Plan):
-    def __init__(self, lbond, rbond, Ldq, mid_dq, Rdq, W1, W2, t_budget_bytes=0, split_kseg_min=0):
+    def __init__(self, lbond, rbond, Ldq, mid_dq, Rdq, W1, W2, t_budget_bytes=0, split_kseg_min=0,
+                 kernel_variant=0):
         lb, rb = (b if isinstance(b, Bond) else Bond(b) for b in (lbond, rbond))
         Lo, Mo, Ro = OpSet(Ldq), OpSet(mid_dq), OpSet(Rdq)
         w1 = W1 if isinstance(W1, MpoSite) else MpoSite.from_entries(W1)
         w2 = W2 if isinstance(W2, MpoSite) else MpoSite.from_entries(W2)
-        opts = _opts(t_budget_bytes, split_kseg_min)
+        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant)
         h = c_void_p()
         check(lib().hx_heff_plan_create(ctypes.byref(lb.c), ctypes.byref(rb.c), ctypes.byref(Lo.c),
                                         ctypes.byref(Mo.c), ctypes.byref(Ro.c), ctypes.byref(w1.c),
@@ -357,12 +360,13 @@ class HeffPlan(Plan):
 class HeffVjpPlan(Plan):
     """Plan of the vector-Jacobian products of sigma = H_eff psi."""
 
-    def __init__(self, lbond, rbond, Ldq, mid_dq, Rdq, W1, W2, t_budget_bytes=0, split_kseg_min=0):
+    def __init__(self, lbond, rbond, Ldq, mid_dq, Rdq, W1, W2, t_budget_bytes=0, split_kseg_min=0,
+                 kernel_variant=0):
         lb, rb = (b if isinstance(b, Bond) else Bond(b) for b in (lbond, rbond))
         Lo, Mo, Ro = OpSet(Ldq), OpSet(mid_dq), OpSet(Rdq)
         w1 = W1 if isinstance(W1, MpoSite) else MpoSite.from_entries(W1)
         w2 = W2 if isinstance(W2, MpoSite) else MpoSite.from_entries(W2)
-        opts = _opts(t_budget_bytes, split_kseg_min)
+        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant)
         h = c_void_p()
         check(lib().hx_heff_vjp_plan_create(ctypes.byref(lb.c), ctypes.byref(rb.c), ctypes.byref(Lo.c),
                                             ctypes.byref(Mo.c), ctypes.byref(Ro.c), ctypes.byref(w1.c),
@@ -426,11 +430,12 @@ class BatchPlan(HeffPlan):
 
 
 class EnvPlan(Plan):
-    def __init__(self, direction, bond_in, bond_out, dq_in, dq_out, W, t_budget_bytes=0, split_kseg_min=0):
+    def __init__(self, direction, bond_in, bond_out, dq_in, dq_out, W, t_budget_bytes=0, split_kseg_min=0,
+                 kernel_variant=0):
         bi, bo = (b if isinstance(b, Bond) else Bond(b) for b in (bond_in, bond_out))
         oi, oo = OpSet(dq_in), OpSet(dq_out)
         w = W if isinstance(W, MpoSite) else MpoSite.from_entries(W)
-        opts = _opts(t_budget_bytes, split_kseg_min)
+        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant)
         h = c_void_p()
         check(lib().hx_env_plan_create(int(direction), ctypes.byref(bi.c), ctypes.byref(bo.c), ctypes.byref(oi.c),
                                        ctypes.byref(oo.c), ctypes.byref(w.c), ctypes.byref(opts), ctypes.byref(h)),

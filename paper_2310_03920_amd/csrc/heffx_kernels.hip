@@ -8,8 +8,8 @@
 // padding) and writes the tile once: no atomics, fixed summation order, so FP64
 // results are bitwise reproducible.  The inner product runs on the FP64 matrix
 // cores (v_mfma_f64_16x16x4_f64); each of the 4 waves owns a 32 x 32 quadrant
-// (2 x 2 MFMA tiles); 16-deep K stages are staged through LDS with a register
-// prefetch of the next stage.
+// (2 x 2 MFMA tiles); K stages (16 or 8 deep) are staged through LDS (one or two
+// buffers) with a register prefetch of the next stage.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -45,10 +45,10 @@ __device__ __forceinline__ T* space_ptr(const BasesT<T>& B, int sp) {
 
 constexpr int NSP_FWD = SP_PART + 1;
 
-// The K range of a tile is walked in 16-deep stages; every task's K is padded to
-// a multiple of 16 with zeros, so a stage belongs to exactly one task and the
-// walk is uniform across the workgroup (scalar registers, one lookup per stage).
-constexpr int KS = 16;
+// The K range of a tile is walked in stages of KSV (16 or 8, the plan's variant);
+// every task's K is padded to a multiple of KSV with zeros, so a stage belongs to
+// exactly one task and the walk is uniform across the workgroup (scalar
+// registers, one lookup per stage).
 
 template <typename T>
 struct Stage {
@@ -59,7 +59,7 @@ struct Stage {
     double alpha;
 };
 
-template <typename T, bool TA, bool TB, int NSP>
+template <typename T, bool TA, bool TB, int NSP, int KSV>
 __device__ __forceinline__ Stage<T> next_stage(int& j, int& kl, int tend, const Task* __restrict__ tasks,
                                                const BasesT<T>& B, int r0, int c0) {
     Stage<T> q;
@@ -78,11 +78,11 @@ __device__ __forceinline__ Stage<T> next_stage(int& j, int& kl, int tend, const 
     q.lda = t.lda;
     q.ldb = t.ldb;
     q.alpha = t.alpha;
-    q.krem = min(KS, t.k - kl);
+    q.krem = min(KSV, t.k - kl);
     const int sp = t.spaces;
     q.a = space_ptr<T, NSP>(B, sp & 0xff) + t.aoff + (TA ? (int64_t)kl * t.lda + r0 : (int64_t)r0 * t.lda + kl);
     q.b = space_ptr<T, NSP>(B, (sp >> 8) & 0xff) + t.boff + (TB ? (int64_t)c0 * t.ldb + kl : (int64_t)kl * t.ldb + c0);
-    kl += KS;
+    kl += KSV;
     return q;
 }
 
@@ -91,12 +91,16 @@ constexpr int LDW = TM + LDS_PAD;
 
 // Element type T: double (v_mfma_f64_16x16x4_f64) or float (v_mfma_f32_16x16x4_f32,
 // FP32 accumulation).  The tile tables are the same for both.
-template <typename T, bool TA, bool TB, int NSP>
+// KSV: K-stage depth (16 or 8); NBUF: LDS buffers (2: the next stage is stored
+// while the current one is read; 1: half the LDS, one more barrier per stage).
+template <typename T, bool TA, bool TB, int NSP, int KSV, int NBUF>
 __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
                                               BasesT<T> B) {
     using acc_t = typename std::conditional<std::is_same<T, double>::value, dbl4, flt4>::type;
-    __shared__ T As[2][KS][LDW];
-    __shared__ T Bs[2][KS][LDW];
+    static_assert(KSV == 8 || KSV == 16, "stage depth");
+    constexpr int NE = KSV / 4;  // elements of A (and of B) each thread stages per K stage
+    __shared__ T As[NBUF][KSV][LDW];
+    __shared__ T Bs[NBUF][KSV][LDW];
     const Tile tl = tiles[blockIdx.x];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -109,30 +113,30 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     const bool r0 = wr0 < m, r1 = wr0 + 16 < m, c0 = wc0 < n, c1 = wc0 + 16 < n;
     const bool any = r0 && c0;
     // load lanes (element e of a thread: idx = tid + 256 e):
-    //  A !TA: k = idx % 16, row = idx / 16 (16 contiguous k per row)
+    //  A !TA: k = idx % KSV, row = idx / KSV (KSV contiguous k per row)
     //  A  TA: row = idx % 64, k = idx / 64 (64 contiguous rows per k)
     //  B !TB: col = idx % 64, k = idx / 64
-    //  B  TB: k = idx % 16, col = idx / 16
-    const int a_r = TA ? (tid & 63) : (tid >> 4);
-    const int a_k = TA ? (tid >> 6) : (tid & 15);
-    const int b_c = TB ? (tid >> 4) : (tid & 63);
-    const int b_k = TB ? (tid & 15) : (tid >> 6);
-    constexpr int a_dr = TA ? 0 : 16, a_dk = TA ? 4 : 0;  // step per element e
-    constexpr int b_dc = TB ? 16 : 0, b_dk = TB ? 0 : 4;
+    //  B  TB: k = idx % KSV, col = idx / KSV
+    const int a_r = TA ? (tid & 63) : (tid / KSV);
+    const int a_k = TA ? (tid >> 6) : (tid % KSV);
+    const int b_c = TB ? (tid / KSV) : (tid & 63);
+    const int b_k = TB ? (tid % KSV) : (tid >> 6);
+    constexpr int a_dr = TA ? 0 : 256 / KSV, a_dk = TA ? 4 : 0;  // step per element e
+    constexpr int b_dc = TB ? 256 / KSV : 0, b_dk = TB ? 0 : 4;
     int cj = tl.tbeg, ckl = 0;  // uniform cursor
 
     acc_t acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
-    T ra[4], rb[4];
+    T ra[NE], rb[NE];
     T alpha = 0;
-    const int nst = tl.ktot / KS;
+    const int nst = tl.ktot / KSV;
 
     // raw loads; alpha is applied at the LDS store so the loads stay in flight
     // across the MFMA work of the current stage
     auto load_stage = [&]() {
-        const Stage<T> q = next_stage<T, TA, TB, NSP>(cj, ckl, tl.tend, tasks, B, tl.r0, tl.c0);
+        const Stage<T> q = next_stage<T, TA, TB, NSP, KSV>(cj, ckl, tl.tend, tasks, B, tl.r0, tl.c0);
         alpha = (T)q.alpha;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
             const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
             T va = 0, vb = 0;
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
+        for (int e = 0; e < NE; ++e) {
             As[buf][a_k + a_dk * e][a_r + a_dr * e] = alpha * ra[e];
             Bs[buf][b_k + b_dk * e][b_c + b_dc * e] = rb[e];
         }
@@ -155,11 +159,11 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         store_stage(0);
         __syncthreads();
         for (int s = 0; s < nst; ++s) {
-            const int buf = s & 1;
+            const int buf = NBUF == 2 ? (s & 1) : 0;
             if (s + 1 < nst) load_stage();
             if (any) {
 #pragma unroll
-                for (int ks = 0; ks < KS / 4; ++ks) {
+                for (int ks = 0; ks < KSV / 4; ++ks) {
                     const int kr = ks * 4 + (lane >> 4);
                     const T a0 = As[buf][kr][wr0 + (lane & 15)];
                     const T a1 = As[buf][kr][wr0 + 16 + (lane & 15)];
@@ -178,8 +182,16 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
                     }
                 }
             }
-            if (s + 1 < nst) store_stage(buf ^ 1);
-            __syncthreads();
+            if constexpr (NBUF == 2) {
+                if (s + 1 < nst) store_stage(buf ^ 1);
+                __syncthreads();
+            } else {
+                __syncthreads();
+                if (s + 1 < nst) {
+                    store_stage(0);
+                    __syncthreads();
+                }
+            }
         }
     }
     // epilogue (lane layouts measured on gfx950): v_mfma_f64_16x16x4_f64 gives lane l
@@ -464,26 +476,45 @@ static Bases make_bases(const Plan* P, const double* psi, double* out, const dou
     return b;
 }
 
+template <typename T, int NSP, int KSV, int NBUF>
+static int launch_kind(int kind, dim3 grid, const Tile* tiles, const Task* tasks, const BasesT<T>& B,
+                       hipStream_t s) {
+    const dim3 block(256);
+    switch (kind) {
+        case NN:
+            hipLaunchKernelGGL((bsgemm<T, false, false, NSP, KSV, NBUF>), grid, block, 0, s, tiles, tasks, B);
+            return HX_OK;
+        case NT:
+            hipLaunchKernelGGL((bsgemm<T, false, true, NSP, KSV, NBUF>), grid, block, 0, s, tiles, tasks, B);
+            return HX_OK;
+        case TN_:
+            hipLaunchKernelGGL((bsgemm<T, true, false, NSP, KSV, NBUF>), grid, block, 0, s, tiles, tasks, B);
+            return HX_OK;
+        default:
+            set_error("internal: bad GEMM kind");
+            return HX_EINVAL;
+    }
+}
+
 template <typename T, int NSP = NSP_FWD>
 static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipStream_t s) {
     if (L.ntile <= 0) return HX_OK;
     const Tile* tiles = reinterpret_cast<const Tile*>(static_cast<const char*>(P->dev) + P->off_tiles) + L.tile0;
     const Task* tasks = reinterpret_cast<const Task*>(static_cast<const char*>(P->dev) + P->off_tasks);
-    dim3 grid((unsigned)L.ntile), block(256);
-    switch (L.kind) {
-        case NN:
-            hipLaunchKernelGGL((bsgemm<T, false, false, NSP>), grid, block, 0, s, tiles, tasks, B);
+    dim3 grid((unsigned)L.ntile);
+    int rk;
+    switch (P->variant) {
+        case 1:
+            rk = launch_kind<T, NSP, 16, 1>(L.kind, grid, tiles, tasks, B, s);
             break;
-        case NT:
-            hipLaunchKernelGGL((bsgemm<T, false, true, NSP>), grid, block, 0, s, tiles, tasks, B);
-            break;
-        case TN_:
-            hipLaunchKernelGGL((bsgemm<T, true, false, NSP>), grid, block, 0, s, tiles, tasks, B);
+        case 2:
+            rk = launch_kind<T, NSP, 8, 2>(L.kind, grid, tiles, tasks, B, s);
             break;
         default:
-            set_error("internal: bad GEMM kind");
-            return HX_EINVAL;
+            rk = launch_kind<T, NSP, 16, 2>(L.kind, grid, tiles, tasks, B, s);
+            break;
     }
+    if (rk) return rk;
     int rc = hip_check(hipGetLastError(), "bsgemm launch");
     if (rc || L.nred <= 0) return rc;
     const Reduce* red = reinterpret_cast<const Reduce*>(static_cast<const char*>(P->dev) + P->off_reduces) + L.red0;

@@ -402,7 +402,20 @@ struct Builder {
 };
 
 // K of a task as walked by the kernel: padded to the 16-deep LDS stage with zeros.
-static inline int32_t kpad(int32_t k) { return (k + 15) & ~15; }
+static inline int32_t kpad(int32_t k, int ks) { return (k + ks - 1) / ks * ks; }
+
+// Kernel variant of a plan (hx_plan_opts.kernel_variant): LDS buffering and K-stage depth.
+static int apply_opts(Plan& P, const hx_plan_opts* o) {
+    if (o && o->split_kseg_min > 0) P.split_kseg_min = o->split_kseg_min;
+    const int v = o ? o->kernel_variant : 0;
+    if (v < 0 || v > 2) {
+        set_error("plan options: kernel_variant must be 0, 1 or 2");
+        return HX_EINVAL;
+    }
+    P.variant = v;
+    P.kstage = v == 2 ? 8 : 16;
+    return HX_OK;
+}
 
 // Split-K: when a launch has too few tiles to fill the GPU, cut long task lists
 // at task boundaries into segments that write partial tiles; a reduction then
@@ -437,7 +450,7 @@ static void split_launch(Plan& P, Launch& L) {
         while (a < tl.tend) {
             int32_t b = a;
             int64_t ks = 0;
-            while (b < tl.tend && (ks < kseg || b == a)) ks += kpad(P.tasks[b++].k);
+            while (b < tl.tend && (ks < kseg || b == a)) ks += kpad(P.tasks[b++].k, P.kstage);
             Tile p = tl;
             p.tbeg = a;
             p.tend = b;
@@ -509,7 +522,7 @@ static void emit_mixing(Plan& P, Mixer& M, std::vector<Launch>& seq) {
                 t.set_spaces(ta_, M.env_space);
                 t.alpha = 1.0;
                 P.tasks.push_back(t);
-                ktot += kpad(t.k);
+                ktot += kpad(t.k, P.kstage);
                 w = w1;
             }
             int32_t tend = (int32_t)P.tasks.size();
@@ -563,7 +576,7 @@ static void flush_blocks(Plan& P, std::vector<OutBlockTasks>& blocks, int kind, 
         int32_t ktot = 0;
         for (auto& t : ob.tasks) {
             P.tasks.push_back(t);
-            ktot += kpad(t.k);
+            ktot += kpad(t.k, P.kstage);
             L.flops += 2.0 * ob.m * ob.n * (double)t.k;
         }
         int32_t tend = (int32_t)P.tasks.size();
@@ -589,7 +602,10 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                       const OpSet& Ro, const std::vector<Entry>& e1, const std::vector<Entry>& e2,
                       const hx_plan_opts* opts) {
     P.kind = PK_HEFF;
-    if (opts && opts->split_kseg_min > 0) P.split_kseg_min = opts->split_kseg_min;
+    {
+        int rc0 = apply_opts(P, opts);
+        if (rc0) return rc0;
+    }
     EnvLayout Ll = env_layout(lb, Lo), Rl = env_layout(rb, Ro);
     PsiLayout psi = psi_layout(lb, rb);
     P.psi_nnz = psi.nnz;
@@ -1028,7 +1044,10 @@ static int build_heff_vjp(Plan& P, const Bond& lb, const Bond& rb, const OpSet& 
                           const OpSet& Ro, const std::vector<Entry>& e1, const std::vector<Entry>& e2,
                           const hx_plan_opts* opts) {
     P.kind = PK_HEFF_VJP;
-    if (opts && opts->split_kseg_min > 0) P.split_kseg_min = opts->split_kseg_min;
+    {
+        int rc0 = apply_opts(P, opts);
+        if (rc0) return rc0;
+    }
     EnvLayout Ll = env_layout(lb, Lo), Rl = env_layout(rb, Ro);
     PsiLayout psi = psi_layout(lb, rb);
     P.psi_nnz = psi.nnz;
@@ -1446,7 +1465,10 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
     // dir 0: bin = bond k (lb), bout = bond k+1; site tensor between bin and bout.
     // dir 1: bin = bond k+1 (rb), bout = bond k; site tensor between bout and bin.
     P.kind = dir == 0 ? PK_ENV_LEFT : PK_ENV_RIGHT;
-    if (opts && opts->split_kseg_min > 0) P.split_kseg_min = opts->split_kseg_min;
+    {
+        int rc0 = apply_opts(P, opts);
+        if (rc0) return rc0;
+    }
     EnvLayout Lin = env_layout(bin, oin), Lout = env_layout(bout, oout);
     SiteLayout S = dir == 0 ? site_layout(bin, bout) : site_layout(bout, bin);
     P.in_nnz = Lin.op_off.back();
@@ -1645,10 +1667,16 @@ static void finalize_tables(Plan& P) {
 static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
     M.kind = PK_HEFF;
     M.n_chunks = 1;
+    M.variant = in.empty() ? 0 : in[0]->variant;
+    M.kstage = in.empty() ? 16 : in[0]->kstage;
     std::vector<std::array<int64_t, SP_N>> off(in.size());
     int64_t o_psi = 0, o_L = 0, o_R = 0, o_ws = 0, o_tab = 0;
     for (size_t i = 0; i < in.size(); ++i) {
         const Plan& P = *in[i];
+        if (P.variant != M.variant) {
+            set_error("plan_batch: instances use different kernel variants");
+            return HX_EUNSUP;
+        }
         if (P.kind != PK_HEFF || P.n_chunks != 1) {
             set_error("plan_batch: every instance must be a single-chunk sigma-vector plan "
                       "(raise t_budget_bytes)");

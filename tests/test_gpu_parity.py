@@ -58,12 +58,12 @@ def _close(got, ref, rtol=RTOL):
         assert err <= rtol * scale, (k, err, scale)
 
 
-def _run_heff(device, lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi, budget=0, diag=False, kseg=0):
+def _run_heff(device, lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi, budget=0, diag=False, kseg=0, variant=0):
     import torch
     from paper_2310_03920_amd import _lib as X
     lbB, rbB = X.Bond(lb), X.Bond(rb)
     plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, t_budget_bytes=budget,
-                      split_kseg_min=kseg).upload(device)
+                      split_kseg_min=kseg, kernel_variant=variant).upload(device)
     Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
     Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
     pt = torch.from_numpy(X.pack_psi(lbB, rbB, psi)).to(device)
@@ -102,6 +102,18 @@ def test_heff_apply_split_k(device, kseg):
     prob = _problem(6, True)
     res = _run_heff(device, *prob, kseg=kseg, budget=512 * 1024)
     _close(res["sigma"], _dense_sigma(*prob))
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+def test_heff_apply_kernel_variants(device, variant):
+    """One-buffer and 8-deep pipelines: same results as the oracle, incl. split-K and diag."""
+    print(f"[heff_apply variant] {variant}", flush=True)
+    lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = prob = _problem(2, True)
+    res = _run_heff(device, *prob, kseg=16, variant=variant, diag=True)
+    _close(res["sigma"], _dense_sigma(*prob))
+    d = contract.heff_diag(contract.dense_env(L, lb), contract.dense_mpo(W1, len(Ldq), len(Mdq)),
+                           contract.dense_mpo(W2, len(Mdq), len(Rdq)), contract.dense_env(R, rb))
+    _close(res["diag"], mps.two_site_blocks_from_dense(d, lb, rb, two_site_blocks(lb, rb)))
 
 
 def test_heff_diag_random_operands(device):

@@ -211,3 +211,33 @@ def test_vjp_plan_builds_for_every_site_of_the_nc_mpo():
         v = X.HeffVjpPlan(*args)
         assert v.info.psi_nnz == f.info.psi_nnz and v.info.in_nnz == f.info.in_nnz
         assert v.info.flops_apply > 2.0 * f.info.flops_apply
+
+
+def test_autotune_coordinate_search_finds_separable_minimum():
+    from paper_2310_03920_amd import autotune as A
+    cost = {"kernel_variant": {0: 3.0, 1: 1.0, 2: 2.0}, "split_kseg_min": {1024: 0.5, 2048: 0.7, 4096: 0.9},
+            "t_budget_bytes": {1 << 29: 0.3, 1 << 30: 0.2, 1 << 31: 0.1}}
+    calls = []
+
+    def timer(o):
+        calls.append(o)
+        if o["kernel_variant"] == 2:
+            return None  # a rejected candidate never wins
+        return sum(cost[k][v] for k, v in o.items())
+
+    best, seen = A.coordinate_search(timer)
+    assert best == {"kernel_variant": 1, "split_kseg_min": 1024, "t_budget_bytes": 1 << 31}
+    assert len(calls) == len(seen) == 7  # start + 2 per axis, no repeats
+
+
+def test_autotune_signature_depends_on_shape():
+    from paper_2310_03920_amd import autotune as A
+    K = 8
+    m = M.build_nc_mpo(*make_integrals(K, seed=0))
+    b = bond_sector_tables(K, K, 0, 32)
+    w = [X.MpoSite.from_entries(M.site_entries(m, i)) for i in (3, 4)]
+    s1 = A.signature(b[3], b[5], m.dq[3], m.dq[4], m.dq[5], *w)
+    s2 = A.signature(b[3], b[5], m.dq[3], m.dq[4], m.dq[5], *w)
+    b2 = bond_sector_tables(K, K, 0, 40)
+    s3 = A.signature(b2[3], b2[5], m.dq[3], m.dq[4], m.dq[5], *w)
+    assert s1 == s2 != s3
