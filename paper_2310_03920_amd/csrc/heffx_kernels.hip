@@ -50,41 +50,61 @@ constexpr int NSP_FWD = SP_PART + 1;
 // exactly one task and the walk is uniform across the workgroup (scalar
 // registers, one lookup per stage).
 
-template <typename T>
-struct Stage {
-    const T* a;   // A at the tile origin and the stage's first k
-    const T* b;
-    int lda, ldb;
-    int krem;          // valid k in this stage (0..16)
-    double alpha;
-};
-
+// Uniform task cursor of a tile.  The current task's operand bases are kept in
+// scalar registers and the next task's descriptor is fetched one task ahead, so
+// a K stage inside a task issues no scalar memory load before its vector loads.
 template <typename T, bool TA, bool TB, int NSP, int KSV>
-__device__ __forceinline__ Stage<T> next_stage(int& j, int& kl, int tend, const Task* __restrict__ tasks,
-                                               const BasesT<T>& B, int r0, int c0) {
-    Stage<T> q;
-    while (j < tend && kl >= tasks[j].k) {
-        ++j;
+struct Cursor {
+    int j, tend, kl;
+    int lda, ldb, k;
+    T alpha;
+    const T* a;  // A at the tile origin, first k of the task
+    const T* b;
+    Task nxt;
+
+    __device__ __forceinline__ void bind(const Task& t, const BasesT<T>& B, int r0, int c0) {
+        lda = t.lda;
+        ldb = t.ldb;
+        k = t.k;
+        alpha = (T)t.alpha;
+        a = space_ptr<T, NSP>(B, t.spaces & 0xff) + t.aoff + (TA ? (int64_t)r0 : (int64_t)r0 * t.lda);
+        b = space_ptr<T, NSP>(B, (t.spaces >> 8) & 0xff) + t.boff + (TB ? (int64_t)c0 * t.ldb : (int64_t)c0);
+    }
+
+    __device__ __forceinline__ void start(int tbeg, int tend_, const Task* __restrict__ tasks, const BasesT<T>& B,
+                                          int r0, int c0) {
+        j = tbeg;
+        tend = tend_;
         kl = 0;
+        k = 0;
+        if (j < tend) bind(tasks[j], B, r0, c0);
+        if (j + 1 < tend) nxt = tasks[j + 1];
     }
-    if (j >= tend) {
-        q.a = q.b = nullptr;
-        q.lda = q.ldb = 0;
-        q.krem = 0;
-        q.alpha = 0.0;
-        return q;
+
+    // Position of the next K stage: operand pointers at its first k, valid depth krem.
+    __device__ __forceinline__ void next(const Task* __restrict__ tasks, const BasesT<T>& B, int r0, int c0,
+                                         const T*& pa, const T*& pb, int& krem, T& al) {
+        while (j < tend && kl >= k) {
+            ++j;
+            kl = 0;
+            if (j < tend) {
+                bind(nxt, B, r0, c0);
+                if (j + 1 < tend) nxt = tasks[j + 1];
+            }
+        }
+        if (j >= tend) {
+            pa = pb = nullptr;
+            krem = 0;
+            al = 0;
+            return;
+        }
+        pa = a + (TA ? (int64_t)kl * lda : (int64_t)kl);
+        pb = b + (TB ? (int64_t)kl : (int64_t)kl * ldb);
+        krem = min(KSV, k - kl);
+        al = alpha;
+        kl += KSV;
     }
-    const Task& t = tasks[j];
-    q.lda = t.lda;
-    q.ldb = t.ldb;
-    q.alpha = t.alpha;
-    q.krem = min(KSV, t.k - kl);
-    const int sp = t.spaces;
-    q.a = space_ptr<T, NSP>(B, sp & 0xff) + t.aoff + (TA ? (int64_t)kl * t.lda + r0 : (int64_t)r0 * t.lda + kl);
-    q.b = space_ptr<T, NSP>(B, (sp >> 8) & 0xff) + t.boff + (TB ? (int64_t)c0 * t.ldb + kl : (int64_t)kl * t.ldb + c0);
-    kl += KSV;
-    return q;
-}
+};
 
 constexpr int LDS_PAD = 1;
 constexpr int LDW = TM + LDS_PAD;
@@ -123,7 +143,8 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     const int b_k = TB ? (tid % KSV) : (tid >> 6);
     constexpr int a_dr = TA ? 0 : 256 / KSV, a_dk = TA ? 4 : 0;  // step per element e
     constexpr int b_dc = TB ? 256 / KSV : 0, b_dk = TB ? 0 : 4;
-    int cj = tl.tbeg, ckl = 0;  // uniform cursor
+    Cursor<T, TA, TB, NSP, KSV> cur;
+    cur.start(tl.tbeg, tl.tend, tasks, B, tl.r0, tl.c0);
 
     acc_t acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
     T ra[NE], rb[NE];
@@ -133,15 +154,17 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     // raw loads; alpha is applied at the LDS store so the loads stay in flight
     // across the MFMA work of the current stage
     auto load_stage = [&]() {
-        const Stage<T> q = next_stage<T, TA, TB, NSP, KSV>(cj, ckl, tl.tend, tasks, B, tl.r0, tl.c0);
-        alpha = (T)q.alpha;
+        const T *qa, *qb;
+        int krem;
+        cur.next(tasks, B, tl.r0, tl.c0, qa, qb, krem, alpha);
+        const int lda = cur.lda, ldb = cur.ldb;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
             const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
             T va = 0, vb = 0;
-            if (ka < q.krem && r < m) va = TA ? q.a[(int64_t)ka * q.lda + r] : q.a[(int64_t)r * q.lda + ka];
-            if (kb < q.krem && c < n) vb = TB ? q.b[(int64_t)c * q.ldb + kb] : q.b[(int64_t)kb * q.ldb + c];
+            if (ka < krem && r < m) va = TA ? qa[(int64_t)ka * lda + r] : qa[(int64_t)r * lda + ka];
+            if (kb < krem && c < n) vb = TB ? qb[(int64_t)c * ldb + kb] : qb[(int64_t)kb * ldb + c];
             ra[e] = va;
             rb[e] = vb;
         }
