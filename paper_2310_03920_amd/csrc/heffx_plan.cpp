@@ -472,11 +472,63 @@ static void split_launch(Plan& P, Launch& L) {
     P.part_tiles = std::max(P.part_tiles, pidx);
 }
 
-// Sort a launch's tiles by decreasing work (longest-processing-time first).
+// Order a launch's tiles for the 8 XCDs (workgroup i runs on XCD i mod 8, each XCD
+// with its own L2).  Tiles of one output block share their task list and thus
+// their operand blocks, so they form a group kept on one XCD, consecutive in its
+// dispatch order.  Groups are taken by decreasing work (longest first) and each
+// goes to the XCD queue holding the fewest tiles; the queues are then interleaved.
 static void sort_tiles(Plan& P, int64_t t0) {
-    std::stable_sort(P.tiles.begin() + t0, P.tiles.end(), [](const Tile& a, const Tile& b) {
-        return (int64_t)a.ktot * a.m * a.n > (int64_t)b.ktot * b.m * b.n;
-    });
+    constexpr int NXCD = 8;
+    const int64_t n = (int64_t)P.tiles.size() - t0;
+    if (n <= 1) return;
+    struct Group {
+        int64_t first, count;
+        double work;
+    };
+    std::vector<Group> groups;
+    std::map<std::pair<int32_t, int32_t>, size_t> gid;
+    std::vector<size_t> tile_group(n);
+    for (int64_t t = 0; t < n; ++t) {
+        const Tile& tl = P.tiles[t0 + t];
+        auto key = std::make_pair(tl.tbeg, tl.tend);
+        auto it = gid.find(key);
+        size_t g;
+        if (it == gid.end() || tl.tbeg == tl.tend) {  // empty task lists are independent tiles
+            g = groups.size();
+            if (tl.tbeg != tl.tend) gid[key] = g;
+            groups.push_back({t, 0, 0.0});
+        } else {
+            g = it->second;
+        }
+        tile_group[t] = g;
+        groups[g].count++;
+        groups[g].work += (double)tl.ktot * tl.m * tl.n;
+    }
+    std::vector<std::vector<int64_t>> members(groups.size());
+    for (int64_t t = 0; t < n; ++t) members[tile_group[t]].push_back(t);
+    std::vector<size_t> order(groups.size());
+    for (size_t g = 0; g < order.size(); ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return groups[a].work > groups[b].work; });
+    std::vector<std::vector<int64_t>> queue(NXCD);
+    for (size_t g : order) {
+        int q = 0;
+        for (int x = 1; x < NXCD; ++x)
+            if (queue[x].size() < queue[q].size()) q = x;
+        for (int64_t t : members[g]) queue[q].push_back(t);
+    }
+    std::vector<Tile> out;
+    out.reserve(n);
+    std::vector<size_t> pos(NXCD, 0);
+    for (bool more = true; more;) {
+        more = false;
+        for (int x = 0; x < NXCD; ++x)
+            if (pos[x] < queue[x].size()) {
+                out.push_back(P.tiles[t0 + queue[x][pos[x]++]]);
+                more = true;
+            }
+    }
+    std::copy(out.begin(), out.end(), P.tiles.begin() + t0);
 }
 
 // Emit the mixing GEMMs of a mixer: rows of a class in slabs of TM.
