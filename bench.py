@@ -34,6 +34,8 @@ sys.path.insert(0, ROOT)
 METRIC = "H_eff·ψ GFLOP/s & %MFMA peak at M=1000; Davidson energy err vs FP64 oracle"
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_BF16_TFLOPS = 2500.0
+PEAKS = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFLOPS}
 
 
 def log(*a):
@@ -168,17 +170,29 @@ def bench_batch(args):
         axes = [a for a in autotune.AXES[:2] if not (a[0] == "kernel_variant" and args.variant is not None)
                 and not (a[0] == "split_kseg_min" and args.kseg)]
 
+        if args.mode == "bf16":  # BF16 products need 16-deep stages
+            axes = [(k, tuple(v for v in vals if v != 2)) if k == "kernel_variant" else (k, vals)
+                    for k, vals in axes]
+        Pt32, St32 = Pc.float(), torch.empty_like(Pc, dtype=torch.float32)
+
         def build(o):
             b = X.BatchPlan(make_plans(o)).upload(device)
             b.prepare(Lc, Rc)
+            if args.mode != "f64":
+                b.lower_f32(Lc, Rc)
             return b
 
         def run(b):
-            b.apply(Lc, Rc, Pc, Sc)
-            return Sc
+            # tuned on the sigma-vector of the benchmarked precision
+            if args.mode == "f64":
+                b.apply(Lc, Rc, Pc, Sc)
+                return Sc
+            (b.apply_bf16 if args.mode == "bf16" else b.apply_f32)(Pt32, St32)
+            return St32
 
         t1 = time.time()
-        opts, timings = autotune.tune(build, run, axes=axes, reps=3, start=opts)
+        opts, timings = autotune.tune(build, run, axes=axes, reps=3, start=opts,
+                                      rtol={"f64": 1e-11, "f32": 1e-4, "bf16": 1e-2}[args.mode])
         tune_s = time.time() - t1
         log(f"autotune in {tune_s:.1f}s: {opts} "
             f"({', '.join(f'{k}: {1e3 * v:.2f} ms' for k, v in timings.items() if v is not None)})")
@@ -187,7 +201,8 @@ def bench_batch(args):
     for p in plans:
         p.upload(device)
     log(f"batch {B.info.flops_apply / 1e9:.2f} GFLOP/apply, tiles {B.info.n_tiles}, ws {B.info.ws_bytes / 1e9:.2f} GB")
-    f32 = args.mode == "f32"
+    f32 = args.mode != "f64"
+    bf = args.mode == "bf16"
     for p, L, R in zip(plans, Ls, Rs):
         p.prepare(L, R)
         if f32:
@@ -198,14 +213,14 @@ def bench_batch(args):
         P32 = [x.float() for x in Ps]
         S32 = [torch.empty_like(x) for x in P32]
         Pc32, Sc32 = Pc.float(), torch.empty_like(Pc, dtype=torch.float32)
-        graph = X.Graph(B, X.GRAPH_APPLY_F32, B.L32, B.R32, B.ws32, Pc32, Sc32)
+        graph = X.Graph(B, X.GRAPH_APPLY_BF16 if bf else X.GRAPH_APPLY_F32, B.L32, B.R32, B.ws32, Pc32, Sc32)
 
         def one_by_one():
             for p, x, y in zip(plans, P32, S32):
-                p.apply_f32(x, y)
+                (p.apply_bf16 if bf else p.apply_f32)(x, y)
 
         def batched():
-            B.apply_f32(Pc32, Sc32)
+            (B.apply_bf16 if bf else B.apply_f32)(Pc32, Sc32)
     else:
         graph = X.Graph(B, X.GRAPH_APPLY, Lc, Rc, B.ws, Pc, Sc)
 
@@ -245,7 +260,7 @@ def bench_batch(args):
     t_bat, w_bat = timed(batched, reps)
     t_gr, w_gr = timed(graph.launch, reps)
     fl = B.info.flops_apply
-    peak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
+    peak = PEAKS[args.mode]
     achieved = fl / t_gr / 1e12
     out = {
         "metric": METRIC,
@@ -296,18 +311,28 @@ def plan_options(args, X, mpo, bonds, i, Lenv, Renv, tb, device):
     W1 = X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats)
     W2 = X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats)
     sig = torch.empty_like(psi)
+    psi32, sig32 = psi.float(), torch.empty_like(psi, dtype=torch.float32)
+    if args.mode == "bf16":  # BF16 products need 16-deep stages
+        axes = [(k, tuple(v for v in vals if v != 2)) if k == "kernel_variant" else (k, vals) for k, vals in axes]
 
     def build(o):
         p = X.HeffPlan(lb, rb, mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2], W1, W2, **o).upload(device)
         p.prepare(Lenv, Renv)
+        if args.mode != "f64":
+            p.lower_f32(Lenv, Renv)
         return p
 
     def run(p):
-        p.apply(Lenv, Renv, psi, sig)
-        return sig
+        # tuned on the sigma-vector of the benchmarked precision
+        if args.mode == "f64":
+            p.apply(Lenv, Renv, psi, sig)
+            return sig
+        (p.apply_bf16 if args.mode == "bf16" else p.apply_f32)(psi32, sig32)
+        return sig32
 
     t0 = time.time()
-    best, timings = autotune.tune(build, run, axes=axes, reps=2, start=opts)
+    best, timings = autotune.tune(build, run, axes=axes, reps=2, start=opts,
+                                  rtol={"f64": 1e-11, "f32": 1e-4, "bf16": 1e-2}[args.mode])
     log(f"autotune in {time.time() - t0:.1f}s: {best} "
         f"({', '.join(f'{k}: {1e3 * v:.1f} ms' for k, v in timings.items() if v is not None)})")
     torch.cuda.empty_cache()
@@ -326,14 +351,15 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
     psi = torch.from_numpy(X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2], np.random.default_rng(3)))).to(device)
     sig = torch.empty_like(psi)
     plan.prepare(Lenv, Renv)
-    f32 = args.mode == "f32"
+    f32 = args.mode != "f64"
     if f32:
         plan.lower_f32(Lenv, Renv)
         psi32, sig32 = psi.float(), torch.empty_like(psi, dtype=torch.float32)
+        low = plan.apply_bf16 if args.mode == "bf16" else plan.apply_f32
 
     def one():
         if f32:
-            plan.apply_f32(psi32, sig32)
+            low(psi32, sig32)
         else:
             plan.apply(Lenv, Renv, psi, sig)
 
@@ -350,7 +376,7 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
         ms.append(s.elapsed_time(e))
     info = plan.info
     avg = float(np.mean(ms)) / 1e3
-    peak = PEAK_FP32_TFLOPS if f32 else PEAK_FP64_TFLOPS
+    peak = PEAKS[args.mode]
     achieved = info.flops_apply / avg / 1e12
     src = torch.ones(1 << 26, dtype=torch.float64, device=device)
     dst = torch.empty_like(src)
@@ -381,8 +407,8 @@ def main():
     ap.add_argument("--pre-iter", type=int, default=100)
     ap.add_argument("--t-budget-gb", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["f64", "f32"], default="f64",
-                    help="precision of the block contractions; Davidson is FP64 in both")
+    ap.add_argument("--mode", choices=["f64", "f32", "bf16"], default="f64",
+                    help="precision of the block contractions; Davidson is FP64 in all")
     ap.add_argument("--workload", choices=["middle", "batch", "apply"], default="middle",
                     help="middle: one DMRG step at the chain's middle; batch: many small sigma-vectors; "
                          "apply: sigma-vectors only at the middle step (profiling), ending with a 512 MiB "
@@ -408,7 +434,7 @@ def main():
 
     import torch
     from paper_2310_03920_amd import _lib as X
-    from paper_2310_03920_amd.dmrg import Davidson, split
+    from paper_2310_03920_amd.dmrg import PRECISIONS, Davidson, split
     from paper_2310_03920_amd.engine import site_payload
     from paper_2310_03920_amd.mpo import build_nc_mpo
     from synth import (bond_sector_tables, make_integrals, random_left_canonical_mps,
@@ -468,11 +494,13 @@ def main():
         e.record()
         ev.append((s, e))
 
+    low_apply = plan.apply_bf16 if args.mode == "bf16" else plan.apply_f32
+
     def mv32(v, out):
         X.convert_f64_f32(v, v32)
         s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         s.record()
-        plan.apply_f32(v32, s32)
+        low_apply(v32, s32)
         e.record()
         ev32.append((s, e))
         X.convert_f32_f64(s32, out)
@@ -482,9 +510,10 @@ def main():
     def site_step():
         plan.prepare(Lenv, Renv)
         plan.diag(Lenv, Renv, diag)
-        if args.mode == "f32":
+        if args.mode != "f64":
             plan.lower_f32(Lenv, Renv)
-            theta, rnorm, n32, n64 = dav.solve_mixed(mv32, mv, psi0, diag, tol=args.tol, max_iter=args.max_iter)
+            theta, rnorm, n32, n64 = dav.solve_mixed(mv32, mv, psi0, diag, tol=args.tol, max_iter=args.max_iter,
+                                                     **PRECISIONS[args.mode])
             counts["f32"] += n32
             counts["f64"] += n64
             nmv = n32 + n64
@@ -521,7 +550,7 @@ def main():
         res.append(site_step())
         torch.cuda.synchronize()
         times.append(time.perf_counter() - ts)
-    main_ev = ev32 if args.mode == "f32" else ev
+    main_ev = ev32 if args.mode != "f64" else ev
     apply_ms = [s.elapsed_time(e) for s, e in main_ev]
     nmv = sum(r[2] for r in res)
     step_flops = [info.flops_prepare + r[2] * info.flops_apply + einfo.flops_apply for r in res]
@@ -529,7 +558,7 @@ def main():
     value = sum(step_flops) / total_t / 1e9
     avg_apply = float(np.mean(apply_ms)) / 1e3
     achieved = info.flops_apply / avg_apply / 1e12
-    peak = PEAK_FP32_TFLOPS if args.mode == "f32" else PEAK_FP64_TFLOPS
+    peak = PEAKS[args.mode]
     theta, rnorm = res[-1][0], res[-1][1]
     out = {
         "metric": METRIC,
@@ -564,7 +593,9 @@ def main():
         "energy_err_vs_fp64": abs(theta - e_ref),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None,
-                     "kernel": ("bsgemm<float> (all launches of one hx_heff_apply_f32)" if args.mode == "f32"
+                     "kernel": ({"f32": "bsgemm<float> (all launches of one hx_heff_apply_f32)",
+                                 "bf16": "bsgemm<float, BF16 products> (all launches of one hx_heff_apply_bf16)"
+                                 }[args.mode] if args.mode != "f64"
                                 else "bsgemm<double> (all launches of one hx_heff_apply)")},
     }
     if not args.no_cpu_baseline:

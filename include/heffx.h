@@ -233,6 +233,7 @@ typedef struct hx_graph hx_graph;
 #define HX_GRAPH_APPLY 1          /* hx_heff_apply (FP64 pointers) */
 #define HX_GRAPH_PREPARE_APPLY 2  /* hx_heff_prepare then hx_heff_apply (FP64 pointers) */
 #define HX_GRAPH_APPLY_F32 3      /* hx_heff_apply_f32 (L32, R32, ws32, psi32, sigma32) */
+#define HX_GRAPH_APPLY_BF16 4     /* hx_heff_apply_bf16 (same operands as HX_GRAPH_APPLY_F32) */
 
 /* Capture the launch sequence `what` of an uploaded sigma-vector plan (single
  * or batched) with these operand pointers into an executable HIP graph, so one
@@ -266,6 +267,16 @@ int hx_heff_lower_f32(const hx_plan* plan, const double* L, const double* R, con
  * ws32 must hold the result of hx_heff_lower_f32. */
 int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
                       float* sigma32, hx_stream stream);
+
+/* sigma32 = H_eff psi32 with the block products in BF16 on the matrix cores
+ * (v_mfma_f32_16x16x16_bf16, FP32 accumulation): operands are read in FP32 from
+ * the same buffers as hx_heff_apply_f32 and rounded to BF16 (nearest even) when
+ * staged, the stage-1 intermediate is kept in FP32 between the two rounds.
+ * Relative operand precision 2^-9, so sigma carries ~1e-3 relative error; the
+ * Davidson work stays FP64 (mixed-precision mode).  Needs kernel_variant 0 or 1
+ * (HX_EUNSUP for 2). */
+int hx_heff_apply_bf16(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
+                       float* sigma32, hx_stream stream);
 
 /* ---- Davidson (Davidson 1975; the eigensolver of the sweep) ----------------- */
 

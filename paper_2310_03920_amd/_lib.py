@@ -23,7 +23,7 @@ EXPORTED = (
     "hx_heff_diag", "hx_env_update", "hx_davidson_ws_bytes", "hx_davidson_step", "hx_dots",
     "hx_normalize", "hx_convert_f64_f32", "hx_convert_f32_f64", "hx_heff_lower_f32", "hx_heff_apply_f32",
     "hx_heff_plan_batch", "hx_batch_offsets", "hx_heff_graph_create", "hx_graph_launch", "hx_graph_destroy",
-    "hx_heff_vjp_plan_create", "hx_heff_apply_backward", "hx_last_error",
+    "hx_heff_vjp_plan_create", "hx_heff_apply_backward", "hx_heff_apply_bf16", "hx_last_error",
 )
 
 
@@ -93,6 +93,7 @@ def lib():
     L.hx_convert_f32_f64.argtypes = [c_int64, c_void_p, c_void_p, c_void_p]
     L.hx_heff_lower_f32.argtypes = [c_void_p] + [c_void_p] * 7
     L.hx_heff_apply_f32.argtypes = [c_void_p] + [c_void_p] * 6
+    L.hx_heff_apply_bf16.argtypes = [c_void_p] + [c_void_p] * 6
     L.hx_heff_plan_batch.argtypes = [P(c_void_p), c_int32, P(c_void_p)]
     L.hx_batch_offsets.argtypes = [c_void_p, c_int32, P(c_int64), P(c_int64), P(c_int64)]
     L.hx_heff_vjp_plan_create.argtypes = L.hx_heff_plan_create.argtypes
@@ -356,6 +357,11 @@ class HeffPlan(Plan):
         check(lib().hx_heff_apply_f32(self.h, _ptr(self.L32), _ptr(self.R32), _ptr(self.ws32), _ptr(psi32),
                                       _ptr(sigma32), _stream()), "heff_apply_f32")
 
+    def apply_bf16(self, psi32, sigma32):
+        """BF16 block products on the FP32 operands of lower_f32."""
+        check(lib().hx_heff_apply_bf16(self.h, _ptr(self.L32), _ptr(self.R32), _ptr(self.ws32), _ptr(psi32),
+                                       _ptr(sigma32), _stream()), "heff_apply_bf16")
+
 
 class HeffVjpPlan(Plan):
     """Plan of the vector-Jacobian products of sigma = H_eff psi."""
@@ -385,7 +391,7 @@ class HeffVjpPlan(Plan):
               "heff_apply_backward")
 
 
-GRAPH_APPLY, GRAPH_PREPARE_APPLY, GRAPH_APPLY_F32 = 1, 2, 3
+GRAPH_APPLY, GRAPH_PREPARE_APPLY, GRAPH_APPLY_F32, GRAPH_APPLY_BF16 = 1, 2, 3, 4
 
 
 class Graph:

@@ -25,6 +25,14 @@ using namespace hx;
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16 with round-to-nearest-even on the bit pattern (finite inputs).
+__device__ __forceinline__ unsigned short to_bf16(float x) {
+    unsigned int u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
 
 template <typename T>
 struct BasesT {
@@ -113,14 +121,21 @@ constexpr int LDW = TM + LDS_PAD;
 // FP32 accumulation).  The tile tables are the same for both.
 // KSV: K-stage depth (16 or 8); NBUF: LDS buffers (2: the next stage is stored
 // while the current one is read; 1: half the LDS, one more barrier per stage).
-template <typename T, bool TA, bool TB, int NSP, int KSV, int NBUF>
+// BF (T = float only): operands are rounded to BF16 at the LDS store and the
+// products run on v_mfma_f32_16x16x16_bf16 with FP32 accumulation; LDS then holds
+// each tile row's 16 k contiguously so a lane's 4 consecutive k are one 8-byte read.
+template <typename T, bool TA, bool TB, int NSP, int KSV, int NBUF, bool BF = false>
 __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
                                               BasesT<T> B) {
     using acc_t = typename std::conditional<std::is_same<T, double>::value, dbl4, flt4>::type;
     static_assert(KSV == 8 || KSV == 16, "stage depth");
+    static_assert(!BF || (std::is_same<T, float>::value && KSV == 16), "BF16 products: FP32 storage, 16-deep stages");
     constexpr int NE = KSV / 4;  // elements of A (and of B) each thread stages per K stage
-    __shared__ T As[NBUF][KSV][LDW];
-    __shared__ T Bs[NBUF][KSV][LDW];
+    constexpr int LDB = KSV + 4; // BF16 row pitch (8-byte aligned rows)
+    __shared__ T As[BF ? 1 : NBUF][BF ? 1 : KSV][BF ? 1 : LDW];
+    __shared__ T Bs[BF ? 1 : NBUF][BF ? 1 : KSV][BF ? 1 : LDW];
+    __shared__ __attribute__((aligned(16))) unsigned short Ah[BF ? NBUF : 1][BF ? TM : 1][BF ? LDB : 1];
+    __shared__ __attribute__((aligned(16))) unsigned short Bh[BF ? NBUF : 1][BF ? TN : 1][BF ? LDB : 1];
     const Tile tl = tiles[blockIdx.x];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -172,8 +187,13 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     auto store_stage = [&](int buf) {
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
-            As[buf][a_k + a_dk * e][a_r + a_dr * e] = alpha * ra[e];
-            Bs[buf][b_k + b_dk * e][b_c + b_dc * e] = rb[e];
+            if constexpr (BF) {
+                Ah[buf][a_r + a_dr * e][a_k + a_dk * e] = to_bf16(alpha * ra[e]);
+                Bh[buf][b_c + b_dc * e][b_k + b_dk * e] = to_bf16(rb[e]);
+            } else {
+                As[buf][a_k + a_dk * e][a_r + a_dr * e] = alpha * ra[e];
+                Bs[buf][b_k + b_dk * e][b_c + b_dc * e] = rb[e];
+            }
         }
     };
 
@@ -184,7 +204,21 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         for (int s = 0; s < nst; ++s) {
             const int buf = NBUF == 2 ? (s & 1) : 0;
             if (s + 1 < nst) load_stage();
-            if (any) {
+            if (BF && any) {
+                // one 16-deep product per 16 x 16 block: lane l supplies row (col) l%16,
+                // k = 4(l/16) .. 4(l/16)+3
+                const int kq = 4 * (lane >> 4), rl = lane & 15;
+                const bf16x4 a0 = *reinterpret_cast<const bf16x4*>(&Ah[buf][wr0 + rl][kq]);
+                const bf16x4 a1 = *reinterpret_cast<const bf16x4*>(&Ah[buf][wr0 + 16 + rl][kq]);
+                const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(&Bh[buf][wc0 + rl][kq]);
+                const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(&Bh[buf][wc0 + 16 + rl][kq]);
+                if constexpr (BF) {
+                    acc00 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc00, 0, 0, 0);
+                    if (c1) acc01 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc01, 0, 0, 0);
+                    if (r1) acc10 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc10, 0, 0, 0);
+                    if (r1 && c1) acc11 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc11, 0, 0, 0);
+                }
+            } else if (any) {
 #pragma unroll
                 for (int ks = 0; ks < KSV / 4; ++ks) {
                     const int kr = ks * 4 + (lane >> 4);
@@ -218,7 +252,8 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         }
     }
     // epilogue (lane layouts measured on gfx950): v_mfma_f64_16x16x4_f64 gives lane l
-    // rows l/16 + 4v of column l%16; v_mfma_f32_16x16x4_f32 rows 4(l/16) + v.
+    // rows l/16 + 4v of column l%16; v_mfma_f32_16x16x4_f32 and
+    // v_mfma_f32_16x16x16_bf16 rows 4(l/16) + v.
     T* C = space_ptr<T, NSP>(B, tl.flags & 0xff) + tl.coff;
     const int ldc = tl.ldc;
     const bool beta = ((tl.flags >> 8) & 0xff) != 0;
@@ -499,19 +534,19 @@ static Bases make_bases(const Plan* P, const double* psi, double* out, const dou
     return b;
 }
 
-template <typename T, int NSP, int KSV, int NBUF>
+template <typename T, int NSP, int KSV, int NBUF, bool BF = false>
 static int launch_kind(int kind, dim3 grid, const Tile* tiles, const Task* tasks, const BasesT<T>& B,
                        hipStream_t s) {
     const dim3 block(256);
     switch (kind) {
         case NN:
-            hipLaunchKernelGGL((bsgemm<T, false, false, NSP, KSV, NBUF>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, false, false, NSP, KSV, NBUF, BF>), grid, block, 0, s, tiles, tasks, B);
             return HX_OK;
         case NT:
-            hipLaunchKernelGGL((bsgemm<T, false, true, NSP, KSV, NBUF>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, false, true, NSP, KSV, NBUF, BF>), grid, block, 0, s, tiles, tasks, B);
             return HX_OK;
         case TN_:
-            hipLaunchKernelGGL((bsgemm<T, true, false, NSP, KSV, NBUF>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, true, false, NSP, KSV, NBUF, BF>), grid, block, 0, s, tiles, tasks, B);
             return HX_OK;
         default:
             set_error("internal: bad GEMM kind");
@@ -519,13 +554,33 @@ static int launch_kind(int kind, dim3 grid, const Tile* tiles, const Task* tasks
     }
 }
 
-template <typename T, int NSP = NSP_FWD>
+// Launch check, then the split-K reduction of the launch (if any).
+template <typename T>
+static int finish_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipStream_t s) {
+    int rc = hip_check(hipGetLastError(), "bsgemm launch");
+    if (rc || L.nred <= 0) return rc;
+    const Reduce* red = reinterpret_cast<const Reduce*>(static_cast<const char*>(P->dev) + P->off_reduces) + L.red0;
+    hipLaunchKernelGGL((reduce_partials<T>), dim3((unsigned)L.nred), dim3(256), 0, s, red, B);
+    return hip_check(hipGetLastError(), "reduce launch");
+}
+
+template <typename T, int NSP = NSP_FWD, bool BF = false>
 static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipStream_t s) {
     if (L.ntile <= 0) return HX_OK;
     const Tile* tiles = reinterpret_cast<const Tile*>(static_cast<const char*>(P->dev) + P->off_tiles) + L.tile0;
     const Task* tasks = reinterpret_cast<const Task*>(static_cast<const char*>(P->dev) + P->off_tasks);
     dim3 grid((unsigned)L.ntile);
     int rk;
+    if constexpr (BF) {
+        if (P->variant == 2) {
+            set_error("BF16 products need a 16-deep kernel variant (0 or 1)");
+            return HX_EUNSUP;
+        }
+        rk = P->variant == 1 ? launch_kind<T, NSP, 16, 1, true>(L.kind, grid, tiles, tasks, B, s)
+                             : launch_kind<T, NSP, 16, 2, true>(L.kind, grid, tiles, tasks, B, s);
+        if (rk) return rk;
+        return finish_gemm(P, L, B, s);
+    }
     switch (P->variant) {
         case 1:
             rk = launch_kind<T, NSP, 16, 1>(L.kind, grid, tiles, tasks, B, s);
@@ -538,11 +593,7 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
             break;
     }
     if (rk) return rk;
-    int rc = hip_check(hipGetLastError(), "bsgemm launch");
-    if (rc || L.nred <= 0) return rc;
-    const Reduce* red = reinterpret_cast<const Reduce*>(static_cast<const char*>(P->dev) + P->off_reduces) + L.red0;
-    hipLaunchKernelGGL((reduce_partials<T>), dim3((unsigned)L.nred), dim3(256), 0, s, red, B);
-    return hip_check(hipGetLastError(), "reduce launch");
+    return finish_gemm(P, L, B, s);
 }
 
 static inline hipStream_t s_of(hx_stream st) { return static_cast<hipStream_t>(st); }
@@ -682,17 +733,20 @@ int hx_heff_lower_f32(const hx_plan* plan, const double* L, const double* R, con
     return HX_OK;
 }
 
-int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
-                      float* sigma32, hx_stream stream) {
+extern "C++" {
+template <bool BF>
+static int apply_lowered(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
+                         float* sigma32, hx_stream stream) {
+    const char* what = BF ? "heff_apply_bf16" : "heff_apply_f32";
     int rc = check_ready(plan, PK_HEFF);
     if (rc) return rc;
     const Plan* P = reinterpret_cast<const Plan*>(plan);
     if (!psi32 || !sigma32 || (P->in_nnz && !L32) || (P->in2_nnz && !R32) || (P->ws_doubles && !ws32)) {
-        set_error("heff_apply_f32: null operand");
+        set_error(std::string(what) + ": null operand");
         return HX_EINVAL;
     }
     if (psi32 == sigma32) {
-        set_error("heff_apply_f32: psi and sigma must not alias");
+        set_error(std::string(what) + ": psi and sigma must not alias");
         return HX_EINVAL;
     }
     BasesT<float> B{};
@@ -704,8 +758,19 @@ int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, v
     B.p[SP_TAB] = nullptr;  // mixing (the only user of the coefficient table) runs in FP64
     B.p[SP_PART] = ws32 ? static_cast<float*>(ws32) + P->part_base : nullptr;
     for (const Launch& l : P->apply)
-        if ((rc = launch_gemm(P, l, B, s_of(stream)))) return rc;
+        if ((rc = launch_gemm<float, NSP_FWD, BF>(P, l, B, s_of(stream)))) return rc;
     return HX_OK;
+}
+}  // extern "C++"
+
+int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
+                      float* sigma32, hx_stream stream) {
+    return apply_lowered<false>(plan, L32, R32, ws32, psi32, sigma32, stream);
+}
+
+int hx_heff_apply_bf16(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
+                       float* sigma32, hx_stream stream) {
+    return apply_lowered<true>(plan, L32, R32, ws32, psi32, sigma32, stream);
 }
 
 int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws, double* diag, hx_stream stream) {
@@ -883,7 +948,8 @@ int hx_heff_graph_create(const hx_plan* plan, int32_t what, const void* L, const
         return HX_EINVAL;
     }
     *out = nullptr;
-    if (what != HX_GRAPH_APPLY && what != HX_GRAPH_PREPARE_APPLY && what != HX_GRAPH_APPLY_F32) {
+    if (what != HX_GRAPH_APPLY && what != HX_GRAPH_PREPARE_APPLY && what != HX_GRAPH_APPLY_F32 &&
+        what != HX_GRAPH_APPLY_BF16) {
         set_error("graph_create: unknown sequence");
         return HX_EINVAL;
     }
@@ -901,6 +967,9 @@ int hx_heff_graph_create(const hx_plan* plan, int32_t what, const void* L, const
     if (rc == HX_OK && what == HX_GRAPH_APPLY_F32)
         rc = hx_heff_apply_f32(plan, static_cast<const float*>(L), static_cast<const float*>(R), ws,
                                static_cast<const float*>(psi), static_cast<float*>(sigma), hs);
+    else if (rc == HX_OK && what == HX_GRAPH_APPLY_BF16)
+        rc = hx_heff_apply_bf16(plan, static_cast<const float*>(L), static_cast<const float*>(R), ws,
+                                static_cast<const float*>(psi), static_cast<float*>(sigma), hs);
     else if (rc == HX_OK)
         rc = hx_heff_apply(plan, static_cast<const double*>(L), static_cast<const double*>(R), ws,
                            static_cast<const double*>(psi), static_cast<double*>(sigma), hs);

@@ -169,22 +169,28 @@ class Davidson:
             k += 1
         return theta, rnorm, nmv
 
-    def solve_mixed(self, mv32, mv64, psi0, diag, tol=1e-8, max_iter=30, low_tol=1e-5, guard=1e-8):
-        """FP32 sigma-vectors until |r| < low_tol (or stagnation near the FP32 rounding
-        floor), then FP64 sigma-vectors restarted from the FP32 Ritz vector until
-        |r| < tol.  Returns (theta, rnorm, n_matvec_f32, n_matvec_f64)."""
+    def solve_mixed(self, mv32, mv64, psi0, diag, tol=1e-8, max_iter=30, low_tol=1e-5, guard=1e-8, floor=1e-3):
+        """Reduced-precision sigma-vectors until |r| < low_tol (or stagnation below
+        `floor`, near the rounding floor of that precision), then FP64 sigma-vectors
+        restarted from that Ritz vector until |r| < tol.
+        Returns (theta, rnorm, n_matvec_low, n_matvec_f64)."""
         hist = []
 
         def watch(it, theta, rn):
-            # stagnation: below 1e-3 and no 2x gain over the last 6 iterations
+            # stagnation: below the floor and no 2x gain over the last 6 iterations
             hist.append(rn)
-            return rn < 1e-3 and len(hist) >= 7 and rn > 0.5 * hist[-7]
+            return rn < floor and len(hist) >= 7 and rn > 0.5 * hist[-7]
 
         _, _, n32 = self.solve(mv32, psi0, diag, tol=low_tol, max_iter=max_iter, guard=guard,
                                on_iter=watch)
         x32 = self.x.clone()
         theta, rnorm, n64 = self.solve(mv64, x32, diag, tol=tol, max_iter=max_iter, guard=guard)
         return theta, rnorm, n32, n64
+
+
+# Reduced-precision phase of the mixed Davidson per block-product precision:
+# stop at |r| < low_tol, or on stagnation below `floor` (the rounding floor).
+PRECISIONS = {"f64": {}, "f32": {"low_tol": 1e-5, "floor": 1e-3}, "bf16": {"low_tol": 3e-3, "floor": 3e-2}}
 
 
 class DMRG:
@@ -197,8 +203,8 @@ class DMRG:
         self.M = M
         self.device = device
         self.tol, self.max_iter, self.kmax = tol, max_iter, kmax
-        if precision not in ("f64", "f32"):
-            raise ValueError("precision must be 'f64' or 'f32'")
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision
         self.mpo = build_nc_mpo(h, g)
         self.bonds = bonds if bonds is not None else bond_sector_tables(self.K, n_elec, twosz, M)
@@ -229,17 +235,19 @@ class DMRG:
         def mv(v, out):
             plan.apply(L, R, v, out)
 
-        if self.precision == "f32":
+        if self.precision != "f64":
             plan.lower_f32(L, R)
             v32 = torch.empty(n, dtype=torch.float32, device=self.device)
             s32 = torch.empty(n, dtype=torch.float32, device=self.device)
+            low = plan.apply_bf16 if self.precision == "bf16" else plan.apply_f32
 
             def mv32(v, out):
                 X.convert_f64_f32(v, v32)
-                plan.apply_f32(v32, s32)
+                low(v32, s32)
                 X.convert_f32_f64(s32, out)
 
-            theta, rnorm, n32, n64 = dav.solve_mixed(mv32, mv, psi_t, diag, tol=self.tol, max_iter=self.max_iter)
+            theta, rnorm, n32, n64 = dav.solve_mixed(mv32, mv, psi_t, diag, tol=self.tol, max_iter=self.max_iter,
+                                                     **PRECISIONS[self.precision])
             nmv = n32 + n64
         else:
             theta, rnorm, nmv = dav.solve(mv, psi_t, diag, tol=self.tol, max_iter=self.max_iter)

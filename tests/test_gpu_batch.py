@@ -121,10 +121,11 @@ def test_graph_replays_match_eager(device):
     del g
 
 
-def test_graph_f32_apply_replays(device):
+@pytest.mark.parametrize("mode", ["f32", "bf16"])
+def test_graph_f32_apply_replays(device, mode):
     import torch
     from paper_2310_03920_amd import _lib as X
-    print("[graph] single-plan f32 apply", flush=True)
+    print(f"[graph] single-plan {mode} apply", flush=True)
     (prob, plan, arrs), = _instances(device, CASES[1:2])
     plan.upload(device)
     L, R, p = (torch.from_numpy(a).to(device) for a in arrs)
@@ -132,9 +133,10 @@ def test_graph_f32_apply_replays(device):
     plan.lower_f32(L, R)
     p32 = p.float()
     s_graph = torch.full_like(p32, float("nan"))
-    g = X.Graph(plan, X.GRAPH_APPLY_F32, plan.L32, plan.R32, plan.ws32, p32, s_graph)
+    what = X.GRAPH_APPLY_BF16 if mode == "bf16" else X.GRAPH_APPLY_F32
+    g = X.Graph(plan, what, plan.L32, plan.R32, plan.ws32, p32, s_graph)
     s_eager = torch.empty_like(p32)
-    plan.apply_f32(p32, s_eager)
+    (plan.apply_bf16 if mode == "bf16" else plan.apply_f32)(p32, s_eager)
     for rep in range(2):
         s_graph.fill_(float("nan"))
         g.launch()

@@ -1,4 +1,4 @@
-"""FP32 precision mode of the block contractions (Davidson stays FP64).
+"""FP32 and BF16 precision modes of the block contractions (Davidson stays FP64).
 
 Parity of the FP32 sigma-vector is unpinned except relative to FP64: each input
 is rounded once to FP32 (relative 2^-24) and the products are accumulated in
@@ -7,6 +7,12 @@ differ from the FP64 definition by at most ~2e3 * 2^-24 * sum|terms|; the test
 bound is 2e-4 of the largest reference element.  Energies are pinned: the mixed
 Davidson refines the FP32 Ritz vector with FP64 sigma-vectors, so its energy
 must equal the FP64 eigenvalue to 1e-10 Ha.
+
+BF16 products: every operand is rounded once to BF16 when staged (relative
+2^-9), T again before the second round, so a product carries at most ~4 * 2^-9
+relative error; these errors are independent between terms and add like the
+terms themselves, so an element lands within a few 2^-7 of the largest
+reference element: the bound is 2e-2.
 """
 
 import numpy as np
@@ -21,9 +27,10 @@ from test_gpu_parity import _close, _dense_sigma, _problem
 pytestmark = pytest.mark.gpu
 
 RTOL32 = 2e-4
+RTOL_BF16 = 2e-2
 
 
-def _f32_sigma(device, prob):
+def _f32_sigma(device, prob, bf16=False):
     import torch
     from paper_2310_03920_amd import _lib as X
     lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = prob
@@ -37,11 +44,12 @@ def _f32_sigma(device, prob):
     p32 = torch.empty(pt.numel(), dtype=torch.float32, device=device)
     s32 = torch.full_like(p32, float("nan"))
     X.convert_f64_f32(pt, p32)
-    plan.apply_f32(p32, s32)
+    low = plan.apply_bf16 if bf16 else plan.apply_f32
+    low(p32, s32)
     s64 = torch.empty_like(pt)
     X.convert_f32_f64(s32, s64)
     s32b = torch.empty_like(p32)
-    plan.apply_f32(p32, s32b)
+    low(p32, s32b)
     torch.cuda.synchronize()
     assert torch.equal(s32, s32b)
     return X.unpack_psi(lbB, rbB, s64.cpu().numpy())
@@ -52,6 +60,13 @@ def test_heff_apply_f32_random_operands(device, seed):
     print(f"[heff_apply_f32] seed={seed}", flush=True)
     prob = _problem(seed, True)
     _close(_f32_sigma(device, prob), _dense_sigma(*prob), rtol=RTOL32)
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_heff_apply_bf16_random_operands(device, seed):
+    print(f"[heff_apply_bf16] seed={seed}", flush=True)
+    prob = _problem(seed, True)
+    _close(_f32_sigma(device, prob, bf16=True), _dense_sigma(*prob), rtol=RTOL_BF16)
 
 
 def test_mixed_davidson_reaches_fp64_energy(device):
@@ -95,10 +110,19 @@ def test_mixed_davidson_reaches_fp64_energy(device):
         plan.apply_f32(v32, s32)
         X.convert_f32_f64(s32, out)
 
+    def mvb(v, out):
+        X.convert_f64_f32(v, v32)
+        plan.apply_bf16(v32, s32)
+        X.convert_f32_f64(s32, out)
+
     dav = Davidson(n, 24, device)
     e64, r64, _ = dav.solve(mv, psi0, diag, tol=1e-9, max_iter=200)
     e32, _, _ = Davidson(n, 24, device).solve(mv32, psi0, diag, tol=1e-5, max_iter=200)
     em, rm, n32, n64 = Davidson(n, 24, device).solve_mixed(mv32, mv, psi0, diag, tol=1e-9, max_iter=200)
+    eb, rb_, nb16, nb64 = Davidson(n, 24, device).solve_mixed(mvb, mv, psi0, diag, tol=1e-9, max_iter=200,
+                                                              low_tol=3e-3, floor=3e-2)
+    print(f"bf16 mixed: E {eb:.12f} ({nb16} bf16 + {nb64} f64 matvecs)", flush=True)
+    assert rb_ < 1e-9 and abs(eb - e64) < 1e-10
     e_fci = fock.fci_energy(h, g, K, 0)
     print(f"E64 {e64:.12f} E32-only {e32:.12f} Emixed {em:.12f} FCI {e_fci:.12f} (f32 {n32}, f64 {n64} matvecs)",
           flush=True)
@@ -108,12 +132,13 @@ def test_mixed_davidson_reaches_fp64_energy(device):
     assert abs(e32 - e64) < 1e-4      # FP32-only energy: within the FP32 rounding floor
 
 
-def test_mixed_precision_sweep_matches_fci(device):
+@pytest.mark.parametrize("precision", ["f32", "bf16"])
+def test_mixed_precision_sweep_matches_fci(device, precision):
     from paper_2310_03920_amd.dmrg import DMRG
-    print("[sweep f32]", flush=True)
+    print(f"[sweep {precision}]", flush=True)
     K = 8
     h, g = make_integrals(K, seed=0)
-    d = DMRG(h, g, K, 0, 64, seed=1, device="cuda", tol=1e-9, max_iter=120, precision="f32")
+    d = DMRG(h, g, K, 0, 64, seed=1, device="cuda", tol=1e-9, max_iter=120, precision=precision)
     d.run(4)
     e_fci = fock.fci_energy(h, g, K, 0)
     for rec in d.log:
