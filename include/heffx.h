@@ -297,6 +297,16 @@ int hx_davidson_step(int64_t n, int32_t k, int32_t kmax, const double* V, int64_
                      const double* S, int64_t lds, const double* diag, double guard, void* ws,
                      double* x, double* hx, double* t, double* scal, hx_stream stream);
 
+/* Thick restart with two vectors: given the current Ritz pair (x, hx = H x, |x| = 1)
+ * and the previous iteration's (xp, hxp = H xp), write v1 = the part of xp
+ * orthogonal to x (two Gram-Schmidt passes), normalised, and s1 = H v1 by the same
+ * linear combination of hx and hxp (no sigma-vector).  scal[3] = |xp - (x.xp) x|
+ * before normalisation (0, and v1 = s1 = 0, when xp adds no direction).  The
+ * Davidson basis then restarts as [x, v1] instead of [x] alone.  ws: the
+ * hx_davidson_step workspace (its projected-matrix rows are not touched). */
+int hx_davidson_restart2(int64_t n, const double* x, const double* hx, const double* xp, const double* hxp,
+                         double* v1, double* s1, void* ws, double* scal, hx_stream stream);
+
 /* Deterministic FP64 dot products out[j] = a_j . b for j < k (a_j = a + j*lda). */
 int hx_dots(int64_t n, int32_t k, const double* a, int64_t lda, const double* b, void* ws,
             double* out, hx_stream stream);

@@ -23,7 +23,8 @@ EXPORTED = (
     "hx_heff_diag", "hx_env_update", "hx_davidson_ws_bytes", "hx_davidson_step", "hx_dots",
     "hx_normalize", "hx_convert_f64_f32", "hx_convert_f32_f64", "hx_heff_lower_f32", "hx_heff_apply_f32",
     "hx_heff_plan_batch", "hx_batch_offsets", "hx_heff_graph_create", "hx_graph_launch", "hx_graph_destroy",
-    "hx_heff_vjp_plan_create", "hx_heff_apply_backward", "hx_heff_apply_bf16", "hx_last_error",
+    "hx_heff_vjp_plan_create", "hx_heff_apply_backward", "hx_heff_apply_bf16", "hx_davidson_restart2",
+    "hx_last_error",
 )
 
 
@@ -94,6 +95,7 @@ def lib():
     L.hx_heff_lower_f32.argtypes = [c_void_p] + [c_void_p] * 7
     L.hx_heff_apply_f32.argtypes = [c_void_p] + [c_void_p] * 6
     L.hx_heff_apply_bf16.argtypes = [c_void_p] + [c_void_p] * 6
+    L.hx_davidson_restart2.argtypes = [c_int64] + [c_void_p] * 9
     L.hx_heff_plan_batch.argtypes = [P(c_void_p), c_int32, P(c_void_p)]
     L.hx_batch_offsets.argtypes = [c_void_p, c_int32, P(c_int64), P(c_int64), P(c_int64)]
     L.hx_heff_vjp_plan_create.argtypes = L.hx_heff_plan_create.argtypes
@@ -462,6 +464,11 @@ def davidson_step(n, k, kmax, V, S, diag, guard, ws, x, hx, t, scal):
     check(lib().hx_davidson_step(int(n), int(k), int(kmax), _ptr(V), V.stride(0), _ptr(S), S.stride(0), _ptr(diag),
                                  float(guard), _ptr(ws), _ptr(x), _ptr(hx), _ptr(t), _ptr(scal), _stream()),
           "davidson_step")
+
+
+def davidson_restart2(x, hx, xp, hxp, v1, s1, ws, scal):
+    check(lib().hx_davidson_restart2(int(x.numel()), _ptr(x), _ptr(hx), _ptr(xp), _ptr(hxp), _ptr(v1), _ptr(s1),
+                                     _ptr(ws), _ptr(scal), _stream()), "davidson_restart2")
 
 
 def dots(a, b, ws, out):

@@ -500,6 +500,27 @@ __global__ void dav_project(int64_t n, int k, const double* __restrict__ V, int6
     }
 }
 
+// v -= c x and s -= c hx with c = *cp (one Gram-Schmidt pass against the Ritz vector)
+__global__ void restart_combine(int64_t n, const double* __restrict__ x, const double* __restrict__ hx, double* v,
+                                double* sv, const double* cp) {
+    const double c = *cp;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        v[e] -= c * x[e];
+        sv[e] -= c * hx[e];
+    }
+}
+
+// v, sv /= sqrt(*nu2) when the norm is not negligible, else both zero; scal[3] = norm
+__global__ void restart_scale(int64_t n, double* v, double* sv, const double* nu2, double* scal) {
+    const double nu = sqrt(fmax(*nu2, 0.0));
+    const double inv = nu > 1e-10 ? 1.0 / nu : 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        v[e] *= inv;
+        sv[e] *= inv;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) scal[3] = nu > 1e-10 ? nu : 0.0;
+}
+
 // t /= sqrt(ws[DW_S+2]) (if > 0); scal[1] = sqrt(|r|^2), scal[2] = |t|
 __global__ void dav_finish(int64_t n, double* ws, double* __restrict__ t, double* scal) {
     const double tn = sqrt(ws[DW_S + 2]);
@@ -933,6 +954,28 @@ int hx_normalize(int64_t n, double* x, void* wsv, double* norm_out, hx_stream st
     return hip_check(hipGetLastError(), "normalize");
 }
 
+int hx_davidson_restart2(int64_t n, const double* x, const double* hx, const double* xp, const double* hxp,
+                         double* v1, double* s1, void* wsv, double* scal, hx_stream stream) {
+    if (n <= 0 || !x || !hx || !xp || !hxp || !v1 || !s1 || !wsv || !scal) {
+        set_error("davidson_restart2: bad arguments");
+        return HX_EINVAL;
+    }
+    hipStream_t s = s_of(stream);
+    double* ws = static_cast<double*>(wsv);
+    const int nb = (int)std::min<int64_t>(2048, (n + 255) / 256);
+    int rc;
+    if ((rc = hip_check(hipMemcpyAsync(v1, xp, n * sizeof(double), hipMemcpyDeviceToDevice, s), "restart copy")) ||
+        (rc = hip_check(hipMemcpyAsync(s1, hxp, n * sizeof(double), hipMemcpyDeviceToDevice, s), "restart copy")))
+        return rc;
+    for (int pass = 0; pass < 2; ++pass) {  // classical Gram-Schmidt, twice
+        if ((rc = dots_into(n, 1, x, n, v1, ws, ws + DW_S + 4, 1, s))) return rc;
+        hipLaunchKernelGGL(restart_combine, dim3(nb), dim3(256), 0, s, n, x, hx, v1, s1, ws + DW_S + 4);
+        if ((rc = hip_check(hipGetLastError(), "restart combine"))) return rc;
+    }
+    if ((rc = dots_into(n, 1, v1, n, v1, ws, ws + DW_S + 5, 1, s))) return rc;
+    hipLaunchKernelGGL(restart_scale, dim3(nb), dim3(256), 0, s, n, v1, s1, ws + DW_S + 5, scal);
+    return hip_check(hipGetLastError(), "restart scale");
+}
 
 // ---- HIP graphs of the sigma-vector launch sequence
 

@@ -135,16 +135,22 @@ class Davidson:
         f64 = dict(dtype=torch.float64, device=device)
         self.V = torch.zeros((kmax, n), **f64)
         self.S = torch.zeros((kmax, n), **f64)
-        self.x = torch.zeros(n, **f64)
-        self.hx = torch.zeros(n, **f64)
+        # Ritz pairs of the current and the previous iteration (alternating buffers)
+        self.xb = torch.zeros((2, n), **f64)
+        self.hxb = torch.zeros((2, n), **f64)
+        self.x, self.hx = self.xb[0], self.hxb[0]
         self.t = torch.zeros(n, **f64)
         self.scal = torch.zeros(4, **f64)
         self.ws = torch.zeros(max(X.davidson_ws_bytes(n, kmax) // 8, 1), **f64)
 
-    def solve(self, matvec, psi0, diag, tol=1e-8, max_iter=30, guard=1e-8, on_iter=None):
+    def solve(self, matvec, psi0, diag, tol=1e-8, max_iter=30, guard=1e-8, on_iter=None, thick=True):
         """Lowest eigenpair of the operator `matvec(v, out)`; returns (theta, rnorm, n_matvec).
 
-        The Ritz vector is left in self.x."""
+        When the basis is full it restarts from the Ritz vector and, with `thick`,
+        also the previous iteration's Ritz vector (orthogonalised against it; its
+        H-image follows by linear combination, so the restart costs no
+        sigma-vector; skipped when the two are nearly parallel, where that
+        combination would lose precision).  The Ritz vector is left in self.x."""
         n, kmax = self.n, self.kmax
         V, S = self.V, self.S
         V[0].copy_(psi0)
@@ -152,21 +158,38 @@ class Davidson:
         matvec(V[0], S[0])
         nmv, k = 1, 1
         theta = rnorm = None
+        cur = 0
+
+        def step(kk, c):
+            X.davidson_step(n, kk, kmax, V, S, diag, guard, self.ws, self.xb[c], self.hxb[c], self.t, self.scal)
+
         for it in range(max_iter):
-            X.davidson_step(n, k, kmax, V, S, diag, guard, self.ws, self.x, self.hx, self.t, self.scal)
+            step(k, cur)
             theta, rnorm, tnorm = (float(v) for v in self.scal[:3].cpu())
             stop = bool(on_iter(it, theta, rnorm)) if on_iter else False
             if stop or rnorm < tol or it == max_iter - 1 or not (tnorm > 1e-14):
                 break
             if k == kmax:
-                V[0].copy_(self.x)
-                S[0].copy_(self.hx)
+                prev = 1 - cur
+                V[0].copy_(self.xb[cur])
+                S[0].copy_(self.hxb[cur])
                 k = 1
-                X.davidson_step(n, k, kmax, V, S, diag, guard, self.ws, self.x, self.hx, self.t, self.scal)
+                if thick and it > 0:
+                    X.davidson_restart2(self.xb[cur], self.hxb[cur], self.xb[prev], self.hxb[prev], V[1], S[1],
+                                        self.ws, self.scal)
+                    # the H-image of v1 is a difference of nearly parallel vectors when x has
+                    # barely moved; use it only while its rounding stays far below tol
+                    if float(self.scal[3].cpu()) > 1e-3:
+                        step(1, prev)  # projected-matrix row 0 of the new basis
+                        k = 2
+                cur = 1 - cur
+                step(k, cur)
             V[k].copy_(self.t)
             matvec(V[k], S[k])
             nmv += 1
             k += 1
+            cur = 1 - cur
+        self.x, self.hx = self.xb[cur], self.hxb[cur]
         return theta, rnorm, nmv
 
     def solve_mixed(self, mv32, mv64, psi0, diag, tol=1e-8, max_iter=30, low_tol=1e-5, guard=1e-8, floor=1e-3):
