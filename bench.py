@@ -36,6 +36,11 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAKS = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFLOPS}
+# HBM bytes of one FP64 sigma-vector at the default workload (36 orbitals, M = 1000,
+# middle step), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a copy of known
+# size, per plan options (kernel_variant, split_kseg_min, intermediate budget).  Only
+# valid for the kernel and tile order they were taken with; other options report null.
+MEASURED_TRAFFIC = {(1, 1024, 1 << 30): 68.91e9, (1, 1024, 1 << 29): 70.24e9}
 
 
 def log(*a):
@@ -592,7 +597,11 @@ def main():
         "rnorm": rnorm,
         "energy_err_vs_fp64": abs(theta - e_ref),
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": (MEASURED_TRAFFIC.get((opts["kernel_variant"], opts["split_kseg_min"],
+                                                       opts["t_budget_bytes"]))
+                                 if (args.mode == "f64" and (K, M) == (36, 1000)) else None),
+                     "traffic_unit": "bytes per sigma-vector (HBM, counter-measured)",
                      "kernel": ({"f32": "bsgemm<float> (all launches of one hx_heff_apply_f32)",
                                  "bf16": "bsgemm<float, BF16 products> (all launches of one hx_heff_apply_bf16)"
                                  }[args.mode] if args.mode != "f64"
