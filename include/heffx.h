@@ -183,7 +183,8 @@ int hx_env_update(const hx_plan* plan, const double* env_in, const double* site,
  * df/dR and df/dW1, df/dW2.  With g = psi these are the derivatives of
  * <psi|H_eff|psi> with respect to L, W and R (the quantities from which reduced
  * density matrices and integral gradients follow, Sec. II.E.1 and the
- * DMRG-CASSCF use of Sec. II.A), and df/dpsi + H_eff psi is its psi gradient.
+ * DMRG-CASSCF gradients of Sec. II.A.8), and df/dpsi + H_eff psi is its psi
+ * gradient.
  * The plan's hx_plan_get_info reports the backward FLOP as flops_apply. */
 int hx_heff_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops,
                             const hx_opset* mid, const hx_opset* Rops, const hx_mpo_site* W1,
