@@ -13,7 +13,10 @@ BUILD = os.path.join(HERE, "_build")
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              # keep packed-FP32 instructions out of generated code
-             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+             # MFMA accumulators in ordinary VGPRs: no AGPR <-> VGPR copies around
+             # the K-stage loop of the block GEMM
+             "-mllvm", "-amdgpu-mfma-vgpr-form"]
 
 
 def _run(cmd):

@@ -197,48 +197,66 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         }
     };
 
-    if (nst > 0) {
+    // Matrix-core work of one K stage.  ACT: the wave's 32 x 32 quadrant meets the
+    // tile; R1 / C1: its second 16-row / 16-column block does.  Each combination is
+    // its own straight-line code (chosen once per tile, wave-uniform), so the
+    // accumulators stay in AGPRs and the skipped blocks cost nothing.  LDS operands
+    // of the next 4-deep step are read before the MFMAs of the current one.
+    auto mma_stage = [&](int buf, auto ACT, auto R1, auto C1) {
+        if constexpr (ACT.value) {
+            constexpr bool r1c = decltype(R1)::value, c1c = decltype(C1)::value;
+            if constexpr (BF) {
+                const int kq = 4 * (lane >> 4), rl = lane & 15;
+                const bf16x4 a0 = *reinterpret_cast<const bf16x4*>(&Ah[buf][wr0 + rl][kq]);
+                const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(&Bh[buf][wc0 + rl][kq]);
+                bf16x4 a1 = {0, 0, 0, 0}, b1 = {0, 0, 0, 0};
+                if constexpr (r1c) a1 = *reinterpret_cast<const bf16x4*>(&Ah[buf][wr0 + 16 + rl][kq]);
+                if constexpr (c1c) b1 = *reinterpret_cast<const bf16x4*>(&Bh[buf][wc0 + 16 + rl][kq]);
+                acc00 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc00, 0, 0, 0);
+                if constexpr (c1c) acc01 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc01, 0, 0, 0);
+                if constexpr (r1c) acc10 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc10, 0, 0, 0);
+                if constexpr (r1c && c1c)
+                    acc11 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc11, 0, 0, 0);
+            } else {
+                constexpr int NK = KSV / 4;
+                T a0[NK], a1[NK], b0[NK], b1[NK];
+                auto rd = [&](int ks) {
+                    const int kr = ks * 4 + (lane >> 4);
+                    a0[ks] = As[buf][kr][wr0 + (lane & 15)];
+                    b0[ks] = Bs[buf][kr][wc0 + (lane & 15)];
+                    if constexpr (r1c) a1[ks] = As[buf][kr][wr0 + 16 + (lane & 15)];
+                    if constexpr (c1c) b1[ks] = Bs[buf][kr][wc0 + 16 + (lane & 15)];
+                };
+                rd(0);
+#pragma unroll
+                for (int ks = 0; ks < NK; ++ks) {
+                    if (ks + 1 < NK) rd(ks + 1);
+                    if constexpr (std::is_same<T, double>::value) {
+                        acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], b0[ks], acc00, 0, 0, 0);
+                        if constexpr (c1c) acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], b1[ks], acc01, 0, 0, 0);
+                        if constexpr (r1c) acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[ks], b0[ks], acc10, 0, 0, 0);
+                        if constexpr (r1c && c1c)
+                            acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[ks], b1[ks], acc11, 0, 0, 0);
+                    } else {
+                        acc00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], b0[ks], acc00, 0, 0, 0);
+                        if constexpr (c1c) acc01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], b1[ks], acc01, 0, 0, 0);
+                        if constexpr (r1c) acc10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], b0[ks], acc10, 0, 0, 0);
+                        if constexpr (r1c && c1c)
+                            acc11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], b1[ks], acc11, 0, 0, 0);
+                    }
+                }
+            }
+        }
+    };
+    auto run = [&](auto ACT, auto R1, auto C1) {
+        if (nst <= 0) return;
         load_stage();
         store_stage(0);
         __syncthreads();
         for (int s = 0; s < nst; ++s) {
             const int buf = NBUF == 2 ? (s & 1) : 0;
             if (s + 1 < nst) load_stage();
-            if (BF && any) {
-                // one 16-deep product per 16 x 16 block: lane l supplies row (col) l%16,
-                // k = 4(l/16) .. 4(l/16)+3
-                const int kq = 4 * (lane >> 4), rl = lane & 15;
-                const bf16x4 a0 = *reinterpret_cast<const bf16x4*>(&Ah[buf][wr0 + rl][kq]);
-                const bf16x4 a1 = *reinterpret_cast<const bf16x4*>(&Ah[buf][wr0 + 16 + rl][kq]);
-                const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(&Bh[buf][wc0 + rl][kq]);
-                const bf16x4 b1 = *reinterpret_cast<const bf16x4*>(&Bh[buf][wc0 + 16 + rl][kq]);
-                if constexpr (BF) {
-                    acc00 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc00, 0, 0, 0);
-                    if (c1) acc01 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc01, 0, 0, 0);
-                    if (r1) acc10 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc10, 0, 0, 0);
-                    if (r1 && c1) acc11 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc11, 0, 0, 0);
-                }
-            } else if (any) {
-#pragma unroll
-                for (int ks = 0; ks < KSV / 4; ++ks) {
-                    const int kr = ks * 4 + (lane >> 4);
-                    const T a0 = As[buf][kr][wr0 + (lane & 15)];
-                    const T a1 = As[buf][kr][wr0 + 16 + (lane & 15)];
-                    const T b0 = Bs[buf][kr][wc0 + (lane & 15)];
-                    const T b1 = Bs[buf][kr][wc0 + 16 + (lane & 15)];
-                    if constexpr (std::is_same<T, double>::value) {
-                        acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
-                        if (c1) acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
-                        if (r1) acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
-                        if (r1 && c1) acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
-                    } else {
-                        acc00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc00, 0, 0, 0);
-                        if (c1) acc01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc01, 0, 0, 0);
-                        if (r1) acc10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc10, 0, 0, 0);
-                        if (r1 && c1) acc11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc11, 0, 0, 0);
-                    }
-                }
-            }
+            mma_stage(buf, ACT, R1, C1);
             if constexpr (NBUF == 2) {
                 if (s + 1 < nst) store_stage(buf ^ 1);
                 __syncthreads();
@@ -250,7 +268,19 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
                 }
             }
         }
-    }
+    };
+    using F = std::false_type;
+    using Tr = std::true_type;
+    if (!any)
+        run(F{}, F{}, F{});
+    else if (r1 && c1)
+        run(Tr{}, Tr{}, Tr{});
+    else if (r1)
+        run(Tr{}, Tr{}, F{});
+    else if (c1)
+        run(Tr{}, F{}, Tr{});
+    else
+        run(Tr{}, F{}, F{});
     // epilogue (lane layouts measured on gfx950): v_mfma_f64_16x16x4_f64 gives lane l
     // rows l/16 + 4v of column l%16; v_mfma_f32_16x16x4_f32 and
     // v_mfma_f32_16x16x16_bf16 rows 4(l/16) + v.
