@@ -168,6 +168,11 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
 
     // raw loads; alpha is applied at the LDS store so the loads stay in flight
     // across the MFMA work of the current stage
+    // Every K stage of a tile lies inside one task (krem >= 1), so indices clamped to
+    // the block are always valid addresses: the FP32 loads issue unconditionally and
+    // stay in flight across the MFMA work; elements outside the block are zeroed at
+    // the LDS store (A through its 0/alpha factor).  Offsets in a block fit in 32 bits.
+    int krem_ld = 0;  // valid depth of the stage held in ra / rb
     auto load_stage = [&]() {
         const T *qa, *qb;
         int krem;
@@ -177,22 +182,38 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         for (int e = 0; e < NE; ++e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
             const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
-            T va = 0, vb = 0;
-            if (ka < krem && r < m) va = TA ? qa[(int64_t)ka * lda + r] : qa[(int64_t)r * lda + ka];
-            if (kb < krem && c < n) vb = TB ? qb[(int64_t)c * ldb + kb] : qb[(int64_t)kb * ldb + c];
-            ra[e] = va;
-            rb[e] = vb;
+            if constexpr (std::is_same<T, double>::value) {
+                // FP64 (measured faster this way): loads under exec masks, so padding
+                // rows and columns issue no memory requests
+                T va = 0, vb = 0;
+                if (ka < krem && r < m) va = qa[TA ? ka * lda + r : r * lda + ka];
+                if (kb < krem && c < n) vb = qb[TB ? c * ldb + kb : kb * ldb + c];
+                ra[e] = va;
+                rb[e] = vb;
+            } else {
+                const int rc = min(r, m - 1), kac = min(ka, krem - 1);
+                const int cc = min(c, n - 1), kbc = min(kb, krem - 1);
+                ra[e] = qa[TA ? kac * lda + rc : rc * lda + kac];
+                rb[e] = qb[TB ? cc * ldb + kbc : kbc * ldb + cc];
+            }
         }
+        krem_ld = krem;
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
+            const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
+            const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
+            // FP64 loads are already zero outside the block (guarded loads)
+            constexpr bool guarded = std::is_same<T, double>::value;
+            const T fa = (guarded || (ka < krem_ld && r < m)) ? alpha : (T)0;
+            const T vb = (guarded || (kb < krem_ld && c < n)) ? rb[e] : (T)0;
             if constexpr (BF) {
-                Ah[buf][a_r + a_dr * e][a_k + a_dk * e] = to_bf16(alpha * ra[e]);
-                Bh[buf][b_c + b_dc * e][b_k + b_dk * e] = to_bf16(rb[e]);
+                Ah[buf][r][ka] = to_bf16(fa * ra[e]);
+                Bh[buf][c][kb] = to_bf16(vb);
             } else {
-                As[buf][a_k + a_dk * e][a_r + a_dr * e] = alpha * ra[e];
-                Bs[buf][b_k + b_dk * e][b_c + b_dc * e] = rb[e];
+                As[buf][ka][r] = fa * ra[e];
+                Bs[buf][kb][c] = vb;
             }
         }
     };
