@@ -90,7 +90,8 @@ typedef struct {
     int32_t split_kseg_min;  /* minimum K of a split-K segment; 0 = default 2048 */
     int32_t kernel_variant;  /* block-GEMM pipeline: 0 = two LDS buffers, 16-deep K stages (default);
                                 1 = one LDS buffer, 16-deep (more workgroups per CU);
-                                2 = two LDS buffers, 8-deep (less K padding, more workgroups per CU).
+                                2 = two LDS buffers, 8-deep (less K padding, more workgroups per CU);
+                                3 = as 1 with persistent workgroups that prefetch their next tile.
                                 Results are identical up to FP rounding order of the padding. */
     int32_t reserved[6];
 } hx_plan_opts;
@@ -274,8 +275,8 @@ int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, v
  * the same buffers as hx_heff_apply_f32 and rounded to BF16 (nearest even) when
  * staged, the stage-1 intermediate is kept in FP32 between the two rounds.
  * Relative operand precision 2^-9, so sigma carries ~1e-3 relative error; the
- * Davidson work stays FP64 (mixed-precision mode).  Needs kernel_variant 0 or 1
- * (HX_EUNSUP for 2). */
+ * Davidson work stays FP64 (mixed-precision mode).  Needs a 16-deep kernel
+ * variant (HX_EUNSUP for kernel_variant 2). */
 int hx_heff_apply_bf16(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
                        float* sigma32, hx_stream stream);
 

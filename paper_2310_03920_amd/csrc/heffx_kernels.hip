@@ -124,9 +124,13 @@ constexpr int LDW = TM + LDS_PAD;
 // BF (T = float only): operands are rounded to BF16 at the LDS store and the
 // products run on v_mfma_f32_16x16x16_bf16 with FP32 accumulation; LDS then holds
 // each tile row's 16 k contiguously so a lane's 4 consecutive k are one 8-byte read.
-template <typename T, bool TA, bool TB, int NSP, int KSV, int NBUF, bool BF = false>
+// PERS: persistent workgroups.  Workgroup w computes tiles w, w + G, w + 2G, ...
+// (G = grid size, a multiple of 8, so they all stay on the XCD the tile order chose)
+// and fetches the first K stage of its next tile during the last stage of the
+// current one, hiding the start-up latency of short-K tiles.
+template <typename T, bool TA, bool TB, int NSP, int KSV, int NBUF, bool BF = false, bool PERS = false>
 __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
-                                              BasesT<T> B) {
+                                              BasesT<T> B, int ntile) {
     using acc_t = typename std::conditional<std::is_same<T, double>::value, dbl4, flt4>::type;
     static_assert(KSV == 8 || KSV == 16, "stage depth");
     static_assert(!BF || (std::is_same<T, float>::value && KSV == 16), "BF16 products: FP32 storage, 16-deep stages");
@@ -136,17 +140,11 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     __shared__ T Bs[BF ? 1 : NBUF][BF ? 1 : KSV][BF ? 1 : LDW];
     __shared__ __attribute__((aligned(16))) unsigned short Ah[BF ? NBUF : 1][BF ? TM : 1][BF ? LDB : 1];
     __shared__ __attribute__((aligned(16))) unsigned short Bh[BF ? NBUF : 1][BF ? TN : 1][BF ? LDB : 1];
-    const Tile tl = tiles[blockIdx.x];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wr0 = (wave & 1) * 32;
     const int wc0 = (wave >> 1) * 32;
-    const int m = tl.m, n = tl.n;
-    // 16 x 16 MFMA blocks wholly outside the tile's extent are skipped (wave-uniform
-    // branches), so matrix-core work follows the block shape at 16 x 16 granularity
-    const bool r0 = wr0 < m, r1 = wr0 + 16 < m, c0 = wc0 < n, c1 = wc0 + 16 < n;
-    const bool any = r0 && c0;
     // load lanes (element e of a thread: idx = tid + 256 e):
     //  A !TA: k = idx % KSV, row = idx / KSV (KSV contiguous k per row)
     //  A  TA: row = idx % 64, k = idx / 64 (64 contiguous rows per k)
@@ -158,46 +156,56 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     const int b_k = TB ? (tid % KSV) : (tid >> 6);
     constexpr int a_dr = TA ? 0 : 256 / KSV, a_dk = TA ? 4 : 0;  // step per element e
     constexpr int b_dc = TB ? 256 / KSV : 0, b_dk = TB ? 0 : 4;
-    Cursor<T, TA, TB, NSP, KSV> cur;
-    cur.start(tl.tbeg, tl.tend, tasks, B, tl.r0, tl.c0);
 
-    acc_t acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
+    int t = blockIdx.x;
+    Tile tl = tiles[t];
+    acc_t acc00, acc01, acc10, acc11;
     T ra[NE], rb[NE];
     T alpha = 0;
-    const int nst = tl.ktot / KSV;
 
-    // raw loads; alpha is applied at the LDS store so the loads stay in flight
-    // across the MFMA work of the current stage
+    // Loader: the tile whose K stages are being fetched (the current one, or the next
+    // one during the current tile's last stage) and the stage held in ra / rb.
+    Cursor<T, TA, TB, NSP, KSV> cur;
+    int lm = 0, ln = 0, lr0 = 0, lc0 = 0;       // extent and origin of the loader's tile
+    int krem_ld = 0, m_ld = 0, n_ld = 0;         // valid depth / extent of the held stage
+    auto bind_loader = [&](const Tile& x) {
+        lm = x.m;
+        ln = x.n;
+        lr0 = x.r0;
+        lc0 = x.c0;
+        cur.start(x.tbeg, x.tend, tasks, B, lr0, lc0);
+    };
     // Every K stage of a tile lies inside one task (krem >= 1), so indices clamped to
     // the block are always valid addresses: the FP32 loads issue unconditionally and
     // stay in flight across the MFMA work; elements outside the block are zeroed at
-    // the LDS store (A through its 0/alpha factor).  Offsets in a block fit in 32 bits.
-    int krem_ld = 0;  // valid depth of the stage held in ra / rb
+    // the LDS store (A through its 0/alpha factor).  FP64 (measured faster this way)
+    // loads under exec masks, so padding rows and columns issue no memory requests.
+    // Offsets inside one block fit in 32 bits.
     auto load_stage = [&]() {
         const T *qa, *qb;
         int krem;
-        cur.next(tasks, B, tl.r0, tl.c0, qa, qb, krem, alpha);
+        cur.next(tasks, B, lr0, lc0, qa, qb, krem, alpha);
         const int lda = cur.lda, ldb = cur.ldb;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
             const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
             if constexpr (std::is_same<T, double>::value) {
-                // FP64 (measured faster this way): loads under exec masks, so padding
-                // rows and columns issue no memory requests
                 T va = 0, vb = 0;
-                if (ka < krem && r < m) va = qa[TA ? ka * lda + r : r * lda + ka];
-                if (kb < krem && c < n) vb = qb[TB ? c * ldb + kb : kb * ldb + c];
+                if (ka < krem && r < lm) va = qa[TA ? ka * lda + r : r * lda + ka];
+                if (kb < krem && c < ln) vb = qb[TB ? c * ldb + kb : kb * ldb + c];
                 ra[e] = va;
                 rb[e] = vb;
             } else {
-                const int rc = min(r, m - 1), kac = min(ka, krem - 1);
-                const int cc = min(c, n - 1), kbc = min(kb, krem - 1);
+                const int rc = min(r, lm - 1), kac = min(ka, krem - 1);
+                const int cc = min(c, ln - 1), kbc = min(kb, krem - 1);
                 ra[e] = qa[TA ? kac * lda + rc : rc * lda + kac];
                 rb[e] = qb[TB ? cc * ldb + kbc : kbc * ldb + cc];
             }
         }
         krem_ld = krem;
+        m_ld = lm;
+        n_ld = ln;
     };
     auto store_stage = [&](int buf) {
 #pragma unroll
@@ -206,8 +214,8 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
             const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
             // FP64 loads are already zero outside the block (guarded loads)
             constexpr bool guarded = std::is_same<T, double>::value;
-            const T fa = (guarded || (ka < krem_ld && r < m)) ? alpha : (T)0;
-            const T vb = (guarded || (kb < krem_ld && c < n)) ? rb[e] : (T)0;
+            const T fa = (guarded || (ka < krem_ld && r < m_ld)) ? alpha : (T)0;
+            const T vb = (guarded || (kb < krem_ld && c < n_ld)) ? rb[e] : (T)0;
             if constexpr (BF) {
                 Ah[buf][r][ka] = to_bf16(fa * ra[e]);
                 Bh[buf][c][kb] = to_bf16(vb);
@@ -220,9 +228,9 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
 
     // Matrix-core work of one K stage.  ACT: the wave's 32 x 32 quadrant meets the
     // tile; R1 / C1: its second 16-row / 16-column block does.  Each combination is
-    // its own straight-line code (chosen once per tile, wave-uniform), so the
-    // accumulators stay in AGPRs and the skipped blocks cost nothing.  LDS operands
-    // of the next 4-deep step are read before the MFMAs of the current one.
+    // its own straight-line code (chosen once per tile, wave-uniform), so the skipped
+    // blocks cost nothing.  LDS operands of the next 4-deep step are read before the
+    // MFMAs of the current one.
     auto mma_stage = [&](int buf, auto ACT, auto R1, auto C1) {
         if constexpr (ACT.value) {
             constexpr bool r1c = decltype(R1)::value, c1c = decltype(C1)::value;
@@ -269,60 +277,93 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
             }
         }
     };
-    auto run = [&](auto ACT, auto R1, auto C1) {
-        if (nst <= 0) return;
-        load_stage();
-        store_stage(0);
-        __syncthreads();
-        for (int s = 0; s < nst; ++s) {
-            const int buf = NBUF == 2 ? (s & 1) : 0;
-            if (s + 1 < nst) load_stage();
-            mma_stage(buf, ACT, R1, C1);
-            if constexpr (NBUF == 2) {
-                if (s + 1 < nst) store_stage(buf ^ 1);
-                __syncthreads();
-            } else {
-                __syncthreads();
+
+    bind_loader(tl);
+    if (tl.ktot > 0) load_stage();
+    for (;;) {
+        const int m = tl.m, n = tl.n;
+        const int nst = tl.ktot / KSV;
+        // 16 x 16 MFMA blocks wholly outside the tile's extent are skipped (wave-uniform
+        // branches), so matrix-core work follows the block shape at 16 x 16 granularity
+        const bool r1 = wr0 + 16 < m, c1 = wc0 + 16 < n;
+        const bool any = wr0 < m && wc0 < n;
+        const int tn = t + (int)gridDim.x;
+        const bool has_next = PERS && tn < ntile;
+        Tile nx = tl;
+        if (has_next) nx = tiles[tn];
+        bool next_loaded = false;
+        acc00 = acc_t{0, 0, 0, 0};
+        acc01 = acc_t{0, 0, 0, 0};
+        acc10 = acc_t{0, 0, 0, 0};
+        acc11 = acc_t{0, 0, 0, 0};
+        auto run = [&](auto ACT, auto R1, auto C1) {
+            if (nst <= 0) return;
+            store_stage(0);
+            __syncthreads();
+            for (int s = 0; s < nst; ++s) {
+                const int buf = NBUF == 2 ? (s & 1) : 0;
                 if (s + 1 < nst) {
-                    store_stage(0);
+                    load_stage();
+                } else if (has_next && nx.ktot > 0) {
+                    bind_loader(nx);  // first stage of the next tile, in flight across this one
+                    load_stage();
+                    next_loaded = true;
+                }
+                mma_stage(buf, ACT, R1, C1);
+                if constexpr (NBUF == 2) {
+                    if (s + 1 < nst) store_stage(buf ^ 1);
                     __syncthreads();
+                } else {
+                    __syncthreads();
+                    if (s + 1 < nst) {
+                        store_stage(0);
+                        __syncthreads();
+                    }
                 }
             }
-        }
-    };
-    using F = std::false_type;
-    using Tr = std::true_type;
-    if (!any)
-        run(F{}, F{}, F{});
-    else if (r1 && c1)
-        run(Tr{}, Tr{}, Tr{});
-    else if (r1)
-        run(Tr{}, Tr{}, F{});
-    else if (c1)
-        run(Tr{}, F{}, Tr{});
-    else
-        run(Tr{}, F{}, F{});
-    // epilogue (lane layouts measured on gfx950): v_mfma_f64_16x16x4_f64 gives lane l
-    // rows l/16 + 4v of column l%16; v_mfma_f32_16x16x4_f32 and
-    // v_mfma_f32_16x16x16_bf16 rows 4(l/16) + v.
-    T* C = space_ptr<T, NSP>(B, tl.flags & 0xff) + tl.coff;
-    const int ldc = tl.ldc;
-    const bool beta = ((tl.flags >> 8) & 0xff) != 0;
-    auto put = [&](const acc_t& a, int rb0_, int cb0) {
-        const int col = cb0 + (lane & 15);
+        };
+        using F = std::false_type;
+        using Tr = std::true_type;
+        if (!any)
+            run(F{}, F{}, F{});
+        else if (r1 && c1)
+            run(Tr{}, Tr{}, Tr{});
+        else if (r1)
+            run(Tr{}, Tr{}, F{});
+        else if (c1)
+            run(Tr{}, F{}, Tr{});
+        else
+            run(Tr{}, F{}, F{});
+
+        // epilogue (lane layouts measured on gfx950): v_mfma_f64_16x16x4_f64 gives lane l
+        // rows l/16 + 4v of column l%16; v_mfma_f32_16x16x4_f32 and
+        // v_mfma_f32_16x16x16_bf16 rows 4(l/16) + v.
+        T* C = space_ptr<T, NSP>(B, tl.flags & 0xff) + tl.coff;
+        const int ldc = tl.ldc;
+        const bool beta = ((tl.flags >> 8) & 0xff) != 0;
+        auto put = [&](const acc_t& a, int rb0_, int cb0) {
+            const int col = cb0 + (lane & 15);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = std::is_same<T, double>::value ? rb0_ + (lane >> 4) + 4 * v : rb0_ + 4 * (lane >> 4) + v;
-            if (row < m && col < n) {
-                T* p = C + (int64_t)row * ldc + col;
-                *p = beta ? (*p + a[v]) : a[v];
+            for (int v = 0; v < 4; ++v) {
+                const int row = std::is_same<T, double>::value ? rb0_ + (lane >> 4) + 4 * v : rb0_ + 4 * (lane >> 4) + v;
+                if (row < m && col < n) {
+                    T* p = C + (int64_t)row * ldc + col;
+                    *p = beta ? (*p + a[v]) : a[v];
+                }
             }
+        };
+        put(acc00, wr0, wc0);
+        put(acc01, wr0, wc0 + 16);
+        put(acc10, wr0 + 16, wc0);
+        put(acc11, wr0 + 16, wc0 + 16);
+        if (!has_next) break;
+        t = tn;
+        tl = nx;
+        if (!next_loaded) {
+            bind_loader(tl);
+            if (tl.ktot > 0) load_stage();
         }
-    };
-    put(acc00, wr0, wc0);
-    put(acc01, wr0, wc0 + 16);
-    put(acc10, wr0 + 16, wc0);
-    put(acc11, wr0 + 16, wc0 + 16);
+    }
 }
 
 // Fixed-order sum of split-K partial tiles into the owning output tile.
@@ -606,19 +647,25 @@ static Bases make_bases(const Plan* P, const double* psi, double* out, const dou
     return b;
 }
 
-template <typename T, int NSP, int KSV, int NBUF, bool BF = false>
-static int launch_kind(int kind, dim3 grid, const Tile* tiles, const Task* tasks, const BasesT<T>& B,
+template <typename T, int NSP, int KSV, int NBUF, bool BF = false, bool PERS = false>
+static int launch_kind(int kind, int64_t ntile, const Tile* tiles, const Task* tasks, const BasesT<T>& B,
                        hipStream_t s) {
     const dim3 block(256);
+    // persistent: 6 resident workgroups per CU on 256 CUs (a multiple of the 8 XCDs)
+    const dim3 grid((unsigned)(PERS ? std::min<int64_t>(ntile, 256 * 6) : ntile));
+    const int nt = (int)ntile;
     switch (kind) {
         case NN:
-            hipLaunchKernelGGL((bsgemm<T, false, false, NSP, KSV, NBUF, BF>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, false, false, NSP, KSV, NBUF, BF, PERS>), grid, block, 0, s, tiles, tasks, B,
+                               nt);
             return HX_OK;
         case NT:
-            hipLaunchKernelGGL((bsgemm<T, false, true, NSP, KSV, NBUF, BF>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, false, true, NSP, KSV, NBUF, BF, PERS>), grid, block, 0, s, tiles, tasks, B,
+                               nt);
             return HX_OK;
         case TN_:
-            hipLaunchKernelGGL((bsgemm<T, true, false, NSP, KSV, NBUF, BF>), grid, block, 0, s, tiles, tasks, B);
+            hipLaunchKernelGGL((bsgemm<T, true, false, NSP, KSV, NBUF, BF, PERS>), grid, block, 0, s, tiles, tasks, B,
+                               nt);
             return HX_OK;
         default:
             set_error("internal: bad GEMM kind");
@@ -641,27 +688,42 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
     if (L.ntile <= 0) return HX_OK;
     const Tile* tiles = reinterpret_cast<const Tile*>(static_cast<const char*>(P->dev) + P->off_tiles) + L.tile0;
     const Task* tasks = reinterpret_cast<const Task*>(static_cast<const char*>(P->dev) + P->off_tasks);
-    dim3 grid((unsigned)L.ntile);
+    if (L.ntile > INT32_MAX) {
+        set_error("launch has more than 2^31 tiles");
+        return HX_EINVAL;
+    }
+    const int64_t nt = L.ntile;
     int rk;
     if constexpr (BF) {
-        if (P->variant == 2) {
-            set_error("BF16 products need a 16-deep kernel variant (0 or 1)");
-            return HX_EUNSUP;
+        switch (P->variant) {
+            case 1:
+                rk = launch_kind<T, NSP, 16, 1, true>(L.kind, nt, tiles, tasks, B, s);
+                break;
+            case 3:
+                rk = launch_kind<T, NSP, 16, 1, true, true>(L.kind, nt, tiles, tasks, B, s);
+                break;
+            case 0:
+                rk = launch_kind<T, NSP, 16, 2, true>(L.kind, nt, tiles, tasks, B, s);
+                break;
+            default:
+                set_error("BF16 products need a 16-deep kernel variant (0, 1 or 3)");
+                return HX_EUNSUP;
         }
-        rk = P->variant == 1 ? launch_kind<T, NSP, 16, 1, true>(L.kind, grid, tiles, tasks, B, s)
-                             : launch_kind<T, NSP, 16, 2, true>(L.kind, grid, tiles, tasks, B, s);
         if (rk) return rk;
         return finish_gemm(P, L, B, s);
     }
     switch (P->variant) {
         case 1:
-            rk = launch_kind<T, NSP, 16, 1>(L.kind, grid, tiles, tasks, B, s);
+            rk = launch_kind<T, NSP, 16, 1>(L.kind, nt, tiles, tasks, B, s);
             break;
         case 2:
-            rk = launch_kind<T, NSP, 8, 2>(L.kind, grid, tiles, tasks, B, s);
+            rk = launch_kind<T, NSP, 8, 2>(L.kind, nt, tiles, tasks, B, s);
+            break;
+        case 3:
+            rk = launch_kind<T, NSP, 16, 1, false, true>(L.kind, nt, tiles, tasks, B, s);
             break;
         default:
-            rk = launch_kind<T, NSP, 16, 2>(L.kind, grid, tiles, tasks, B, s);
+            rk = launch_kind<T, NSP, 16, 2>(L.kind, nt, tiles, tasks, B, s);
             break;
     }
     if (rk) return rk;

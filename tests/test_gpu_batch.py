@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 CASES = [(0, False, 0), (1, True, 0), (2, False, 8), (3, True, 16), (4, True, 0)]
 
 
-def _instances(device, cases=CASES):
+def _instances(device, cases=CASES, variant=0):
     import torch
     from paper_2310_03920_amd import _lib as X
     out = []
@@ -24,7 +24,7 @@ def _instances(device, cases=CASES):
         prob = _problem(seed, big)
         lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = prob
         lbB, rbB = X.Bond(lb), X.Bond(rb)
-        plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, split_kseg_min=kseg)
+        plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, split_kseg_min=kseg, kernel_variant=variant)
         arrs = (X.pack_env(lbB, Ldq, L), X.pack_env(rbB, Rdq, R), X.pack_psi(lbB, rbB, psi))
         out.append((prob, plan, arrs))
     return out
@@ -61,11 +61,14 @@ def _individual(device, plan, arrs, f32=False):
     return res
 
 
-def test_batched_apply_and_diag_match_instances_bitwise(device):
+@pytest.mark.parametrize("variant", [0, 3])
+def test_batched_apply_and_diag_match_instances_bitwise(device, variant):
+    """Variant 3 (persistent workgroups): the batched stage-1 launch has more tiles
+    (2219) than workgroups (1536), so workgroups run several tiles and prefetch."""
     import torch
     from paper_2310_03920_amd import _lib as X
-    print("[batch] 5 instances, f64 + f32", flush=True)
-    insts = _instances(device)
+    print(f"[batch] 5 instances, f64 + f32, variant {variant}", flush=True)
+    insts = _instances(device, variant=variant)
     ref = [_individual(device, plan, arrs, f32=True) for _, plan, arrs in insts]
     B = X.BatchPlan([plan for _, plan, _ in insts]).upload(device)
     assert B.info.flops_apply == pytest.approx(sum(p.info.flops_apply for _, p, _ in insts), rel=1e-12)
