@@ -229,6 +229,7 @@ class DMRG:
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision
+        self.h, self.g = np.asarray(h, dtype=np.float64), np.asarray(g, dtype=np.float64)
         self.mpo = build_nc_mpo(h, g)
         self.bonds = bonds if bonds is not None else bond_sector_tables(self.K, n_elec, twosz, M)
         self.tensors = tensors if tensors is not None else random_right_canonical_mps(self.bonds, seed)
@@ -241,6 +242,101 @@ class DMRG:
         self.center = None      # one-site center tensor after a split
         self.center_site = None
         self.log = []
+
+    def _grad_step(self, i, psi0):
+        """Adjoint at sites (i, i+1) with cotangent psi: d<psi|H_eff|psi>/dW for the
+        two site tensors of the MPO (each half of the symmetric derivative)."""
+        import torch
+        bl, br = self.bonds[i], self.bonds[i + 2]
+        Lb, Rb = X.Bond(bl), X.Bond(br)
+        L, R = self.eng.left[i], self.eng.right[i + 2]
+        vjp = self.eng.vjp_plan(i, bl, br)
+        psi = torch.from_numpy(X.pack_psi(Lb, Rb, psi0)).to(self.device)
+        X.normalize(psi, self._gws)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        g_psi = torch.empty_like(psi)
+        g_L, g_R = torch.empty(max(L.numel(), 1), **f64), torch.empty(max(R.numel(), 1), **f64)
+        g_w1 = torch.empty(max(16 * vjp.nnz1, 1), **f64)
+        g_w2 = torch.empty(max(16 * vjp.nnz2, 1), **f64)
+        vjp.prepare(L, R)
+        vjp.backward(L, R, psi, psi, g_psi, g_L, g_R, g_w1, g_w2)
+        # with cotangent psi the W parts of the VJP are d<psi|H_eff|psi>/dW at fixed psi,
+        # and g_psi = H_eff^T psi gives E = <psi, g_psi>
+        energy = float(torch.dot(psi, g_psi))
+        for site, gw, nnz in ((i, g_w1, vjp.nnz1), (i + 1, g_w2, vjp.nnz2)):
+            if site not in self._wgrad:
+                self._wgrad[site] = gw[:16 * nnz].view(nnz, 4, 4).cpu().numpy()
+        self.log.append({"pass": "grad", "i": i, "energy": energy})
+        return psi0
+
+    def mpo_gradients(self):
+        """dE/d(MPO values) of E = <MPS|H|MPS> for the current, normalised MPS.
+
+        E depends on the values of site k's MPO tensor only through the two-site
+        H_eff of any pair containing k, so one pass that moves the two-site centre
+        over the chain (splitting without truncation: the bond ranks never exceed M
+        after a sweep) and takes the adjoint of the sigma-vector with cotangent psi
+        at each pair gives every site's gradient.  Must follow a right-to-left pass
+        (centre at sites 0, 1).  Returns a list over sites of (nnz, 4, 4) arrays
+        aligned with mpo.sites[k] entries."""
+        import torch
+        if self.center_site != 1:
+            raise RuntimeError("mpo_gradients: run an even number of passes first (centre at sites 0, 1)")
+        self._wgrad = {}
+        self._gws = torch.zeros(max(X.davidson_ws_bytes(1, 1) // 8, 1), dtype=torch.float64, device=self.device)
+        K = self.K
+        psi0 = contract_two(self.tensors[0], self.center, self.bonds[0], self.bonds[1], self.bonds[2])
+        for i in range(0, K - 1):
+            if i > 0:
+                psi0 = contract_two(self.center, self.tensors[i + 1], self.bonds[i], self.bonds[i + 1],
+                                    self.bonds[i + 2])
+            psi = self._grad_step(i, psi0)
+            if i < K - 2:
+                nb, A, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 0)
+                self.bonds[i + 1] = nb
+                self.tensors[i] = A
+                self.center, self.center_site = C, i + 1
+                self.eng.update_left(i, self.bonds[i], self.bonds[i + 1],
+                                     site_payload(self.bonds[i], self.bonds[i + 1], A, self.device))
+            else:
+                nb, B, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 1)
+                self.bonds[i + 1] = nb
+                self.tensors[i + 1] = B
+                self.center, self.center_site = C, i
+                self.eng.update_right(i + 1, self.bonds[i + 1], self.bonds[i + 2],
+                                      site_payload(self.bonds[i + 1], self.bonds[i + 2], B, self.device))
+        return [self._wgrad[k] for k in range(K)]
+
+    def integral_derivative(self, wgrad, dh, dg):
+        """Directional derivative dE/dt of E(h + t dh, g + t dg) at fixed MPS from the
+        MPO-value gradients: the NC MPO values are affine in the integrals, so the
+        change of every value along (dh, dg) is (W(h + dh) - W(h - dh)) / 2 exactly."""
+        plus = build_nc_mpo(self.h + dh, self.g + dg)
+        minus = build_nc_mpo(self.h - dh, self.g - dg)
+        total = 0.0
+        for k in range(self.K):
+            sp, sm, s0 = plus.sites[k], minus.sites[k], self.mpo.sites[k]
+            if not (np.array_equal(sp.rows, s0.rows) and np.array_equal(sp.cols, s0.cols)
+                    and np.array_equal(sm.rows, s0.rows) and np.array_equal(sm.cols, s0.cols)):
+                raise RuntimeError("integral_derivative: MPO structure changed along the direction")
+            dW = 0.5 * (np.asarray(sp.mats).reshape(-1, 4, 4) - np.asarray(sm.mats).reshape(-1, 4, 4))
+            total += float(np.sum(wgrad[k] * dW))
+        return total
+
+    def one_rdm(self, wgrad):
+        """Spin-summed 1-RDM gamma_pq = <sum_s a+_ps a_qs> of the current MPS as the
+        integral gradient dE/dh (symmetric directions: e_pp, and e_pq + e_qp which
+        gives gamma_pq + gamma_qp = 2 gamma_pq)."""
+        K = self.K
+        gam = np.zeros((K, K))
+        zg = np.zeros_like(self.g)
+        for p in range(K):
+            for q in range(p, K):
+                dh = np.zeros((K, K))
+                dh[p, q] = dh[q, p] = 1.0
+                d = self.integral_derivative(wgrad, dh, zg)
+                gam[p, q] = gam[q, p] = d if p == q else 0.5 * d
+        return gam
 
     def _step(self, i, psi0, pass_id):
         import torch

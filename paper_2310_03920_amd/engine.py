@@ -64,6 +64,11 @@ class Engine:
             self._heff_plans[key] = p
         return p
 
+    def vjp_plan(self, i, bond_i, bond_i2):
+        """Adjoint plan of the sigma-vector at sites (i, i+1) (built per call)."""
+        return X.HeffVjpPlan(bond_i, bond_i2, self.mpo.dq[i], self.mpo.dq[i + 1], self.mpo.dq[i + 2],
+                             self._w[i], self._w[i + 1], t_budget_bytes=self.t_budget).upload(self.device)
+
     def drop_plans(self):
         self._env_plans.clear()
         self._heff_plans.clear()
