@@ -351,9 +351,11 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
     plan = X.HeffPlan(bonds[i], bonds[i + 2], mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2],
                       X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats),
                       X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats),
-                      **opts).upload(device)
+                      n_roots=args.roots, **opts).upload(device)
     lb, rb = X.Bond(bonds[i]), X.Bond(bonds[i + 2])
-    psi = torch.from_numpy(X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2], np.random.default_rng(3)))).to(device)
+    rng = np.random.default_rng(3)
+    psis = [X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2], rng)) for _ in range(args.roots)]
+    psi = torch.from_numpy(X.pack_roots(lb, rb, psis) if args.roots > 1 else psis[0]).to(device)
     sig = torch.empty_like(psi)
     plan.prepare(Lenv, Renv)
     f32 = args.mode != "f64"
@@ -393,7 +395,8 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * avg, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.mode, "data": "synthetic",
         "config": {"workload": f"sigma-vectors only at sites ({i},{i + 1}) of the {mpo.K}-orbital chain, "
-                               f"M={args.bond_dim}", "chunks": int(info.n_chunks), "tiles": int(info.n_tiles),
+                               f"M={args.bond_dim}, {args.roots} vector(s) per call", "roots": args.roots,
+                   "chunks": int(info.n_chunks), "tiles": int(info.n_tiles),
                    "apply_ms_each": ms, "plan_opts": opts, "autotune_s": tune_s},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None},
@@ -419,6 +422,7 @@ def main():
                          "apply: sigma-vectors only at the middle step (profiling), ending with a 512 MiB "
                          "device copy that calibrates HBM byte counters")
     ap.add_argument("--instances", type=int, default=16)
+    ap.add_argument("--roots", type=int, default=1, help="apply workload: vectors per sigma-vector call")
     ap.add_argument("--kseg", type=int, default=0, help="split-K minimum segment (0 = default)")
     ap.add_argument("--variant", type=int, default=None,
                     help="block-GEMM kernel variant (0, 1, 2); default: chosen by the autotuner")

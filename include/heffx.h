@@ -93,7 +93,14 @@ typedef struct {
                                 2 = two LDS buffers, 8-deep (less K padding, more workgroups per CU);
                                 3 = as 1 with persistent workgroups that prefetch their next tile.
                                 Results are identical up to FP rounding order of the padding. */
-    int32_t reserved[6];
+    int32_t n_roots;         /* sigma-vector plans: number of vectors R applied per call (0 = 1, at
+                                most 64; the state-averaged multi-root form of Sec. II.A.3).  psi and
+                                sigma then hold, in every column block (s2, ir), the R roots side by
+                                side: element (row, rho, r) at R*off + row*R*dim(ir) + rho*dim(ir) + r,
+                                off = the single-root offset of the column block; the second GEMM
+                                round runs on R times the columns.  diag stays single-root.  Adjoint
+                                plans need R = 1. */
+    int32_t reserved[5];
 } hx_plan_opts;
 
 typedef struct {

@@ -43,7 +43,7 @@ class HxMpoSite(ctypes.Structure):
 
 class HxPlanOpts(ctypes.Structure):
     _fields_ = [("t_budget_bytes", c_int64), ("split_kseg_min", c_int32), ("kernel_variant", c_int32),
-                ("reserved", c_int32 * 6)]
+                ("n_roots", c_int32), ("reserved", c_int32 * 5)]
 
 
 class HxPlanInfo(ctypes.Structure):
@@ -230,6 +230,39 @@ def unpack_env(bond, ops_dq, flat):
     return res
 
 
+def pack_roots(lbond, rbond, flats):
+    """R single-root payloads -> the multi-root layout (roots side by side per column block)."""
+    keys, off = psi_layout(lbond, rbond)
+    R = len(flats)
+    out = np.zeros(int(off[-1]) * R)
+    cols = {}
+    for i, (il, s1, s2, ir) in enumerate(keys):
+        cols.setdefault((s2, ir), []).append(i)
+    for (s2, ir), idx in cols.items():
+        dr = rbond.sectors[ir][1]
+        a, b = int(off[idx[0]]), int(off[idx[-1] + 1])
+        rows = (b - a) // dr
+        blk = np.stack([np.asarray(f[a:b]).reshape(rows, dr) for f in flats], axis=1)  # rows x R x dr
+        out[R * a:R * b] = blk.ravel()
+    return out
+
+
+def unpack_roots(lbond, rbond, flat, R):
+    keys, off = psi_layout(lbond, rbond)
+    outs = [np.zeros(int(off[-1])) for _ in range(R)]
+    cols = {}
+    for i, (il, s1, s2, ir) in enumerate(keys):
+        cols.setdefault((s2, ir), []).append(i)
+    for (s2, ir), idx in cols.items():
+        dr = rbond.sectors[ir][1]
+        a, b = int(off[idx[0]]), int(off[idx[-1] + 1])
+        rows = (b - a) // dr
+        blk = np.asarray(flat[R * a:R * b]).reshape(rows, R, dr)
+        for rho in range(R):
+            outs[rho][a:b] = blk[:, rho, :].ravel()
+    return outs
+
+
 def pack_psi(lbond, rbond, psi):
     keys, off = psi_layout(lbond, rbond)
     out = np.zeros(int(off[-1]))
@@ -310,22 +343,24 @@ class Plan:
             pass
 
 
-def _opts(t_budget_bytes=0, split_kseg_min=0, kernel_variant=0):
+def _opts(t_budget_bytes=0, split_kseg_min=0, kernel_variant=0, n_roots=1):
     o = HxPlanOpts()
     o.t_budget_bytes = int(t_budget_bytes)
     o.split_kseg_min = int(split_kseg_min)
     o.kernel_variant = int(kernel_variant)
+    o.n_roots = int(n_roots)
     return o
 
 
 class HeffPlan(Plan):
     def __init__(self, lbond, rbond, Ldq, mid_dq, Rdq, W1, W2, t_budget_bytes=0, split_kseg_min=0,
-                 kernel_variant=0):
+                 kernel_variant=0, n_roots=1):
         lb, rb = (b if isinstance(b, Bond) else Bond(b) for b in (lbond, rbond))
         Lo, Mo, Ro = OpSet(Ldq), OpSet(mid_dq), OpSet(Rdq)
         w1 = W1 if isinstance(W1, MpoSite) else MpoSite.from_entries(W1)
         w2 = W2 if isinstance(W2, MpoSite) else MpoSite.from_entries(W2)
-        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant)
+        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant, n_roots)
+        self.n_roots = int(n_roots)
         h = c_void_p()
         check(lib().hx_heff_plan_create(ctypes.byref(lb.c), ctypes.byref(rb.c), ctypes.byref(Lo.c),
                                         ctypes.byref(Mo.c), ctypes.byref(Ro.c), ctypes.byref(w1.c),

@@ -144,6 +144,7 @@ struct Plan {
     int64_t split_kseg_min = 2048;
     int variant = 0;            // block-GEMM pipeline variant (see hx_plan_opts.kernel_variant)
     int kstage = 16;            // K-stage depth of that variant; task K is padded to it
+    int n_roots = 1;            // vectors per sigma-vector call (roots side by side in column blocks)
     double flops_apply = 0, flops_prepare = 0, bytes_apply = 0;
     int64_t n_tasks_apply = 0, n_tiles_apply = 0;
     int n_chunks = 0, n_mixed = 0;

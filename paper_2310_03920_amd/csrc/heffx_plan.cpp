@@ -414,6 +414,12 @@ static int apply_opts(Plan& P, const hx_plan_opts* o) {
     }
     P.variant = v;
     P.kstage = v == 2 ? 8 : 16;
+    const int r = (o && o->n_roots > 0) ? o->n_roots : 1;
+    if (r > 64) {
+        set_error("plan options: n_roots must be at most 64");
+        return HX_EINVAL;
+    }
+    P.n_roots = r;
     return HX_OK;
 }
 
@@ -660,7 +666,8 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
     }
     EnvLayout Ll = env_layout(lb, Lo), Rl = env_layout(rb, Ro);
     PsiLayout psi = psi_layout(lb, rb);
-    P.psi_nnz = psi.nnz;
+    const int R = P.n_roots;  // roots side by side in every column block (see heffx.h)
+    P.psi_nnz = psi.nnz * R;
     P.in_nnz = Ll.op_off.back();
     P.in2_nnz = Rl.op_off.back();
 
@@ -711,7 +718,8 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                 const PsiCol& pc = psi.cols[ci];
                 int irp = rb.find(rb.qn[pc.ir][0] + tr.m.dn, rb.qn[pc.ir][1] + tr.m.ds);
                 if (irp < 0) continue;
-                if (seen.emplace((int64_t)tr.so * 65536 + irp, 1).second) tsize[b] += (int64_t)pc.rows * rb.dim[irp];
+                if (seen.emplace((int64_t)tr.so * 65536 + irp, 1).second)
+                    tsize[b] += (int64_t)pc.rows * rb.dim[irp] * R;
             }
     }
     int64_t budget = default_budget(opts);
@@ -766,33 +774,37 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                     auto it = tidx.find(key);
                     int ti;
                     if (it == tidx.end()) {
-                        ti = (int)tblocks.size();
+                        // one T block (rows x R*np, roots side by side), one output block per root
+                        ti = (int)tinfo.size();
                         tidx[key] = ti;
-                        OutBlockTasks ob;
-                        ob.coff = toff;
-                        ob.ldc = rb.dim[irp];
-                        ob.m = pc.rows;
-                        ob.n = rb.dim[irp];
-                        tblocks.push_back(std::move(ob));
+                        for (int rho = 0; rho < R; ++rho) {
+                            OutBlockTasks ob;
+                            ob.coff = toff + (int64_t)rho * rb.dim[irp];
+                            ob.ldc = R * rb.dim[irp];
+                            ob.m = pc.rows;
+                            ob.n = rb.dim[irp];
+                            tblocks.push_back(std::move(ob));
+                        }
                         tinfo.push_back({b, cj, tr.so, irp, toff});
-                        toff += (int64_t)pc.rows * rb.dim[irp];
+                        toff += (int64_t)pc.rows * rb.dim[irp] * R;
                     } else {
                         ti = it->second;
-                        if (tblocks[ti].m != pc.rows) {
+                        if (tblocks[(size_t)ti * R].m != pc.rows) {
                             set_error("internal: stacked intermediate rows inconsistent");
                             return HX_EINVAL;
                         }
                     }
-                    Task t;
-                    t.aoff = pc.off;
-                    t.lda = rb.dim[pc.ir];
-                    const int ta_ = SP_PSI;
-                    t.boff = tr.m.base + sl.rel[pc.ir];
-                    t.ldb = rb.dim[pc.ir];
-                    t.set_spaces(ta_, tr.m.space);
-                    t.k = rb.dim[pc.ir];
+                    for (int rho = 0; rho < R; ++rho) {
+                        Task t;
+                        t.aoff = pc.off * R + (int64_t)rho * rb.dim[pc.ir];
+                        t.lda = R * rb.dim[pc.ir];
+                        t.boff = tr.m.base + sl.rel[pc.ir];
+                        t.ldb = rb.dim[pc.ir];
+                        t.set_spaces(SP_PSI, tr.m.space);
+                        t.k = rb.dim[pc.ir];
                         t.alpha = tr.m.alpha;
-                    tblocks[ti].tasks.push_back(t);
+                        tblocks[(size_t)ti * R + rho].tasks.push_back(t);
+                    }
                 }
             }
         }
@@ -803,10 +815,10 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
         std::vector<OutBlockTasks> sblocks(psi.blocks.size());
         for (size_t i = 0; i < psi.blocks.size(); ++i) {
             const PsiBlock& pb = psi.blocks[i];
-            sblocks[i].coff = pb.off;
-            sblocks[i].ldc = rb.dim[pb.ir];
+            sblocks[i].coff = pb.off * R;  // all roots of the block: one GEMM with R x the columns
+            sblocks[i].ldc = R * rb.dim[pb.ir];
             sblocks[i].m = lb.dim[pb.il];
-            sblocks[i].n = rb.dim[pb.ir];
+            sblocks[i].n = R * rb.dim[pb.ir];
         }
         for (const TInfo& ti : tinfo) {
             const PsiCol& pc = psi.cols[ti.col];
@@ -826,8 +838,8 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                     t.aoff = tr.m.base + sl.rel[il];
                     t.lda = lb.dim[il];
                     const int ta_ = tr.m.space;
-                    t.boff = ti.off + (int64_t)roff * rb.dim[ti.irp];
-                    t.ldb = rb.dim[ti.irp];
+                    t.boff = ti.off + (int64_t)roff * rb.dim[ti.irp] * R;
+                    t.ldb = R * rb.dim[ti.irp];
                     t.set_spaces(ta_, SP_WS);
                     t.k = lb.dim[il];
                         t.alpha = tr.m.alpha;
@@ -851,7 +863,7 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
             for (auto& tr : MR.trans[b]) seen[{tr.m.space, tr.m.base}] = rshift(tr.m.dn, tr.m.ds).size;
         }
         for (auto& kv : seen) ob += 8.0 * kv.second;
-        P.bytes_apply = ob + 16.0 * psi.nnz + tbytes;
+        P.bytes_apply = ob + 16.0 * psi.nnz * R + tbytes;
     }
 
     // ---- diagonal: diag[l,s1,s2,r](x,y) = sum_b DL[(l,s1)][x,b] DR[(s2,r)][b,y]
@@ -1099,6 +1111,10 @@ static int build_heff_vjp(Plan& P, const Bond& lb, const Bond& rb, const OpSet& 
     {
         int rc0 = apply_opts(P, opts);
         if (rc0) return rc0;
+    }
+    if (P.n_roots != 1) {
+        set_error("vjp plan: n_roots must be 1");
+        return HX_EUNSUP;
     }
     EnvLayout Ll = env_layout(lb, Lo), Rl = env_layout(rb, Ro);
     PsiLayout psi = psi_layout(lb, rb);
@@ -1721,10 +1737,15 @@ static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
     M.n_chunks = 1;
     M.variant = in.empty() ? 0 : in[0]->variant;
     M.kstage = in.empty() ? 16 : in[0]->kstage;
+    M.n_roots = in.empty() ? 1 : in[0]->n_roots;
     std::vector<std::array<int64_t, SP_N>> off(in.size());
     int64_t o_psi = 0, o_L = 0, o_R = 0, o_ws = 0, o_tab = 0;
     for (size_t i = 0; i < in.size(); ++i) {
         const Plan& P = *in[i];
+        if (P.n_roots != in[0]->n_roots) {
+            set_error("plan_batch: instances have different n_roots");
+            return HX_EUNSUP;
+        }
         if (P.variant != M.variant) {
             set_error("plan_batch: instances use different kernel variants");
             return HX_EUNSUP;

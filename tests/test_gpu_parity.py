@@ -116,6 +116,30 @@ def test_heff_apply_kernel_variants(device, variant):
     _close(res["diag"], mps.two_site_blocks_from_dense(d, lb, rb, two_site_blocks(lb, rb)))
 
 
+@pytest.mark.parametrize("roots,variant", [(3, 0), (2, 1)])
+def test_heff_apply_multi_root(device, roots, variant):
+    """R vectors per call (roots side by side in every column block): each root's
+    sigma equals the oracle's."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    print(f"[heff_apply multi-root] R={roots} variant={variant}", flush=True)
+    lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = _problem(1, True)
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, kernel_variant=variant, n_roots=roots).upload(device)
+    rng = np.random.default_rng(31)
+    psis = [psi] + [random_psi(lb, rb, rng) for _ in range(roots - 1)]
+    pm = torch.from_numpy(X.pack_roots(lbB, rbB, [X.pack_psi(lbB, rbB, q) for q in psis])).to(device)
+    assert pm.numel() == plan.info.psi_nnz
+    Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
+    Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
+    sm = torch.full_like(pm, float("nan"))
+    plan.prepare(Lt, Rt)
+    plan.apply(Lt, Rt, pm, sm)
+    torch.cuda.synchronize()
+    for q, flat in zip(psis, X.unpack_roots(lbB, rbB, sm.cpu().numpy(), roots)):
+        _close(X.unpack_psi(lbB, rbB, flat), _dense_sigma(lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, q))
+
+
 def test_heff_diag_random_operands(device):
     print("[heff_diag]", flush=True)
     lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = _problem(4, True)
