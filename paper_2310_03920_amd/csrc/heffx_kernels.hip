@@ -168,6 +168,7 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     Cursor<T, TA, TB, NSP, KSV> cur;
     int lm = 0, ln = 0, lr0 = 0, lc0 = 0;       // extent and origin of the loader's tile
     int krem_ld = 0, m_ld = 0, n_ld = 0;         // valid depth / extent of the held stage
+    int kst0 = 0, kst1 = 0;                      // valid depth of the stage in LDS buffer 0 / 1
     auto bind_loader = [&](const Tile& x) {
         lm = x.m;
         ln = x.n;
@@ -208,6 +209,10 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         n_ld = ln;
     };
     auto store_stage = [&](int buf) {
+        if (buf == 0)
+            kst0 = krem_ld;
+        else
+            kst1 = krem_ld;
 #pragma unroll
         for (int e = 0; e < NE; ++e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
@@ -247,6 +252,9 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
                 if constexpr (r1c && c1c)
                     acc11 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc11, 0, 0, 0);
             } else {
+                // 4-deep steps past the stage's valid depth (the zero padding of a
+                // task's last stage) are skipped: a uniform branch per step
+                const int kcur = buf == 0 ? kst0 : kst1;
                 constexpr int NK = KSV / 4;
                 T a0[NK], a1[NK], b0[NK], b1[NK];
                 auto rd = [&](int ks) {
@@ -259,7 +267,8 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
                 rd(0);
 #pragma unroll
                 for (int ks = 0; ks < NK; ++ks) {
-                    if (ks + 1 < NK) rd(ks + 1);
+                    if (ks * 4 >= kcur) break;
+                    if (ks + 1 < NK && (ks + 1) * 4 < kcur) rd(ks + 1);
                     if constexpr (std::is_same<T, double>::value) {
                         acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], b0[ks], acc00, 0, 0, 0);
                         if constexpr (c1c) acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], b1[ks], acc01, 0, 0, 0);
