@@ -66,6 +66,25 @@ def heff_apply(Ld, W1, W2, Rd, psi):
     return np.einsum("czw,cxsuw->xsuz", Rd, z, optimize=True)
 
 
+def heff1_apply(Ld, W, Rd, psi1):
+    """One-site sigma (the one-site sweep, Sec. II.A.2) for dense L[a,l',l], W[a,b,s',s],
+    R[b,r',r], psi1[l,s,r]:  sigma[x,s,z] = sum L[a,x,y] W[a,b,s,t] R[b,z,w] psi1[y,t,w]."""
+    x = np.einsum("axy,ytw->axtw", Ld, psi1, optimize=True)
+    y = np.einsum("abst,axtw->bxsw", W, x, optimize=True)
+    return np.einsum("bzw,bxsw->xsz", Rd, y, optimize=True)
+
+
+def heff1_matrix_kron(Ld, W, Rd):
+    """Brute force: H_eff = sum_ab kron(L_a, W_ab, R_b) (tiny sizes only)."""
+    n = Ld.shape[1] * 4 * Rd.shape[1]
+    H = np.zeros((n, n))
+    for a in range(Ld.shape[0]):
+        for b in range(W.shape[1]):
+            if np.any(W[a, b]):
+                H += np.kron(np.kron(Ld[a], W[a, b]), Rd[b])
+    return H
+
+
 def heff_vjp(Ld, W1, W2, Rd, psi, g):
     """Vector-Jacobian products of sigma = heff_apply(L, W1, W2, R, psi) with the
     cotangent g[x,s,u,z]: the derivatives of <g, sigma> with respect to each

@@ -123,3 +123,31 @@ class Embedding:
         """Dense P^T H P over the listed two-site blocks."""
         P = self.embedding_matrix(keys)
         return P.T @ (self.H @ P)
+
+
+class Embedding1:
+    """P for the one-site step at site i (left basis x site x right basis), restricted
+    to the target sector: H_eff := P^T H P by definition, without an MPO."""
+
+    def __init__(self, h, g, N, twosz, left_tensors, right_tensors, bonds, i):
+        K = h.shape[0]
+        self.K, self.i, self.bonds = K, i, bonds
+        self.Lmat = left_basis(left_tensors, bonds)              # (4^i, D_i)
+        self.Rmat = right_basis(right_tensors, bonds, i + 1)    # (D_{i+1}, 4^{K-i-1})
+        self.dets = fock.sector_dets(K, N, twosz)
+        self.pidx = fock.product_index(self.dets, K)
+        self.H = fock.hamiltonian(h, g, self.dets)
+
+    def to_fock(self, psi1_dense):
+        phi = np.einsum("xl,lsr,ry->xsy", self.Lmat, psi1_dense, self.Rmat)
+        return phi.ravel()[self.pidx]
+
+    def from_fock(self, vec):
+        full = np.zeros(4 ** self.K)
+        full[self.pidx] = vec
+        phi = full.reshape(self.Lmat.shape[0], 4, self.Rmat.shape[1])
+        return np.einsum("xl,xsy,ry->lsr", self.Lmat, phi, self.Rmat)
+
+    def apply(self, psi1_dense):
+        """sigma = P^T H P psi on dense (D_i, 4, D_{i+1}) arrays."""
+        return self.from_fock(self.H @ self.to_fock(psi1_dense))

@@ -14,6 +14,7 @@ from synth import (bond_sector_tables, hubbard_integrals, make_integrals,
 from synth.blocks import random_env, random_psi, random_site_ops, random_site_tensor, two_site_blocks
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+SITE_N, SITE_S = (0, 1, 1, 2), (0, 1, -1, 0)  # (N, 2Sz) of [empty, alpha, beta, alpha-beta]
 
 
 # ---------------------------------------------------------------- Fock space
@@ -252,6 +253,50 @@ def test_sigma_rows_match_dense_definition():
         for (s2, ir), vec in acc.items():
             full[s2, ro[ir]:ro[ir] + len(vec)] += vec
         np.testing.assert_allclose(full, s[lo[il] + x, s1], atol=1e-12)
+
+
+def test_one_site_sigma_matches_kron_bruteforce_and_identity_mpo():
+    rng = np.random.default_rng(8)
+    A, B, Dl, Dr = 3, 4, 5, 6
+    L, W, R = rng.standard_normal((A, Dl, Dl)), rng.standard_normal((A, B, 4, 4)), rng.standard_normal((B, Dr, Dr))
+    psi = rng.standard_normal((Dl, 4, Dr))
+    s = contract.heff1_apply(L, W, R, psi)
+    np.testing.assert_allclose(s.ravel(), contract.heff1_matrix_kron(L, W, R) @ psi.ravel(), atol=1e-11)
+    # identity MPO: sigma[:, s, :] = L psi[:, s, :] R^T
+    s1 = contract.heff1_apply(L[:1], np.eye(4)[None, None], R[:1], psi)
+    for t in range(4):
+        np.testing.assert_allclose(s1[:, t, :], L[0] @ psi[:, t, :] @ R[0].T, atol=1e-12)
+
+
+@pytest.mark.parametrize("K,i", [(5, 2), (6, 2), (6, 3)])
+def test_one_site_embedding_complete_basis_gives_fci(K, i):
+    """Where bond i spans the whole left space and bond i+1 the whole right space
+    (centre sites: i >= (K-2)/2 and i <= K/2), the one-site P^T H P holds the ground
+    state: its lowest eigenvalue is the FCI energy, and P is an isometry."""
+    h, g = make_integrals(K, seed=4)
+    tsz = K % 2
+    bonds = bond_sector_tables(K, K, tsz, 10 ** 6)
+    left = random_left_canonical_mps(bonds, 3)
+    right = random_right_canonical_mps(bonds, 4)
+    emb = mps.Embedding1(h, g, K, tsz, left[:i], right[i + 1:], bonds, i)
+    lb, rb = bonds[i], bonds[i + 1]
+    lo, Dl = mps.bond_offsets(lb)
+    ro, Dr = mps.bond_offsets(rb)
+    cols = []
+    for il, (ql, ml) in enumerate(lb):
+        for s_ in range(4):
+            for ir, (qr, mr) in enumerate(rb):
+                if (ql[0] + SITE_N[s_], ql[1] + SITE_S[s_]) != tuple(qr):
+                    continue
+                for x in range(ml):
+                    for y in range(mr):
+                        e = np.zeros((Dl, 4, Dr))
+                        e[lo[il] + x, s_, ro[ir] + y] = 1.0
+                        cols.append(emb.to_fock(e))
+    P = np.array(cols).T
+    np.testing.assert_allclose(P.T @ P, np.eye(P.shape[1]), atol=1e-10)
+    w = np.linalg.eigvalsh(P.T @ (emb.H @ P))
+    assert w[0] == pytest.approx(fock.fci_energy(h, g, K, tsz), abs=1e-10)
 
 
 def _dense_random_operands(seed):
