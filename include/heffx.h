@@ -183,6 +183,25 @@ int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws
 int hx_env_update(const hx_plan* plan, const double* env_in, const double* site, void* ws,
                   double* env_out, hx_stream stream);
 
+/* ---- one-site sweep ---------------------------------------------------------- */
+
+/* One-site wavefunction layout (the one-site sweep of Sec. II.A.2): column blocks ir
+ * ascending; inside one, row blocks (il, s) ascending with q(il) + q(s) = q(ir);
+ * block (dim il x dim ir) row-major.  keys: (il, s, ir) as 3 int32; otherwise as
+ * hx_psi_layout. */
+int64_t hx_psi1_layout(const hx_bond* lbond, const hx_bond* rbond, int64_t max_blocks,
+                       int32_t* keys, int64_t* off);
+
+/* Plan of the one-site sigma = sum_{a,b} L_a (x) W_ab (x) R_b psi between bond lbond
+ * (left environment Lops) and bond rbond (right environment Rops), W the MPO tensor of
+ * the site (rows Lops, cols Rops).  Used with hx_plan_get_info / upload / destroy,
+ * hx_heff_prepare, hx_heff_apply, hx_heff_diag, the FP32/BF16 entry points and graphs,
+ * exactly as a two-site plan, with psi in the hx_psi1_layout layout.  Same kernels:
+ * the absent second site makes the right mixed operators the R_b themselves. */
+int hx_heff1_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops,
+                         const hx_opset* Rops, const hx_mpo_site* W, const hx_plan_opts* opts,
+                         hx_plan** out);
+
 /* ---- adjoint (vector-Jacobian products of the sigma-vector) ----------------- */
 
 /* Build (host only) the plan of the VJP of sigma = H_eff(L, W1, W2, R) psi, same

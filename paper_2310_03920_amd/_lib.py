@@ -24,6 +24,7 @@ EXPORTED = (
     "hx_normalize", "hx_convert_f64_f32", "hx_convert_f32_f64", "hx_heff_lower_f32", "hx_heff_apply_f32",
     "hx_heff_plan_batch", "hx_batch_offsets", "hx_heff_graph_create", "hx_graph_launch", "hx_graph_destroy",
     "hx_heff_vjp_plan_create", "hx_heff_apply_backward", "hx_heff_apply_bf16", "hx_davidson_restart2",
+    "hx_heff1_plan_create", "hx_psi1_layout",
     "hx_last_error",
 )
 
@@ -99,6 +100,10 @@ def lib():
     L.hx_heff_plan_batch.argtypes = [P(c_void_p), c_int32, P(c_void_p)]
     L.hx_batch_offsets.argtypes = [c_void_p, c_int32, P(c_int64), P(c_int64), P(c_int64)]
     L.hx_heff_vjp_plan_create.argtypes = L.hx_heff_plan_create.argtypes
+    L.hx_heff1_plan_create.argtypes = [P(HxBond), P(HxBond), P(HxOpset), P(HxOpset), P(HxMpoSite), P(HxPlanOpts),
+                                       P(c_void_p)]
+    L.hx_psi1_layout.argtypes = [P(HxBond), P(HxBond), c_int64, P(c_int32), P(c_int64)]
+    L.hx_psi1_layout.restype = c_int64
     L.hx_heff_apply_backward.argtypes = [c_void_p] * 11 + [c_void_p]
     L.hx_heff_graph_create.argtypes = [c_void_p, c_int32] + [c_void_p] * 5 + [P(c_void_p)]
     L.hx_graph_launch.argtypes = [c_void_p, c_void_p]
@@ -180,6 +185,38 @@ def psi_layout(lbond, rbond):
     if n2 < 0:
         check(int(n2), "psi_layout")
     return [tuple(int(x) for x in k) for k in keys[:n]], off
+
+
+def psi1_layout(lbond, rbond):
+    n = lib().hx_psi1_layout(ctypes.byref(lbond.c), ctypes.byref(rbond.c), 0, None, None)
+    if n < 0:
+        check(int(n), "psi1_layout")
+    keys = np.zeros((max(n, 1), 3), np.int32)
+    off = np.zeros(n + 1, np.int64)
+    n2 = lib().hx_psi1_layout(ctypes.byref(lbond.c), ctypes.byref(rbond.c), n,
+                              keys.ctypes.data_as(POINTER(c_int32)), off.ctypes.data_as(POINTER(c_int64)))
+    if n2 < 0:
+        check(int(n2), "psi1_layout")
+    return [tuple(int(x) for x in k) for k in keys[:n]], off
+
+
+def pack_psi1(lbond, rbond, t):
+    """One-site tensor {(il, s, ir): block} -> flat payload in the one-site layout."""
+    keys, off = psi1_layout(lbond, rbond)
+    out = np.zeros(int(off[-1]))
+    for i, k in enumerate(keys):
+        if k in t:
+            out[off[i]:off[i + 1]] = t[k].ravel()
+    return out
+
+
+def unpack_psi1(lbond, rbond, flat):
+    keys, off = psi1_layout(lbond, rbond)
+    res = {}
+    for i, (il, s, ir) in enumerate(keys):
+        res[(il, s, ir)] = np.asarray(flat[off[i]:off[i + 1]]).reshape(lbond.sectors[il][1],
+                                                                      rbond.sectors[ir][1]).copy()
+    return res
 
 
 def site_layout(lbond, rbond):
@@ -398,6 +435,24 @@ class HeffPlan(Plan):
         """BF16 block products on the FP32 operands of lower_f32."""
         check(lib().hx_heff_apply_bf16(self.h, _ptr(self.L32), _ptr(self.R32), _ptr(self.ws32), _ptr(psi32),
                                        _ptr(sigma32), _stream()), "heff_apply_bf16")
+
+
+class Heff1Plan(HeffPlan):
+    """One-site sigma-vector plan (psi in the one-site layout)."""
+
+    def __init__(self, lbond, rbond, Ldq, Rdq, W, t_budget_bytes=0, split_kseg_min=0, kernel_variant=0,
+                 n_roots=1):
+        lb, rb = (b if isinstance(b, Bond) else Bond(b) for b in (lbond, rbond))
+        Lo, Ro = OpSet(Ldq), OpSet(Rdq)
+        w = W if isinstance(W, MpoSite) else MpoSite.from_entries(W)
+        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant, n_roots)
+        self.n_roots = int(n_roots)
+        h = c_void_p()
+        check(lib().hx_heff1_plan_create(ctypes.byref(lb.c), ctypes.byref(rb.c), ctypes.byref(Lo.c),
+                                         ctypes.byref(Ro.c), ctypes.byref(w.c), ctypes.byref(opts),
+                                         ctypes.byref(h)), "heff1_plan_create")
+        Plan.__init__(self, h, (lb, rb, Lo, Ro, w))
+        self.lbond, self.rbond = lb, rb
 
 
 class HeffVjpPlan(Plan):

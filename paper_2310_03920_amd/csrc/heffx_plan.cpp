@@ -158,10 +158,12 @@ struct PsiLayout {
 };
 
 // Blocks ordered by column block (s2, ir), then by (il, s1): each column block is a
-// contiguous dense matrix and each block a contiguous row range of it.
-static PsiLayout psi_layout(const Bond& lb, const Bond& rb) {
+// contiguous dense matrix and each block a contiguous row range of it.  With
+// one_site the second site is absent: s2 = 0 only, with quantum number (0, 0),
+// i.e. the one-site tensor (il, s1, ir) grouped by ir.
+static PsiLayout psi_layout(const Bond& lb, const Bond& rb, bool one_site = false) {
     PsiLayout P;
-    for (int s2 = 0; s2 < 4; ++s2)
+    for (int s2 = 0; s2 < (one_site ? 1 : 4); ++s2)
         for (int ir = 0; ir < rb.nsec(); ++ir) {
             PsiCol c;
             c.s2 = s2;
@@ -656,16 +658,30 @@ static bool check_task_index_range(const Plan& P) {
     return true;
 }
 
+// one_site: the one-site H_eff (Sec. II.A.2) -- the second site is absent, Mo == Ro and
+// e2 is ignored: the right "mixed" operator of middle operator b is R_b itself.
 static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, const OpSet& Mo,
-                      const OpSet& Ro, const std::vector<Entry>& e1, const std::vector<Entry>& e2,
-                      const hx_plan_opts* opts) {
+                      const OpSet& Ro, const std::vector<Entry>& e1, const std::vector<Entry>& e2_in,
+                      const hx_plan_opts* opts, bool one_site = false) {
     P.kind = PK_HEFF;
     {
         int rc0 = apply_opts(P, opts);
         if (rc0) return rc0;
     }
     EnvLayout Ll = env_layout(lb, Lo), Rl = env_layout(rb, Ro);
-    PsiLayout psi = psi_layout(lb, rb);
+    PsiLayout psi = psi_layout(lb, rb, one_site);
+    std::vector<Entry> e2_one;
+    if (one_site) {  // identity coupling b -> b on the absent site
+        for (int b2 = 0; b2 < (int)Ro.dq.size(); ++b2) {
+            Entry en;
+            en.src = b2;
+            en.tgt = b2;
+            for (double& v : en.v) v = 0.0;
+            en.v[0] = 1.0;
+            e2_one.push_back(en);
+        }
+    }
+    const std::vector<Entry>& e2 = one_site ? e2_one : e2_in;
     const int R = P.n_roots;  // roots side by side in every column block (see heffx.h)
     P.psi_nnz = psi.nnz * R;
     P.in_nnz = Ll.op_off.back();
@@ -1973,6 +1989,53 @@ int hx_heff_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_ops
     finalize_tables(*P);
     *out = reinterpret_cast<hx_plan*>(P);
     return HX_OK;
+}
+
+int hx_heff1_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops, const hx_opset* Rops,
+                         const hx_mpo_site* W, const hx_plan_opts* opts, hx_plan** out) {
+    if (!out) {
+        set_error("heff1_plan_create: null output");
+        return HX_EINVAL;
+    }
+    *out = nullptr;
+    Bond lb, rb;
+    OpSet Lo, Ro;
+    if (!parse_bond(lbond, lb, "heff1 left bond") || !parse_bond(rbond, rb, "heff1 right bond")) return HX_EINVAL;
+    if (!parse_ops(Lops, Lo, "heff1 Lops") || !parse_ops(Rops, Ro, "heff1 Rops")) return HX_EINVAL;
+    std::vector<Entry> e1;
+    if (!parse_mpo(W, Lo, Ro, true, e1, "heff1 W")) return HX_EINVAL;
+    Plan* P = new Plan();
+    int rc = build_heff(*P, lb, rb, Lo, Ro, Ro, e1, {}, opts, true);
+    if (rc != HX_OK) {
+        delete P;
+        return rc;
+    }
+    finalize_tables(*P);
+    *out = reinterpret_cast<hx_plan*>(P);
+    return HX_OK;
+}
+
+int64_t hx_psi1_layout(const hx_bond* lbond, const hx_bond* rbond, int64_t max_blocks, int32_t* keys,
+                       int64_t* off) {
+    Bond lb, rb;
+    if (!parse_bond(lbond, lb, "psi1_layout left bond") || !parse_bond(rbond, rb, "psi1_layout right bond"))
+        return HX_EINVAL;
+    PsiLayout P = psi_layout(lb, rb, true);
+    const int64_t n = (int64_t)P.blocks.size();
+    if (keys && off) {
+        if (max_blocks < n) {
+            set_error("psi1_layout: max_blocks too small");
+            return HX_EINVAL;
+        }
+        for (int64_t i = 0; i < n; ++i) {
+            keys[3 * i] = P.blocks[i].il;
+            keys[3 * i + 1] = P.blocks[i].s1;
+            keys[3 * i + 2] = P.blocks[i].ir;
+            off[i] = P.blocks[i].off;
+        }
+        off[n] = P.nnz;
+    }
+    return n;
 }
 
 int hx_heff_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops, const hx_opset* mid,

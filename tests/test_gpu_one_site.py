@@ -1,0 +1,91 @@
+"""One-site sigma-vector (the one-site sweep's H_eff) on the GPU against the oracle.
+
+Tolerance as for the two-site sigma-vector (FP64, 1e-11 of the largest element).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import contract, mps
+from synth import bond_sector_tables, make_integrals, random_left_canonical_mps, random_right_canonical_mps
+from synth.blocks import random_env, random_site_ops, random_site_tensor
+from test_gpu_parity import DQS, _bonds
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-11
+
+
+def _check(got, ref_dense, lb, rb):
+    lo, _ = mps.bond_offsets(lb)
+    ro, _ = mps.bond_offsets(rb)
+    scale = np.abs(ref_dense).max()
+    for (il, s, ir), blk in got.items():
+        ref = ref_dense[lo[il]:lo[il] + blk.shape[0], s, ro[ir]:ro[ir] + blk.shape[1]]
+        assert np.abs(blk - ref).max() <= RTOL * scale, (il, s, ir)
+
+
+@pytest.mark.parametrize("seed,big,variant", [(0, False, 0), (1, True, 1), (2, True, 3)])
+def test_one_site_apply_and_diag_random_operands(device, seed, big, variant):
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    print(f"[heff1] seed={seed} big={big} variant={variant}", flush=True)
+    rng = np.random.default_rng(seed)
+    lb, rb = _bonds(seed, big)
+    Ldq = [DQS[i % len(DQS)] for i in range(7)]
+    Rdq = [DQS[(i * 7 + 3) % len(DQS)] for i in range(7)]
+    L, R = random_env(lb, Ldq, rng), random_env(rb, Rdq, rng)
+    W = random_site_ops(Ldq, Rdq, rng, per_col=3)
+    t = random_site_tensor(lb, rb, rng)
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    plan = X.Heff1Plan(lbB, rbB, Ldq, Rdq, W, kernel_variant=variant, split_kseg_min=16).upload(device)
+    Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
+    Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
+    pt = torch.from_numpy(X.pack_psi1(lbB, rbB, t)).to(device)
+    st = torch.full_like(pt, float("nan"))
+    dt = torch.full_like(pt, float("nan"))
+    plan.prepare(Lt, Rt)
+    plan.apply(Lt, Rt, pt, st)
+    plan.diag(Lt, Rt, dt)
+    torch.cuda.synchronize()
+    Ld, Wd, Rd = contract.dense_env(L, lb), contract.dense_mpo(W, len(Ldq), len(Rdq)), contract.dense_env(R, rb)
+    _check(X.unpack_psi1(lbB, rbB, st.cpu().numpy()), contract.heff1_apply(Ld, Wd, Rd, mps.dense_site_tensor(t, lb, rb)),
+           lb, rb)
+    if not big:  # diag against the brute-force Kronecker matrix
+        shape = (Ld.shape[1], 4, Rd.shape[1])
+        _check(X.unpack_psi1(lbB, rbB, dt.cpu().numpy()),
+               np.diag(contract.heff1_matrix_kron(Ld, Wd, Rd)).reshape(shape), lb, rb)
+
+
+@pytest.mark.parametrize("i", [2, 4])
+def test_one_site_sigma_with_gpu_environments_equals_PtHP(device, i):
+    """NC MPO + GPU environment chain + GPU one-site sigma == P^T H P psi."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.engine import Engine, site_payload
+    from paper_2310_03920_amd.mpo import build_nc_mpo
+    print(f"[heff1 vs PtHP] i={i}", flush=True)
+    K, Mb = 8, 64
+    h, g = make_integrals(K, seed=0)
+    bonds = bond_sector_tables(K, K, 0, Mb)
+    left = random_left_canonical_mps(bonds, 1)
+    right = random_right_canonical_mps(bonds, 2)
+    m = build_nc_mpo(h, g)
+    eng = Engine(m, device=device)
+    eng.init_boundaries()
+    for k in range(i):
+        eng.update_left(k, bonds[k], bonds[k + 1], site_payload(bonds[k], bonds[k + 1], left[k], device))
+    for k in range(K - 1, i, -1):
+        eng.update_right(k, bonds[k], bonds[k + 1], site_payload(bonds[k], bonds[k + 1], right[k], device))
+    lb, rb = X.Bond(bonds[i]), X.Bond(bonds[i + 1])
+    plan = X.Heff1Plan(lb, rb, m.dq[i], m.dq[i + 1], X.MpoSite(m.sites[i].rows, m.sites[i].cols, m.sites[i].mats))
+    plan.upload(device)
+    t = random_site_tensor(bonds[i], bonds[i + 1], np.random.default_rng(7))
+    pt = torch.from_numpy(X.pack_psi1(lb, rb, t)).to(device)
+    st = torch.empty_like(pt)
+    plan.prepare(eng.left[i], eng.right[i + 1])
+    plan.apply(eng.left[i], eng.right[i + 1], pt, st)
+    torch.cuda.synchronize()
+    emb = mps.Embedding1(h, g, K, 0, left[:i], right[i + 1:], bonds, i)
+    ref = emb.apply(mps.dense_site_tensor(t, bonds[i], bonds[i + 1]))
+    _check(X.unpack_psi1(lb, rb, st.cpu().numpy()), ref, bonds[i], bonds[i + 1])

@@ -241,3 +241,13 @@ def test_autotune_signature_depends_on_shape():
     b2 = bond_sector_tables(K, K, 0, 40)
     s3 = A.signature(b2[3], b2[5], m.dq[3], m.dq[4], m.dq[5], *w)
     assert s1 == s2 != s3
+
+
+def test_psi1_layout_groups_site_blocks_by_right_sector():
+    b = bond_sector_tables(8, 8, 0, 64)
+    lb, rb = X.Bond(b[3]), X.Bond(b[4])
+    keys, off = X.psi1_layout(lb, rb)
+    skeys, soff = X.site_layout(lb, rb)
+    assert sorted(keys) == sorted(skeys) and off[-1] == soff[-1]
+    assert keys == sorted(keys, key=lambda k: (k[2], k[0], k[1]))
+    np.testing.assert_array_equal(np.diff(off), [b[3][k[0]][1] * b[4][k[2]][1] for k in keys])
