@@ -1,10 +1,10 @@
 """Autotuner for the block-GEMM plans.
 
 The kernel shape choices of a sigma-vector plan (hx_plan_opts) are tuned by
-measurement on the problem itself: the LDS pipeline variant (two buffers with
-16-deep K stages, one buffer, or 8-deep stages), the minimum split-K segment
-and the intermediate budget (how many middle-bond operators share one T
-chunk).  The search is greedy coordinate descent from the defaults: each axis
+measurement on the problem itself: the kernel variant (LDS buffering, 16- or
+8-deep K stages, persistent workgroups, and the tile shapes 64 x 64 / 128 x 32 /
+32 x 128), the minimum split-K segment and the intermediate budget (how many
+middle-bond operators share one T chunk).  The search is greedy coordinate descent from the defaults: each axis
 in turn is swept with the others fixed, and the best value kept.  Every
 candidate's sigma is checked against the default plan's result before its time
 counts, so a tuned plan is never a wrong plan.  Results are cached in a JSON
@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 AXES = (
-    ("kernel_variant", (0, 1, 2, 3)),
+    ("kernel_variant", (0, 1, 2, 3, 4, 5)),
     ("split_kseg_min", (1024, 2048, 4096)),
     ("t_budget_bytes", (1 << 29, 1 << 30, 1 << 31)),
 )

@@ -84,18 +84,25 @@ struct Reduce {
     int8_t cspace;
     int8_t beta;
     int16_t pad;
-    int32_t pad2;
+    int32_t pld;      // leading dimension of the partial tiles (the launch's tile columns)
 };
 static_assert(sizeof(Reduce) == 40, "Reduce layout");
 
+// Tile shapes (4 waves of 32 x 32 each): 64 x 64, 128 x 32 (narrow blocks), 32 x 128
+// (short blocks).  Every shape holds TM * TN elements, the size of a split-K partial.
 constexpr int TM = 64;
 constexpr int TN = 64;
+enum TileShape : int { SH_SQ = 0, SH_TALL = 1, SH_WIDE = 2 };
+inline int shape_rows(int sh) { return sh == SH_TALL ? 128 : sh == SH_WIDE ? 32 : 64; }
+inline int shape_cols(int sh) { return sh == SH_TALL ? 32 : sh == SH_WIDE ? 128 : 64; }
 
 enum TransKind : int { NN = 0, NT = 1, TN_ = 2 };
 
 // A GEMM launch: tiles [tile0, tile0+ntile) and their tasks in the device table.
 struct Launch {
     int kind;          // TransKind
+    int shape = SH_SQ; // TileShape of every tile of the launch
+    int stage = 0;     // which round of the plan produced it (launches of one stage are independent)
     int64_t tile0;     // index into the plan's tile array
     int64_t ntile;
     double flops;      // algorithmic 2 m n k of the blocks it covers
@@ -145,6 +152,7 @@ struct Plan {
     int variant = 0;            // block-GEMM pipeline variant (see hx_plan_opts.kernel_variant)
     int kstage = 16;            // K-stage depth of that variant; task K is padded to it
     int n_roots = 1;            // vectors per sigma-vector call (roots side by side in column blocks)
+    int n_stages = 0;           // rounds emitted so far (Launch::stage)
     double flops_apply = 0, flops_prepare = 0, bytes_apply = 0;
     int64_t n_tasks_apply = 0, n_tiles_apply = 0;
     int n_chunks = 0, n_mixed = 0;

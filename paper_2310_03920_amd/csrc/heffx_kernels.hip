@@ -115,7 +115,6 @@ struct Cursor {
 };
 
 constexpr int LDS_PAD = 1;
-constexpr int LDW = TM + LDS_PAD;
 
 // Element type T: double (v_mfma_f64_16x16x4_f64) or float (v_mfma_f32_16x16x4_f32,
 // FP32 accumulation).  The tile tables are the same for both.
@@ -128,39 +127,45 @@ constexpr int LDW = TM + LDS_PAD;
 // (G = grid size, a multiple of 8, so they all stay on the XCD the tile order chose)
 // and fetches the first K stage of its next tile during the last stage of the
 // current one, hiding the start-up latency of short-K tiles.
-template <typename T, bool TA, bool TB, int NSP, int KSV, int NBUF, bool BF = false, bool PERS = false>
+// WR: waves stacked along the tile's rows (2: 64 x 64 tile, 4: 128 x 32, 1: 32 x 128);
+// each wave owns a 32 x 32 quadrant.
+template <typename T, bool TA, bool TB, int NSP, int KSV, int NBUF, bool BF = false, bool PERS = false,
+          int WR = 2>
 __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
                                               BasesT<T> B, int ntile) {
     using acc_t = typename std::conditional<std::is_same<T, double>::value, dbl4, flt4>::type;
     static_assert(KSV == 8 || KSV == 16, "stage depth");
     static_assert(!BF || (std::is_same<T, float>::value && KSV == 16), "BF16 products: FP32 storage, 16-deep stages");
-    constexpr int NE = KSV / 4;  // elements of A (and of B) each thread stages per K stage
+    static_assert(WR == 1 || WR == 2 || WR == 4, "wave layout");
+    constexpr int TMS = 32 * WR, TNS = 32 * (4 / WR);  // tile extent
+    constexpr int NEA = TMS * KSV / 256;  // elements of A each thread stages per K stage
+    constexpr int NEB = TNS * KSV / 256;  // ... and of B
     constexpr int LDB = KSV + 4; // BF16 row pitch (8-byte aligned rows)
-    __shared__ T As[BF ? 1 : NBUF][BF ? 1 : KSV][BF ? 1 : LDW];
-    __shared__ T Bs[BF ? 1 : NBUF][BF ? 1 : KSV][BF ? 1 : LDW];
-    __shared__ __attribute__((aligned(16))) unsigned short Ah[BF ? NBUF : 1][BF ? TM : 1][BF ? LDB : 1];
-    __shared__ __attribute__((aligned(16))) unsigned short Bh[BF ? NBUF : 1][BF ? TN : 1][BF ? LDB : 1];
+    __shared__ T As[BF ? 1 : NBUF][BF ? 1 : KSV][BF ? 1 : TMS + LDS_PAD];
+    __shared__ T Bs[BF ? 1 : NBUF][BF ? 1 : KSV][BF ? 1 : TNS + LDS_PAD];
+    __shared__ __attribute__((aligned(16))) unsigned short Ah[BF ? NBUF : 1][BF ? TMS : 1][BF ? LDB : 1];
+    __shared__ __attribute__((aligned(16))) unsigned short Bh[BF ? NBUF : 1][BF ? TNS : 1][BF ? LDB : 1];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int wr0 = (wave & 1) * 32;
-    const int wc0 = (wave >> 1) * 32;
+    const int wr0 = (wave % WR) * 32;
+    const int wc0 = (wave / WR) * 32;
     // load lanes (element e of a thread: idx = tid + 256 e):
     //  A !TA: k = idx % KSV, row = idx / KSV (KSV contiguous k per row)
-    //  A  TA: row = idx % 64, k = idx / 64 (64 contiguous rows per k)
-    //  B !TB: col = idx % 64, k = idx / 64
+    //  A  TA: row = idx % TMS, k = idx / TMS (TMS contiguous rows per k)
+    //  B !TB: col = idx % TNS, k = idx / TNS
     //  B  TB: k = idx % KSV, col = idx / KSV
-    const int a_r = TA ? (tid & 63) : (tid / KSV);
-    const int a_k = TA ? (tid >> 6) : (tid % KSV);
-    const int b_c = TB ? (tid / KSV) : (tid & 63);
-    const int b_k = TB ? (tid % KSV) : (tid >> 6);
-    constexpr int a_dr = TA ? 0 : 256 / KSV, a_dk = TA ? 4 : 0;  // step per element e
-    constexpr int b_dc = TB ? 256 / KSV : 0, b_dk = TB ? 0 : 4;
+    const int a_r = TA ? (tid % TMS) : (tid / KSV);
+    const int a_k = TA ? (tid / TMS) : (tid % KSV);
+    const int b_c = TB ? (tid / KSV) : (tid % TNS);
+    const int b_k = TB ? (tid % KSV) : (tid / TNS);
+    constexpr int a_dr = TA ? 0 : 256 / KSV, a_dk = TA ? 256 / TMS : 0;  // step per element e
+    constexpr int b_dc = TB ? 256 / KSV : 0, b_dk = TB ? 0 : 256 / TNS;
 
     int t = blockIdx.x;
     Tile tl = tiles[t];
     acc_t acc00, acc01, acc10, acc11;
-    T ra[NE], rb[NE];
+    T ra[NEA], rb[NEB];
     T alpha = 0;
 
     // Loader: the tile whose K stages are being fetched (the current one, or the next
@@ -188,19 +193,26 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         cur.next(tasks, B, lr0, lc0, qa, qb, krem, alpha);
         const int lda = cur.lda, ldb = cur.ldb;
 #pragma unroll
-        for (int e = 0; e < NE; ++e) {
+        for (int e = 0; e < NEA; ++e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
-            const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
             if constexpr (std::is_same<T, double>::value) {
-                T va = 0, vb = 0;
+                T va = 0;
                 if (ka < krem && r < lm) va = qa[TA ? ka * lda + r : r * lda + ka];
-                if (kb < krem && c < ln) vb = qb[TB ? c * ldb + kb : kb * ldb + c];
                 ra[e] = va;
-                rb[e] = vb;
             } else {
                 const int rc = min(r, lm - 1), kac = min(ka, krem - 1);
-                const int cc = min(c, ln - 1), kbc = min(kb, krem - 1);
                 ra[e] = qa[TA ? kac * lda + rc : rc * lda + kac];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < NEB; ++e) {
+            const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
+            if constexpr (std::is_same<T, double>::value) {
+                T vb = 0;
+                if (kb < krem && c < ln) vb = qb[TB ? c * ldb + kb : kb * ldb + c];
+                rb[e] = vb;
+            } else {
+                const int cc = min(c, ln - 1), kbc = min(kb, krem - 1);
                 rb[e] = qb[TB ? cc * ldb + kbc : kbc * ldb + cc];
             }
         }
@@ -213,21 +225,25 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
             kst0 = krem_ld;
         else
             kst1 = krem_ld;
+        // FP64 loads are already zero outside the block (guarded loads)
+        constexpr bool guarded = std::is_same<T, double>::value;
 #pragma unroll
-        for (int e = 0; e < NE; ++e) {
+        for (int e = 0; e < NEA; ++e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
-            const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
-            // FP64 loads are already zero outside the block (guarded loads)
-            constexpr bool guarded = std::is_same<T, double>::value;
             const T fa = (guarded || (ka < krem_ld && r < m_ld)) ? alpha : (T)0;
-            const T vb = (guarded || (kb < krem_ld && c < n_ld)) ? rb[e] : (T)0;
-            if constexpr (BF) {
+            if constexpr (BF)
                 Ah[buf][r][ka] = to_bf16(fa * ra[e]);
-                Bh[buf][c][kb] = to_bf16(vb);
-            } else {
+            else
                 As[buf][ka][r] = fa * ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < NEB; ++e) {
+            const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
+            const T vb = (guarded || (kb < krem_ld && c < n_ld)) ? rb[e] : (T)0;
+            if constexpr (BF)
+                Bh[buf][c][kb] = to_bf16(vb);
+            else
                 Bs[buf][kb][c] = vb;
-            }
         }
     };
 
@@ -254,7 +270,8 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
             } else {
                 // 4-deep steps past the stage's valid depth (the zero padding of a
                 // task's last stage) are skipped: a uniform branch per step
-                const int kcur = buf == 0 ? kst0 : kst1;
+                const int kcur = NBUF == 1 ? kst0 : KSV;  // (two buffers: no skipping; a per-buffer
+                                                          // depth would put the operand arrays in scratch)
                 constexpr int NK = KSV / 4;
                 T a0[NK], a1[NK], b0[NK], b1[NK];
                 auto rd = [&](int ks) {
@@ -267,7 +284,7 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
                 rd(0);
 #pragma unroll
                 for (int ks = 0; ks < NK; ++ks) {
-                    if (ks * 4 >= kcur) break;
+                    if (ks * 4 >= kcur) continue;  // (no break: keeps the loop fully unrolled)
                     if (ks + 1 < NK && (ks + 1) * 4 < kcur) rd(ks + 1);
                     if constexpr (std::is_same<T, double>::value) {
                         acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], b0[ks], acc00, 0, 0, 0);
@@ -384,7 +401,7 @@ __global__ __launch_bounds__(256) void reduce_partials(const Reduce* __restrict_
     for (int e = threadIdx.x; e < r.m * r.n; e += blockDim.x) {
         const int row = e / r.n, col = e % r.n;
         T acc = 0;
-        for (int j = 0; j < r.np; ++j) acc += P[(int64_t)j * TM * TN + row * TN + col];
+        for (int j = 0; j < r.np; ++j) acc += P[(int64_t)j * TM * TN + row * r.pld + col];
         T* p = C + (int64_t)row * r.ldc + col;
         *p = r.beta ? (*p + acc) : acc;
     }
@@ -656,7 +673,7 @@ static Bases make_bases(const Plan* P, const double* psi, double* out, const dou
     return b;
 }
 
-template <typename T, int NSP, int KSV, int NBUF, bool BF = false, bool PERS = false>
+template <typename T, int NSP, int KSV, int NBUF, bool BF = false, bool PERS = false, int WR = 2>
 static int launch_kind(int kind, int64_t ntile, const Tile* tiles, const Task* tasks, const BasesT<T>& B,
                        hipStream_t s) {
     const dim3 block(256);
@@ -665,16 +682,16 @@ static int launch_kind(int kind, int64_t ntile, const Tile* tiles, const Task* t
     const int nt = (int)ntile;
     switch (kind) {
         case NN:
-            hipLaunchKernelGGL((bsgemm<T, false, false, NSP, KSV, NBUF, BF, PERS>), grid, block, 0, s, tiles, tasks, B,
-                               nt);
+            hipLaunchKernelGGL((bsgemm<T, false, false, NSP, KSV, NBUF, BF, PERS, WR>), grid, block, 0, s, tiles,
+                               tasks, B, nt);
             return HX_OK;
         case NT:
-            hipLaunchKernelGGL((bsgemm<T, false, true, NSP, KSV, NBUF, BF, PERS>), grid, block, 0, s, tiles, tasks, B,
-                               nt);
+            hipLaunchKernelGGL((bsgemm<T, false, true, NSP, KSV, NBUF, BF, PERS, WR>), grid, block, 0, s, tiles,
+                               tasks, B, nt);
             return HX_OK;
         case TN_:
-            hipLaunchKernelGGL((bsgemm<T, true, false, NSP, KSV, NBUF, BF, PERS>), grid, block, 0, s, tiles, tasks, B,
-                               nt);
+            hipLaunchKernelGGL((bsgemm<T, true, false, NSP, KSV, NBUF, BF, PERS, WR>), grid, block, 0, s, tiles,
+                               tasks, B, nt);
             return HX_OK;
         default:
             set_error("internal: bad GEMM kind");
@@ -703,19 +720,41 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
     }
     const int64_t nt = L.ntile;
     int rk;
+    if (L.shape != SH_SQ && P->variant != 4 && P->variant != 5) {
+        set_error("internal: tile shape without its kernel variant");
+        return HX_EINVAL;
+    }
+    // the wave layout of the launch's tile shape (64 x 64 unless variant 4 or 5)
+    auto shaped = [&](auto KIND_NBUF, auto BFC) -> int {
+        constexpr int NB = decltype(KIND_NBUF)::value;
+        constexpr bool BFv = decltype(BFC)::value;
+        switch (L.shape) {
+            case SH_TALL:
+                return launch_kind<T, NSP, 16, NB, BFv, false, 4>(L.kind, nt, tiles, tasks, B, s);
+            case SH_WIDE:
+                return launch_kind<T, NSP, 16, NB, BFv, false, 1>(L.kind, nt, tiles, tasks, B, s);
+            default:
+                return launch_kind<T, NSP, 16, NB, BFv, false, 2>(L.kind, nt, tiles, tasks, B, s);
+        }
+    };
+    using One = std::integral_constant<int, 1>;
+    using Two = std::integral_constant<int, 2>;
+    using BFc = std::integral_constant<bool, BF>;
     if constexpr (BF) {
         switch (P->variant) {
             case 1:
-                rk = launch_kind<T, NSP, 16, 1, true>(L.kind, nt, tiles, tasks, B, s);
+            case 5:
+                rk = shaped(One{}, BFc{});
                 break;
             case 3:
                 rk = launch_kind<T, NSP, 16, 1, true, true>(L.kind, nt, tiles, tasks, B, s);
                 break;
             case 0:
-                rk = launch_kind<T, NSP, 16, 2, true>(L.kind, nt, tiles, tasks, B, s);
+            case 4:
+                rk = shaped(Two{}, BFc{});
                 break;
             default:
-                set_error("BF16 products need a 16-deep kernel variant (0, 1 or 3)");
+                set_error("BF16 products need a 16-deep kernel variant (not 2)");
                 return HX_EUNSUP;
         }
         if (rk) return rk;
@@ -723,7 +762,8 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
     }
     switch (P->variant) {
         case 1:
-            rk = launch_kind<T, NSP, 16, 1>(L.kind, nt, tiles, tasks, B, s);
+        case 5:
+            rk = shaped(One{}, BFc{});
             break;
         case 2:
             rk = launch_kind<T, NSP, 8, 2>(L.kind, nt, tiles, tasks, B, s);
@@ -732,7 +772,7 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
             rk = launch_kind<T, NSP, 16, 1, false, true>(L.kind, nt, tiles, tasks, B, s);
             break;
         default:
-            rk = launch_kind<T, NSP, 16, 2>(L.kind, nt, tiles, tasks, B, s);
+            rk = shaped(Two{}, BFc{});
             break;
     }
     if (rk) return rk;

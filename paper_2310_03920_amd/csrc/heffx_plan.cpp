@@ -382,16 +382,16 @@ static int64_t place_mixer(Mixer& M, int64_t ws0) {
 
 struct Builder {
     Plan* P;
-    void add_block_tiles(int kind_unused, int64_t coff, int ldc, int m, int n, int8_t cspace, int8_t beta,
+    void add_block_tiles(int shape, int64_t coff, int ldc, int m, int n, int8_t cspace, int8_t beta,
                          int32_t tbeg, int32_t tend, int32_t ktot) {
-        (void)kind_unused;
-        for (int r0 = 0; r0 < m; r0 += TM)
-            for (int c0 = 0; c0 < n; c0 += TN) {
+        const int tm = shape_rows(shape), tn = shape_cols(shape);
+        for (int r0 = 0; r0 < m; r0 += tm)
+            for (int c0 = 0; c0 < n; c0 += tn) {
                 Tile t;
                 t.coff = coff + (int64_t)r0 * ldc + c0;
                 t.ldc = ldc;
-                t.m = std::min(TM, m - r0);
-                t.n = std::min(TN, n - c0);
+                t.m = std::min(tm, m - r0);
+                t.n = std::min(tn, n - c0);
                 t.r0 = r0;
                 t.c0 = c0;
                 t.tbeg = tbeg;
@@ -410,8 +410,8 @@ static inline int32_t kpad(int32_t k, int ks) { return (k + ks - 1) / ks * ks; }
 static int apply_opts(Plan& P, const hx_plan_opts* o) {
     if (o && o->split_kseg_min > 0) P.split_kseg_min = o->split_kseg_min;
     const int v = o ? o->kernel_variant : 0;
-    if (v < 0 || v > 3) {
-        set_error("plan options: kernel_variant must be 0, 1, 2 or 3");
+    if (v < 0 || v > 5) {
+        set_error("plan options: kernel_variant must be 0 .. 5");
         return HX_EINVAL;
     }
     P.variant = v;
@@ -451,7 +451,7 @@ static void split_launch(Plan& P, Launch& L) {
         r.cspace = (int8_t)tl.cspace();
         r.beta = (int8_t)tl.beta();
         r.pad = 0;
-        r.pad2 = 0;
+        r.pld = shape_cols(L.shape);
         r.pbase = pidx * TM * TN;
         r.np = 0;
         int32_t a = tl.tbeg;
@@ -465,7 +465,7 @@ static void split_launch(Plan& P, Launch& L) {
             p.ktot = (int32_t)ks;
             p.set_out(SP_PART, 0);
             p.coff = pidx * TM * TN;
-            p.ldc = TN;
+            p.ldc = shape_cols(L.shape);
             out.push_back(p);
             ++pidx;
             ++r.np;
@@ -544,6 +544,8 @@ static void emit_mixing(Plan& P, Mixer& M, std::vector<Launch>& seq) {
     if (M.classes.empty()) return;
     Launch L;
     L.kind = NN;
+    L.shape = SH_SQ;
+    L.stage = P.n_stages++;
     L.tile0 = (int64_t)P.tiles.size();
     L.flops = M.flops;
     Builder B{&P};
@@ -623,31 +625,51 @@ struct OutBlockTasks {
     std::vector<Task> tasks;
 };
 
+// Tile shape of an output block (kernel variants 4 and 5): narrow blocks (at most 32
+// columns, more than 64 rows) get 128 x 32 tiles and short ones 32 x 128, so all 4
+// waves of a workgroup meet the block; the rest 64 x 64.  Each shape is a launch of
+// its own, so a round costs up to three launches (their tails), which the tuner
+// weighs against the better-filled workgroups.
+static int block_shape(const Plan& P, int m, int n) {
+    if (P.variant != 4 && P.variant != 5) return SH_SQ;
+    if (n <= 32 && m > 64) return SH_TALL;
+    if (m <= 32 && n > 64) return SH_WIDE;
+    return SH_SQ;
+}
+
+// One round of block GEMMs: one launch per tile shape present (their output blocks are
+// disjoint, so the launches are independent).
 static void flush_blocks(Plan& P, std::vector<OutBlockTasks>& blocks, int kind, int8_t cspace, int8_t beta,
                          bool keep_empty, std::vector<Launch>& seq, double* flops_out, int64_t* ntask_out) {
-    Launch L;
-    L.kind = kind;
-    L.tile0 = (int64_t)P.tiles.size();
-    L.flops = 0;
-    Builder B{&P};
-    for (auto& ob : blocks) {
-        if (ob.tasks.empty() && !keep_empty) continue;
-        int32_t tbeg = (int32_t)P.tasks.size();
-        int32_t ktot = 0;
-        for (auto& t : ob.tasks) {
-            P.tasks.push_back(t);
-            ktot += kpad(t.k, P.kstage);
-            L.flops += 2.0 * ob.m * ob.n * (double)t.k;
+    const int stage = P.n_stages++;
+    for (int sh = SH_SQ; sh <= SH_WIDE; ++sh) {
+        Launch L;
+        L.kind = kind;
+        L.shape = sh;
+        L.stage = stage;
+        L.tile0 = (int64_t)P.tiles.size();
+        L.flops = 0;
+        Builder B{&P};
+        for (auto& ob : blocks) {
+            if (ob.tasks.empty() && !keep_empty) continue;
+            if (block_shape(P, ob.m, ob.n) != sh) continue;
+            int32_t tbeg = (int32_t)P.tasks.size();
+            int32_t ktot = 0;
+            for (auto& t : ob.tasks) {
+                P.tasks.push_back(t);
+                ktot += kpad(t.k, P.kstage);
+                L.flops += 2.0 * ob.m * ob.n * (double)t.k;
+            }
+            int32_t tend = (int32_t)P.tasks.size();
+            if (ntask_out) *ntask_out += tend - tbeg;
+            B.add_block_tiles(sh, ob.coff, ob.ldc, ob.m, ob.n, cspace, beta, tbeg, tend, ktot);
         }
-        int32_t tend = (int32_t)P.tasks.size();
-        if (ntask_out) *ntask_out += tend - tbeg;
-        B.add_block_tiles(kind, ob.coff, ob.ldc, ob.m, ob.n, cspace, beta, tbeg, tend, ktot);
+        L.ntile = (int64_t)P.tiles.size() - L.tile0;
+        split_launch(P, L);
+        sort_tiles(P, L.tile0);
+        if (flops_out) *flops_out += L.flops;
+        if (L.ntile > 0) seq.push_back(L);
     }
-    L.ntile = (int64_t)P.tiles.size() - L.tile0;
-    split_launch(P, L);
-    sort_tiles(P, L.tile0);
-    if (flops_out) *flops_out += L.flops;
-    if (L.ntile > 0) seq.push_back(L);
 }
 
 static bool check_task_index_range(const Plan& P) {
@@ -1806,24 +1828,30 @@ static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
         return off_in + off[i][sp];
     };
     // merge the k-th launches of each instance's sequence into one launch
+    // Each instance's launches stay in their order; the next launches of all instances
+    // that share kind and tile shape are merged into one (instances touch disjoint data,
+    // so only the order within an instance matters).
     auto merge_seq = [&](std::vector<Launch> Plan::*seq, std::vector<Launch>& out) -> int {
-        size_t len = 0;
-        for (auto* P : in) len = std::max(len, (P->*seq).size());
-        for (size_t k = 0; k < len; ++k) {
+        std::vector<size_t> pos(in.size(), 0);
+        for (;;) {
+            int lead = -1;
+            for (size_t i = 0; i < in.size() && lead < 0; ++i)
+                if (pos[i] < (in[i]->*seq).size()) lead = (int)i;
+            if (lead < 0) break;
+            const Launch& K0 = (in[lead]->*seq)[pos[lead]];
             Launch L;
-            L.kind = -1;
+            L.kind = K0.kind;
+            L.shape = K0.shape;
+            L.stage = (int)out.size();
             L.tile0 = (int64_t)M.tiles.size();
             L.flops = 0;
             std::vector<Reduce> reds;
             for (size_t i = 0; i < in.size(); ++i) {
                 const Plan& P = *in[i];
-                if (k >= (P.*seq).size()) continue;
-                const Launch& S = (P.*seq)[k];
-                if (L.kind >= 0 && L.kind != S.kind) {
-                    set_error("plan_batch: instances have different launch sequences");
-                    return HX_EUNSUP;
-                }
-                L.kind = S.kind;
+                if (pos[i] >= (P.*seq).size()) continue;
+                const Launch& S = (P.*seq)[pos[i]];
+                if (S.kind != L.kind || S.shape != L.shape) continue;
+                ++pos[i];
                 L.flops += S.flops;
                 const int32_t tbase = (int32_t)M.tasks.size();
                 int32_t tmin = INT32_MAX, tmax = 0;
@@ -1863,7 +1891,7 @@ static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
             L.red0 = (int64_t)M.reduces.size();
             L.nred = (int64_t)reds.size();
             M.reduces.insert(M.reduces.end(), reds.begin(), reds.end());
-            if (L.ntile > 0) out.push_back(L);
+            if (L.ntile > 0 || L.nred > 0) out.push_back(L);
         }
         return HX_OK;
     };
