@@ -19,7 +19,7 @@ import numpy as np
 
 AXES = (
     ("kernel_variant", (0, 1, 2, 3, 4, 5)),
-    ("split_kseg_min", (1024, 2048, 4096)),
+    ("split_kseg_min", (512, 1024, 2048, 4096)),
     ("t_budget_bytes", (1 << 29, 1 << 30, 1 << 31)),
 )
 DEFAULT = {"kernel_variant": 0, "split_kseg_min": 2048, "t_budget_bytes": 1 << 30}

@@ -392,16 +392,31 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     }
 }
 
-// Fixed-order sum of split-K partial tiles into the owning output tile.
+// Fixed-order sum of split-K partial tiles into the owning output tile.  Block
+// (x, y) sums the y-th of gridDim.y slices of tile x's elements; the partials of an
+// element are added in index order (loads issued four at a time).
 template <typename T>
 __global__ __launch_bounds__(256) void reduce_partials(const Reduce* __restrict__ red, BasesT<T> B) {
     const Reduce r = red[blockIdx.x];
     const T* P = B.p[SP_PART] + r.pbase;
     T* C = space_ptr(B, r.cspace) + r.coff;
-    for (int e = threadIdx.x; e < r.m * r.n; e += blockDim.x) {
+    const int total = r.m * r.n;
+    const int slice = (total + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int e1 = min(total, slice * ((int)blockIdx.y + 1));
+    for (int e = slice * (int)blockIdx.y + (int)threadIdx.x; e < e1; e += blockDim.x) {
         const int row = e / r.n, col = e % r.n;
+        const T* q = P + row * r.pld + col;
         T acc = 0;
-        for (int j = 0; j < r.np; ++j) acc += P[(int64_t)j * TM * TN + row * r.pld + col];
+        int j = 0;
+        for (; j + 4 <= r.np; j += 4) {
+            const T p0 = q[(int64_t)j * TM * TN], p1 = q[(int64_t)(j + 1) * TM * TN];
+            const T p2 = q[(int64_t)(j + 2) * TM * TN], p3 = q[(int64_t)(j + 3) * TM * TN];
+            acc += p0;
+            acc += p1;
+            acc += p2;
+            acc += p3;
+        }
+        for (; j < r.np; ++j) acc += q[(int64_t)j * TM * TN];
         T* p = C + (int64_t)row * r.ldc + col;
         *p = r.beta ? (*p + acc) : acc;
     }
@@ -705,7 +720,7 @@ static int finish_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
     int rc = hip_check(hipGetLastError(), "bsgemm launch");
     if (rc || L.nred <= 0) return rc;
     const Reduce* red = reinterpret_cast<const Reduce*>(static_cast<const char*>(P->dev) + P->off_reduces) + L.red0;
-    hipLaunchKernelGGL((reduce_partials<T>), dim3((unsigned)L.nred), dim3(256), 0, s, red, B);
+    hipLaunchKernelGGL((reduce_partials<T>), dim3((unsigned)L.nred, 8), dim3(256), 0, s, red, B);
     return hip_check(hipGetLastError(), "reduce launch");
 }
 

@@ -429,7 +429,7 @@ static int apply_opts(Plan& P, const hx_plan_opts* o) {
 // at task boundaries into segments that write partial tiles; a reduction then
 // sums the partials of each tile in a fixed order (deterministic).
 static void split_launch(Plan& P, Launch& L) {
-    const int64_t want = 2048;
+    const int64_t want = 8192;
     if (L.ntile >= want) return;
     int64_t total = 0;
     for (int64_t t = L.tile0; t < L.tile0 + L.ntile; ++t) total += P.tiles[t].ktot;
