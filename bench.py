@@ -40,7 +40,7 @@ PEAKS = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFL
 # middle step), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a copy of known
 # size, per plan options (kernel_variant, split_kseg_min, intermediate budget).  Only
 # valid for the kernel and tile order they were taken with; other options report null.
-MEASURED_TRAFFIC = {(1, 1024, 1 << 30): 73.87e9, (1, 1024, 1 << 29): 73.34e9}
+MEASURED_TRAFFIC = {(1, 512, 1 << 31): 75.91e9, (1, 512, 1 << 30): 76.17e9, (1, 512, 1 << 29): 78.52e9}
 
 
 def log(*a):

@@ -672,11 +672,21 @@ static void flush_blocks(Plan& P, std::vector<OutBlockTasks>& blocks, int kind, 
     }
 }
 
+// The kernels address an operand element relative to its tile's first element
+// with a 32-bit offset (at most 128 rows or columns of one block times the leading
+// dimension), so leading dimensions are bounded by 2^20.
+constexpr int32_t MAX_LD = 1 << 20;
+
 static bool check_task_index_range(const Plan& P) {
     if (P.tasks.size() > (size_t)INT32_MAX) {
         set_error("plan too large: more than 2^31 GEMM tasks");
         return false;
     }
+    for (const Task& t : P.tasks)
+        if (t.lda > MAX_LD || t.ldb > MAX_LD || t.lda < 0 || t.ldb < 0) {
+            set_error("operand leading dimension above 2^20 (block too large)");
+            return false;
+        }
     return true;
 }
 
