@@ -142,6 +142,33 @@ def hamiltonian_bruteforce(h, g, dets):
     return H.tocsr()
 
 
+def one_rdm(vec, dets, K):
+    """Spin-summed 1-RDM gamma_pq = <v| E_pq |v> (Sec. II.E.1) of a real vector on
+    the span of `dets`."""
+    E = excitation_ops(dets, K)
+    return np.array([[vec @ (E[(p, q)] @ vec) for q in range(K)] for p in range(K)])
+
+
+def two_rdm(vec, dets, K):
+    """Spin-summed 2-RDM Gamma_pqrs = <v| sum_st a+_ps a+_rt a_st a_qs |v> (Sec. II.E.1),
+    from the anticommutation identity sum_st a+_ps a+_rt a_st a_qs = E_pq E_rs -
+    delta_qr E_ps.  With it E = sum h_pq gamma_pq + 1/2 sum g_pqrs Gamma_pqrs for the
+    Hamiltonian of this module."""
+    E = excitation_ops(dets, K)
+    Ev = {k: m @ vec for k, m in E.items()}
+    G = np.zeros((K, K, K, K))
+    for p in range(K):
+        for q in range(K):
+            left = E[(q, p)] @ vec  # <v| E_pq = (E_qp v)^T
+            for r in range(K):
+                for s in range(K):
+                    G[p, q, r, s] = left @ Ev[(r, s)]
+    gam = np.array([[vec @ Ev[(p, q)] for q in range(K)] for p in range(K)])
+    for q in range(K):
+        G[:, q, q, :] -= gam
+    return G
+
+
 def fci_energy(h, g, N, twosz, nroots=1):
     K = h.shape[0]
     dets = sector_dets(K, N, twosz)

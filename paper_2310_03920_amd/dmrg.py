@@ -338,6 +338,38 @@ class DMRG:
                 gam[p, q] = gam[q, p] = d if p == q else 0.5 * d
         return gam
 
+    def two_rdm(self, wgrad):
+        """Spin-summed 2-RDM Gamma_pqrs = <sum_st a+_ps a+_rt a_st a_qs> of the current
+        MPS, symmetrised over the eight index permutations that leave (pq|rs)
+        integrals unchanged -- the part the energy sees, E = sum h gamma + 1/2 sum g
+        Gamma (Sec. II.E.1).  For each permutation orbit O, the direction dg = 1 on O
+        gives dE/dt = 1/2 sum_O Gamma; the MPO values are affine in g, so their change
+        along dg is W(g + dg) - W(g) exactly.  One MPO construction per orbit (about
+        K^4 / 8): meant for small active spaces."""
+        K = self.K
+        base = [np.asarray(self.mpo.sites[k].mats).reshape(-1, 4, 4) for k in range(K)]
+        pairs = [(p, q) for p in range(K) for q in range(p + 1)]
+        gam2 = np.zeros((K, K, K, K))
+        for a in range(len(pairs)):
+            for b in range(a + 1):
+                (p, q), (r, s) = pairs[a], pairs[b]
+                orbit = {(p, q, r, s), (q, p, r, s), (p, q, s, r), (q, p, s, r),
+                         (r, s, p, q), (s, r, p, q), (r, s, q, p), (s, r, q, p)}
+                dg = np.zeros_like(self.g)
+                for x in orbit:
+                    dg[x] = 1.0
+                plus = build_nc_mpo(self.h, self.g + dg)
+                d = 0.0
+                for k in range(K):
+                    sp, s0 = plus.sites[k], self.mpo.sites[k]
+                    if not (np.array_equal(sp.rows, s0.rows) and np.array_equal(sp.cols, s0.cols)):
+                        raise RuntimeError("two_rdm: MPO structure changed along a direction")
+                    d += float(np.sum(wgrad[k] * (np.asarray(sp.mats).reshape(-1, 4, 4) - base[k])))
+                val = 2.0 * d / len(orbit)
+                for x in orbit:
+                    gam2[x] = val
+        return gam2
+
     def _step(self, i, psi0, pass_id):
         import torch
         bl, br = self.bonds[i], self.bonds[i + 2]
@@ -416,6 +448,88 @@ class DMRG:
                 self.center, self.center_site = C, i + 1
                 self.eng.update_left(i, self.bonds[i], self.bonds[i + 1],
                                      site_payload(self.bonds[i], self.bonds[i + 1], A, self.device))
+
+    # -- one-site passes (Sec. II.A.2): the bond spaces are the ones the two-site
+    # passes chose; each step solves the one-site H_eff and moves the centre with an
+    # SVD that keeps every sector's dimension.
+    def _step1(self, i, pass_id):
+        import torch
+        bl, br = self.bonds[i], self.bonds[i + 1]
+        plan = self.eng.heff1_plan(i, bl, br)
+        Lb, Rb = X.Bond(bl), X.Bond(br)
+        L, R = self.eng.left[i], self.eng.right[i + 1]
+        n = int(plan.info.psi_nnz)
+        psi_t = torch.from_numpy(X.pack_psi1(Lb, Rb, self.center)).to(self.device)
+        diag = torch.empty(n, dtype=torch.float64, device=self.device)
+        plan.prepare(L, R)
+        plan.diag(L, R, diag)
+        dav = Davidson(n, min(self.kmax, max(n, 1)), self.device)
+
+        def mv(v, out):
+            plan.apply(L, R, v, out)
+
+        theta, rnorm, nmv = dav.solve(mv, psi_t, diag, tol=self.tol, max_iter=self.max_iter)
+        self.center = X.unpack_psi1(Lb, Rb, dav.x.cpu().numpy())
+        self.log.append({"pass": pass_id, "i": i, "one_site": True, "energy": theta, "rnorm": rnorm,
+                         "n_matvec": nmv})
+        return theta
+
+    def _move1(self, i, direction):
+        """Move the one-site centre from site i to i+1 (direction 0) or i-1 (1)."""
+        if direction == 0:
+            psi2 = {(il, s, 0, ir): b for (il, s, ir), b in self.center.items()}
+            fixed = {tuple(q): m for q, m in self.bonds[i + 1]}
+            nb, A, F, _ = split(psi2, self.bonds[i], self.bonds[i + 1], self.M, 0, fixed=fixed)
+            self.bonds[i + 1] = nb
+            self.tensors[i] = A
+            self.eng.update_left(i, self.bonds[i], self.bonds[i + 1],
+                                 site_payload(self.bonds[i], self.bonds[i + 1], A, self.device))
+            by_l = {}
+            for (ir, s, ir2), b in self.tensors[i + 1].items():
+                by_l.setdefault(ir, []).append((s, ir2, b))
+            c = {}
+            for (q, _, ir), f in F.items():
+                for s, ir2, b in by_l.get(ir, []):
+                    key = (q, s, ir2)
+                    c[key] = c[key] + f @ b if key in c else f @ b
+            self.center, self.center_site = c, i + 1
+        else:
+            psi2 = {(il, 0, s, ir): b for (il, s, ir), b in self.center.items()}
+            fixed = {tuple(q): m for q, m in self.bonds[i]}
+            nb, B, F, _ = split(psi2, self.bonds[i], self.bonds[i + 1], self.M, 1, fixed=fixed)
+            self.bonds[i] = nb
+            self.tensors[i] = B
+            self.eng.update_right(i, self.bonds[i], self.bonds[i + 1],
+                                  site_payload(self.bonds[i], self.bonds[i + 1], B, self.device))
+            by_r = {}
+            for (il, _, q), f in F.items():
+                by_r.setdefault(il, []).append((q, f))
+            c = {}
+            for (il2, s, il), a in self.tensors[i - 1].items():
+                for q, f in by_r.get(il, []):
+                    key = (il2, s, q)
+                    c[key] = c[key] + a @ f if key in c else a @ f
+            self.center, self.center_site = c, i - 1
+
+    def run_one_site(self, n_passes):
+        """Alternating one-site passes from the current centre (after an even number
+        of two-site passes: centre at site 1); returns the last energy of each pass."""
+        if self.center_site is None:
+            raise RuntimeError("run_one_site: run two-site passes first (they fix the bond spaces)")
+        out = []
+        for p in range(n_passes):
+            if p % 2 == 0:
+                for i in range(self.center_site, self.K):
+                    self._step1(i, ("one", p))
+                    if i < self.K - 1:
+                        self._move1(i, 0)
+            else:
+                for i in range(self.center_site, -1, -1):
+                    self._step1(i, ("one", p))
+                    if i > 0:
+                        self._move1(i, 1)
+            out.append(self.log[-1]["energy"])
+        return out
 
     def run(self, n_sweeps):
         """Alternating passes; returns the energy of the last step of each pass."""

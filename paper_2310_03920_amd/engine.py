@@ -64,6 +64,16 @@ class Engine:
             self._heff_plans[key] = p
         return p
 
+    def heff1_plan(self, i, bond_i, bond_i1):
+        """One-site sigma-vector plan at site i (left environment at cut i, right at cut i+1)."""
+        key = ("one", i, self._bkey(bond_i), self._bkey(bond_i1))
+        p = self._heff_plans.get(key)
+        if p is None:
+            p = X.Heff1Plan(bond_i, bond_i1, self.mpo.dq[i], self.mpo.dq[i + 1], self._w[i],
+                            t_budget_bytes=self.t_budget).upload(self.device)
+            self._heff_plans[key] = p
+        return p
+
     def vjp_plan(self, i, bond_i, bond_i2):
         """Adjoint plan of the sigma-vector at sites (i, i+1) (built per call)."""
         return X.HeffVjpPlan(bond_i, bond_i2, self.mpo.dq[i], self.mpo.dq[i + 1], self.mpo.dq[i + 2],

@@ -72,6 +72,35 @@ def test_hamiltonian_conserves_n_and_sz():
     assert np.all(na(r[keep]) == na(c[keep])) and np.all(nb(r[keep]) == nb(c[keep]))
 
 
+@pytest.mark.parametrize("K,N,twosz", [(3, 3, 1), (3, 2, 0)])
+def test_rdms_match_operator_products_traces_and_energy(K, N, twosz):
+    """The E-form 2-RDM equals the four-operator definition term by term; its pair
+    trace is N(N-1), tr(gamma) = N; and <v|H|v> = sum h gamma + 1/2 sum g Gamma with H
+    assembled term by term, for integrals with no symmetry (so a transposed index
+    or a dropped delta term fails)."""
+    import itertools
+    dets = fock.sector_dets(K, N, twosz)
+    rng = np.random.default_rng(K * 10 + N)
+    v = rng.standard_normal(len(dets))
+    v /= np.linalg.norm(v)
+    G = fock.two_rdm(v, dets, K)
+    gam = fock.one_rdm(v, dets, K)
+    B = np.zeros_like(G)
+    for p, q, r, s in itertools.product(range(K), repeat=4):
+        for si in range(2):
+            for ti in range(2):
+                op = fock.op_matrix(dets, [(2 * p + si, True), (2 * r + ti, True), (2 * s + ti, False),
+                                           (2 * q + si, False)])
+                B[p, q, r, s] += v @ (op @ v)
+    np.testing.assert_allclose(G, B, atol=1e-13)
+    assert abs(np.einsum("pprr->", G) - N * (N - 1)) < 1e-12
+    assert abs(np.trace(gam) - N) < 1e-12
+    h = rng.standard_normal((K, K))
+    g = rng.standard_normal((K, K, K, K))
+    H = fock.hamiltonian_bruteforce(h, g, dets)
+    assert abs(v @ (H @ v) - (np.sum(h * gam) + 0.5 * np.sum(g * G))) < 1e-12
+
+
 def test_noninteracting_closed_form():
     K, N = 6, 6
     h, _ = make_integrals(K, seed=5)
