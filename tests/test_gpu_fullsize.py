@@ -1,0 +1,88 @@
+"""Parity at the benchmark's full size.
+
+The middle site pair (17, 18) of the 36-orbital chain at M = 1000 (NC MPO,
+Gaussian sector model of width 1, integrals seed 0), with seeded N(0,1)
+environments and psi, is applied with the plan options the benchmark's autotuner
+chooses for it (kernel variant 1, split-K segments of 512, intermediate budget 1 or
+2 GiB).  Sampled rows of sigma -- the first and last rows of the largest left
+sector (the last one in a ragged 64-row tile), a row of the smallest sector
+and random rows -- are compared with the oracle, which computes each row on its
+own straight from the block formats.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import contract
+from synth import bond_sector_tables, make_integrals
+from synth.blocks import random_env, random_psi
+
+pytestmark = pytest.mark.gpu
+
+K, M = 36, 1000
+SITE = K // 2 - 1
+
+
+@pytest.fixture(scope="module")
+def problem(device):
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.mpo import build_nc_mpo, site_entries
+    print(f"[full size] building {K} orbitals, M={M}, sites ({SITE}, {SITE + 1})", flush=True)
+    mpo = build_nc_mpo(*make_integrals(K, seed=0))
+    bonds = bond_sector_tables(K, K, 0, M, model="gaussian", width=1.0)
+    lb, rb = bonds[SITE], bonds[SITE + 2]
+    rng = np.random.default_rng(2024)
+    Ldq = [tuple(x) for x in mpo.dq[SITE]]
+    Rdq = [tuple(x) for x in mpo.dq[SITE + 2]]
+    L = random_env(lb, Ldq, rng)
+    R = random_env(rb, Rdq, rng)
+    psi = random_psi(lb, rb, rng)
+    W1, W2 = site_entries(mpo, SITE), site_entries(mpo, SITE + 1)
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    dev = dict(
+        L=torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device),
+        R=torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device),
+        psi=torch.from_numpy(X.pack_psi(lbB, rbB, psi)).to(device),
+    )
+    # sampled rows (il', s1', x)
+    big = max(range(len(lb)), key=lambda j: lb[j][1])
+    one = min(range(len(lb)), key=lambda j: lb[j][1])
+    rows = [(big, 1, 0), (big, 2, lb[big][1] - 1), (one, 0, 0)]
+    pick = np.random.default_rng(5)
+    while len(rows) < 6:
+        il = int(pick.integers(len(lb)))
+        rows.append((il, int(pick.integers(4)), int(pick.integers(lb[il][1]))))
+    print(f"[full size] oracle rows {rows}", flush=True)
+    ref = contract.sigma_rows(lb, rb, L, W1, W2, R, psi, rows)
+    W1s = X.MpoSite(mpo.sites[SITE].rows, mpo.sites[SITE].cols, mpo.sites[SITE].mats)
+    W2s = X.MpoSite(mpo.sites[SITE + 1].rows, mpo.sites[SITE + 1].cols, mpo.sites[SITE + 1].mats)
+    return dict(lb=lb, rb=rb, lbB=lbB, rbB=rbB, Ldq=Ldq, Rdq=Rdq, mpo=mpo, W1=W1s, W2=W2s, dev=dev,
+                rows=rows, ref=ref)
+
+
+@pytest.mark.parametrize("budget_gb", [2.0, 1.0])
+def test_fullsize_sigma_rows_match_the_oracle(device, problem, budget_gb):
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    p = problem
+    print(f"[full size] apply, variant 1, kseg 512, budget {budget_gb} GiB", flush=True)
+    mid = [tuple(x) for x in p["mpo"].dq[SITE + 1]]
+    plan = X.HeffPlan(p["lbB"], p["rbB"], p["Ldq"], mid, p["Rdq"], p["W1"], p["W2"],
+                      t_budget_bytes=int(budget_gb * (1 << 30)), split_kseg_min=512,
+                      kernel_variant=1).upload(device)
+    d = p["dev"]
+    plan.prepare(d["L"], d["R"])
+    sigma = torch.full_like(d["psi"], float("nan"))
+    plan.apply(d["L"], d["R"], d["psi"], sigma)
+    torch.cuda.synchronize()
+    got = X.unpack_psi(p["lbB"], p["rbB"], sigma.cpu().numpy())
+    scale = max(float(np.max(np.abs(v))) for r in p["ref"].values() for v in r.values())
+    worst = 0.0
+    for (il, s1, x), cols in p["ref"].items():
+        for (s2, ir), vec in cols.items():
+            g = got[(il, s1, s2, ir)][x]
+            worst = max(worst, float(np.max(np.abs(g - vec))))
+    print(f"[full size] max |gpu - oracle| = {worst:.3e} (scale {scale:.3e})", flush=True)
+    assert worst <= 1e-11 * scale
+    del plan
