@@ -40,7 +40,9 @@
  *
  * Errors: every int-returning call returns 0 on success, HX_EINVAL for a
  * malformed table or argument, HX_EHIP for a HIP failure, HX_EUNSUP for an
- * unsupported request; hx_last_error() returns a thread-local message.
+ * unsupported request; hx_last_error() returns a thread-local message.  A device
+ * buffer may be NULL exactly when the plan gives it length zero (e.g. psi and
+ * sigma of a two-site space with no allowed block: the call is then a no-op).
  */
 #ifndef HEFFX_H
 #define HEFFX_H

@@ -872,11 +872,11 @@ int hx_heff_apply(const hx_plan* plan, const double* L, const double* R, void* w
     int rc = check_ready(plan, PK_HEFF);
     if (rc) return rc;
     const Plan* P = reinterpret_cast<const Plan*>(plan);
-    if (!psi || !sigma || (P->in_nnz && !L) || (P->in2_nnz && !R) || (P->ws_doubles && !ws)) {
+    if ((P->psi_nnz && (!psi || !sigma)) || (P->in_nnz && !L) || (P->in2_nnz && !R) || (P->ws_doubles && !ws)) {
         set_error("heff_apply: null operand");
         return HX_EINVAL;
     }
-    if (psi == sigma) {
+    if (P->psi_nnz && psi == sigma) {
         set_error("heff_apply: psi and sigma must not alias");
         return HX_EINVAL;
     }
@@ -939,11 +939,12 @@ static int apply_lowered(const hx_plan* plan, const float* L32, const float* R32
     int rc = check_ready(plan, PK_HEFF);
     if (rc) return rc;
     const Plan* P = reinterpret_cast<const Plan*>(plan);
-    if (!psi32 || !sigma32 || (P->in_nnz && !L32) || (P->in2_nnz && !R32) || (P->ws_doubles && !ws32)) {
+    if ((P->psi_nnz && (!psi32 || !sigma32)) || (P->in_nnz && !L32) || (P->in2_nnz && !R32) ||
+        (P->ws_doubles && !ws32)) {
         set_error(std::string(what) + ": null operand");
         return HX_EINVAL;
     }
-    if (psi32 == sigma32) {
+    if (P->psi_nnz && psi32 == sigma32) {
         set_error(std::string(what) + ": psi and sigma must not alias");
         return HX_EINVAL;
     }
@@ -975,7 +976,7 @@ int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws
     int rc = check_ready(plan, PK_HEFF);
     if (rc) return rc;
     const Plan* P = reinterpret_cast<const Plan*>(plan);
-    if (!diag || (P->ws_doubles && !ws)) {
+    if ((P->psi_nnz && !diag) || (P->ws_doubles && !ws)) {
         set_error("heff_diag: null operand");
         return HX_EINVAL;
     }
@@ -1003,12 +1004,12 @@ int hx_heff_apply_backward(const hx_plan* plan, const double* L, const double* R
     int rc = check_ready(plan, PK_HEFF_VJP);
     if (rc) return rc;
     const Plan* P = reinterpret_cast<const Plan*>(plan);
-    if (!psi || !g || !g_psi || (P->in_nnz && (!L || !g_L)) || (P->in2_nnz && (!R || !g_R)) ||
+    if ((P->psi_nnz && (!psi || !g || !g_psi)) || (P->in_nnz && (!L || !g_L)) || (P->in2_nnz && (!R || !g_R)) ||
         (P->w1_nnz && !g_W1) || (P->w2_nnz && !g_W2) || (P->ws_doubles && !ws)) {
         set_error("heff_apply_backward: null operand");
         return HX_EINVAL;
     }
-    if (g_psi == psi || g_psi == g) {
+    if (P->psi_nnz && (g_psi == psi || g_psi == g)) {
         set_error("heff_apply_backward: g_psi must not alias psi or g");
         return HX_EINVAL;
     }
