@@ -19,13 +19,19 @@ class Engine:
     right[k] : payload of the right environment at cut k (ops mpo.cuts[k], bond k)
     """
 
-    def __init__(self, mpo, device="cuda", t_budget_bytes=0):
+    # plan options of the sigma-vector, adjoint and environment plans: the one-buffer
+    # pipeline with 512-element split-K segments (what the autotuner picks for the
+    # large middle-chain problems)
+    PLAN_OPTS = {"kernel_variant": 1, "split_kseg_min": 512}
+
+    def __init__(self, mpo, device="cuda", t_budget_bytes=0, plan_opts=None):
         import torch
         self.torch = torch
         self.mpo = mpo
         self.K = mpo.K
         self.device = device
         self.t_budget = t_budget_bytes
+        self.opts = dict(self.PLAN_OPTS if plan_opts is None else plan_opts)
         self.left = {}
         self.right = {}
         self._env_plans = {}
@@ -48,10 +54,10 @@ class Engine:
         if p is None:
             if direction == 0:
                 p = X.EnvPlan(0, bond_k, bond_k1, self.mpo.dq[k], self.mpo.dq[k + 1], self._w[k],
-                              t_budget_bytes=self.t_budget).upload(self.device)
+                              t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
             else:
                 p = X.EnvPlan(1, bond_k1, bond_k, self.mpo.dq[k + 1], self.mpo.dq[k], self._w[k],
-                              t_budget_bytes=self.t_budget).upload(self.device)
+                              t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
             self._env_plans[key] = p
         return p
 
@@ -60,7 +66,7 @@ class Engine:
         p = self._heff_plans.get(key)
         if p is None:
             p = X.HeffPlan(bond_i, bond_i2, self.mpo.dq[i], self.mpo.dq[i + 1], self.mpo.dq[i + 2],
-                           self._w[i], self._w[i + 1], t_budget_bytes=self.t_budget).upload(self.device)
+                           self._w[i], self._w[i + 1], t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
             self._heff_plans[key] = p
         return p
 
@@ -70,14 +76,15 @@ class Engine:
         p = self._heff_plans.get(key)
         if p is None:
             p = X.Heff1Plan(bond_i, bond_i1, self.mpo.dq[i], self.mpo.dq[i + 1], self._w[i],
-                            t_budget_bytes=self.t_budget).upload(self.device)
+                            t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
             self._heff_plans[key] = p
         return p
 
     def vjp_plan(self, i, bond_i, bond_i2):
         """Adjoint plan of the sigma-vector at sites (i, i+1) (built per call)."""
         return X.HeffVjpPlan(bond_i, bond_i2, self.mpo.dq[i], self.mpo.dq[i + 1], self.mpo.dq[i + 2],
-                             self._w[i], self._w[i + 1], t_budget_bytes=self.t_budget).upload(self.device)
+                             self._w[i], self._w[i + 1], t_budget_bytes=self.t_budget,
+                             **self.opts).upload(self.device)
 
     def drop_plans(self):
         self._env_plans.clear()
