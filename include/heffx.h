@@ -221,6 +221,20 @@ int hx_heff_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx
                             const hx_opset* mid, const hx_opset* Rops, const hx_mpo_site* W1,
                             const hx_mpo_site* W2, const hx_plan_opts* opts, hx_plan** out);
 
+/* VJP plan of the one-site sigma-vector (arguments as hx_heff1_plan_create): used
+ * with hx_heff_prepare / hx_heff_apply_backward like a two-site VJP plan, psi and g
+ * in the hx_psi1_layout layout; g_W1 is the gradient of W's values, g_W2 (16 x the
+ * number of Rops operators) belongs to the identity coupling on the absent site and
+ * carries no information.  Environment updates are adjoints of this form: for a
+ * left update L'_b = sum_{a,s',s} W_ab[s',s] A_s'^T L_a A_s and a cotangent G of L',
+ * <G, L'> = <A, H1(L, W, R := G) A> (the same holds for right updates with G as the
+ * left environment), so with psi = g = A this plan gives d<G,L'>/dL (g_L),
+ * d<G,L'>/dW (g_W1) and, with H1 A from the forward plan, d<G,L'>/dA =
+ * H1 A + H1^T A -- the chain through hx_env_update of Sec. II.E.1 gradients. */
+int hx_heff1_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops,
+                             const hx_opset* Rops, const hx_mpo_site* W, const hx_plan_opts* opts,
+                             hx_plan** out);
+
 /* Backward of hx_heff_apply with an uploaded VJP plan whose workspace holds
  * hx_heff_prepare(plan, L, R, ws) for the same L and R.  Outputs (overwritten,
  * device, FP64):
@@ -287,6 +301,20 @@ void hx_graph_destroy(hx_graph* graph);
 /* Element-wise conversions (n elements, device pointers). */
 int hx_convert_f64_f32(int64_t n, const double* src, float* dst, hx_stream stream);
 int hx_convert_f32_f64(int64_t n, const float* src, double* dst, hx_stream stream);
+
+/* Element moves between payload layouts (e.g. a site tensor, hx_site_layout, and the
+ * same tensor as a one-site wavefunction, hx_psi1_layout):
+ *   hx_gather_index : dst[j] = src[idx[j]]   for j < n
+ *   hx_scatter_index: dst[idx[j]] = src[j]   for j < n
+ * idx: n int64 on the device (caller-owned); an index outside [0, nsrc) resp.
+ * [0, ndst) leaves its element unchanged.  hx_axpy: y += a x over n doubles.  All
+ * device, asynchronous on the stream; HX_EINVAL for negative sizes or NULL buffers
+ * of nonzero length. */
+int hx_gather_index(int64_t n, const int64_t* idx, int64_t nsrc, const double* src, double* dst,
+                    hx_stream stream);
+int hx_scatter_index(int64_t n, const int64_t* idx, int64_t ndst, const double* src, double* dst,
+                     hx_stream stream);
+int hx_axpy(int64_t n, double a, const double* x, double* y, hx_stream stream);
 
 /* Round the operands of a prepared sigma-vector plan to FP32: L -> L32 (in_nnz
  * floats), R -> R32 (in2_nnz floats) and the mixed operators held in ws (built

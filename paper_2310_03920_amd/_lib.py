@@ -24,7 +24,8 @@ EXPORTED = (
     "hx_normalize", "hx_convert_f64_f32", "hx_convert_f32_f64", "hx_heff_lower_f32", "hx_heff_apply_f32",
     "hx_heff_plan_batch", "hx_batch_offsets", "hx_heff_graph_create", "hx_graph_launch", "hx_graph_destroy",
     "hx_heff_vjp_plan_create", "hx_heff_apply_backward", "hx_heff_apply_bf16", "hx_davidson_restart2",
-    "hx_heff1_plan_create", "hx_psi1_layout",
+    "hx_heff1_plan_create", "hx_psi1_layout", "hx_heff1_vjp_plan_create", "hx_gather_index",
+    "hx_scatter_index", "hx_axpy",
     "hx_last_error",
 )
 
@@ -102,6 +103,10 @@ def lib():
     L.hx_heff_vjp_plan_create.argtypes = L.hx_heff_plan_create.argtypes
     L.hx_heff1_plan_create.argtypes = [P(HxBond), P(HxBond), P(HxOpset), P(HxOpset), P(HxMpoSite), P(HxPlanOpts),
                                        P(c_void_p)]
+    L.hx_heff1_vjp_plan_create.argtypes = L.hx_heff1_plan_create.argtypes
+    L.hx_gather_index.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+    L.hx_scatter_index.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
+    L.hx_axpy.argtypes = [c_int64, ctypes.c_double, c_void_p, c_void_p, c_void_p]
     L.hx_psi1_layout.argtypes = [P(HxBond), P(HxBond), c_int64, P(c_int32), P(c_int64)]
     L.hx_psi1_layout.restype = c_int64
     L.hx_heff_apply_backward.argtypes = [c_void_p] * 11 + [c_void_p]
@@ -230,6 +235,20 @@ def site_layout(lbond, rbond):
     if n2 < 0:
         check(int(n2), "site_layout")
     return [tuple(int(x) for x in k) for k in keys[:n]], off
+
+
+def site_to_psi1_index(lbond, rbond):
+    """Element permutation between a site tensor's payload (hx_site_layout) and the
+    same tensor in the one-site wavefunction layout (hx_psi1_layout): psi1[j] =
+    site[idx[j]].  Both layouts hold the same blocks (il, s, ir), row-major."""
+    skeys, soff = site_layout(lbond, rbond)
+    pkeys, poff = psi1_layout(lbond, rbond)
+    where = {k: int(soff[i]) for i, k in enumerate(skeys)}
+    idx = np.empty(int(poff[-1]), np.int64)
+    for i, k in enumerate(pkeys):
+        n = int(poff[i + 1] - poff[i])
+        idx[poff[i]:poff[i + 1]] = where[k] + np.arange(n)
+    return idx
 
 
 # ------------------------------------------------------------------ packing (host data marshalling)
@@ -483,6 +502,24 @@ class HeffVjpPlan(Plan):
               "heff_apply_backward")
 
 
+class Heff1VjpPlan(HeffVjpPlan):
+    """Plan of the vector-Jacobian products of the one-site sigma = H1 psi (psi in the
+    one-site layout); nnz2 counts the identity coupling of the absent site."""
+
+    def __init__(self, lbond, rbond, Ldq, Rdq, W, t_budget_bytes=0, split_kseg_min=0, kernel_variant=0):
+        lb, rb = (b if isinstance(b, Bond) else Bond(b) for b in (lbond, rbond))
+        Lo, Ro = OpSet(Ldq), OpSet(Rdq)
+        w = W if isinstance(W, MpoSite) else MpoSite.from_entries(W)
+        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant)
+        h = c_void_p()
+        check(lib().hx_heff1_vjp_plan_create(ctypes.byref(lb.c), ctypes.byref(rb.c), ctypes.byref(Lo.c),
+                                             ctypes.byref(Ro.c), ctypes.byref(w.c), ctypes.byref(opts),
+                                             ctypes.byref(h)), "heff1_vjp_plan_create")
+        Plan.__init__(self, h, (lb, rb, Lo, Ro, w))
+        self.lbond, self.rbond = lb, rb
+        self.nnz1, self.nnz2 = len(w.rows), Ro.nop
+
+
 GRAPH_APPLY, GRAPH_PREPARE_APPLY, GRAPH_APPLY_F32, GRAPH_APPLY_BF16 = 1, 2, 3, 4
 
 
@@ -578,3 +615,24 @@ def convert_f64_f32(src, dst):
 
 def convert_f32_f64(src, dst):
     check(lib().hx_convert_f32_f64(int(src.numel()), _ptr(src), _ptr(dst), _stream()), "convert_f32_f64")
+
+
+def gather_index(idx, src, dst):
+    """dst[j] = src[idx[j]] (device int64 idx of dst's length)."""
+    if str(idx.dtype) != "torch.int64":
+        raise TypeError("gather_index: idx must be int64")
+    check(lib().hx_gather_index(int(dst.numel()), _ptr(idx), int(src.numel()), _ptr(src), _ptr(dst), _stream()),
+          "gather_index")
+
+
+def scatter_index(idx, src, dst):
+    """dst[idx[j]] = src[j] (device int64 idx of src's length)."""
+    if str(idx.dtype) != "torch.int64":
+        raise TypeError("scatter_index: idx must be int64")
+    check(lib().hx_scatter_index(int(src.numel()), _ptr(idx), int(dst.numel()), _ptr(src), _ptr(dst), _stream()),
+          "scatter_index")
+
+
+def axpy(a, x, y):
+    """y += a x on the device."""
+    check(lib().hx_axpy(int(x.numel()), float(a), _ptr(x), _ptr(y), _stream()), "axpy")

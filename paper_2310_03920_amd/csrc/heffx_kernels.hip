@@ -422,6 +422,30 @@ __global__ __launch_bounds__(256) void reduce_partials(const Reduce* __restrict_
     }
 }
 
+// dst[j] = src[idx[j]] / dst[idx[j]] = src[j] for j < n; indices outside [0, nsrc) /
+// [0, ndst) are skipped (the element is left unchanged).
+__global__ void gather_index(int64_t n, const int64_t* __restrict__ idx, int64_t nsrc, const double* __restrict__ src,
+                             double* __restrict__ dst) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx[e];
+        if (i >= 0 && i < nsrc) dst[e] = src[i];
+    }
+}
+
+__global__ void scatter_index(int64_t n, const int64_t* __restrict__ idx, int64_t ndst, const double* __restrict__ src,
+                              double* __restrict__ dst) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx[e];
+        if (i >= 0 && i < ndst) dst[i] = src[e];
+    }
+}
+
+// y += a x
+__global__ void axpy_f64(int64_t n, double a, const double* __restrict__ x, double* __restrict__ y) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] += a * x[e];
+}
+
 __global__ void cvt_f64_f32(int64_t n, const double* __restrict__ s, float* __restrict__ d) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         d[i] = (float)s[i];
@@ -910,6 +934,39 @@ int hx_convert_f32_f64(int64_t n, const float* src, double* dst, hx_stream strea
     const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
     hipLaunchKernelGGL(cvt_f32_f64, dim3(nb), dim3(256), 0, static_cast<hipStream_t>(stream), n, src, dst);
     return hip_check(hipGetLastError(), "convert f32->f64");
+}
+
+int hx_gather_index(int64_t n, const int64_t* idx, int64_t nsrc, const double* src, double* dst, hx_stream stream) {
+    if (n < 0 || nsrc < 0 || (n > 0 && (!idx || !dst || (nsrc > 0 && !src)))) {
+        set_error("gather_index: bad arguments");
+        return HX_EINVAL;
+    }
+    if (n == 0) return HX_OK;
+    const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(gather_index, dim3(nb), dim3(256), 0, static_cast<hipStream_t>(stream), n, idx, nsrc, src, dst);
+    return hip_check(hipGetLastError(), "gather_index");
+}
+
+int hx_scatter_index(int64_t n, const int64_t* idx, int64_t ndst, const double* src, double* dst, hx_stream stream) {
+    if (n < 0 || ndst < 0 || (n > 0 && (!idx || !src || (ndst > 0 && !dst)))) {
+        set_error("scatter_index: bad arguments");
+        return HX_EINVAL;
+    }
+    if (n == 0) return HX_OK;
+    const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(scatter_index, dim3(nb), dim3(256), 0, static_cast<hipStream_t>(stream), n, idx, ndst, src, dst);
+    return hip_check(hipGetLastError(), "scatter_index");
+}
+
+int hx_axpy(int64_t n, double a, const double* x, double* y, hx_stream stream) {
+    if (n < 0 || (n > 0 && (!x || !y))) {
+        set_error("axpy: bad arguments");
+        return HX_EINVAL;
+    }
+    if (n == 0) return HX_OK;
+    const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(axpy_f64, dim3(nb), dim3(256), 0, static_cast<hipStream_t>(stream), n, a, x, y);
+    return hip_check(hipGetLastError(), "axpy");
 }
 
 int hx_heff_lower_f32(const hx_plan* plan, const double* L, const double* R, const void* ws, float* L32, float* R32,

@@ -1152,9 +1152,11 @@ static void grad_class_blocks(const GradSide& G, const EnvLayout& lay, int8_t en
     (void)genv_space;
 }
 
+// one_site: the adjoint of the one-site sigma-vector (as in build_heff: the second site
+// is absent, Mo == Ro, e2 is replaced by the identity coupling b -> b).
 static int build_heff_vjp(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, const OpSet& Mo,
-                          const OpSet& Ro, const std::vector<Entry>& e1, const std::vector<Entry>& e2,
-                          const hx_plan_opts* opts) {
+                          const OpSet& Ro, const std::vector<Entry>& e1, const std::vector<Entry>& e2_in,
+                          const hx_plan_opts* opts, bool one_site = false) {
     P.kind = PK_HEFF_VJP;
     {
         int rc0 = apply_opts(P, opts);
@@ -1164,8 +1166,20 @@ static int build_heff_vjp(Plan& P, const Bond& lb, const Bond& rb, const OpSet& 
         set_error("vjp plan: n_roots must be 1");
         return HX_EUNSUP;
     }
+    std::vector<Entry> e2_one;
+    if (one_site) {
+        for (int b2 = 0; b2 < (int)Ro.dq.size(); ++b2) {
+            Entry en;
+            en.src = b2;
+            en.tgt = b2;
+            for (double& v : en.v) v = 0.0;
+            en.v[0] = 1.0;
+            e2_one.push_back(en);
+        }
+    }
+    const std::vector<Entry>& e2 = one_site ? e2_one : e2_in;
     EnvLayout Ll = env_layout(lb, Lo), Rl = env_layout(rb, Ro);
-    PsiLayout psi = psi_layout(lb, rb);
+    PsiLayout psi = psi_layout(lb, rb, one_site);
     P.psi_nnz = psi.nnz;
     P.in_nnz = Ll.op_off.back();
     P.in2_nnz = Rl.op_off.back();
@@ -2093,6 +2107,30 @@ int hx_heff_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx
     if (!parse_mpo(W1, Lo, Mo, true, e1, "vjp W1") || !parse_mpo(W2, Mo, Ro, false, e2, "vjp W2")) return HX_EINVAL;
     Plan* P = new Plan();
     int rc = build_heff_vjp(*P, lb, rb, Lo, Mo, Ro, e1, e2, opts);
+    if (rc != HX_OK) {
+        delete P;
+        return rc;
+    }
+    finalize_tables(*P);
+    *out = reinterpret_cast<hx_plan*>(P);
+    return HX_OK;
+}
+
+int hx_heff1_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops, const hx_opset* Rops,
+                             const hx_mpo_site* W, const hx_plan_opts* opts, hx_plan** out) {
+    if (!out) {
+        set_error("heff1_vjp_plan_create: null output");
+        return HX_EINVAL;
+    }
+    *out = nullptr;
+    Bond lb, rb;
+    OpSet Lo, Ro;
+    if (!parse_bond(lbond, lb, "vjp1 left bond") || !parse_bond(rbond, rb, "vjp1 right bond")) return HX_EINVAL;
+    if (!parse_ops(Lops, Lo, "vjp1 Lops") || !parse_ops(Rops, Ro, "vjp1 Rops")) return HX_EINVAL;
+    std::vector<Entry> e1;
+    if (!parse_mpo(W, Lo, Ro, true, e1, "vjp1 W")) return HX_EINVAL;
+    Plan* P = new Plan();
+    int rc = build_heff_vjp(*P, lb, rb, Lo, Ro, Ro, e1, {}, opts, true);
     if (rc != HX_OK) {
         delete P;
         return rc;

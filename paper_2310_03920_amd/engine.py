@@ -86,6 +86,42 @@ class Engine:
                              self._w[i], self._w[i + 1], t_budget_bytes=self.t_budget,
                              **self.opts).upload(self.device)
 
+    def env_update_backward(self, direction, k, bond_k, bond_k1, site, env_in, G):
+        """Adjoint of update_left (direction 0: left[k] -> left[k+1]) or update_right
+        (direction 1: right[k+1] -> right[k]) at site k.  For the cotangent G of the
+        updated environment, f = <G, env_out> equals <A, H1 A> for the one-site
+        H_eff of site k whose right (direction 0) or left (direction 1) environment is
+        G, so the one-site sigma and its adjoint (with psi = g = A) give
+          d env_in (payload layout), d site (site payload layout) = H1 A + H1^T A,
+          d W_k (nnz, 4, 4: the values of the site's MPO tensor).
+        Environments and site tensors stay on the device; every step is a library call."""
+        torch = self.torch
+        f64 = dict(dtype=torch.float64, device=self.device)
+        lb, rb = X.Bond(bond_k), X.Bond(bond_k1)
+        L, R = (env_in, G) if direction == 0 else (G, env_in)
+        vjp = X.Heff1VjpPlan(lb, rb, self.mpo.dq[k], self.mpo.dq[k + 1], self._w[k],
+                             t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
+        fwd = self.heff1_plan(k, bond_k, bond_k1)
+        idx = torch.from_numpy(X.site_to_psi1_index(lb, rb)).to(self.device)
+        n = int(vjp.info.psi_nnz)
+        a = torch.empty(n, **f64)
+        X.gather_index(idx, site, a)
+        g_a = torch.empty(n, **f64)
+        g_L = torch.empty(max(L.numel(), 1), **f64)
+        g_R = torch.empty(max(R.numel(), 1), **f64)
+        g_w = torch.empty(max(16 * vjp.nnz1, 1), **f64)
+        g_w2 = torch.empty(max(16 * vjp.nnz2, 1), **f64)
+        vjp.prepare(L, R)
+        vjp.backward(L, R, a, a, g_a, g_L, g_R, g_w, g_w2)
+        sig = torch.empty(n, **f64)
+        fwd.prepare(L, R)
+        fwd.apply(L, R, a, sig)
+        X.axpy(1.0, sig, g_a)
+        d_site = torch.zeros_like(site)
+        X.scatter_index(idx, g_a, d_site)
+        d_env = (g_L[:L.numel()] if direction == 0 else g_R[:R.numel()])
+        return d_env, d_site, g_w[:16 * vjp.nnz1].view(vjp.nnz1, 4, 4)
+
     def drop_plans(self):
         self._env_plans.clear()
         self._heff_plans.clear()
