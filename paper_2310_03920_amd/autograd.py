@@ -61,3 +61,48 @@ class _HeffApply(torch.autograd.Function):
         op.vjp.backward(L, R, psi, g, g_psi, g_L, g_R, g_w1, g_w2)
         s1, s2 = ctx.w_shapes
         return (None, g_L, g_R, g_w1[:16 * op.vjp.nnz1].view(s1), g_w2[:16 * op.vjp.nnz2].view(s2), g_psi)
+
+
+class EnvUpdateOperator:
+    """The environment update of one site as an autograd operation.
+
+    direction 0: left[k] (bond k) -> left[k+1] (bond k+1); direction 1: right[k+1]
+    (bond k+1) -> right[k] (bond k).  Forward is hx_env_update; backward recomputes
+    through the one-site sigma-vector and its adjoint (Engine.env_update_backward),
+    so gradients chain through any number of environment updates to the site
+    tensors, the first environment and the MPO values of every site.  The MPO values
+    are compiled into the plans; the w tensor passed in (`values()`) receives
+    gradients."""
+
+    def __init__(self, engine, direction, k, bond_k, bond_k1):
+        self.eng, self.direction, self.k = engine, direction, k
+        self.bond_k, self.bond_k1 = bond_k, bond_k1
+        self.plan = engine.env_plan(direction, k, bond_k, bond_k1)
+        self.out_nnz = int(self.plan.info.out_nnz)
+
+    def values(self):
+        s = self.eng.mpo.sites[self.k]
+        return torch.from_numpy(np.asarray(s.mats, dtype=np.float64).reshape(-1, 4, 4).copy()).to(self.eng.device)
+
+    def __call__(self, env_in, site, w):
+        return _EnvUpdate.apply(self, env_in, site, w)
+
+
+class _EnvUpdate(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, op, env_in, site, w):
+        env_in, site = env_in.contiguous(), site.contiguous()
+        out = torch.empty(op.out_nnz, dtype=torch.float64, device=env_in.device)
+        op.plan.update(env_in, site, out)
+        ctx.op = op
+        ctx.w_shape = w.shape
+        ctx.save_for_backward(env_in, site)
+        return out
+
+    @staticmethod
+    def backward(ctx, g):
+        env_in, site = ctx.saved_tensors
+        op = ctx.op
+        d_env, d_site, d_w = op.eng.env_update_backward(op.direction, op.k, op.bond_k, op.bond_k1, site, env_in,
+                                                        g.contiguous())
+        return None, d_env, d_site, d_w.reshape(ctx.w_shape)

@@ -98,3 +98,69 @@ def test_env_update_adjoint_matches_oracle_differences(device, direction):
     ref = f(env, [(a, b, op + VW[e][2]) for e, (a, b, op) in enumerate(W)], A) - f0
     print(f"d W: {got:.12e} vs {ref:.12e}", flush=True)
     assert abs(got - ref) <= 1e-11 * scale
+
+
+def test_autograd_chains_through_two_environment_updates(device):
+    """f = <G, left[k+2]> with left[k+2] = upd(upd(left[k], A_k), A_k+1): autograd
+    gradients with respect to A_k, left[k] and the first site's MPO values equal
+    exact differences of the same chain built from the oracle's update."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.autograd import EnvUpdateOperator
+    from paper_2310_03920_amd.engine import Engine
+    from paper_2310_03920_amd.mpo import MPO, SiteMPO
+    print("[env adjoint] autograd chain of two left updates", flush=True)
+    rng = np.random.default_rng(77)
+    b0 = sorted([((2, 0), 9), ((2, 2), 3), ((3, 1), 12), ((3, -1), 1)])
+    b1 = sorted([((3, 1), 10), ((3, -1), 2), ((4, 0), 14), ((4, 2), 5), ((5, 1), 3)])
+    b2 = sorted([((4, 0), 11), ((4, 2), 4), ((5, 1), 13), ((5, -1), 6), ((6, 0), 2)])
+    d0 = [DQS[i % 9] for i in range(5)]
+    d1 = [DQS[(i * 4 + 1) % 9] for i in range(7)]
+    d2 = [DQS[(i * 2 + 3) % 9] for i in range(6)]
+    W0 = random_site_ops(d0, d1, rng, per_col=3)
+    W1 = random_site_ops(d1, d2, rng, per_col=3)
+    site = lambda W: SiteMPO(np.array([w[0] for w in W]), np.array([w[1] for w in W]),  # noqa: E731
+                             np.array([w[2] for w in W]))
+    mpo = MPO(K=2, cuts=[list(range(len(d))) for d in (d0, d1, d2)], sites=[site(W0), site(W1)],
+              dq=[np.array(d) for d in (d0, d1, d2)])
+    E0 = random_env(b0, d0, rng)
+    A0 = random_site_tensor(b0, b1, rng)
+    A1 = random_site_tensor(b1, b2, rng)
+    G = random_env(b2, d2, rng)
+    eng = Engine(mpo, device=device)
+    B0, B1, B2 = X.Bond(b0), X.Bond(b1), X.Bond(b2)
+    u0 = EnvUpdateOperator(eng, 0, 0, b0, b1)
+    u1 = EnvUpdateOperator(eng, 0, 1, b1, b2)
+    e0 = torch.from_numpy(X.pack_env(B0, d0, E0)).to(device).requires_grad_(True)
+    a0 = torch.from_numpy(X.pack_site(B0, B1, A0)).to(device).requires_grad_(True)
+    a1 = torch.from_numpy(X.pack_site(B1, B2, A1)).to(device)
+    w0 = u0.values().requires_grad_(True)
+    g = torch.from_numpy(X.pack_env(B2, d2, G)).to(device)
+    e2 = u1(u0(e0, a0, w0), a1, u1.values())
+    torch.dot(g, e2).backward()
+    torch.cuda.synchronize()
+
+    def f(E, A, W):
+        e1 = contract.env_update_left(contract.dense_env(E, b0), contract.dense_mpo(W, len(d0), len(d1)),
+                                      mps.dense_site_tensor(A, b0, b1))
+        e2d = contract.env_update_left(e1, contract.dense_mpo(W1, len(d1), len(d2)),
+                                       mps.dense_site_tensor(A1, b1, b2))
+        return float(np.sum(contract.dense_env(G, b2) * e2d))
+
+    f0 = f(E0, A0, W0)
+    scale = abs(f0) + 1.0
+    VA = random_site_tensor(b0, b1, rng)
+    got = float(np.dot(a0.grad.cpu().numpy(), X.pack_site(B0, B1, VA)))
+    ref = 0.5 * (f(E0, {k: A0[k] + VA[k] for k in A0}, W0) - f(E0, {k: A0[k] - VA[k] for k in A0}, W0))
+    print(f"d A_k: {got:.12e} vs {ref:.12e}", flush=True)
+    assert abs(got - ref) <= 1e-11 * scale
+    VE = random_env(b0, d0, rng)
+    got = float(np.dot(e0.grad.cpu().numpy(), X.pack_env(B0, d0, VE)))
+    ref = f(_axpy_env(E0, VE, 1.0), A0, W0) - f0
+    print(f"d left[k]: {got:.12e} vs {ref:.12e}", flush=True)
+    assert abs(got - ref) <= 1e-11 * scale
+    VW = [(a, b, np.where(op != 0.0, rng.standard_normal((4, 4)), 0.0)) for a, b, op in W0]
+    got = float(np.sum(w0.grad.cpu().numpy() * np.array([v[2] for v in VW])))
+    ref = f(E0, A0, [(a, b, op + VW[e][2]) for e, (a, b, op) in enumerate(W0)]) - f0
+    print(f"d W_k: {got:.12e} vs {ref:.12e}", flush=True)
+    assert abs(got - ref) <= 1e-11 * scale
