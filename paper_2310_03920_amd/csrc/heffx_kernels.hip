@@ -522,78 +522,101 @@ __global__ __launch_bounds__(DOT_BLOCKS) void dots_pass2(int k, const double* __
 constexpr int64_t DW_G = 0, DW_Y = 1024, DW_C = 1056, DW_S = 1088, DW_P = 1096;
 constexpr int64_t DW_TOTAL = DW_P + (int64_t)DOT_BLOCKS * KMAX;
 
-// Lowest eigenpair of the symmetrised k x k projected matrix by cyclic Jacobi
-// rotations (one wavefront).  theta -> ws[DW_S], y -> ws[DW_Y..].
+// Lowest eigenpair of the symmetrised k x k projected matrix by Jacobi rotations
+// (one wavefront).  Each step rotates k/2 disjoint index pairs at once (round-robin
+// pairing, k - 1 steps per sweep, a dummy index when k is odd): one lane computes each
+// pair's rotation, then the row and the column updates of all pairs run in parallel.
+// theta -> ws[DW_S], y -> ws[DW_Y..].
 __global__ __launch_bounds__(64) void dav_eig(int k, double* ws, double* scal) {
     __shared__ double A[KMAX][KMAX + 1];
     __shared__ double V[KMAX][KMAX + 1];
-    __shared__ double cs[3];
-    __shared__ int flag;
+    __shared__ double rc[KMAX / 2], rs[KMAX / 2];
+    __shared__ int rp[KMAX / 2], rq[KMAX / 2];
+    __shared__ int order[KMAX];
     const int t = threadIdx.x;
+    const int ke = (k + 1) & ~1;
+    const int np = ke / 2;
     const double* G = ws + DW_G;
     for (int idx = t; idx < k * k; idx += 64) {
         int i = idx / k, j = idx % k;
         A[i][j] = 0.5 * (G[i * KMAX + j] + G[j * KMAX + i]);
         V[i][j] = (i == j) ? 1.0 : 0.0;
     }
+    for (int i = t; i < ke; i += 64) order[i] = i;
     __syncthreads();
     for (int sweep = 0; sweep < 60; ++sweep) {
-        if (t == 0) {
-            double off = 0.0, dia = 0.0;
-            for (int i = 0; i < k; ++i)
-                for (int j = 0; j < k; ++j) {
-                    if (i == j)
-                        dia = fmax(dia, fabs(A[i][i]));
-                    else
-                        off = fmax(off, fabs(A[i][j]));
-                }
-            flag = (off <= 1e-16 * fmax(dia, 1e-300)) ? 1 : 0;
+        double off = 0.0, dia = 0.0;
+        for (int idx = t; idx < k * k; idx += 64) {
+            const int i = idx / k, j = idx % k;
+            const double v = fabs(A[i][j]);
+            if (i == j)
+                dia = fmax(dia, v);
+            else
+                off = fmax(off, v);
         }
-        __syncthreads();
-        if (flag) break;
-        for (int p = 0; p < k - 1; ++p)
-            for (int q = p + 1; q < k; ++q) {
-                if (t == 0) {
-                    double apq = A[p][q];
-                    if (fabs(apq) < 1e-300) {
-                        cs[0] = 1.0;
-                        cs[1] = 0.0;
-                        cs[2] = 0.0;
-                    } else {
-                        double th = (A[q][q] - A[p][p]) / (2.0 * apq);
-                        double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
-                        double c = 1.0 / sqrt(tt * tt + 1.0);
-                        cs[0] = c;
-                        cs[1] = tt * c;
-                        cs[2] = tt;
+        for (int m = 32; m > 0; m >>= 1) {
+            off = fmax(off, __shfl_xor(off, m));
+            dia = fmax(dia, __shfl_xor(dia, m));
+        }
+        if (off <= 1e-16 * fmax(dia, 1e-300)) break;  // the same on every lane
+        for (int step = 0; step < ke - 1; ++step) {
+            if (t < np) {
+                int p = order[t], q = order[ke - 1 - t];
+                if (p > q) {
+                    const int x = p;
+                    p = q;
+                    q = x;
+                }
+                double c = 1.0, sn = 0.0;
+                if (q < k) {
+                    const double apq = A[p][q];
+                    if (fabs(apq) >= 1e-300) {
+                        const double th = (A[q][q] - A[p][p]) / (2.0 * apq);
+                        const double tt = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                        c = 1.0 / sqrt(tt * tt + 1.0);
+                        sn = tt * c;
                     }
                 }
-                __syncthreads();
-                const double c = cs[0], s = cs[1], tt = cs[2];
-                if (s != 0.0) {
-                    if (t < k && t != p && t != q) {
-                        double arp = A[t][p], arq = A[t][q];
-                        double np = c * arp - s * arq, nq = s * arp + c * arq;
-                        A[t][p] = np;
-                        A[p][t] = np;
-                        A[t][q] = nq;
-                        A[q][t] = nq;
-                    }
-                    if (t < k) {
-                        double vp = V[t][p], vq = V[t][q];
-                        V[t][p] = c * vp - s * vq;
-                        V[t][q] = s * vp + c * vq;
-                    }
-                    if (t == 0) {
-                        double apq = A[p][q];
-                        A[p][p] -= tt * apq;
-                        A[q][q] += tt * apq;
-                        A[p][q] = 0.0;
-                        A[q][p] = 0.0;
-                    }
-                }
-                __syncthreads();
+                rp[t] = p;
+                rq[t] = q;
+                rc[t] = c;
+                rs[t] = sn;
             }
+            __syncthreads();
+            for (int idx = t; idx < np * k; idx += 64) {  // rows p, q of every pair
+                const int pi = idx / k, j = idx % k;
+                const int p = rp[pi], q = rq[pi];
+                if (q >= k || rs[pi] == 0.0) continue;
+                const double c = rc[pi], sn = rs[pi];
+                const double ap = A[p][j], aq = A[q][j];
+                A[p][j] = c * ap - sn * aq;
+                A[q][j] = sn * ap + c * aq;
+            }
+            __syncthreads();
+            for (int idx = t; idx < np * k; idx += 64) {  // columns p, q of A and V
+                const int pi = idx / k, i = idx % k;
+                const int p = rp[pi], q = rq[pi];
+                if (q >= k || rs[pi] == 0.0) continue;
+                const double c = rc[pi], sn = rs[pi];
+                const double ap = A[i][p], aq = A[i][q];
+                A[i][p] = c * ap - sn * aq;
+                A[i][q] = sn * ap + c * aq;
+                const double vp = V[i][p], vq = V[i][q];
+                V[i][p] = c * vp - sn * vq;
+                V[i][q] = sn * vp + c * vq;
+            }
+            __syncthreads();
+            if (t < np && rq[t] < k && rs[t] != 0.0) {  // the rotated pair's element is zero
+                A[rp[t]][rq[t]] = 0.0;
+                A[rq[t]][rp[t]] = 0.0;
+            }
+            if (t == 0) {  // round-robin: order[0] stays, the rest rotate by one
+                const int last = order[ke - 1];
+                for (int i = ke - 1; i > 1; --i) order[i] = order[i - 1];
+                order[1] = last;
+            }
+            __syncthreads();
+        }
     }
     if (t == 0) {
         int best = 0;
