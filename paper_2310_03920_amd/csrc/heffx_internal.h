@@ -138,6 +138,9 @@ struct Plan {
     // adjoint plans: zero fills before, coefficient-gradient gathers after the GEMM launches
     std::vector<FillLaunch> bw_fill;
     std::vector<GatherLaunch> bw_gather;
+    // adjoint plans: whole-payload copies before (bw_pre) and after (bw_post) the GEMM
+    // launches (environment operators of one shift class staged contiguously)
+    std::vector<GatherLaunch> bw_pre, bw_post;
     int64_t w1_nnz = 0, w2_nnz = 0;  // MPO entries of the two sites (gradient lengths / 16)
     // sizes
     int64_t psi_nnz = 0, in_nnz = 0, in2_nnz = 0, out_nnz = 0;

@@ -464,6 +464,17 @@ __global__ void gather_scale(const Gather* __restrict__ g, Bases B) {
         d[(int64_t)x * gg.dstride] = gg.alpha * s[(int64_t)x * gg.sstride];
 }
 
+// Whole-payload copies (Gather entries with long counts): blockIdx.x picks the entry,
+// the gridDim.y blocks of 256 threads split its elements.
+__global__ void copy_wide(const Gather* __restrict__ g, Bases B) {
+    const Gather gg = g[blockIdx.x];
+    const double* s = space_ptr(B, gg.sspace) + gg.soff;
+    double* d = space_ptr(B, gg.dspace) + gg.doff;
+    for (int64_t x = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; x < gg.count;
+         x += (int64_t)gridDim.y * blockDim.x)
+        d[x * gg.dstride] = gg.alpha * s[x * gg.sstride];
+}
+
 __global__ void fill_zero(double* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0;
@@ -1106,9 +1117,17 @@ int hx_heff_apply_backward(const hx_plan* plan, const double* L, const double* R
         hipLaunchKernelGGL(fill_zero, dim3(nb), dim3(256), 0, s, B.p[f.space] + f.off, f.count);
         if ((rc = hip_check(hipGetLastError(), "backward fill"))) return rc;
     }
+    const Gather* gt = reinterpret_cast<const Gather*>(static_cast<const char*>(P->dev) + P->off_gathers);
+    for (const GatherLaunch& gl : P->bw_pre) {
+        hipLaunchKernelGGL(copy_wide, dim3((unsigned)gl.ng, 16), dim3(256), 0, s, gt + gl.g0, B);
+        if ((rc = hip_check(hipGetLastError(), "backward staging copy"))) return rc;
+    }
     for (const Launch& l : P->apply)
         if ((rc = launch_gemm<double, SP_N>(P, l, B, s))) return rc;
-    const Gather* gt = reinterpret_cast<const Gather*>(static_cast<const char*>(P->dev) + P->off_gathers);
+    for (const GatherLaunch& gl : P->bw_post) {
+        hipLaunchKernelGGL(copy_wide, dim3((unsigned)gl.ng, 16), dim3(256), 0, s, gt + gl.g0, B);
+        if ((rc = hip_check(hipGetLastError(), "backward staging copy"))) return rc;
+    }
     for (const GatherLaunch& gl : P->bw_gather) {
         hipLaunchKernelGGL(gather_scale, dim3((unsigned)gl.ng), dim3(64), 0, s, gt + gl.g0, B);
         if ((rc = hip_check(hipGetLastError(), "backward gather"))) return rc;

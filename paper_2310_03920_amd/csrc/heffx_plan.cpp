@@ -1102,54 +1102,75 @@ static int64_t place_grad_side(Plan& P, GradSide& G, int64_t ws) {
     return ws;
 }
 
-// Class GEMMs of one side: g_env (TN, into genv_space) and the coefficient gradient (NT).
-static void grad_class_blocks(const GradSide& G, const EnvLayout& lay, int8_t env_space, int8_t genv_space,
-                              std::vector<OutBlockTasks>& tn, std::vector<OutBlockTasks>& nt) {
+// Class GEMMs of one side.  The environment operators of a class are in general not
+// adjacent in the payload, so they are staged: copied (before the GEMM launches) into
+// a contiguous (operators x payload) matrix for the coefficient gradient
+// gC = G_class env^T (NT), and the environment gradient g_env = C^T G_class (TN) is
+// written as one contiguous matrix and copied to its operators afterwards.  Each
+// class is then one pair of GEMMs with up to 64 operators per tile.
+static int64_t grad_class_blocks(Plan& P, const GradSide& G, const EnvLayout& lay, int8_t env_space,
+                                 int8_t genv_space, int64_t ws, std::vector<OutBlockTasks>& tn,
+                                 std::vector<OutBlockTasks>& nt, std::vector<Gather>& pre,
+                                 std::vector<Gather>& post) {
     for (const auto& gc : G.classes) {
         const int ncol = (int)gc.cols.size(), ntr = (int)gc.trans.size();
-        int w = 0;
-        while (w < ncol) {
-            int w1 = w + 1;
-            while (w1 < ncol && lay.op_off[gc.cols[w1]] == lay.op_off[gc.cols[w1 - 1]] + gc.size) ++w1;
-            const int64_t eoff = lay.op_off[gc.cols[w]];
-            if (gc.size > 0) {
-                // g_env[run] = C[:, run]^T G_class
-                OutBlockTasks ob;
-                ob.coff = eoff;
-                ob.ldc = (int)gc.size;
-                ob.m = w1 - w;
-                ob.n = (int)gc.size;
-                Task t;
-                t.aoff = gc.coef0 + w;
-                t.lda = ncol;
-                t.boff = gc.g_base;
-                t.ldb = (int32_t)gc.size;
-                t.k = ntr;
-                t.alpha = 1.0;
-                t.set_spaces(SP_TAB, SP_WS);
-                ob.tasks.push_back(t);
-                tn.push_back(std::move(ob));
-                // gC[:, run] = G_class env[run]^T
-                OutBlockTasks oc;
-                oc.coff = gc.gc_base + w;
-                oc.ldc = ncol;
-                oc.m = ntr;
-                oc.n = w1 - w;
-                Task u;
-                u.aoff = gc.g_base;
-                u.lda = (int32_t)gc.size;
-                u.boff = eoff;
-                u.ldb = (int32_t)gc.size;
-                u.k = (int32_t)gc.size;
-                u.alpha = 1.0;
-                u.set_spaces(SP_WS, env_space);
-                oc.tasks.push_back(u);
-                nt.push_back(std::move(oc));
-            }
-            w = w1;
+        if (gc.size <= 0 || ncol == 0) continue;
+        const int64_t env_stage = ws, genv_stage = ws + (int64_t)ncol * gc.size;
+        ws += 2 * (int64_t)ncol * gc.size;
+        for (int w = 0; w < ncol; ++w) {
+            Gather g;
+            g.soff = lay.op_off[gc.cols[w]];
+            g.doff = env_stage + (int64_t)w * gc.size;
+            g.sstride = 1;
+            g.dstride = 1;
+            g.count = (int32_t)gc.size;
+            g.sspace = env_space;
+            g.dspace = SP_WS;
+            g.pad = 0;
+            g.alpha = 1.0;
+            pre.push_back(g);
+            Gather h = g;
+            h.soff = genv_stage + (int64_t)w * gc.size;
+            h.doff = lay.op_off[gc.cols[w]];
+            h.sspace = SP_WS;
+            h.dspace = genv_space;
+            post.push_back(h);
         }
+        // g_env[class] = C^T G_class
+        OutBlockTasks ob;
+        ob.coff = genv_stage;
+        ob.ldc = (int)gc.size;
+        ob.m = ncol;
+        ob.n = (int)gc.size;
+        Task t;
+        t.aoff = gc.coef0;
+        t.lda = ncol;
+        t.boff = gc.g_base;
+        t.ldb = (int32_t)gc.size;
+        t.k = ntr;
+        t.alpha = 1.0;
+        t.set_spaces(SP_TAB, SP_WS);
+        ob.tasks.push_back(t);
+        tn.push_back(std::move(ob));
+        // gC = G_class env[class]^T
+        OutBlockTasks oc;
+        oc.coff = gc.gc_base;
+        oc.ldc = ncol;
+        oc.m = ntr;
+        oc.n = ncol;
+        Task u;
+        u.aoff = gc.g_base;
+        u.lda = (int32_t)gc.size;
+        u.boff = env_stage;
+        u.ldb = (int32_t)gc.size;
+        u.k = (int32_t)gc.size;
+        u.alpha = 1.0;
+        u.set_spaces(SP_WS, SP_WS);
+        oc.tasks.push_back(u);
+        nt.push_back(std::move(oc));
     }
-    (void)genv_space;
+    (void)P;
+    return ws;
 }
 
 // one_site: the adjoint of the one-site sigma-vector (as in build_heff: the second site
@@ -1537,15 +1558,23 @@ static int build_heff_vjp(Plan& P, const Bond& lb, const Bond& rb, const OpSet& 
             flush_blocks(P, blocks, TN_, SP_WS, 0, true, P.apply, &fl, &ntask);
         }
     }
-    // ---- class GEMMs: environment gradients (TN) and coefficient gradients (NT)
+    // ---- class GEMMs: environment gradients (TN) and coefficient gradients (NT),
+    // on class-contiguous staged copies
     {
-        std::vector<OutBlockTasks> tnL, ntL, tnR, ntR;
-        grad_class_blocks(GL, Ll, SP_L, SP_GL, tnL, ntL);
-        grad_class_blocks(GR, Rl, SP_R, SP_GR, tnR, ntR);
-        flush_blocks(P, tnL, TN_, SP_GL, 0, false, P.apply, &fl, &ntask);
-        flush_blocks(P, tnR, TN_, SP_GR, 0, false, P.apply, &fl, &ntask);
-        ntL.insert(ntL.end(), ntR.begin(), ntR.end());
-        flush_blocks(P, ntL, NT, SP_WS, 0, false, P.apply, &fl, &ntask);
+        std::vector<OutBlockTasks> tn, nt;
+        std::vector<Gather> pre, post;
+        ws = grad_class_blocks(P, GL, Ll, SP_L, SP_GL, ws, tn, nt, pre, post);
+        ws = grad_class_blocks(P, GR, Rl, SP_R, SP_GR, ws, tn, nt, pre, post);
+        flush_blocks(P, tn, TN_, SP_WS, 0, false, P.apply, &fl, &ntask);
+        flush_blocks(P, nt, NT, SP_WS, 0, false, P.apply, &fl, &ntask);
+        if (!pre.empty()) {
+            P.bw_pre.push_back({(int64_t)P.gathers.size(), (int64_t)pre.size()});
+            P.gathers.insert(P.gathers.end(), pre.begin(), pre.end());
+        }
+        if (!post.empty()) {
+            P.bw_post.push_back({(int64_t)P.gathers.size(), (int64_t)post.size()});
+            P.gathers.insert(P.gathers.end(), post.begin(), post.end());
+        }
     }
     // ---- scatter the coefficient gradients to the MPO value layout
     {
@@ -1585,6 +1614,30 @@ static int build_heff_vjp(Plan& P, const Bond& lb, const Bond& rb, const OpSet& 
     ws += P.part_tiles * TM * TN;
     P.ws_doubles = ws;
     if (!check_task_index_range(P)) return HX_EINVAL;
+    // every copy of the adjoint stays inside its source and destination buffers
+    auto space_size = [&](int sp) -> int64_t {
+        switch (sp) {
+            case SP_L: case SP_GL: return P.in_nnz;
+            case SP_R: case SP_GR: return P.in2_nnz;
+            case SP_WS: return P.ws_doubles;
+            case SP_TAB: return (int64_t)P.coef.size();
+            case SP_GW1: return 16 * P.w1_nnz;
+            case SP_GW2: return 16 * P.w2_nnz;
+            default: return P.psi_nnz;
+        }
+    };
+    for (auto* seq : {&P.bw_pre, &P.bw_post, &P.bw_gather})
+        for (const GatherLaunch& gl : *seq)
+            for (int64_t q = gl.g0; q < gl.g0 + gl.ng; ++q) {
+                const Gather& g = P.gathers[q];
+                const int64_t last = (int64_t)std::max(g.count - 1, 0);
+                if (g.count < 0 || g.soff < 0 || g.doff < 0 ||
+                    g.soff + last * g.sstride >= space_size(g.sspace) ||
+                    g.doff + last * g.dstride >= space_size(g.dspace)) {
+                    set_error("internal: adjoint copy out of range");
+                    return HX_EINVAL;
+                }
+            }
     return HX_OK;
 }
 

@@ -86,3 +86,57 @@ def test_fullsize_sigma_rows_match_the_oracle(device, problem, budget_gb):
     print(f"[full size] max |gpu - oracle| = {worst:.3e} (scale {scale:.3e})", flush=True)
     assert worst <= 1e-11 * scale
     del plan
+
+
+def test_backward_at_config5_size_satisfies_euler_identities(device):
+    """Adjoint at the middle of the 24-orbital chain, M = 500 (NC MPO, seeded N(0,1)
+    environments, psi and cotangent g).  sigma is linear in each of psi, L, R, W1,
+    W2 separately, so <g_X, X> = <g, sigma> for every one of them -- identities
+    that hold at any size and fail for a dropped, duplicated or misplaced term."""
+    import time
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.mpo import build_nc_mpo
+    K2, M2 = 24, 500
+    i = K2 // 2 - 1
+    print(f"[full size] backward, {K2} orbitals, M={M2}", flush=True)
+    mpo = build_nc_mpo(*make_integrals(K2, seed=0))
+    bonds = bond_sector_tables(K2, K2, 0, M2, model="gaussian", width=1.0)
+    lb, rb = bonds[i], bonds[i + 2]
+    rng = np.random.default_rng(11)
+    Ldq = [tuple(x) for x in mpo.dq[i]]
+    Mdq = [tuple(x) for x in mpo.dq[i + 1]]
+    Rdq = [tuple(x) for x in mpo.dq[i + 2]]
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    W1 = X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats)
+    W2 = X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats)
+    opts = dict(kernel_variant=1, split_kseg_min=512)
+    fwd = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, **opts).upload(device)
+    vjp = X.HeffVjpPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, **opts).upload(device)
+    f64 = dict(dtype=torch.float64, device=device)
+    L = torch.from_numpy(X.pack_env(lbB, Ldq, random_env(lb, Ldq, rng))).to(device)
+    R = torch.from_numpy(X.pack_env(rbB, Rdq, random_env(rb, Rdq, rng))).to(device)
+    psi = torch.from_numpy(X.pack_psi(lbB, rbB, random_psi(lb, rb, rng))).to(device)
+    g = torch.from_numpy(X.pack_psi(lbB, rbB, random_psi(lb, rb, rng))).to(device)
+    sigma = torch.empty_like(psi)
+    fwd.prepare(L, R)
+    fwd.apply(L, R, psi, sigma)
+    g_psi, g_L, g_R = torch.empty_like(psi), torch.empty_like(L), torch.empty_like(R)
+    g_w1 = torch.empty(16 * vjp.nnz1, **f64)
+    g_w2 = torch.empty(16 * vjp.nnz2, **f64)
+    vjp.prepare(L, R)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    vjp.backward(L, R, psi, g, g_psi, g_L, g_R, g_w1, g_w2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    ref = float(torch.dot(g, sigma))
+    w1 = torch.from_numpy(W1.vals.ravel().copy()).to(device)
+    w2 = torch.from_numpy(W2.vals.ravel().copy()).to(device)
+    got = {"psi": float(torch.dot(g_psi, psi)), "L": float(torch.dot(g_L, L)), "R": float(torch.dot(g_R, R)),
+           "W1": float(torch.dot(g_w1, w1)), "W2": float(torch.dot(g_w2, w2))}
+    print(f"[full size] backward {1e3 * dt:.1f} ms ({vjp.info.flops_apply / 1e12:.3f} TFLOP); <g, sigma> = {ref:.12e}; "
+          + ", ".join(f"{k}: {v:.12e}" for k, v in got.items()), flush=True)
+    for k, v in got.items():
+        assert abs(v - ref) <= 1e-11 * (abs(ref) + float(torch.linalg.vector_norm(g)) *
+                                         float(torch.linalg.vector_norm(sigma))), k
