@@ -251,6 +251,15 @@ int hx_heff_apply_backward(const hx_plan* plan, const double* L, const double* R
                            const double* psi, const double* g, double* g_psi, double* g_L,
                            double* g_R, double* g_W1, double* g_W2, hx_stream stream);
 
+/* hx_heff_apply_backward with FP32 operands and FP32 MFMA accumulation: L32, R32 and
+ * ws32 from hx_heff_lower_f32 on the VJP plan (after hx_heff_prepare in FP64), psi32
+ * and g32 in FP32, all outputs FP32 in the layouts of hx_heff_apply_backward.  The
+ * precision mode of the gradients (the FP32 case of the differentiation
+ * configuration); relative error ~1e-6 of the operands' scale. */
+int hx_heff_apply_backward_f32(const hx_plan* plan, const float* L32, const float* R32, void* ws32,
+                               const float* psi32, const float* g32, float* g_psi32, float* g_L32,
+                               float* g_R32, float* g_W1_32, float* g_W2_32, hx_stream stream);
+
 /* ---- batching: many independent sigma-vector problems per launch ----------- */
 
 /* Merge n single-chunk sigma-vector plans (each built by hx_heff_plan_create
@@ -318,7 +327,10 @@ int hx_axpy(int64_t n, double a, const double* x, double* y, hx_stream stream);
 
 /* Round the operands of a prepared sigma-vector plan to FP32: L -> L32 (in_nnz
  * floats), R -> R32 (in2_nnz floats) and the mixed operators held in ws (built
- * in FP64 by hx_heff_prepare) -> ws32 (a separate buffer of ws_bytes/2 bytes). */
+ * in FP64 by hx_heff_prepare) -> ws32 (a separate buffer of ws_bytes/2 bytes).
+ * Also accepts a prepared VJP plan (hx_heff_vjp_plan_create / hx_heff1_vjp_plan_create),
+ * whose coefficient table is then rounded into ws32 as well, for
+ * hx_heff_apply_backward_f32. */
 int hx_heff_lower_f32(const hx_plan* plan, const double* L, const double* R, const void* ws, float* L32,
                       float* R32, void* ws32, hx_stream stream);
 

@@ -25,7 +25,7 @@ EXPORTED = (
     "hx_heff_plan_batch", "hx_batch_offsets", "hx_heff_graph_create", "hx_graph_launch", "hx_graph_destroy",
     "hx_heff_vjp_plan_create", "hx_heff_apply_backward", "hx_heff_apply_bf16", "hx_davidson_restart2",
     "hx_heff1_plan_create", "hx_psi1_layout", "hx_heff1_vjp_plan_create", "hx_gather_index",
-    "hx_scatter_index", "hx_axpy",
+    "hx_scatter_index", "hx_axpy", "hx_heff_apply_backward_f32",
     "hx_last_error",
 )
 
@@ -107,6 +107,7 @@ def lib():
     L.hx_gather_index.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
     L.hx_scatter_index.argtypes = [c_int64, c_void_p, c_int64, c_void_p, c_void_p, c_void_p]
     L.hx_axpy.argtypes = [c_int64, ctypes.c_double, c_void_p, c_void_p, c_void_p]
+    L.hx_heff_apply_backward_f32.argtypes = [c_void_p] + [c_void_p] * 11
     L.hx_psi1_layout.argtypes = [P(HxBond), P(HxBond), c_int64, P(c_int32), P(c_int64)]
     L.hx_psi1_layout.restype = c_int64
     L.hx_heff_apply_backward.argtypes = [c_void_p] * 11 + [c_void_p]
@@ -500,6 +501,15 @@ class HeffVjpPlan(Plan):
         check(lib().hx_heff_apply_backward(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(psi), _ptr(g), _ptr(g_psi),
                                            _ptr(g_L), _ptr(g_R), _ptr(g_W1), _ptr(g_W2), _stream()),
               "heff_apply_backward")
+
+    def lower_f32(self, L, R):
+        """FP32 copies of L, R, the prepared mixed operators and the coefficient table."""
+        HeffPlan.lower_f32(self, L, R)
+
+    def backward_f32(self, psi32, g32, g_psi32, g_L32, g_R32, g_W1_32, g_W2_32):
+        check(lib().hx_heff_apply_backward_f32(self.h, _ptr(self.L32), _ptr(self.R32), _ptr(self.ws32), _ptr(psi32),
+                                               _ptr(g32), _ptr(g_psi32), _ptr(g_L32), _ptr(g_R32), _ptr(g_W1_32),
+                                               _ptr(g_W2_32), _stream()), "heff_apply_backward_f32")
 
 
 class Heff1VjpPlan(HeffVjpPlan):

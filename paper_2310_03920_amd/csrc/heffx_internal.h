@@ -146,6 +146,7 @@ struct Plan {
     int64_t psi_nnz = 0, in_nnz = 0, in2_nnz = 0, out_nnz = 0;
     int64_t ws_doubles = 0;
     int64_t part_base = 0;      // workspace offset (doubles) of the split-K partial region
+    int64_t coef32_base = -1;   // adjoint plans: FP32 copy of the coefficient table (workspace elements)
     int64_t mix_end = 0;        // workspace elements [0, mix_end) hold the mixed operators
     std::vector<std::pair<int64_t, int64_t>> mix_ranges;  // batched plans: per-instance mixed ranges
     // batched plans: per-instance element offsets of psi/sigma, L, R in the concatenated buffers

@@ -456,28 +456,31 @@ __global__ void cvt_f32_f64(int64_t n, const float* __restrict__ s, double* __re
         d[i] = (double)s[i];
 }
 
-__global__ void gather_scale(const Gather* __restrict__ g, Bases B) {
+template <typename T>
+__global__ void gather_scale(const Gather* __restrict__ g, BasesT<T> B) {
     const Gather gg = g[blockIdx.x];
-    const double* s = space_ptr(B, gg.sspace) + gg.soff;
-    double* d = space_ptr(B, gg.dspace) + gg.doff;
+    const T* s = space_ptr(B, gg.sspace) + gg.soff;
+    T* d = space_ptr(B, gg.dspace) + gg.doff;
     for (int x = threadIdx.x; x < gg.count; x += blockDim.x)
-        d[(int64_t)x * gg.dstride] = gg.alpha * s[(int64_t)x * gg.sstride];
+        d[(int64_t)x * gg.dstride] = (T)gg.alpha * s[(int64_t)x * gg.sstride];
 }
 
 // Whole-payload copies (Gather entries with long counts): blockIdx.x picks the entry,
 // the gridDim.y blocks of 256 threads split its elements.
-__global__ void copy_wide(const Gather* __restrict__ g, Bases B) {
+template <typename T>
+__global__ void copy_wide(const Gather* __restrict__ g, BasesT<T> B) {
     const Gather gg = g[blockIdx.x];
-    const double* s = space_ptr(B, gg.sspace) + gg.soff;
-    double* d = space_ptr(B, gg.dspace) + gg.doff;
+    const T* s = space_ptr(B, gg.sspace) + gg.soff;
+    T* d = space_ptr(B, gg.dspace) + gg.doff;
     for (int64_t x = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; x < gg.count;
          x += (int64_t)gridDim.y * blockDim.x)
-        d[x * gg.dstride] = gg.alpha * s[x * gg.sstride];
+        d[x * gg.dstride] = (T)gg.alpha * s[x * gg.sstride];
 }
 
-__global__ void fill_zero(double* p, int64_t n) {
+template <typename T>
+__global__ void fill_zero(T* p, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = 0.0;
+        p[i] = (T)0;
 }
 
 // ---------------------------------------------------------------- Davidson
@@ -1005,7 +1008,7 @@ int hx_axpy(int64_t n, double a, const double* x, double* y, hx_stream stream) {
 
 int hx_heff_lower_f32(const hx_plan* plan, const double* L, const double* R, const void* ws, float* L32, float* R32,
                       void* ws32, hx_stream stream) {
-    int rc = check_ready(plan, PK_HEFF);
+    int rc = check_ready(plan, PK_HEFF, PK_HEFF_VJP);
     if (rc) return rc;
     const Plan* P = reinterpret_cast<const Plan*>(plan);
     if ((P->in_nnz && (!L || !L32)) || (P->in2_nnz && (!R || !R32)) || (P->ws_doubles && (!ws || !ws32))) {
@@ -1019,6 +1022,11 @@ int hx_heff_lower_f32(const hx_plan* plan, const double* L, const double* R, con
         if ((rc = cvt(r.second - r.first, static_cast<const double*>(ws) + r.first, static_cast<float*>(ws32) + r.first,
                       s)))
             return rc;
+    if (P->kind == PK_HEFF_VJP && P->coef32_base >= 0 &&
+        (rc = cvt((int64_t)P->coef.size(),
+                  reinterpret_cast<const double*>(static_cast<const char*>(P->dev) + P->off_coef),
+                  static_cast<float*>(ws32) + P->coef32_base, s)))
+        return rc;
     return HX_OK;
 }
 
@@ -1076,12 +1084,12 @@ int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws
     for (const FillLaunch& f : P->diag_fill) {
         if (f.count <= 0) continue;
         int nb = (int)std::min<int64_t>(4096, (f.count + 255) / 256);
-        hipLaunchKernelGGL(fill_zero, dim3(nb), dim3(256), 0, s, B.p[f.space] + f.off, f.count);
+        hipLaunchKernelGGL(fill_zero<double>, dim3(nb), dim3(256), 0, s, B.p[f.space] + f.off, f.count);
         if ((rc = hip_check(hipGetLastError(), "diag fill"))) return rc;
     }
     const Gather* g = reinterpret_cast<const Gather*>(static_cast<const char*>(P->dev) + P->off_gathers);
     for (const GatherLaunch& gl : P->diag_gather) {
-        hipLaunchKernelGGL(gather_scale, dim3((unsigned)gl.ng), dim3(128), 0, s, g + gl.g0, B);
+        hipLaunchKernelGGL(gather_scale<double>, dim3((unsigned)gl.ng), dim3(128), 0, s, g + gl.g0, B);
         if ((rc = hip_check(hipGetLastError(), "diag gather"))) return rc;
     }
     for (const Launch& l : P->diag_gemm)
@@ -1089,24 +1097,41 @@ int hx_heff_diag(const hx_plan* plan, const double* L, const double* R, void* ws
     return HX_OK;
 }
 
-int hx_heff_apply_backward(const hx_plan* plan, const double* L, const double* R, void* ws, const double* psi,
-                           const double* g, double* g_psi, double* g_L, double* g_R, double* g_W1, double* g_W2,
-                           hx_stream stream) {
+}  // extern "C"
+
+// The backward launch sequence for FP64 or FP32 operands (FP32: environments, mixed
+// operators and coefficient table lowered by hx_heff_lower_f32).
+template <typename T>
+static int backward_impl(const hx_plan* plan, const T* L, const T* R, void* ws, const T* psi, const T* g, T* g_psi,
+                         T* g_L, T* g_R, T* g_W1, T* g_W2, hx_stream stream, const char* what) {
     int rc = check_ready(plan, PK_HEFF_VJP);
     if (rc) return rc;
     const Plan* P = reinterpret_cast<const Plan*>(plan);
     if ((P->psi_nnz && (!psi || !g || !g_psi)) || (P->in_nnz && (!L || !g_L)) || (P->in2_nnz && (!R || !g_R)) ||
         (P->w1_nnz && !g_W1) || (P->w2_nnz && !g_W2) || (P->ws_doubles && !ws)) {
-        set_error("heff_apply_backward: null operand");
+        set_error(std::string(what) + ": null operand");
         return HX_EINVAL;
     }
     if (P->psi_nnz && (g_psi == psi || g_psi == g)) {
-        set_error("heff_apply_backward: g_psi must not alias psi or g");
+        set_error(std::string(what) + ": g_psi must not alias psi or g");
+        return HX_EINVAL;
+    }
+    constexpr bool f64 = std::is_same<T, double>::value;
+    if (!f64 && P->coef32_base < 0) {
+        set_error(std::string(what) + ": plan has no FP32 coefficient table");
         return HX_EINVAL;
     }
     hipStream_t s = s_of(stream);
-    Bases B = make_bases(P, psi, g_psi, L, R, ws);
-    B.p[SP_G] = const_cast<double*>(g);
+    T* w = static_cast<T*>(ws);
+    BasesT<T> B{};
+    B.p[SP_PSI] = const_cast<T*>(psi);
+    B.p[SP_OUT] = g_psi;
+    B.p[SP_L] = const_cast<T*>(L);
+    B.p[SP_R] = const_cast<T*>(R);
+    B.p[SP_WS] = w;
+    B.p[SP_TAB] = f64 ? reinterpret_cast<T*>(static_cast<char*>(P->dev) + P->off_coef) : (w ? w + P->coef32_base : nullptr);
+    B.p[SP_PART] = w ? w + P->part_base : nullptr;
+    B.p[SP_G] = const_cast<T*>(g);
     B.p[SP_GL] = g_L;
     B.p[SP_GR] = g_R;
     B.p[SP_GW1] = g_W1;
@@ -1114,25 +1139,41 @@ int hx_heff_apply_backward(const hx_plan* plan, const double* L, const double* R
     for (const FillLaunch& f : P->bw_fill) {
         if (f.count <= 0) continue;
         int nb = (int)std::min<int64_t>(4096, (f.count + 255) / 256);
-        hipLaunchKernelGGL(fill_zero, dim3(nb), dim3(256), 0, s, B.p[f.space] + f.off, f.count);
+        hipLaunchKernelGGL(fill_zero<T>, dim3(nb), dim3(256), 0, s, B.p[f.space] + f.off, f.count);
         if ((rc = hip_check(hipGetLastError(), "backward fill"))) return rc;
     }
     const Gather* gt = reinterpret_cast<const Gather*>(static_cast<const char*>(P->dev) + P->off_gathers);
     for (const GatherLaunch& gl : P->bw_pre) {
-        hipLaunchKernelGGL(copy_wide, dim3((unsigned)gl.ng, 16), dim3(256), 0, s, gt + gl.g0, B);
+        hipLaunchKernelGGL(copy_wide<T>, dim3((unsigned)gl.ng, 16), dim3(256), 0, s, gt + gl.g0, B);
         if ((rc = hip_check(hipGetLastError(), "backward staging copy"))) return rc;
     }
     for (const Launch& l : P->apply)
-        if ((rc = launch_gemm<double, SP_N>(P, l, B, s))) return rc;
+        if ((rc = launch_gemm<T, SP_N>(P, l, B, s))) return rc;
     for (const GatherLaunch& gl : P->bw_post) {
-        hipLaunchKernelGGL(copy_wide, dim3((unsigned)gl.ng, 16), dim3(256), 0, s, gt + gl.g0, B);
+        hipLaunchKernelGGL(copy_wide<T>, dim3((unsigned)gl.ng, 16), dim3(256), 0, s, gt + gl.g0, B);
         if ((rc = hip_check(hipGetLastError(), "backward staging copy"))) return rc;
     }
     for (const GatherLaunch& gl : P->bw_gather) {
-        hipLaunchKernelGGL(gather_scale, dim3((unsigned)gl.ng), dim3(64), 0, s, gt + gl.g0, B);
+        hipLaunchKernelGGL(gather_scale<T>, dim3((unsigned)gl.ng), dim3(64), 0, s, gt + gl.g0, B);
         if ((rc = hip_check(hipGetLastError(), "backward gather"))) return rc;
     }
     return HX_OK;
+}
+
+extern "C" {
+
+int hx_heff_apply_backward(const hx_plan* plan, const double* L, const double* R, void* ws, const double* psi,
+                           const double* g, double* g_psi, double* g_L, double* g_R, double* g_W1, double* g_W2,
+                           hx_stream stream) {
+    return backward_impl<double>(plan, L, R, ws, psi, g, g_psi, g_L, g_R, g_W1, g_W2, stream,
+                                 "heff_apply_backward");
+}
+
+int hx_heff_apply_backward_f32(const hx_plan* plan, const float* L32, const float* R32, void* ws32,
+                               const float* psi32, const float* g32, float* g_psi32, float* g_L32, float* g_R32,
+                               float* g_W1_32, float* g_W2_32, hx_stream stream) {
+    return backward_impl<float>(plan, L32, R32, ws32, psi32, g32, g_psi32, g_L32, g_R32, g_W1_32, g_W2_32, stream,
+                                "heff_apply_backward_f32");
 }
 
 int hx_env_update(const hx_plan* plan, const double* env_in, const double* site, void* ws, double* env_out,

@@ -1610,6 +1610,8 @@ static int build_heff_vjp(Plan& P, const Bond& lb, const Bond& rb, const OpSet& 
     P.flops_apply = fl;
     P.n_tasks_apply = ntask;
     for (auto& L : P.apply) P.n_tiles_apply += L.ntile;
+    P.coef32_base = ws;  // FP32 coefficient table of the FP32 backward (hx_heff_lower_f32)
+    ws += (int64_t)P.coef.size();
     P.part_base = ws;
     ws += P.part_tiles * TM * TN;
     P.ws_doubles = ws;

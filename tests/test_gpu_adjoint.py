@@ -151,3 +151,34 @@ def test_autograd_energy_gradient_matches_central_differences(device):
               (energy(*args, Wm, W2) if slot == 3 else energy(*args, W1, Wm))) / (2 * h)
         an = float((grads[slot].cpu() * torch.from_numpy(np.array(V))).sum())
         assert an == pytest.approx(fd, rel=1e-6), (slot, an, fd)
+
+
+@pytest.mark.parametrize("seed,opts", [(1, {}), (6, {"t_budget_bytes": 256 * 1024, "kernel_variant": 1})])
+def test_backward_f32_matches_oracle_to_fp32_accuracy(device, seed, opts):
+    """FP32 operands and accumulation (hx_heff_apply_backward_f32): every gradient
+    within 2e-4 of the oracle's FP64 value, relative to its largest entry (inputs
+    rounded once to 2^-24, FP32 sums over <= ~2e3 terms), same as the FP32 sigma."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    print(f"[backward f32] seed={seed} {opts}", flush=True)
+    lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = _problem(seed, True)
+    rng = np.random.default_rng(70 + seed)
+    g = random_psi(lb, rb, rng)
+    ref = _oracle_vjp(X, lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi, g)
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    plan = X.HeffVjpPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, **opts).upload(device)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(device)  # noqa: E731
+    Lt, Rt = t(X.pack_env(lbB, Ldq, L)), t(X.pack_env(rbB, Rdq, R))
+    p32 = t(X.pack_psi(lbB, rbB, psi)).float()
+    g32 = t(X.pack_psi(lbB, rbB, g)).float()
+    plan.prepare(Lt, Rt)
+    plan.lower_f32(Lt, Rt)
+    out = {k: torch.full((n,), float("nan"), dtype=torch.float32, device=device)
+           for k, n in (("psi", p32.numel()), ("L", Lt.numel()), ("R", Rt.numel()),
+                        ("W1", 16 * len(W1)), ("W2", 16 * len(W2)))}
+    plan.backward_f32(p32, g32, out["psi"], out["L"], out["R"], out["W1"], out["W2"])
+    torch.cuda.synchronize()
+    for k in ref:
+        err = _rel(out[k].double().cpu().numpy(), ref[k])
+        print(f"  {k}: rel err {err:.2e}", flush=True)
+        assert err <= 2e-4, (k, err)
