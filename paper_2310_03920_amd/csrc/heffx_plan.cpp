@@ -494,16 +494,17 @@ static void sort_tiles(Plan& P, int64_t t0) {
         double work;
     };
     std::vector<Group> groups;
-    std::map<std::pair<int32_t, int32_t>, size_t> gid;
+    std::unordered_map<uint64_t, size_t> gid;
+    gid.reserve((size_t)n);
     std::vector<size_t> tile_group(n);
     for (int64_t t = 0; t < n; ++t) {
         const Tile& tl = P.tiles[t0 + t];
-        auto key = std::make_pair(tl.tbeg, tl.tend);
-        auto it = gid.find(key);
+        const uint64_t key = ((uint64_t)(uint32_t)tl.tbeg << 32) | (uint32_t)tl.tend;
         size_t g;
-        if (it == gid.end() || tl.tbeg == tl.tend) {  // empty task lists are independent tiles
+        auto it = tl.tbeg == tl.tend ? gid.end() : gid.find(key);
+        if (it == gid.end()) {  // a new group (empty task lists are independent tiles)
             g = groups.size();
-            if (tl.tbeg != tl.tend) gid[key] = g;
+            if (tl.tbeg != tl.tend) gid.emplace(key, g);
             groups.push_back({t, 0, 0.0});
         } else {
             g = it->second;
@@ -512,8 +513,12 @@ static void sort_tiles(Plan& P, int64_t t0) {
         groups[g].count++;
         groups[g].work += (double)tl.ktot * tl.m * tl.n;
     }
-    std::vector<std::vector<int64_t>> members(groups.size());
-    for (int64_t t = 0; t < n; ++t) members[tile_group[t]].push_back(t);
+    // members of each group in increasing tile order (counting sort)
+    std::vector<int64_t> mstart(groups.size() + 1, 0), mpos, mlist(n);
+    for (int64_t t = 0; t < n; ++t) ++mstart[tile_group[t] + 1];
+    for (size_t g = 0; g < groups.size(); ++g) mstart[g + 1] += mstart[g];
+    mpos.assign(mstart.begin(), mstart.end() - 1);
+    for (int64_t t = 0; t < n; ++t) mlist[mpos[tile_group[t]]++] = t;
     std::vector<size_t> order(groups.size());
     for (size_t g = 0; g < order.size(); ++g) order[g] = g;
     std::stable_sort(order.begin(), order.end(),
@@ -523,7 +528,7 @@ static void sort_tiles(Plan& P, int64_t t0) {
         int q = 0;
         for (int x = 1; x < NXCD; ++x)
             if (queue[x].size() < queue[q].size()) q = x;
-        for (int64_t t : members[g]) queue[q].push_back(t);
+        for (int64_t m = mstart[g]; m < mstart[g + 1]; ++m) queue[q].push_back(mlist[m]);
     }
     std::vector<Tile> out;
     out.reserve(n);
