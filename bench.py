@@ -457,6 +457,7 @@ def main():
     ap.add_argument("--bond-dim", type=int, default=1000)
     ap.add_argument("--max-iter", type=int, default=200)
     ap.add_argument("--tol", type=float, default=1e-7)
+    ap.add_argument("--kmax", type=int, default=24, help="Davidson subspace size (at most 32)")
     ap.add_argument("--pre-iter", type=int, default=100)
     ap.add_argument("--t-budget-gb", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -541,7 +542,7 @@ def main():
     psi0 = torch.from_numpy(X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2], rng))).to(device)
     diag = torch.empty(n, dtype=torch.float64, device=device)
     Lnew = torch.empty(int(einfo.out_nnz), dtype=torch.float64, device=device)
-    dav = Davidson(n, 24, device)
+    dav = Davidson(n, args.kmax, device)
     fixed = dict(bonds[i + 1])
     ev = []
 
@@ -642,7 +643,7 @@ def main():
                         f"environments from a seeded random MPS, NC-partition MPO",
             "orbitals": K, "electrons": N, "bond_dim": M, "psi_nnz": n,
             "mpo_bond_dims": [len(mpo.cuts[k]) for k in (i, i + 1, i + 2)],
-            "davidson": {"tol": args.tol, "max_iter": args.max_iter, "kmax": 24, "matvecs_per_step": nmv / args.steps,
+            "davidson": {"tol": args.tol, "max_iter": args.max_iter, "kmax": args.kmax, "matvecs_per_step": nmv / args.steps,
                          "warm_start_rnorm": r_pre, "reference_energy": e_ref, "reference_rnorm": r_ref,
                          "f32_matvecs_per_step": counts["f32"] / args.steps,
                          "f64_matvecs_per_step": counts["f64"] / args.steps, "precision": args.mode},
