@@ -175,8 +175,8 @@ def bench_batch(args):
         axes = [a for a in autotune.AXES[:2] if not (a[0] == "kernel_variant" and args.variant is not None)
                 and not (a[0] == "split_kseg_min" and args.kseg)]
 
-        if args.mode == "bf16":  # BF16 products need 16-deep stages
-            axes = [(k, tuple(v for v in vals if v != 2)) if k == "kernel_variant" else (k, vals)
+        if args.mode == "bf16":  # BF16 products need 16-deep stages and 4-wave tiles
+            axes = [(k, tuple(v for v in vals if v not in (2, 6))) if k == "kernel_variant" else (k, vals)
                     for k, vals in axes]
         Pt32, St32 = Pc.float(), torch.empty_like(Pc, dtype=torch.float32)
 
@@ -317,8 +317,8 @@ def plan_options(args, X, mpo, bonds, i, Lenv, Renv, tb, device):
     W2 = X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats)
     sig = torch.empty_like(psi)
     psi32, sig32 = psi.float(), torch.empty_like(psi, dtype=torch.float32)
-    if args.mode == "bf16":  # BF16 products need 16-deep stages
-        axes = [(k, tuple(v for v in vals if v != 2)) if k == "kernel_variant" else (k, vals) for k, vals in axes]
+    if args.mode == "bf16":  # BF16 products need 16-deep stages and 4-wave tiles
+        axes = [(k, tuple(v for v in vals if v not in (2, 6))) if k == "kernel_variant" else (k, vals) for k, vals in axes]
 
     def build(o):
         p = X.HeffPlan(lb, rb, mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2], W1, W2, **o).upload(device)
@@ -472,7 +472,7 @@ def main():
     ap.add_argument("--roots", type=int, default=1, help="apply workload: vectors per sigma-vector call")
     ap.add_argument("--kseg", type=int, default=0, help="split-K minimum segment (0 = default)")
     ap.add_argument("--variant", type=int, default=None,
-                    help="block-GEMM kernel variant (0, 1, 2); default: chosen by the autotuner")
+                    help="block-GEMM kernel variant (0 .. 6); default: chosen by the autotuner")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library defaults (or the given --variant/--kseg) instead of tuning")
     args = ap.parse_args()

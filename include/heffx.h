@@ -95,7 +95,9 @@ typedef struct {
                                 2 = two LDS buffers, 8-deep (less K padding, more workgroups per CU);
                                 3 = as 1 with persistent workgroups that prefetch their next tile;
                                 4, 5 = as 0, 1 with 128 x 32 tiles for narrow and 32 x 128 tiles for
-                                short blocks (one launch per tile shape).
+                                short blocks (one launch per tile shape);
+                                6 = as 1 with single-wave 32 x 32 tiles for blocks of at most
+                                32 x 32 (FP64 / FP32; BF16 products: HX_EUNSUP).
                                 Results are identical up to FP rounding order of the padding. */
     int32_t n_roots;         /* sigma-vector plans: number of vectors R applied per call (0 = 1, at
                                 most 64; the state-averaged multi-root form of Sec. II.A.3).  psi and

@@ -18,7 +18,7 @@ import os
 import numpy as np
 
 AXES = (
-    ("kernel_variant", (0, 1, 2, 3, 4, 5)),
+    ("kernel_variant", (0, 1, 2, 3, 4, 5, 6)),
     ("split_kseg_min", (512, 1024, 2048, 4096)),
     ("t_budget_bytes", (1 << 29, 1 << 30, 1 << 31)),
 )

@@ -89,12 +89,13 @@ struct Reduce {
 static_assert(sizeof(Reduce) == 40, "Reduce layout");
 
 // Tile shapes (4 waves of 32 x 32 each): 64 x 64, 128 x 32 (narrow blocks), 32 x 128
-// (short blocks).  Every shape holds TM * TN elements, the size of a split-K partial.
+// (short blocks); and 32 x 32 computed by a single wave (blocks of at most 32 x 32).
+// A split-K partial slot holds TM * TN elements, enough for every shape.
 constexpr int TM = 64;
 constexpr int TN = 64;
-enum TileShape : int { SH_SQ = 0, SH_TALL = 1, SH_WIDE = 2 };
-inline int shape_rows(int sh) { return sh == SH_TALL ? 128 : sh == SH_WIDE ? 32 : 64; }
-inline int shape_cols(int sh) { return sh == SH_TALL ? 32 : sh == SH_WIDE ? 128 : 64; }
+enum TileShape : int { SH_SQ = 0, SH_TALL = 1, SH_WIDE = 2, SH_SMALL = 3 };
+inline int shape_rows(int sh) { return sh == SH_TALL ? 128 : (sh == SH_WIDE || sh == SH_SMALL) ? 32 : 64; }
+inline int shape_cols(int sh) { return sh == SH_WIDE ? 128 : (sh == SH_TALL || sh == SH_SMALL) ? 32 : 64; }
 
 enum TransKind : int { NN = 0, NT = 1, TN_ = 2 };
 

@@ -392,6 +392,112 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     }
 }
 
+// Single-wave variant for blocks of at most 32 x 32 (SH_SMALL tiles): one wavefront
+// computes a 32 x 32 tile (2 x 2 MFMA blocks) over its task list with 16-deep K stages
+// staged through one LDS buffer, the same arithmetic and summation order as bsgemm's
+// quadrant.  FP64 or FP32 operands (no BF16 rounding).
+template <typename T, bool TA, bool TB, int NSP>
+__global__ __launch_bounds__(64) void bsgemm_w1(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
+                                                BasesT<T> B) {
+    using acc_t = typename std::conditional<std::is_same<T, double>::value, dbl4, flt4>::type;
+    constexpr int KSV = 16, TS = 32, NE = TS * KSV / 64;  // 8 elements of A and of B per lane
+    __shared__ T As[KSV][TS + LDS_PAD];
+    __shared__ T Bs[KSV][TS + LDS_PAD];
+    const int lane = threadIdx.x;
+    // load lanes (element e: idx = lane + 64 e): A !TA: k = idx % 16, row = idx / 16;
+    // A TA: row = idx % 32, k = idx / 32; B !TB: col = idx % 32, k = idx / 32;
+    // B TB: k = idx % 16, col = idx / 16
+    const int a_r = TA ? (lane % TS) : (lane / KSV);
+    const int a_k = TA ? (lane / TS) : (lane % KSV);
+    const int b_c = TB ? (lane / KSV) : (lane % TS);
+    const int b_k = TB ? (lane % KSV) : (lane / TS);
+    constexpr int a_dr = TA ? 0 : 64 / KSV, a_dk = TA ? 64 / TS : 0;
+    constexpr int b_dc = TB ? 64 / KSV : 0, b_dk = TB ? 0 : 64 / TS;
+
+    const Tile tl = tiles[blockIdx.x];
+    const int m = tl.m, n = tl.n;
+    Cursor<T, TA, TB, NSP, KSV> cur;
+    cur.start(tl.tbeg, tl.tend, tasks, B, tl.r0, tl.c0);
+    T ra[NE], rb[NE];
+    T alpha = 0;
+    int krem_ld = 0;
+    auto load_stage = [&]() {
+        const T *qa, *qb;
+        int krem;
+        cur.next(tasks, B, tl.r0, tl.c0, qa, qb, krem, alpha);
+        const int lda = cur.lda, ldb = cur.ldb;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
+            T va = 0;
+            if (ka < krem && r < m) va = qa[TA ? ka * lda + r : r * lda + ka];
+            ra[e] = va;
+        }
+#pragma unroll
+        for (int e = 0; e < NE; ++e) {
+            const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
+            T vb = 0;
+            if (kb < krem && c < n) vb = qb[TB ? c * ldb + kb : kb * ldb + c];
+            rb[e] = vb;
+        }
+        krem_ld = krem;
+    };
+    auto store_stage = [&]() {
+#pragma unroll
+        for (int e = 0; e < NE; ++e) As[a_k + a_dk * e][a_r + a_dr * e] = alpha * ra[e];
+#pragma unroll
+        for (int e = 0; e < NE; ++e) Bs[b_k + b_dk * e][b_c + b_dc * e] = rb[e];
+    };
+    acc_t acc00 = {0, 0, 0, 0}, acc01 = {0, 0, 0, 0}, acc10 = {0, 0, 0, 0}, acc11 = {0, 0, 0, 0};
+    const bool r1 = 16 < m, c1 = 16 < n;
+    const int nst = tl.ktot / KSV;
+    if (nst > 0) load_stage();
+    for (int s = 0; s < nst; ++s) {
+        store_stage();
+        const int kcur = krem_ld;
+        __syncthreads();
+        if (s + 1 < nst) load_stage();
+#pragma unroll
+        for (int ks = 0; ks < KSV / 4; ++ks) {
+            if (ks * 4 >= kcur) continue;
+            const int kr = ks * 4 + (lane >> 4);
+            const T a0 = As[kr][lane & 15], b0 = Bs[kr][lane & 15];
+            const T a1 = r1 ? As[kr][16 + (lane & 15)] : (T)0;
+            const T b1 = c1 ? Bs[kr][16 + (lane & 15)] : (T)0;
+            if constexpr (std::is_same<T, double>::value) {
+                acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc00, 0, 0, 0);
+                if (c1) acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc01, 0, 0, 0);
+                if (r1) acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc10, 0, 0, 0);
+                if (r1 && c1) acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
+            } else {
+                acc00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc00, 0, 0, 0);
+                if (c1) acc01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc01, 0, 0, 0);
+                if (r1) acc10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc10, 0, 0, 0);
+                if (r1 && c1) acc11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc11, 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    T* C = space_ptr<T, NSP>(B, tl.flags & 0xff) + tl.coff;
+    const int ldc = tl.ldc;
+    const bool beta = ((tl.flags >> 8) & 0xff) != 0;
+    auto put = [&](const acc_t& a, int rb0_, int cb0) {
+        const int col = cb0 + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int row = std::is_same<T, double>::value ? rb0_ + (lane >> 4) + 4 * v : rb0_ + 4 * (lane >> 4) + v;
+            if (row < m && col < n) {
+                T* p = C + (int64_t)row * ldc + col;
+                *p = beta ? (*p + a[v]) : a[v];
+            }
+        }
+    };
+    put(acc00, 0, 0);
+    put(acc01, 0, 16);
+    put(acc10, 16, 0);
+    put(acc11, 16, 16);
+}
+
 // Fixed-order sum of split-K partial tiles into the owning output tile.  Block
 // (x, y) sums the y-th of gridDim.y slices of tile x's elements; the partials of an
 // element are added in index order (loads issued four at a time).
@@ -796,7 +902,7 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
     }
     const int64_t nt = L.ntile;
     int rk;
-    if (L.shape != SH_SQ && P->variant != 4 && P->variant != 5) {
+    if (L.shape != SH_SQ && !((L.shape == SH_SMALL) ? P->variant == 6 : (P->variant == 4 || P->variant == 5))) {
         set_error("internal: tile shape without its kernel variant");
         return HX_EINVAL;
     }
@@ -820,6 +926,13 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
         switch (P->variant) {
             case 1:
             case 5:
+                rk = shaped(One{}, BFc{});
+                break;
+            case 6:
+                if (L.shape == SH_SMALL) {
+                    set_error("BF16 products have no single-wave tiles (kernel variant 6)");
+                    return HX_EUNSUP;
+                }
                 rk = shaped(One{}, BFc{});
                 break;
             case 3:
@@ -846,6 +959,28 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
             break;
         case 3:
             rk = launch_kind<T, NSP, 16, 1, false, true>(L.kind, nt, tiles, tasks, B, s);
+            break;
+        case 6:
+            if (L.shape == SH_SMALL) {
+                const dim3 grid((unsigned)nt), block(64);
+                switch (L.kind) {
+                    case NN:
+                        hipLaunchKernelGGL((bsgemm_w1<T, false, false, NSP>), grid, block, 0, s, tiles, tasks, B);
+                        break;
+                    case NT:
+                        hipLaunchKernelGGL((bsgemm_w1<T, false, true, NSP>), grid, block, 0, s, tiles, tasks, B);
+                        break;
+                    case TN_:
+                        hipLaunchKernelGGL((bsgemm_w1<T, true, false, NSP>), grid, block, 0, s, tiles, tasks, B);
+                        break;
+                    default:
+                        set_error("internal: bad GEMM kind");
+                        return HX_EINVAL;
+                }
+                rk = HX_OK;
+            } else {
+                rk = shaped(One{}, BFc{});
+            }
             break;
         default:
             rk = shaped(Two{}, BFc{});

@@ -410,8 +410,8 @@ static inline int32_t kpad(int32_t k, int ks) { return (k + ks - 1) / ks * ks; }
 static int apply_opts(Plan& P, const hx_plan_opts* o) {
     if (o && o->split_kseg_min > 0) P.split_kseg_min = o->split_kseg_min;
     const int v = o ? o->kernel_variant : 0;
-    if (v < 0 || v > 5) {
-        set_error("plan options: kernel_variant must be 0 .. 5");
+    if (v < 0 || v > 6) {
+        set_error("plan options: kernel_variant must be 0 .. 6");
         return HX_EINVAL;
     }
     P.variant = v;
@@ -635,7 +635,10 @@ struct OutBlockTasks {
 // waves of a workgroup meet the block; the rest 64 x 64.  Each shape is a launch of
 // its own, so a round costs up to three launches (their tails), which the tuner
 // weighs against the better-filled workgroups.
+// Variant 6: blocks of at most 32 x 32 get single-wave 32 x 32 tiles (no idle waves,
+// four times as many tiles in flight per CU), the rest 64 x 64.
 static int block_shape(const Plan& P, int m, int n) {
+    if (P.variant == 6) return (m <= 32 && n <= 32) ? SH_SMALL : SH_SQ;
     if (P.variant != 4 && P.variant != 5) return SH_SQ;
     if (n <= 32 && m > 64) return SH_TALL;
     if (m <= 32 && n > 64) return SH_WIDE;
@@ -647,7 +650,7 @@ static int block_shape(const Plan& P, int m, int n) {
 static void flush_blocks(Plan& P, std::vector<OutBlockTasks>& blocks, int kind, int8_t cspace, int8_t beta,
                          bool keep_empty, std::vector<Launch>& seq, double* flops_out, int64_t* ntask_out) {
     const int stage = P.n_stages++;
-    for (int sh = SH_SQ; sh <= SH_WIDE; ++sh) {
+    for (int sh = SH_SQ; sh <= SH_SMALL; ++sh) {
         Launch L;
         L.kind = kind;
         L.shape = sh;

@@ -61,7 +61,7 @@ def _individual(device, plan, arrs, f32=False):
     return res
 
 
-@pytest.mark.parametrize("variant", [0, 3, 5])
+@pytest.mark.parametrize("variant", [0, 3, 5, 6])
 def test_batched_apply_and_diag_match_instances_bitwise(device, variant):
     """Variant 3 (persistent workgroups): the batched stage-1 launch has more tiles
     (2219) than workgroups (1536), so workgroups run several tiles and prefetch."""

@@ -215,7 +215,7 @@ def test_vjp_plan_builds_for_every_site_of_the_nc_mpo():
 
 def test_autotune_coordinate_search_finds_separable_minimum():
     from paper_2310_03920_amd import autotune as A
-    cost = {"kernel_variant": {0: 3.0, 1: 1.0, 2: 2.0, 3: 1.5, 4: 2.5, 5: 1.2},
+    cost = {"kernel_variant": {0: 3.0, 1: 1.0, 2: 2.0, 3: 1.5, 4: 2.5, 5: 1.2, 6: 1.1},
             "split_kseg_min": {512: 0.6, 1024: 0.5, 2048: 0.7, 4096: 0.9},
             "t_budget_bytes": {1 << 29: 0.3, 1 << 30: 0.2, 1 << 31: 0.1}}
     calls = []
@@ -228,7 +228,7 @@ def test_autotune_coordinate_search_finds_separable_minimum():
 
     best, seen = A.coordinate_search(timer)
     assert best == {"kernel_variant": 1, "split_kseg_min": 1024, "t_budget_bytes": 1 << 31}
-    assert len(calls) == len(seen) == 11  # start + the other values of each axis, no repeats
+    assert len(calls) == len(seen) == 12  # start + the other values of each axis, no repeats
 
 
 def test_autotune_signature_depends_on_shape():
