@@ -416,7 +416,8 @@ def bench_sweep(args):
     K, M = args.orbitals, args.bond_dim
     h, g = make_integrals(K, seed=0)
     t0 = time.time()
-    d = DMRG(h, g, K, 0, M, seed=0, device="cuda", tol=args.tol, max_iter=args.max_iter)
+    switch = K // 2 if args.partition == "nc-cn" else None
+    d = DMRG(h, g, K, 0, M, seed=0, device="cuda", tol=args.tol, max_iter=args.max_iter, mpo_switch=switch)
     torch.cuda.synchronize()
     log(f"set-up (MPO, random MPS, right environments) {time.time() - t0:.1f}s; "
         f"MPO bond dims {[len(x) for x in d.mpo.dq]}")
@@ -442,7 +443,8 @@ def bench_sweep(args):
         "steps": args.steps, "warmup": 0, "ms_per_step": 1e3 * avg, "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"two-site DMRG passes over a {K}-orbital ab initio chain, {K} electrons, "
-                               f"2Sz=0, M={M}, integrals seed 0, seeded random initial MPS, NC-partition MPO",
+                               f"2Sz=0, M={M}, integrals seed 0, seeded random initial MPS, "
+                               + ("NC-partition MPO" if switch is None else f"NC-partition MPO up to cut {switch}, CN after"),
                    "orbitals": K, "bond_dim": M, "davidson": {"tol": args.tol, "max_iter": args.max_iter},
                    "mpo_bond_dims": [len(x) for x in d.mpo.dq]},
         "passes": passes, "peak_gpu_gb": torch.cuda.max_memory_allocated() / 1e9}))
@@ -468,6 +470,8 @@ def main():
                          "apply: sigma-vectors only at the middle step (profiling), ending with a 512 MiB "
                          "device copy that calibrates HBM byte counters; sweep: whole two-site passes "
                          "(24 orbitals, M=500 unless given)")
+    ap.add_argument("--partition", choices=["nc", "nc-cn"], default="nc",
+                    help="sweep workload: NC MPO at every cut, or NC up to the middle cut and CN after it")
     ap.add_argument("--instances", type=int, default=16)
     ap.add_argument("--roots", type=int, default=1, help="apply workload: vectors per sigma-vector call")
     ap.add_argument("--kseg", type=int, default=0, help="split-K minimum segment (0 = default)")

@@ -18,7 +18,7 @@ import numpy as np
 
 from . import _lib as X
 from .engine import Engine, site_payload
-from .mpo import SITE_QN, build_nc_mpo
+from .mpo import SITE_QN, build_mpo
 
 
 def _add(q, d, sign=1):
@@ -220,7 +220,7 @@ class DMRG:
     """Two-site DMRG for H(h, g) in the (n_elec, twosz) sector at bond dimension M."""
 
     def __init__(self, h, g, n_elec, twosz, M, seed=0, device="cuda", tol=1e-8, max_iter=30, kmax=24,
-                 bonds=None, tensors=None, t_budget_bytes=0, precision="f64"):
+                 bonds=None, tensors=None, t_budget_bytes=0, precision="f64", mpo_switch=None):
         from synth import bond_sector_tables, random_right_canonical_mps
         self.K = h.shape[0]
         self.M = M
@@ -230,7 +230,10 @@ class DMRG:
             raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
         self.precision = precision
         self.h, self.g = np.asarray(h, dtype=np.float64), np.asarray(g, dtype=np.float64)
-        self.mpo = build_nc_mpo(h, g)
+        # mpo_switch: None = NC partition at every cut; c = NC up to cut c and CN
+        # after it (same operator, smaller bonds on the right half for c ~ K/2)
+        self.mpo_switch = mpo_switch
+        self.mpo = self._mpo(self.h, self.g)
         self.bonds = bonds if bonds is not None else bond_sector_tables(self.K, n_elec, twosz, M)
         self.tensors = tensors if tensors is not None else random_right_canonical_mps(self.bonds, seed)
         self.eng = Engine(self.mpo, device=device, t_budget_bytes=t_budget_bytes)
@@ -307,12 +310,15 @@ class DMRG:
                                       site_payload(self.bonds[i + 1], self.bonds[i + 2], B, self.device))
         return [self._wgrad[k] for k in range(K)]
 
+    def _mpo(self, h, g):
+        return build_mpo(h, g, switch=self.mpo_switch)
+
     def integral_derivative(self, wgrad, dh, dg):
         """Directional derivative dE/dt of E(h + t dh, g + t dg) at fixed MPS from the
-        MPO-value gradients: the NC MPO values are affine in the integrals, so the
+        MPO-value gradients: the MPO values are affine in the integrals, so the
         change of every value along (dh, dg) is (W(h + dh) - W(h - dh)) / 2 exactly."""
-        plus = build_nc_mpo(self.h + dh, self.g + dg)
-        minus = build_nc_mpo(self.h - dh, self.g - dg)
+        plus = self._mpo(self.h + dh, self.g + dg)
+        minus = self._mpo(self.h - dh, self.g - dg)
         total = 0.0
         for k in range(self.K):
             sp, sm, s0 = plus.sites[k], minus.sites[k], self.mpo.sites[k]
@@ -358,7 +364,7 @@ class DMRG:
                 dg = np.zeros_like(self.g)
                 for x in orbit:
                     dg[x] = 1.0
-                plus = build_nc_mpo(self.h, self.g + dg)
+                plus = self._mpo(self.h, self.g + dg)
                 d = 0.0
                 for k in range(K):
                     sp, s0 = plus.sites[k], self.mpo.sites[k]

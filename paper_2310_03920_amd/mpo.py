@@ -68,6 +68,13 @@ def op_dq(key):
         return (1, _spin_sign(key[1]))
     if kind == "Td":
         return (-1, -_spin_sign(key[1]))
+    # complementary pair operators: minus the change of their right partner
+    if kind == "Pa":  # partner a+_r a+_s
+        return (-2, -_spin_sign(key[1]) - _spin_sign(key[2]))
+    if kind == "Pd":  # partner a_s a_r
+        return (2, _spin_sign(key[1]) + _spin_sign(key[2]))
+    if kind == "Q":   # partner a+_r a_s
+        return (0, _spin_sign(key[2]) - _spin_sign(key[1]))
     raise KeyError(key)
 
 
@@ -75,8 +82,13 @@ def op_parity(key):
     return 1 if key[0] in ("C", "D", "T", "Td") else 0
 
 
-def cut_ops(K, k):
-    """Bond operators at cut k (before pruning), in a fixed order."""
+def cut_ops(K, k, cn=False):
+    """Bond operators at cut k (before pruning), in a fixed order.
+
+    NC cut: normal pair operators A, Ad, B of the left block.  CN cut: in their
+    place the complementary pair operators Pa_rs, Pd_rs, Q_rs (r, s right of the
+    cut), each the left factor of all two-body terms whose right part is
+    a+_r a+_s, a_s a_r or a+_r a_s respectively (r < s for Pa and Pd)."""
     ops = []
     if k < K:
         ops.append(("I",))
@@ -86,11 +98,17 @@ def cut_ops(K, k):
         n = 2 * k
         ops += [("C", x) for x in range(n)]
         ops += [("D", x) for x in range(n)]
-        ops += [("A", x, y) for x in range(n) for y in range(x + 1, n)]
-        ops += [("Ad", x, y) for x in range(n) for y in range(x + 1, n)]
-        ops += [("B", x, y) for x in range(n) for y in range(n)]
+        if not cn:
+            ops += [("A", x, y) for x in range(n) for y in range(x + 1, n)]
+            ops += [("Ad", x, y) for x in range(n) for y in range(x + 1, n)]
+            ops += [("B", x, y) for x in range(n) for y in range(n)]
         ops += [("T", j) for j in range(n, 2 * K)]
         ops += [("Td", j) for j in range(n, 2 * K)]
+        if cn:
+            m = range(n, 2 * K)
+            ops += [("Pa", r, s) for r in m for s in m if r < s]
+            ops += [("Pd", r, s) for r in m for s in m if r < s]
+            ops += [("Q", r, s) for r in m for s in m]
     return ops
 
 
@@ -149,6 +167,9 @@ class _Index:
         self.B = np.full((n2, n2), -1)
         self.T = np.full(n2, -1)
         self.Td = np.full(n2, -1)
+        self.Pa = np.full((n2, n2), -1)
+        self.Pd = np.full((n2, n2), -1)
+        self.Q = np.full((n2, n2), -1)
         for i, key in enumerate(ops):
             kind = key[0]
             if kind == "I":
@@ -192,8 +213,12 @@ class _Sink:
         return r[starts], c[starts], np.add.reduceat(m, starts, axis=0)
 
 
-def _site_entries(K, k, coef, ops_k, ops_k1):
-    """W^(k) entries as arrays (row op index at cut k, col op index at cut k+1, 4x4)."""
+def _site_entries(K, k, coef, ops_k, ops_k1, rows_cn=False, cols_cn=False):
+    """W^(k) entries as arrays (row op index at cut k, col op index at cut k+1, 4x4).
+
+    rows_cn / cols_cn: cut k / cut k+1 is a CN cut (complementary pair operators
+    instead of normal ones).  NC rows with CN columns is the switch site, where
+    the integrals are folded into the left normal pairs."""
     ik, ik1 = _Index(K, ops_k), _Index(K, ops_k1)
     out = _Sink()
     n = 2 * k
@@ -207,22 +232,23 @@ def _site_entries(K, k, coef, ops_k, ops_k1):
     for s in range(2):
         out.add(ik.I, ik1.C[kap[s]], 1.0, CR[s] @ _P)
         out.add(ik.I, ik1.D[kap[s]], 1.0, AN[s] @ _P)
-    if n:
-        X, Y = np.meshgrid(xs, xs, indexing="ij")
-        up = X < Y
-        out.add(ik.A[X[up], Y[up]], ik1.A[X[up], Y[up]], 1.0, _I)
-        out.add(ik.Ad[X[up], Y[up]], ik1.Ad[X[up], Y[up]], 1.0, _I)
-        out.add(ik.B[X, Y], ik1.B[X, Y], 1.0, _I)
-    for s in range(2):
-        out.add(ik.C[xs], ik1.A[xs, kap[s]], 1.0, CR[s])
-        out.add(ik.D[xs], ik1.Ad[xs, kap[s]], -1.0, AN[s])
-        out.add(ik.C[xs], ik1.B[xs, kap[s]], 1.0, AN[s])
-        out.add(ik.D[xs], ik1.B[kap[s], xs], -1.0, CR[s])
-    out.add(ik.I, ik1.A[kap[0], kap[1]], 1.0, CR[0] @ CR[1])
-    out.add(ik.I, ik1.Ad[kap[0], kap[1]], 1.0, AN[1] @ AN[0])
-    for s in range(2):
-        for t in range(2):
-            out.add(ik.I, ik1.B[kap[s], kap[t]], 1.0, CR[s] @ AN[t])
+    if not cols_cn:
+        if n:
+            X, Y = np.meshgrid(xs, xs, indexing="ij")
+            up = X < Y
+            out.add(ik.A[X[up], Y[up]], ik1.A[X[up], Y[up]], 1.0, _I)
+            out.add(ik.Ad[X[up], Y[up]], ik1.Ad[X[up], Y[up]], 1.0, _I)
+            out.add(ik.B[X, Y], ik1.B[X, Y], 1.0, _I)
+        for s in range(2):
+            out.add(ik.C[xs], ik1.A[xs, kap[s]], 1.0, CR[s])
+            out.add(ik.D[xs], ik1.Ad[xs, kap[s]], -1.0, AN[s])
+            out.add(ik.C[xs], ik1.B[xs, kap[s]], 1.0, AN[s])
+            out.add(ik.D[xs], ik1.B[kap[s], xs], -1.0, CR[s])
+        out.add(ik.I, ik1.A[kap[0], kap[1]], 1.0, CR[0] @ CR[1])
+        out.add(ik.I, ik1.Ad[kap[0], kap[1]], 1.0, AN[1] @ AN[0])
+        for s in range(2):
+            for t in range(2):
+                out.add(ik.I, ik1.B[kap[s], kap[t]], 1.0, CR[s] @ AN[t])
     js = np.arange(2 * k + 2, 2 * K)
     out.add(ik.T[js], ik1.T[js], 1.0, _P)
     out.add(ik.Td[js], ik1.Td[js], 1.0, _P)
@@ -230,6 +256,27 @@ def _site_entries(K, k, coef, ops_k, ops_k1):
     for s in range(2):
         out.add(ik.T[kap[s]], ik1.H, 1.0, AN[s])
         out.add(ik.Td[kap[s]], ik1.H, 1.0, CR[s])
+    if rows_cn:
+        # Complementary pairs of a CN cut already hold their integrals: pairs
+        # right of site k carry on; a pair on site k closes into H (times the
+        # partner on the site); a pair (site k, j) becomes part of T_j or Td_j.
+        # Sum over terms = sum_O P_O * O, so with x the site factor and
+        # O = eta * x * a_j (or a+_j), T_j (Td_j) gains eta * P_O (x) x . P.
+        R, S = np.meshgrid(js, js, indexing="ij")
+        up = R < S
+        out.add(ik.Pa[R[up], S[up]], ik1.Pa[R[up], S[up]], 1.0, _I)
+        out.add(ik.Pd[R[up], S[up]], ik1.Pd[R[up], S[up]], 1.0, _I)
+        out.add(ik.Q[R, S], ik1.Q[R, S], 1.0, _I)
+        out.add(ik.Pa[kap[0], kap[1]], ik1.H, 1.0, CR[0] @ CR[1])
+        out.add(ik.Pd[kap[0], kap[1]], ik1.H, 1.0, AN[1] @ AN[0])
+        for s in range(2):
+            for t in range(2):
+                out.add(ik.Q[kap[s], kap[t]], ik1.H, 1.0, CR[s] @ AN[t])
+        for s in range(2):
+            out.add(ik.Q[kap[s], js], ik1.T[js], 1.0, CR[s] @ _P)     # a+_ks a_j
+            out.add(ik.Pd[kap[s], js], ik1.T[js], -1.0, AN[s] @ _P)   # a_j a_ks = -a_ks a_j
+            out.add(ik.Pa[kap[s], js], ik1.Td[js], 1.0, CR[s] @ _P)   # a+_ks a+_j
+            out.add(ik.Q[js, kap[s]], ik1.Td[js], -1.0, AN[s] @ _P)   # a+_j a_ks = -a_ks a+_j
 
     # remaining H and T/Td contributions: enumerate operator-slot patterns
     Lidx = xs
@@ -245,17 +292,25 @@ def _site_entries(K, k, coef, ops_k, ops_k1):
             if target == "H":
                 if nout or nk < 2:
                     continue
+            elif target == "P":
+                # a left pair of a CN cut carries on by itself; at the switch
+                # the left normal pair is contracted with the integrals here
+                if nout != 2 or nslot != 4 or (nk == 0 and rows_cn):
+                    continue
             elif nout != 1 or nk < 1:
                 continue
+            if rows_cn and target != "P" and regs.count(0) == 2:
+                continue  # from the complementary pairs above
             yield regs
 
+    targets = ("H", "T", "Td") + (("P",) if cols_cn else ())
     for daggers, cfn in (one, two):
         ns = len(daggers)
-        for target in ("H", "T", "Td"):
+        for target in targets:
             if target != "H" and len(outs) == 0:
                 continue
             for regs in slot_patterns(ns, target):
-                if target != "H":
+                if target in ("T", "Td"):
                     pos = regs.index(2)
                     if target == "T" and daggers[pos]:
                         continue
@@ -266,7 +321,7 @@ def _site_entries(K, k, coef, ops_k, ops_k1):
                 if len(lslots) > 2 or (lslots and n == 0):
                     continue
                 sign = -1.0 if _inversions(regs) % 2 else 1.0
-                par_b = 0 if target == "H" else 1
+                par_b = 1 if target in ("T", "Td") else 0
                 for spins in itertools.product(range(2), repeat=len(kslots)):
                     site = _I
                     for p, s in zip(kslots, spins):
@@ -298,6 +353,20 @@ def _emit(out, ik, ik1, target, daggers, lslots, regs, cval, site, outs):
     if target == "H":
         cval = cval[..., None]
         cols = np.array([ik1.H])
+    elif target == "P":
+        # outside pair (slot order) -> canonical complementary pair and its sign
+        o1, o2 = [p for p in range(len(regs)) if regs[p] == 2]
+        cval = np.moveaxis(cval, [kept.index(o1), kept.index(o2)], [-2, -1])
+        R, S = np.meshgrid(outs, outs, indexing="ij")
+        lo, hi = np.minimum(R, S), np.maximum(R, S)
+        if daggers[o1] and daggers[o2]:      # a+_r a+_s = +-Pa partner
+            cols, sg = ik1.Pa[lo, hi], np.sign(S - R)
+        elif not daggers[o1] and not daggers[o2]:  # a_r a_s: partner a_hi a_lo
+            cols, sg = ik1.Pd[lo, hi], np.sign(R - S)
+        else:                                # a+_r a_s
+            cols, sg = ik1.Q[R, S], np.ones_like(R)
+        cval = (cval * sg).reshape(cval.shape[:-2] + (-1,))
+        cols = cols.ravel()
     else:
         oax = kept.index(regs.index(2))
         cval = np.moveaxis(cval, oax, -1)  # outside index last
@@ -332,12 +401,24 @@ def _emit(out, ik, ik1, target, daggers, lslots, regs, cval, site, outs):
 
 def build_nc_mpo(h, g, prune=True, tol=0.0):
     """Return the NC-partition MPO of H(h, g) for K = h.shape[0] orbitals."""
+    return build_mpo(h, g, switch=None, prune=prune, tol=tol)
+
+
+def build_mpo(h, g, switch=None, prune=True, tol=0.0):
+    """MPO of H(h, g) in the NC partition up to cut `switch` and the CN partition
+    after it (Sec. II.B.2: normal operators on the smaller side of each cut).
+    switch=None is NC everywhere; switch=K//2 keeps every bond near 8 k^2 with k
+    the orbitals on the smaller side instead of the left one.  The operator is the
+    same for every switch position; only the bond operators differ."""
     K = h.shape[0]
+    sw = K if switch is None else int(switch)
+    if not 0 <= sw <= K:
+        raise ValueError(f"switch cut must be in 0 .. {K}")
     coef = _Coef(np.asarray(h, float), np.asarray(g, float))
-    cuts = [cut_ops(K, k) for k in range(K + 1)]
+    cuts = [cut_ops(K, k, cn=k > sw) for k in range(K + 1)]
     raw = []
     for k in range(K):
-        r, c, m = _site_entries(K, k, coef, cuts[k], cuts[k + 1])
+        r, c, m = _site_entries(K, k, coef, cuts[k], cuts[k + 1], rows_cn=k > sw, cols_cn=k + 1 > sw)
         keep = np.abs(m).reshape(len(m), -1).max(axis=1) > tol if len(m) else np.zeros(0, bool)
         raw.append((r[keep], c[keep], m[keep]))
     alive = [np.ones(len(c), bool) for c in cuts]

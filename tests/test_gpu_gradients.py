@@ -1,7 +1,7 @@
 """Integral gradients and the 1-RDM from the sigma-vector adjoint, on the GPU.
 
 E(h, g) = <MPS|H(h, g)|MPS> at a fixed (converged, untruncated) MPS.  A pass of
-adjoints with cotangent psi gives dE/d(MPO values) at every site; the NC MPO is
+adjoints with cotangent psi gives dE/d(MPO values) at every site; the MPO (NC, or NC->CN switched) is
 affine in the integrals, so directional derivatives along (dh, dg) follow.  They
 are checked against the oracle's <Psi|H(dh, dg)|Psi> (Psi = the MPS embedded in
 Fock space, H from the determinant-space definition) and against closed forms:
@@ -31,12 +31,15 @@ def _sym_dg(rng, K):
     return 0.125 * a
 
 
-def test_integral_gradients_and_one_rdm_match_the_oracle(device):
+@pytest.mark.parametrize("switch", [None, 3])
+def test_integral_gradients_and_one_rdm_match_the_oracle(device, switch):
+    """switch=None: NC MPO; switch=3: NC up to cut 3, CN after it (Sec. II.B.2) --
+    the gradients of the same energy, through different bond operators."""
     from paper_2310_03920_amd.dmrg import DMRG, contract_two
-    print("[gradients] K=6 converged MPS", flush=True)
+    print(f"[gradients] K=6 converged MPS, MPO switch {switch}", flush=True)
     K = 6
     h, g = make_integrals(K, seed=3)
-    d = DMRG(h, g, K, 0, 64, seed=2, device="cuda", tol=1e-10, max_iter=150)
+    d = DMRG(h, g, K, 0, 64, seed=2, device="cuda", tol=1e-10, max_iter=150, mpo_switch=switch)
     energies = d.run(4)
     e = energies[-1]
     # oracle view of the state before the gradient pass: centre at sites (0, 1)

@@ -59,6 +59,75 @@ def test_nc_mpo_bond_dimension_grows_quadratically():
         assert 6 * k * k < D[k] < 10 * k * k + 4 * K + 8
 
 
+@pytest.mark.parametrize("K", [2, 3, 4, 5])
+def test_switched_mpo_densifies_to_fock_hamiltonian_at_every_switch(K):
+    """NC bond operators up to cut c and CN ones after it (Sec. II.B.2): the same
+    operator for every switch position c, including pure CN (c = 0)."""
+    h, g = make_integrals(K, seed=K + 30)
+    dets = fock.all_dets(K)
+    Hf = fock.hamiltonian(h, g, dets).toarray()
+    p = fock.product_index(dets, K)
+    Hp = np.zeros_like(Hf)
+    Hp[np.ix_(p, p)] = Hf
+    for c in range(K + 1):
+        np.testing.assert_allclose(M.densify(M.build_mpo(h, g, switch=c)), Hp, atol=1e-12, err_msg=str(c))
+
+
+def test_switched_mpo_entries_conserve_quantum_numbers_and_parity():
+    """Every nonzero element (s', s) of an entry W[a, b] changes (N, 2Sz) by exactly
+    dq(b) - dq(a) and flips parity by parity(b) - parity(a): the bond labels that
+    the plans rely on are consistent with the site operators."""
+    K = 6
+    qn = np.array(M.SITE_QN)
+    par = np.array([0, 1, 1, 0])
+    h, g = make_integrals(K, seed=2)
+    for c in (None, 0, 2, 3, 5):
+        m = M.build_mpo(h, g, switch=c)
+        for k in range(K):
+            s = m.sites[k]
+            for a, b, w in zip(s.rows, s.cols, s.mats):
+                sp, ss = np.nonzero(w)
+                assert (qn[sp] - qn[ss] == m.dq[k + 1][b] - m.dq[k][a]).all(), (c, k)
+                assert ((par[sp] + par[ss]) % 2 == (m.parity[k + 1][b] + m.parity[k][a]) % 2).all(), (c, k)
+
+
+def test_switched_mpo_bond_dimension_follows_the_smaller_side():
+    """With the switch at the middle cut, bonds right of it hold the normal pairs of
+    the right block: D ~ 8 (K - k)^2 there instead of 8 k^2."""
+    K = 12
+    h, g = make_integrals(K, seed=1)
+    nc = [len(c) for c in M.build_nc_mpo(h, g).cuts]
+    sw = [len(c) for c in M.build_mpo(h, g, switch=K // 2).cuts]
+    assert sw[:K // 2 + 1] == nc[:K // 2 + 1]
+    for k in range(K // 2 + 1, K - 1):
+        r = K - k
+        assert 6 * r * r < sw[k] < 10 * r * r + 4 * K + 8, (k, sw[k])
+    assert max(sw) < 0.5 * max(nc)
+
+
+def test_plans_build_on_the_switched_mpo_with_less_work_right_of_the_switch():
+    """Host plan validation (quantum-number conservation of every task) passes at
+    every site of the switched MPO; the same site step does less work right of the
+    switch than with NC operators there."""
+    K = 8
+    h, g = make_integrals(K, seed=0)
+    nc, sw = M.build_nc_mpo(h, g), M.build_mpo(h, g, switch=K // 2)
+    b = bond_sector_tables(K, K, 0, 32)
+    for i in range(K - 1):
+        f = []
+        for m in (nc, sw):
+            args = (b[i], b[i + 2], m.dq[i], m.dq[i + 1], m.dq[i + 2], M.site_entries(m, i),
+                    M.site_entries(m, i + 1))
+            f.append(X.HeffPlan(*args).info.flops_apply)
+            X.HeffVjpPlan(*args)
+            X.EnvPlan(0, b[i], b[i + 1], m.dq[i], m.dq[i + 1], M.site_entries(m, i))
+            X.EnvPlan(1, b[i + 1], b[i], m.dq[i + 1], m.dq[i], M.site_entries(m, i))
+        if i + 2 <= K // 2:
+            assert f[1] == f[0]
+        if i >= K // 2:
+            assert f[1] < f[0]
+
+
 def test_psi_layout_matches_block_enumeration():
     """Blocks are ordered by column block (s2, ir) and then (il, s1), so every
     column block is one contiguous dense matrix."""
