@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdint>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -290,18 +291,39 @@ struct Mixer {
 
 static void build_mixer(Mixer& M, const std::vector<Entry>& ents, int ntgt) {
     M.trans.assign(ntgt, {});
-    // terms[tgt][(so,si)] -> (src -> coef)
-    std::vector<std::map<int, std::map<int, double>>> terms(ntgt);
+    // terms (tgt, site element t = 4 so + si, src, coef), ordered by (tgt, t, src);
+    // the stable sort keeps repeated entries in input order, so their sum is
+    // formed in a fixed order
+    struct Term {
+        int tgt, t, src;
+        double v;
+    };
+    std::vector<Term> terms;
+    terms.reserve(ents.size() * 4);
     for (const Entry& e : ents)
         for (int t = 0; t < 16; ++t)
-            if (e.v[t] != 0.0) terms[e.tgt][t][e.src] += e.v[t];
-    std::map<std::vector<std::pair<int, uint64_t>>, std::pair<int, int>> seen;  // normalised -> (class,row)
-    for (int b = 0; b < ntgt; ++b) {
-        for (auto& kv : terms[b]) {
-            int t = kv.first;
-            std::vector<std::pair<int, double>> lst;
-            for (auto& sc : kv.second)
-                if (sc.second != 0.0) lst.push_back(sc);
+            if (e.v[t] != 0.0) terms.push_back({e.tgt, t, e.src, e.v[t]});
+    std::stable_sort(terms.begin(), terms.end(), [](const Term& a, const Term& b) {
+        if (a.tgt != b.tgt) return a.tgt < b.tgt;
+        if (a.t != b.t) return a.t < b.t;
+        return a.src < b.src;
+    });
+    // normalised term list (bytes of (src, coef / first coef) pairs) -> (class, row)
+    std::unordered_map<std::string, std::pair<int, int>> seen;
+    std::vector<std::pair<int, double>> lst;
+    for (size_t g0 = 0; g0 < terms.size();) {
+        const int b = terms[g0].tgt, t = terms[g0].t;
+        size_t g1 = g0;
+        lst.clear();
+        while (g1 < terms.size() && terms[g1].tgt == b && terms[g1].t == t) {
+            const int src = terms[g1].src;
+            double sum = 0.0;
+            for (; g1 < terms.size() && terms[g1].tgt == b && terms[g1].t == t && terms[g1].src == src; ++g1)
+                sum += terms[g1].v;
+            if (sum != 0.0) lst.push_back({src, sum});
+        }
+        g0 = g1;
+        {
             if (lst.empty()) continue;
             const auto& dq = M.ops->dq[lst[0].first];
             Trans tr;
@@ -315,14 +337,14 @@ static void build_mixer(Mixer& M, const std::vector<Entry>& ents, int ntgt) {
                 tr.m.alpha = lst[0].second;
             } else {
                 double c0 = lst[0].second;
-                std::vector<std::pair<int, uint64_t>> key;
+                std::string key(lst.size() * 12, '\0');
                 std::vector<std::pair<int, double>> norm;
-                for (auto& sc : lst) {
-                    double v = sc.second / c0;
-                    uint64_t bits;
-                    std::memcpy(&bits, &v, 8);
-                    key.push_back({sc.first, bits});
-                    norm.push_back({sc.first, v});
+                norm.reserve(lst.size());
+                for (size_t j = 0; j < lst.size(); ++j) {
+                    double v = lst[j].second / c0;
+                    std::memcpy(&key[12 * j], &lst[j].first, 4);
+                    std::memcpy(&key[12 * j + 4], &v, 8);
+                    norm.push_back({lst[j].first, v});
                 }
                 auto ck = std::make_pair(dq[0], dq[1]);
                 int cls;
@@ -495,20 +517,28 @@ static void sort_tiles(Plan& P, int64_t t0) {
     };
     std::vector<Group> groups;
     std::unordered_map<uint64_t, size_t> gid;
-    gid.reserve((size_t)n);
+    gid.reserve((size_t)n / 8 + 16);
     std::vector<size_t> tile_group(n);
+    uint64_t prev_key = 0;
+    size_t prev_g = SIZE_MAX;
     for (int64_t t = 0; t < n; ++t) {
         const Tile& tl = P.tiles[t0 + t];
         const uint64_t key = ((uint64_t)(uint32_t)tl.tbeg << 32) | (uint32_t)tl.tend;
         size_t g;
-        auto it = tl.tbeg == tl.tend ? gid.end() : gid.find(key);
-        if (it == gid.end()) {  // a new group (empty task lists are independent tiles)
-            g = groups.size();
-            if (tl.tbeg != tl.tend) gid.emplace(key, g);
-            groups.push_back({t, 0, 0.0});
+        if (tl.tbeg != tl.tend && prev_g != SIZE_MAX && key == prev_key) {
+            g = prev_g;  // tiles of one block are mostly emitted one after another
         } else {
-            g = it->second;
+            auto it = tl.tbeg == tl.tend ? gid.end() : gid.find(key);
+            if (it == gid.end()) {  // a new group (empty task lists are independent tiles)
+                g = groups.size();
+                if (tl.tbeg != tl.tend) gid.emplace(key, g);
+                groups.push_back({t, 0, 0.0});
+            } else {
+                g = it->second;
+            }
         }
+        prev_key = key;
+        prev_g = tl.tbeg != tl.tend ? g : SIZE_MAX;
         tile_group[t] = g;
         groups[g].count++;
         groups[g].work += (double)tl.ktot * tl.m * tl.n;
@@ -519,10 +549,11 @@ static void sort_tiles(Plan& P, int64_t t0) {
     for (size_t g = 0; g < groups.size(); ++g) mstart[g + 1] += mstart[g];
     mpos.assign(mstart.begin(), mstart.end() - 1);
     for (int64_t t = 0; t < n; ++t) mlist[mpos[tile_group[t]]++] = t;
+    std::vector<std::pair<double, size_t>> byw(groups.size());  // heaviest first, ties in tile order
+    for (size_t g = 0; g < byw.size(); ++g) byw[g] = {-groups[g].work, g};
+    std::sort(byw.begin(), byw.end());
     std::vector<size_t> order(groups.size());
-    for (size_t g = 0; g < order.size(); ++g) order[g] = g;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return groups[a].work > groups[b].work; });
+    for (size_t g = 0; g < order.size(); ++g) order[g] = byw[g].second;
     std::vector<std::vector<int64_t>> queue(NXCD);
     for (size_t g : order) {
         int q = 0;

@@ -424,6 +424,7 @@ class DMRG:
             if i < K - 2:
                 nb, A, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 0)
                 self.bonds[i + 1] = nb
+                self.eng.prefetch_heff_plan(i + 1, self.bonds[i + 1], self.bonds[i + 3])
                 self.tensors[i] = A
                 self.center, self.center_site = C, i + 1
                 self.eng.update_left(i, self.bonds[i], self.bonds[i + 1],
@@ -443,6 +444,7 @@ class DMRG:
             if i > 0:
                 nb, B, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 1)
                 self.bonds[i + 1] = nb
+                self.eng.prefetch_heff_plan(i - 1, self.bonds[i - 1], self.bonds[i + 1])
                 self.tensors[i + 1] = B
                 self.center, self.center_site = C, i
                 self.eng.update_right(i + 1, self.bonds[i + 1], self.bonds[i + 2],

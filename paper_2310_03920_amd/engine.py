@@ -36,6 +36,8 @@ class Engine:
         self.right = {}
         self._env_plans = {}
         self._heff_plans = {}
+        self._pending = {}   # heff plan key -> future of its host build
+        self._pool = None
         self._w = [X.MpoSite(s.rows, s.cols, s.mats) for s in mpo.sites]
 
     # -- boundaries: the vacuum bond carries the identity, the full bond carries H
@@ -61,12 +63,31 @@ class Engine:
             self._env_plans[key] = p
         return p
 
+    def _build_heff(self, i, bond_i, bond_i2):
+        return X.HeffPlan(bond_i, bond_i2, self.mpo.dq[i], self.mpo.dq[i + 1], self.mpo.dq[i + 2],
+                          self._w[i], self._w[i + 1], t_budget_bytes=self.t_budget, **self.opts)
+
+    def prefetch_heff_plan(self, i, bond_i, bond_i2):
+        """Start the host build of the sigma-vector plan of sites (i, i+1) on a
+        worker thread (the library's plan builder is host-only and reentrant, and
+        the binding releases the GIL during the call), so that it overlaps the
+        environment plan and update that come first; heff_plan collects it and
+        uploads it on the calling thread."""
+        key = (i, self._bkey(bond_i), self._bkey(bond_i2))
+        if key in self._heff_plans or key in self._pending:
+            return
+        if self._pool is None:
+            from concurrent.futures import ThreadPoolExecutor
+            self._pool = ThreadPoolExecutor(max_workers=1, thread_name_prefix="heffx-plan")
+        self._pending[key] = self._pool.submit(self._build_heff, i, list(bond_i), list(bond_i2))
+
     def heff_plan(self, i, bond_i, bond_i2):
         key = (i, self._bkey(bond_i), self._bkey(bond_i2))
         p = self._heff_plans.get(key)
         if p is None:
-            p = X.HeffPlan(bond_i, bond_i2, self.mpo.dq[i], self.mpo.dq[i + 1], self.mpo.dq[i + 2],
-                           self._w[i], self._w[i + 1], t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
+            fut = self._pending.pop(key, None)
+            p = fut.result() if fut is not None else self._build_heff(i, bond_i, bond_i2)
+            p.upload(self.device)
             self._heff_plans[key] = p
         return p
 
@@ -123,6 +144,9 @@ class Engine:
         return d_env, d_site, g_w[:16 * vjp.nnz1].view(vjp.nnz1, 4, 4)
 
     def drop_plans(self):
+        for fut in self._pending.values():
+            fut.result()
+        self._pending.clear()
         self._env_plans.clear()
         self._heff_plans.clear()
 

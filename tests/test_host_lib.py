@@ -128,6 +128,28 @@ def test_plans_build_on_the_switched_mpo_with_less_work_right_of_the_switch():
             assert f[1] < f[0]
 
 
+def test_plans_built_on_concurrent_threads_equal_sequential_builds():
+    """The sweep builds the next sigma-vector plan on a worker thread while the
+    environment plan is built on the caller's: the host builder is reentrant, so
+    plans built at the same time on several threads equal those built one by one."""
+    from concurrent.futures import ThreadPoolExecutor
+    K = 10
+    m = M.build_mpo(*make_integrals(K, seed=3), switch=K // 2)
+    b = bond_sector_tables(K, K, 0, 48)
+
+    def build(i):
+        p = X.HeffPlan(b[i], b[i + 2], m.dq[i], m.dq[i + 1], m.dq[i + 2], M.site_entries(m, i),
+                       M.site_entries(m, i + 1), split_kseg_min=64)
+        e = X.EnvPlan(0, b[i], b[i + 1], m.dq[i], m.dq[i + 1], M.site_entries(m, i), split_kseg_min=64)
+        return [(x.info.flops_apply, x.info.n_tasks, x.info.n_tiles, x.info.table_bytes, x.info.ws_bytes)
+                for x in (p, e)]
+
+    seq = [build(i) for i in range(K - 1)]
+    with ThreadPoolExecutor(max_workers=4) as ex:
+        par = list(ex.map(build, list(range(K - 1)) * 2))
+    assert par == seq + seq
+
+
 def test_psi_layout_matches_block_enumeration():
     """Blocks are ordered by column block (s2, ir) and then (il, s1), so every
     column block is one contiguous dense matrix."""
