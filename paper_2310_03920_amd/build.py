@@ -29,7 +29,7 @@ def build_library(verbose=True):
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     objs = []
     plan_o = os.path.join(BUILD, "heffx_plan.o")
-    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE, "-I", CSRC, "-c",
+    _run(["g++", "-O2", "-std=c++17", "-fPIC", "-pthread", "-Wall", "-I", INCLUDE, "-I", CSRC, "-c",
           os.path.join(CSRC, "heffx_plan.cpp"), "-o", plan_o])
     objs.append(plan_o)
     kern_o = os.path.join(BUILD, "heffx_kernels.o")
@@ -37,7 +37,7 @@ def build_library(verbose=True):
                                 os.path.join(CSRC, "heffx_kernels.hip"), "-o", kern_o])
     objs.append(kern_o)
     tmp = LIB + ".tmp"
-    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs)
     os.replace(tmp, LIB)
     return LIB
 

@@ -153,6 +153,9 @@ struct Plan {
     // batched plans: per-instance element offsets of psi/sigma, L, R in the concatenated buffers
     std::vector<int64_t> inst_psi, inst_L, inst_R;
     int64_t part_tiles = 0;     // partial tiles needed by the largest launch
+    // tile ranges [first, first + count) of launches whose XCD ordering is still to be
+    // done (the ranges are disjoint; they are ordered on host threads before packing)
+    std::vector<std::pair<int64_t, int64_t>> sort_ranges;
     int64_t split_kseg_min = 2048;
     int variant = 0;            // block-GEMM pipeline variant (see hx_plan_opts.kernel_variant)
     int kstage = 16;            // K-stage depth of that variant; task K is padded to it

@@ -13,12 +13,14 @@
 // GEMMs:  T_b = psi Rhat_b^T  and  sigma += Lhat_b T_b.
 #include <algorithm>
 #include <array>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <map>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <unordered_map>
 #include <vector>
 
@@ -507,17 +509,29 @@ static void split_launch(Plan& P, Launch& L) {
 // their operand blocks, so they form a group kept on one XCD, consecutive in its
 // dispatch order.  Groups are taken by decreasing work (longest first) and each
 // goes to the XCD queue holding the fewest tiles; the queues are then interleaved.
-static void sort_tiles(Plan& P, int64_t t0) {
+static void sort_tiles(Plan& P, int64_t t0, int64_t n) {
     constexpr int NXCD = 8;
-    const int64_t n = (int64_t)P.tiles.size() - t0;
     if (n <= 1) return;
     struct Group {
         int64_t first, count;
         double work;
     };
     std::vector<Group> groups;
+    // Non-empty task ranges of one launch are disjoint blocks or split-K segments
+    // of them, so distinct groups start at distinct tasks: a group is found by its
+    // first task through a direct table (with the range end checked; a hash map
+    // takes any range that does not fit that pattern).
+    int32_t tlo = INT32_MAX, thi = 0;
+    for (int64_t t = 0; t < n; ++t) {
+        const Tile& tl = P.tiles[t0 + t];
+        if (tl.tbeg != tl.tend) {
+            tlo = std::min(tlo, tl.tbeg);
+            thi = std::max(thi, tl.tbeg);
+        }
+    }
+    std::vector<int64_t> by_first(tlo <= thi ? (size_t)(thi - tlo + 1) : 0, -1);
     std::unordered_map<uint64_t, size_t> gid;
-    gid.reserve((size_t)n / 8 + 16);
+    std::vector<int32_t> gend;  // range end of each group (non-empty ranges)
     std::vector<size_t> tile_group(n);
     uint64_t prev_key = 0;
     size_t prev_g = SIZE_MAX;
@@ -527,14 +541,27 @@ static void sort_tiles(Plan& P, int64_t t0) {
         size_t g;
         if (tl.tbeg != tl.tend && prev_g != SIZE_MAX && key == prev_key) {
             g = prev_g;  // tiles of one block are mostly emitted one after another
+        } else if (tl.tbeg == tl.tend) {  // empty task lists are independent tiles
+            g = groups.size();
+            groups.push_back({t, 0, 0.0});
+            gend.push_back(tl.tend);
         } else {
-            auto it = tl.tbeg == tl.tend ? gid.end() : gid.find(key);
-            if (it == gid.end()) {  // a new group (empty task lists are independent tiles)
-                g = groups.size();
-                if (tl.tbeg != tl.tend) gid.emplace(key, g);
-                groups.push_back({t, 0, 0.0});
+            int64_t& slot = by_first[(size_t)(tl.tbeg - tlo)];
+            if (slot >= 0 && gend[(size_t)slot] == tl.tend) {
+                g = (size_t)slot;
             } else {
-                g = it->second;
+                auto it = slot >= 0 ? gid.find(key) : gid.end();
+                if (it != gid.end()) {
+                    g = it->second;
+                } else {
+                    g = groups.size();
+                    groups.push_back({t, 0, 0.0});
+                    gend.push_back(tl.tend);
+                    if (slot < 0)
+                        slot = (int64_t)g;
+                    else
+                        gid.emplace(key, g);
+                }
             }
         }
         prev_key = key;
@@ -644,7 +671,7 @@ static void emit_mixing(Plan& P, Mixer& M, std::vector<Launch>& seq) {
         }
     }
     L.ntile = (int64_t)P.tiles.size() - L.tile0;
-    sort_tiles(P, L.tile0);
+    P.sort_ranges.push_back({L.tile0, L.ntile});  // ordered in finalize_tables
     seq.push_back(L);
 }
 
@@ -705,7 +732,7 @@ static void flush_blocks(Plan& P, std::vector<OutBlockTasks>& blocks, int kind, 
         }
         L.ntile = (int64_t)P.tiles.size() - L.tile0;
         split_launch(P, L);
-        sort_tiles(P, L.tile0);
+        P.sort_ranges.push_back({L.tile0, L.ntile});  // ordered in finalize_tables
         if (flops_out) *flops_out += L.flops;
         if (L.ntile > 0) seq.push_back(L);
     }
@@ -1866,7 +1893,35 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
 }
 
 static void finalize_tables(Plan& P);
+// XCD ordering of every recorded launch.  Each range is reordered in place and
+// ranges are disjoint, so large plans spread them over host threads (largest
+// first); the result does not depend on the thread count.
+static void run_tile_sorts(Plan& P) {
+    auto& R = P.sort_ranges;
+    int64_t total = 0;
+    for (auto& r : R) total += r.second;
+    std::vector<size_t> ord(R.size());
+    std::iota(ord.begin(), ord.end(), (size_t)0);
+    std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return R[a].second > R[b].second; });
+    std::atomic<size_t> next{0};
+    auto work = [&]() {
+        for (size_t j; (j = next.fetch_add(1)) < ord.size();) sort_tiles(P, R[ord[j]].first, R[ord[j]].second);
+    };
+    unsigned hw = std::thread::hardware_concurrency();
+    int nth = (int)std::min<size_t>({R.size(), (size_t)16, (size_t)std::max(1u, hw)});
+    if (total < 32768 || nth <= 1) {
+        work();
+    } else {
+        std::vector<std::thread> pool;
+        for (int i = 1; i < nth; ++i) pool.emplace_back(work);
+        work();
+        for (auto& t : pool) t.join();
+    }
+    R.clear();
+}
+
 static void finalize_tables(Plan& P) {
+    run_tile_sorts(P);
     auto al = [](int64_t x) { return (x + 255) & ~(int64_t)255; };
     int64_t o = 0;
     P.off_tiles = o;
@@ -2005,7 +2060,7 @@ static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
                 }
             }
             L.ntile = (int64_t)M.tiles.size() - L.tile0;
-            sort_tiles(M, L.tile0);
+            M.sort_ranges.push_back({L.tile0, L.ntile});
             L.red0 = (int64_t)M.reduces.size();
             L.nred = (int64_t)reds.size();
             M.reduces.insert(M.reduces.end(), reds.begin(), reds.end());
