@@ -652,17 +652,22 @@ __global__ __launch_bounds__(64) void dav_eig(int k, double* ws, double* scal) {
     __shared__ double V[KMAX][KMAX + 1];
     __shared__ double rc[KMAX / 2], rs[KMAX / 2];
     __shared__ int rp[KMAX / 2], rq[KMAX / 2];
-    __shared__ int order[KMAX];
     const int t = threadIdx.x;
     const int ke = (k + 1) & ~1;
     const int np = ke / 2;
+    // round-robin pairing: index 0 stays, indices 1 .. ke-1 rotate by one place per
+    // step (the identity again after ke - 1 steps, i.e. at every sweep), so the
+    // index at position i in step `step` has a closed form
+    auto order = [ke](int i, int step) {
+        const int m = ke - 1;
+        return i == 0 ? 0 : 1 + ((i - 1 - step) % m + m) % m;
+    };
     const double* G = ws + DW_G;
     for (int idx = t; idx < k * k; idx += 64) {
         int i = idx / k, j = idx % k;
         A[i][j] = 0.5 * (G[i * KMAX + j] + G[j * KMAX + i]);
         V[i][j] = (i == j) ? 1.0 : 0.0;
     }
-    for (int i = t; i < ke; i += 64) order[i] = i;
     __syncthreads();
     for (int sweep = 0; sweep < 60; ++sweep) {
         double off = 0.0, dia = 0.0;
@@ -681,7 +686,7 @@ __global__ __launch_bounds__(64) void dav_eig(int k, double* ws, double* scal) {
         if (off <= 1e-16 * fmax(dia, 1e-300)) break;  // the same on every lane
         for (int step = 0; step < ke - 1; ++step) {
             if (t < np) {
-                int p = order[t], q = order[ke - 1 - t];
+                int p = order(t, step), q = order(ke - 1 - t, step);
                 if (p > q) {
                     const int x = p;
                     p = q;
@@ -729,11 +734,6 @@ __global__ __launch_bounds__(64) void dav_eig(int k, double* ws, double* scal) {
             if (t < np && rq[t] < k && rs[t] != 0.0) {  // the rotated pair's element is zero
                 A[rp[t]][rq[t]] = 0.0;
                 A[rq[t]][rp[t]] = 0.0;
-            }
-            if (t == 0) {  // round-robin: order[0] stays, the rest rotate by one
-                const int last = order[ke - 1];
-                for (int i = ke - 1; i > 1; --i) order[i] = order[i - 1];
-                order[1] = last;
             }
             __syncthreads();
         }
