@@ -37,11 +37,13 @@ static const int SITE_Q[4][2] = {{0, 0}, {1, 1}, {1, -1}, {2, 0}};
 struct Bond {
     std::vector<std::array<int, 2>> qn;
     std::vector<int> dim;
-    std::unordered_map<int64_t, int> idx;
-    static int64_t key(int n, int s) { return (int64_t)(n + (1 << 20)) * (1 << 21) + (s + (1 << 20)); }
+    // sector lookup: a dense table over the (N, 2Sz) box spanned by the sectors
+    int nlo = 0, slo = 0, nw = 0, sw = 0;
+    std::vector<int> tab;
     int find(int n, int s) const {
-        auto it = idx.find(key(n, s));
-        return it == idx.end() ? -1 : it->second;
+        const int i = n - nlo, j = s - slo;
+        if (i < 0 || i >= nw || j < 0 || j >= sw) return -1;
+        return tab[(size_t)i * sw + j];
     }
     int nsec() const { return (int)dim.size(); }
 };
@@ -68,8 +70,24 @@ static bool parse_bond(const hx_bond* b, Bond& out, const char* what) {
             set_error(std::string(what) + ": N and 2Sz must have equal parity");
             return false;
         }
-        out.idx[Bond::key(out.qn[i][0], out.qn[i][1])] = i;
     }
+    int nhi = out.qn[0][0], shi = out.qn[0][1];
+    out.nlo = nhi;
+    out.slo = shi;
+    for (const auto& q : out.qn) {
+        out.nlo = std::min(out.nlo, q[0]);
+        nhi = std::max(nhi, q[0]);
+        out.slo = std::min(out.slo, q[1]);
+        shi = std::max(shi, q[1]);
+    }
+    if ((int64_t)(nhi - out.nlo + 1) * (shi - out.slo + 1) > (int64_t)1 << 24) {
+        set_error(std::string(what) + ": quantum numbers span too wide a range");
+        return false;
+    }
+    out.nw = nhi - out.nlo + 1;
+    out.sw = shi - out.slo + 1;
+    out.tab.assign((size_t)out.nw * out.sw, -1);
+    for (int i = 0; i < b->nsec; ++i) out.tab[(size_t)(out.qn[i][0] - out.nlo) * out.sw + (out.qn[i][1] - out.slo)] = i;
     return true;
 }
 
@@ -151,12 +169,13 @@ struct PsiCol {
 struct PsiLayout {
     std::vector<PsiBlock> blocks;
     std::vector<PsiCol> cols;
-    std::unordered_map<int64_t, int> by_key;  // (il, s1, s2) -> block
+    std::vector<int> by_key;  // (il, s1, s2) -> block or -1
+    int nl = 0;
     int64_t nnz = 0;
     static int64_t key(int il, int s1, int s2) { return ((int64_t)il * 4 + s1) * 4 + s2; }
     int find(int il, int s1, int s2) const {
-        auto it = by_key.find(key(il, s1, s2));
-        return it == by_key.end() ? -1 : it->second;
+        if (il < 0 || il >= nl || s1 < 0 || s1 > 3 || s2 < 0 || s2 > 3) return -1;
+        return by_key[(size_t)key(il, s1, s2)];
     }
 };
 
@@ -166,6 +185,8 @@ struct PsiLayout {
 // i.e. the one-site tensor (il, s1, ir) grouped by ir.
 static PsiLayout psi_layout(const Bond& lb, const Bond& rb, bool one_site = false) {
     PsiLayout P;
+    P.nl = lb.nsec();
+    P.by_key.assign((size_t)lb.nsec() * 16, -1);
     for (int s2 = 0; s2 < (one_site ? 1 : 4); ++s2)
         for (int ir = 0; ir < rb.nsec(); ++ir) {
             PsiCol c;
