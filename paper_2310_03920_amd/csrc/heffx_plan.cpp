@@ -321,16 +321,26 @@ static void build_mixer(Mixer& M, const std::vector<Entry>& ents, int ntgt) {
         int tgt, t, src;
         double v;
     };
-    std::vector<Term> terms;
-    terms.reserve(ents.size() * 4);
-    for (const Entry& e : ents)
+    // stable counting sort by target, then a stable sort of each target's terms
+    std::vector<int64_t> cnt((size_t)ntgt + 1, 0);
+    for (const Entry& e : ents) {
+        if ((unsigned)e.tgt >= (unsigned)ntgt) continue;  // parse_mpo keeps targets in range
         for (int t = 0; t < 16; ++t)
-            if (e.v[t] != 0.0) terms.push_back({e.tgt, t, e.src, e.v[t]});
-    std::stable_sort(terms.begin(), terms.end(), [](const Term& a, const Term& b) {
-        if (a.tgt != b.tgt) return a.tgt < b.tgt;
-        if (a.t != b.t) return a.t < b.t;
-        return a.src < b.src;
-    });
+            if (e.v[t] != 0.0) ++cnt[(size_t)e.tgt + 1];
+    }
+    for (int b = 0; b < ntgt; ++b) cnt[(size_t)b + 1] += cnt[(size_t)b];
+    std::vector<Term> terms((size_t)cnt[(size_t)ntgt]);
+    {
+        std::vector<int64_t> pos(cnt.begin(), cnt.end() - 1);
+        for (const Entry& e : ents) {
+            if ((unsigned)e.tgt >= (unsigned)ntgt) continue;
+            for (int t = 0; t < 16; ++t)
+                if (e.v[t] != 0.0) terms[(size_t)pos[(size_t)e.tgt]++] = {e.tgt, t, e.src, e.v[t]};
+        }
+    }
+    for (int b = 0; b < ntgt; ++b)
+        std::stable_sort(terms.begin() + cnt[(size_t)b], terms.begin() + cnt[(size_t)b + 1],
+                         [](const Term& x, const Term& y) { return x.t != y.t ? x.t < y.t : x.src < y.src; });
     // normalised term list (bytes of (src, coef / first coef) pairs) -> (class, row)
     std::unordered_map<std::string, std::pair<int, int>> seen;
     std::vector<std::pair<int, double>> lst;
