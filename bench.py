@@ -395,7 +395,10 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * avg, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.mode, "data": "synthetic",
         "config": {"workload": f"sigma-vectors only at sites ({i},{i + 1}) of the {mpo.K}-orbital chain, "
-                               f"M={args.bond_dim}, {args.roots} vector(s) per call", "roots": args.roots,
+                               f"M={args.bond_dim}, {args.roots} vector(s) per call, "
+                               + ("NC-partition MPO" if args.partition == "nc" else f"NC->CN switch at cut {mpo.K // 2}"),
+                   "roots": args.roots, "tflop_per_call": info.flops_apply / 1e12,
+                   "mpo_bond_dims": [len(mpo.cuts[k]) for k in (i, i + 1, i + 2)],
                    "chunks": int(info.n_chunks), "tiles": int(info.n_tiles),
                    "apply_ms_each": ms, "plan_opts": opts, "autotune_s": tune_s},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
@@ -471,7 +474,7 @@ def main():
                          "device copy that calibrates HBM byte counters; sweep: whole two-site passes "
                          "(24 orbitals, M=500 unless given)")
     ap.add_argument("--partition", choices=["nc", "nc-cn"], default="nc",
-                    help="sweep workload: NC MPO at every cut, or NC up to the middle cut and CN after it")
+                    help="NC MPO at every cut (default), or NC up to the middle cut and CN after it")
     ap.add_argument("--instances", type=int, default=16)
     ap.add_argument("--roots", type=int, default=1, help="apply workload: vectors per sigma-vector call")
     ap.add_argument("--kseg", type=int, default=0, help="split-K minimum segment (0 = default)")
@@ -503,7 +506,7 @@ def main():
     from paper_2310_03920_amd import _lib as X
     from paper_2310_03920_amd.dmrg import PRECISIONS, Davidson, split
     from paper_2310_03920_amd.engine import site_payload
-    from paper_2310_03920_amd.mpo import build_nc_mpo
+    from paper_2310_03920_amd.mpo import build_mpo
     from synth import (bond_sector_tables, make_integrals, random_left_canonical_mps,
                        random_right_canonical_mps)
     from synth.blocks import random_psi
@@ -514,7 +517,7 @@ def main():
     i = K // 2 - 1
     t0 = time.time()
     h, g = make_integrals(K, seed=0)
-    mpo = build_nc_mpo(h, g)
+    mpo = build_mpo(h, g, switch=K // 2 if args.partition == "nc-cn" else None)
     bonds = bond_sector_tables(K, N, 0, M, model="gaussian", width=1.0)
     left = random_left_canonical_mps(bonds, 1)
     right = random_right_canonical_mps(bonds, 2)
@@ -644,7 +647,8 @@ def main():
             "workload": f"two-site DMRG middle step (sites {i},{i + 1}) of a {K}-orbital ab initio chain, "
                         f"{N} electrons, 2Sz=0, M={M} (Gaussian sectors, width 1), integrals seed 0 "
                         f"(h ~ N(0,1)/sqrt(K), g = sum of 16 rank-1 terms of symmetric 0.1*N(0,1)), "
-                        f"environments from a seeded random MPS, NC-partition MPO",
+                        f"environments from a seeded random MPS, "
+                        + ("NC-partition MPO" if args.partition == "nc" else f"NC-partition MPO up to cut {K // 2}, CN after"),
             "orbitals": K, "electrons": N, "bond_dim": M, "psi_nnz": n,
             "mpo_bond_dims": [len(mpo.cuts[k]) for k in (i, i + 1, i + 2)],
             "davidson": {"tol": args.tol, "max_iter": args.max_iter, "kmax": args.kmax, "matvecs_per_step": nmv / args.steps,
