@@ -854,19 +854,25 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
     // T sizes per b (for chunking): one stacked column block per (s2', r')
     std::vector<int64_t> tsize(nmid, 0);
     std::vector<char> active(nmid, 0);
+    // T blocks of one b are keyed by (s2', r'): a dense index into tables whose
+    // entries count as set for b when their stamp is b + 1 (no clearing between b)
+    std::vector<int> tstamp((size_t)4 * rb.nsec(), 0), tslot((size_t)4 * rb.nsec(), 0);
     for (int b = 0; b < nmid; ++b) {
         if (ML.trans[b].empty() || MR.trans[b].empty()) continue;
         active[b] = 1;
-        std::unordered_map<int64_t, char> seen;
         for (auto& tr : MR.trans[b])
             for (int ci : col_by_s2[tr.si]) {
                 const PsiCol& pc = psi.cols[ci];
                 int irp = rb.find(rb.qn[pc.ir][0] + tr.m.dn, rb.qn[pc.ir][1] + tr.m.ds);
                 if (irp < 0) continue;
-                if (seen.emplace((int64_t)tr.so * 65536 + irp, 1).second)
+                int& st = tstamp[(size_t)tr.so * rb.nsec() + irp];
+                if (st != b + 1) {
+                    st = b + 1;
                     tsize[b] += (int64_t)pc.rows * rb.dim[irp] * R;
+                }
             }
     }
+    std::fill(tstamp.begin(), tstamp.end(), 0);
     int64_t budget = default_budget(opts);
     std::vector<std::pair<int, int>> chunks;  // [b0, b1)
     {
@@ -904,24 +910,22 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
             int64_t off;
         };
         std::vector<TInfo> tinfo;
-        std::unordered_map<int64_t, int> tidx;
         int64_t toff = t_ws;
         for (int b = chunks[ci].first; b < chunks[ci].second; ++b) {
             if (!active[b]) continue;
-            tidx.clear();
             for (auto& tr : MR.trans[b]) {
                 const ShiftLayout& sl = rshift(tr.m.dn, tr.m.ds);
                 for (int cj : col_by_s2[tr.si]) {
                     const PsiCol& pc = psi.cols[cj];
                     int irp = rb.find(rb.qn[pc.ir][0] + tr.m.dn, rb.qn[pc.ir][1] + tr.m.ds);
                     if (irp < 0) continue;
-                    int64_t key = (int64_t)tr.so * 65536 + irp;
-                    auto it = tidx.find(key);
+                    const size_t key = (size_t)tr.so * rb.nsec() + irp;
                     int ti;
-                    if (it == tidx.end()) {
+                    if (tstamp[key] != b + 1) {
                         // one T block (rows x R*np, roots side by side), one output block per root
                         ti = (int)tinfo.size();
-                        tidx[key] = ti;
+                        tstamp[key] = b + 1;
+                        tslot[key] = ti;
                         for (int rho = 0; rho < R; ++rho) {
                             OutBlockTasks ob;
                             ob.coff = toff + (int64_t)rho * rb.dim[irp];
@@ -933,7 +937,7 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                         tinfo.push_back({b, cj, tr.so, irp, toff});
                         toff += (int64_t)pc.rows * rb.dim[irp] * R;
                     } else {
-                        ti = it->second;
+                        ti = tslot[key];
                         if (tblocks[(size_t)ti * R].m != pc.rows) {
                             set_error("internal: stacked intermediate rows inconsistent");
                             return HX_EINVAL;
@@ -1775,10 +1779,14 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
     std::vector<std::vector<int>> by_s(4);
     for (int i = 0; i < (int)S.blocks.size(); ++i) by_s[S.blocks[i].s].push_back(i);
 
+    // intermediate blocks are keyed by (xp, so, y): a dense index; per operator b a
+    // table entry counts as set when its stamp is b + 1 (no clearing between b)
+    const int64_t nkey = (int64_t)bin.nsec() * 4 * bout.nsec();
+    auto ykey = [&](int xp, int so, int y) { return ((int64_t)xp * 4 + so) * bout.nsec() + y; };
+    std::vector<int> stamp((size_t)nkey, 0), slot((size_t)nkey, 0);
     // intermediate size per b
     std::vector<int64_t> ysize(nout, 0);
     for (int b = 0; b < nout; ++b) {
-        std::unordered_map<int64_t, char> seen;
         for (auto& tr : M.trans[b])
             for (int si : by_s[tr.si]) {
                 const SiteBlock& sb = S.blocks[si];
@@ -1786,10 +1794,14 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
                 int xp = bin.find(bin.qn[x][0] + tr.m.dn, bin.qn[x][1] + tr.m.ds);
                 if (xp < 0) continue;
                 int y = dir == 0 ? sb.ir : sb.il;   // the free index (in bout)
-                int64_t key = ((int64_t)xp * 4 + tr.so) * 65536 + y;
-                if (seen.emplace(key, 1).second) ysize[b] += (int64_t)bin.dim[xp] * bout.dim[y];
+                int& st = stamp[(size_t)ykey(xp, tr.so, y)];
+                if (st != b + 1) {
+                    st = b + 1;
+                    ysize[b] += (int64_t)bin.dim[xp] * bout.dim[y];
+                }
             }
     }
+    std::fill(stamp.begin(), stamp.end(), 0);
     int64_t budget = default_budget(opts);
     std::vector<std::pair<int, int>> chunks;
     {
@@ -1823,10 +1835,8 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
             int64_t off;
         };
         std::vector<YInfo> yinfo;
-        std::unordered_map<int64_t, int> yidx;
         int64_t yoff = y_ws;
         for (int b = ch.first; b < ch.second; ++b) {
-            yidx.clear();
             for (auto& tr : M.trans[b]) {
                 const ShiftLayout& sl = shift(tr.m.dn, tr.m.ds);
                 for (int si : by_s[tr.si]) {
@@ -1835,12 +1845,12 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
                     int y = dir == 0 ? sb.ir : sb.il;
                     int xp = bin.find(bin.qn[x][0] + tr.m.dn, bin.qn[x][1] + tr.m.ds);
                     if (xp < 0) continue;
-                    int64_t key = ((int64_t)xp * 4 + tr.so) * 65536 + y;
-                    auto it = yidx.find(key);
+                    const size_t key = (size_t)ykey(xp, tr.so, y);
                     int yi;
-                    if (it == yidx.end()) {
+                    if (stamp[key] != b + 1) {
                         yi = (int)yblocks.size();
-                        yidx[key] = yi;
+                        stamp[key] = b + 1;
+                        slot[key] = yi;
                         OutBlockTasks ob;
                         ob.coff = yoff;
                         ob.m = bin.dim[xp];
@@ -1850,7 +1860,7 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
                         yinfo.push_back({b, xp, tr.so, y, yoff});
                         yoff += (int64_t)bin.dim[xp] * bout.dim[y];
                     } else {
-                        yi = it->second;
+                        yi = slot[key];
                     }
                     Task t;
                     t.aoff = tr.m.base + sl.rel[x];   // mixed op block (xp <- x)
@@ -1869,7 +1879,8 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
 
         // E2: out_b[y' <- y] = sum_{(xp, so)} op(site[(xp,so) -> y']) Y_b[xp, so, y]
         std::vector<OutBlockTasks> oblocks;
-        std::unordered_map<int64_t, int> oidx;
+        // output block of (b, y) in this chunk, or -1
+        std::vector<int> oidx((size_t)(ch.second - ch.first) * bout.nsec(), -1);
         for (int b = ch.first; b < ch.second; ++b)
             for (int y = 0; y < bout.nsec(); ++y) {
                 int64_t off = Lout.blk(b, y);
@@ -1880,7 +1891,7 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
                 ob.m = bout.dim[yp];
                 ob.n = bout.dim[y];
                 ob.ldc = ob.n;
-                oidx[(int64_t)b * 65536 + y] = (int)oblocks.size();
+                oidx[(size_t)(b - ch.first) * bout.nsec() + y] = (int)oblocks.size();
                 oblocks.push_back(std::move(ob));
             }
         for (const YInfo& yi : yinfo) {
@@ -1894,8 +1905,8 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
                 sbk = S.find(yp, yi.so);     // B block (yp, so) -> must land on xp
                 if (sbk < 0 || S.blocks[sbk].ir != yi.xp) continue;
             }
-            auto it = oidx.find((int64_t)yi.b * 65536 + yi.y);
-            if (it == oidx.end()) {
+            const int ob_i = oidx[(size_t)(yi.b - ch.first) * bout.nsec() + yi.y];
+            if (ob_i < 0) {
                 set_error("internal: environment block missing");
                 return HX_EINVAL;
             }
@@ -1908,7 +1919,7 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
             t.set_spaces(ta_, SP_WS);
             t.k = bin.dim[yi.xp];
             t.alpha = 1.0;
-            oblocks[it->second].tasks.push_back(t);
+            oblocks[ob_i].tasks.push_back(t);
         }
         flush_blocks(P, oblocks, dir == 0 ? TN_ : NN, SP_OUT, 0, true, P.apply, &fl, &nt);
     }
