@@ -57,20 +57,21 @@ def test_one_site_apply_and_diag_random_operands(device, seed, big, variant):
                np.diag(contract.heff1_matrix_kron(Ld, Wd, Rd)).reshape(shape), lb, rb)
 
 
-@pytest.mark.parametrize("i", [2, 4])
-def test_one_site_sigma_with_gpu_environments_equals_PtHP(device, i):
-    """NC MPO + GPU environment chain + GPU one-site sigma == P^T H P psi."""
+@pytest.mark.parametrize("i,switch", [(2, None), (4, None), (4, 4), (6, 4)])
+def test_one_site_sigma_with_gpu_environments_equals_PtHP(device, i, switch):
+    """MPO (NC, or NC->CN switched at cut 4) + GPU environment chain + GPU one-site
+    sigma == P^T H P psi."""
     import torch
     from paper_2310_03920_amd import _lib as X
     from paper_2310_03920_amd.engine import Engine, site_payload
-    from paper_2310_03920_amd.mpo import build_nc_mpo
-    print(f"[heff1 vs PtHP] i={i}", flush=True)
+    from paper_2310_03920_amd.mpo import build_mpo
+    print(f"[heff1 vs PtHP] i={i} switch={switch}", flush=True)
     K, Mb = 8, 64
     h, g = make_integrals(K, seed=0)
     bonds = bond_sector_tables(K, K, 0, Mb)
     left = random_left_canonical_mps(bonds, 1)
     right = random_right_canonical_mps(bonds, 2)
-    m = build_nc_mpo(h, g)
+    m = build_mpo(h, g, switch=switch)
     eng = Engine(m, device=device)
     eng.init_boundaries()
     for k in range(i):
@@ -91,16 +92,19 @@ def test_one_site_sigma_with_gpu_environments_equals_PtHP(device, i):
     _check(X.unpack_psi1(lb, rb, st.cpu().numpy()), ref, bonds[i], bonds[i + 1])
 
 
-def test_one_site_sweep_complete_basis_gives_fci(device):
+@pytest.mark.parametrize("switch", [None, 3])
+def test_one_site_sweep_complete_basis_gives_fci(device, switch):
     """After two-site passes at 6 orbitals, M=64 (every bond basis complete), each
-    one-site step's energy is E_FCI."""
+    one-site step's energy is E_FCI -- with the NC MPO and with the NC->CN switch
+    at cut 3 (Sec. II.B.2), whose one-site steps right of the switch see
+    complementary pair operators in the left environments."""
     from oracle import fock
     from paper_2310_03920_amd.dmrg import DMRG
-    print("[one-site sweep] K=6 complete", flush=True)
+    print(f"[one-site sweep] K=6 complete, MPO switch {switch}", flush=True)
     K = 6
     h, g = make_integrals(K, seed=4)
     e_fci = fock.fci_energy(h, g, K, 0)
-    d = DMRG(h, g, K, 0, 64, seed=3, device="cuda", tol=1e-10, max_iter=150)
+    d = DMRG(h, g, K, 0, 64, seed=3, device="cuda", tol=1e-10, max_iter=150, mpo_switch=switch)
     d.run(2)
     d.run_one_site(3)
     steps = [r for r in d.log if r.get("one_site")]

@@ -260,20 +260,23 @@ def test_davidson_step_matches_oracle(device):
             St[k] = torch.from_numpy(S[k]).to(device)
 
 
-@pytest.mark.parametrize("i", [1, 3, 5])
-def test_sigma_with_gpu_environments_equals_PtHP(device, i):
-    """Product MPO + GPU environment chain + GPU sigma == P^T H P psi (definition)."""
+@pytest.mark.parametrize("i,switch", [(1, None), (3, None), (5, None), (2, 4), (3, 4), (5, 4)])
+def test_sigma_with_gpu_environments_equals_PtHP(device, i, switch):
+    """Product MPO + GPU environment chain + GPU sigma == P^T H P psi (definition),
+    for the NC MPO and for the NC->CN switch at cut 4 (Sec. II.B.2): sites (2, 3)
+    have NC operators on all three cuts, (3, 4) the switch cut on the right, (5, 6)
+    CN operators on all three."""
     import torch
     from paper_2310_03920_amd import _lib as X
     from paper_2310_03920_amd.engine import Engine, site_payload
-    from paper_2310_03920_amd.mpo import build_nc_mpo
-    print(f"[sigma vs PtHP] i={i}", flush=True)
+    from paper_2310_03920_amd.mpo import build_mpo
+    print(f"[sigma vs PtHP] i={i} switch={switch}", flush=True)
     K, Mb = 8, 64
     h, g = make_integrals(K, seed=0)
     bonds = bond_sector_tables(K, K, 0, Mb)
     left = random_left_canonical_mps(bonds, 1)
     right = random_right_canonical_mps(bonds, 2)
-    eng = Engine(build_nc_mpo(h, g), device=device)
+    eng = Engine(build_mpo(h, g, switch=switch), device=device)
     eng.init_boundaries()
     for k in range(i):
         eng.update_left(k, bonds[k], bonds[k + 1], site_payload(bonds[k], bonds[k + 1], left[k], device))
