@@ -1,4 +1,5 @@
-"""Normal/complementary (NC) partition MPO for the ab initio Hamiltonian.
+"""Normal/complementary (NC) partition MPO for the ab initio Hamiltonian, with an
+optional switch to the CN partition.
 
 Sec. II.C.1 builds the ab initio Hamiltonian as a symbolic MPO whose bond
 operators are the normal and complementary renormalised operators of
@@ -22,6 +23,13 @@ traditional DMRG, in the NC partition.  This module builds that MPO explicitly:
   bond operator at cut k+1 built from a bond operator at cut k and an on-site
   product x of ladder operators has site factor x . P^{parity of the new operator},
   and H = W^(0) W^(1) ... W^(K-1) with every product a plain Kronecker product.
+
+* CN cuts (right of the switch cut of `build_mpo`, Sec. II.B.2): the same
+  operators except that the left normal pairs A, Ad, B are replaced by the
+  complementary pairs Pa_rs, Pd_rs, Q_rs (r, s right of the cut): the left
+  factors, integrals included, of all two-body terms whose right part is
+  a+_r a+_s, a_s a_r or a+_r a_s.  The bond then grows with the orbitals on the
+  right, which is the smaller side past the middle of the chain.
 
 Two-body coefficients: H2 = 1/2 sum V_ijkl a+_i a+_j a_k a_l with
 V_ijkl = g[p_i, p_l, p_j, p_k] delta(s_i, s_l) delta(s_j, s_k) (chemists'
