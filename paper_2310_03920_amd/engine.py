@@ -37,6 +37,10 @@ class Engine:
         self._env_plans = {}
         self._heff_plans = {}
         self._pending = {}   # heff plan key -> future of its host build
+        # one cached plan per site and kind: bond tables change with every
+        # truncation, so a plan for older tables of the same site is dropped when
+        # the new one is made (device tables and workspace are freed with it)
+        self._latest = {}
         self._pool = None
         self._w = [X.MpoSite(s.rows, s.cols, s.mats) for s in mpo.sites]
 
@@ -50,10 +54,17 @@ class Engine:
     def _bkey(bond):
         return tuple((tuple(q), int(m)) for q, m in bond)
 
+    def _keep_latest(self, cache, slot, key):
+        old = self._latest.get(slot)
+        if old is not None and old != key:
+            cache.pop(old, None)
+        self._latest[slot] = key
+
     def env_plan(self, direction, k, bond_k, bond_k1):
         key = (direction, k, self._bkey(bond_k), self._bkey(bond_k1))
         p = self._env_plans.get(key)
         if p is None:
+            self._keep_latest(self._env_plans, ("env", direction, k), key)
             if direction == 0:
                 p = X.EnvPlan(0, bond_k, bond_k1, self.mpo.dq[k], self.mpo.dq[k + 1], self._w[k],
                               t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
@@ -87,6 +98,7 @@ class Engine:
         if p is None:
             fut = self._pending.pop(key, None)
             p = fut.result() if fut is not None else self._build_heff(i, bond_i, bond_i2)
+            self._keep_latest(self._heff_plans, ("heff", i), key)
             p.upload(self.device)
             self._heff_plans[key] = p
         return p
@@ -96,6 +108,7 @@ class Engine:
         key = ("one", i, self._bkey(bond_i), self._bkey(bond_i1))
         p = self._heff_plans.get(key)
         if p is None:
+            self._keep_latest(self._heff_plans, ("one", i), key)
             p = X.Heff1Plan(bond_i, bond_i1, self.mpo.dq[i], self.mpo.dq[i + 1], self._w[i],
                             t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
             self._heff_plans[key] = p
@@ -149,6 +162,7 @@ class Engine:
         self._pending.clear()
         self._env_plans.clear()
         self._heff_plans.clear()
+        self._latest.clear()
 
     def update_left(self, k, bond_k, bond_k1, A):
         """left[k+1] from left[k] and the left-canonical tensor A (payload) of site k."""
