@@ -485,8 +485,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the sharding over the MPO middle-bond index is described in DESIGN.md).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(the sigma-vector would shard over the MPO middle-bond index, one all-reduce per call).",
+              file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch":
