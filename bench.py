@@ -420,7 +420,8 @@ def bench_sweep(args):
     h, g = make_integrals(K, seed=0)
     t0 = time.time()
     switch = K // 2 if args.partition == "nc-cn" else None
-    d = DMRG(h, g, K, 0, M, seed=0, device="cuda", tol=args.tol, max_iter=args.max_iter, mpo_switch=switch)
+    d = DMRG(h, g, K, 0, M, seed=0, device="cuda", tol=args.tol, max_iter=args.max_iter, mpo_switch=switch,
+             precision=args.mode)
     torch.cuda.synchronize()
     log(f"set-up (MPO, random MPS, right environments) {time.time() - t0:.1f}s; "
         f"MPO bond dims {[len(x) for x in d.mpo.dq]}")
@@ -444,7 +445,7 @@ def bench_sweep(args):
     print(json.dumps({
         "metric": "two-site DMRG pass wall time", "value": avg, "unit": "s/pass", "n_gpus": 1,
         "steps": args.steps, "warmup": 0, "ms_per_step": 1e3 * avg, "higher_is_better": False,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": args.mode, "data": "synthetic",
         "config": {"workload": f"two-site DMRG passes over a {K}-orbital ab initio chain, {K} electrons, "
                                f"2Sz=0, M={M}, integrals seed 0, seeded random initial MPS, "
                                + ("NC-partition MPO" if switch is None else f"NC-partition MPO up to cut {switch}, CN after"),
