@@ -362,6 +362,39 @@ def _ptr(t):
     return c_void_p(0) if t is None else c_void_p(t.data_ptr())
 
 
+def need_all(device, *items):
+    """need() over (tensor, name, n, dtype) items: every operand's type, dtype,
+    layout and length first, then where they live."""
+    for t, name, n, dt in items:
+        need(t, name, n, dt, device, where=False)
+    for t, name, n, dt in items:
+        need(t, name, n, dt, device)
+
+
+def need(t, name, n, dtype="float64", device=None, where=True):
+    """Check a device operand before its pointer reaches the library, whose entry
+    points take bare pointers with lengths implied by the plan: a torch tensor of
+    the given dtype, contiguous, with at least n elements and (with `where`) on
+    the plan's GPU.  A missing operand (None) is accepted only when n == 0.
+    Raises TypeError / ValueError; no device work is issued."""
+    import torch
+    if t is None:
+        if n == 0:
+            return
+        raise ValueError(f"{name}: missing (the plan needs {n} elements)")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    want = getattr(torch, dtype)
+    if t.dtype != want:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {want}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if t.numel() < n:
+        raise ValueError(f"{name}: {t.numel()} elements, the plan needs {n}")
+    if where and (not t.is_cuda or (device is not None and t.device != device)):
+        raise ValueError(f"{name}: must be a tensor on the plan's device ({device or 'a GPU'}), got {t.device}")
+
+
 def _stream():
     import torch
     return c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -390,6 +423,20 @@ class Plan:
         nws = max(int(self.info.ws_bytes) // 8, 1)
         self.ws = torch.empty(nws, dtype=torch.float64, device=device)
         return self
+
+    @property
+    def device(self):
+        return None if self.ws is None else self.ws.device
+
+    def _uploaded(self, what):
+        if self.ws is None or self.tables is None:
+            raise RuntimeError(f"{what}: upload the plan to a device first")
+
+    def _env_items(self, L, R, dtype="float64"):
+        return [(L, "L", int(self.info.in_nnz), dtype), (R, "R", int(self.info.in2_nnz), dtype)]
+
+    def _check_env(self, L, R, dtype="float64"):
+        need_all(self.device, *self._env_items(L, R, dtype))
 
     def __del__(self):
         try:
@@ -427,18 +474,33 @@ class HeffPlan(Plan):
         self.lbond, self.rbond = lb, rb
 
     def prepare(self, L, R):
+        self._check_env(L, R)
+        self._uploaded("heff_prepare")
         check(lib().hx_heff_prepare(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _stream()), "heff_prepare")
 
+    def _check_vecs(self, psi, sigma, dtype="float64", env=()):
+        n = int(self.info.psi_nnz)
+        need_all(self.device, *env, (psi, "psi", n, dtype), (sigma, "sigma", n, dtype))
+        if psi is not None and sigma is not None and n and psi.data_ptr() == sigma.data_ptr():
+            raise ValueError("psi and sigma must not overlap")
+
     def apply(self, L, R, psi, sigma):
+        self._check_vecs(psi, sigma, env=self._env_items(L, R))
+        self._uploaded("heff_apply")
         check(lib().hx_heff_apply(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(psi), _ptr(sigma), _stream()),
               "heff_apply")
 
     def diag(self, L, R, out):
+        nd = int(self.info.psi_nnz) // max(getattr(self, "n_roots", 1), 1)
+        need_all(self.device, *self._env_items(L, R), (out, "diag", nd, "float64"))
+        self._uploaded("heff_diag")
         check(lib().hx_heff_diag(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(out), _stream()), "heff_diag")
 
     # FP32 mode: operands rounded once per (L, R); Davidson stays FP64
     def lower_f32(self, L, R):
         import torch
+        self._check_env(L, R)
+        self._uploaded("heff_lower_f32")
         dev = self.ws.device
         if getattr(self, "ws32", None) is None:
             self.ws32 = torch.empty(max(int(self.info.ws_bytes) // 8, 1), dtype=torch.float32, device=dev)
@@ -447,12 +509,20 @@ class HeffPlan(Plan):
         check(lib().hx_heff_lower_f32(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(self.L32), _ptr(self.R32),
                                       _ptr(self.ws32), _stream()), "heff_lower_f32")
 
+    def _lowered(self, what):
+        if getattr(self, "L32", None) is None:
+            raise RuntimeError(f"{what}: call lower_f32 first")
+
     def apply_f32(self, psi32, sigma32):
+        self._check_vecs(psi32, sigma32, "float32")
+        self._lowered("heff_apply_f32")
         check(lib().hx_heff_apply_f32(self.h, _ptr(self.L32), _ptr(self.R32), _ptr(self.ws32), _ptr(psi32),
                                       _ptr(sigma32), _stream()), "heff_apply_f32")
 
     def apply_bf16(self, psi32, sigma32):
         """BF16 block products on the FP32 operands of lower_f32."""
+        self._check_vecs(psi32, sigma32, "float32")
+        self._lowered("heff_apply_bf16")
         check(lib().hx_heff_apply_bf16(self.h, _ptr(self.L32), _ptr(self.R32), _ptr(self.ws32), _ptr(psi32),
                                        _ptr(sigma32), _stream()), "heff_apply_bf16")
 
@@ -495,9 +565,21 @@ class HeffVjpPlan(Plan):
         self.nnz1, self.nnz2 = len(w1.rows), len(w2.rows)
 
     def prepare(self, L, R):
+        self._check_env(L, R)
+        self._uploaded("heff_prepare")
         check(lib().hx_heff_prepare(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _stream()), "heff_prepare")
 
+    def _check_backward(self, psi, g, g_psi, g_L, g_R, g_W1, g_W2, dtype, env=()):
+        n = int(self.info.psi_nnz)
+        need_all(self.device, *env, (psi, "psi", n, dtype), (g, "g", n, dtype), (g_psi, "g_psi", n, dtype),
+                 (g_L, "g_L", int(self.info.in_nnz), dtype), (g_R, "g_R", int(self.info.in2_nnz), dtype),
+                 (g_W1, "g_W1", 16 * self.nnz1, dtype), (g_W2, "g_W2", 16 * self.nnz2, dtype))
+        if n and g_psi.data_ptr() in (psi.data_ptr(), g.data_ptr()):
+            raise ValueError("g_psi must not alias psi or g")
+
     def backward(self, L, R, psi, g, g_psi, g_L, g_R, g_W1, g_W2):
+        self._check_backward(psi, g, g_psi, g_L, g_R, g_W1, g_W2, "float64", env=self._env_items(L, R))
+        self._uploaded("heff_apply_backward")
         check(lib().hx_heff_apply_backward(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(psi), _ptr(g), _ptr(g_psi),
                                            _ptr(g_L), _ptr(g_R), _ptr(g_W1), _ptr(g_W2), _stream()),
               "heff_apply_backward")
@@ -507,6 +589,8 @@ class HeffVjpPlan(Plan):
         HeffPlan.lower_f32(self, L, R)
 
     def backward_f32(self, psi32, g32, g_psi32, g_L32, g_R32, g_W1_32, g_W2_32):
+        self._check_backward(psi32, g32, g_psi32, g_L32, g_R32, g_W1_32, g_W2_32, "float32")
+        self._lowered("heff_apply_backward_f32")
         check(lib().hx_heff_apply_backward_f32(self.h, _ptr(self.L32), _ptr(self.R32), _ptr(self.ws32), _ptr(psi32),
                                                _ptr(g32), _ptr(g_psi32), _ptr(g_L32), _ptr(g_R32), _ptr(g_W1_32),
                                                _ptr(g_W2_32), _stream()), "heff_apply_backward_f32")
@@ -588,6 +672,10 @@ class EnvPlan(Plan):
         super().__init__(h, (bi, bo, oi, oo, w))
 
     def update(self, env_in, site, env_out):
+        need_all(self.device, (env_in, "env_in", int(self.info.in_nnz), "float64"),
+                 (site, "site", int(self.info.in2_nnz), "float64"),
+                 (env_out, "env_out", int(self.info.out_nnz), "float64"))
+        self._uploaded("env_update")
         check(lib().hx_env_update(self.h, _ptr(env_in), _ptr(site), _ptr(self.ws), _ptr(env_out), _stream()),
               "env_update")
 
@@ -598,6 +686,14 @@ def davidson_ws_bytes(n, kmax):
 
 def davidson_step(n, k, kmax, V, S, diag, guard, ws, x, hx, t, scal):
     """Tensors: V, S (kmax, n) row-major float64; diag, x, hx, t (n,); ws bytes; scal (>=3,)."""
+    if not 1 <= k <= kmax <= 32:
+        raise ValueError("davidson_step: need 1 <= k <= kmax <= 32")
+    for m, name in ((V, "V"), (S, "S")):
+        if m.dim() != 2 or m.shape[0] < k or m.shape[1] < n or m.stride(1) != 1:
+            raise ValueError(f"davidson_step: {name} must be a row-major (>= k, >= n) matrix")
+    need_all(diag.device, (diag, "diag", n, "float64"), (x, "x", n, "float64"), (hx, "hx", n, "float64"),
+             (t, "t", n, "float64"), (scal, "scal", 3, "float64"), (V, "V", 0, "float64"), (S, "S", 0, "float64"),
+             (ws, "ws", davidson_ws_bytes(n, kmax) // ws.element_size(), str(ws.dtype).split(".")[-1]))
     check(lib().hx_davidson_step(int(n), int(k), int(kmax), _ptr(V), V.stride(0), _ptr(S), S.stride(0), _ptr(diag),
                                  float(guard), _ptr(ws), _ptr(x), _ptr(hx), _ptr(t), _ptr(scal), _stream()),
           "davidson_step")

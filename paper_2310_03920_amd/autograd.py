@@ -32,6 +32,9 @@ class HeffOperator:
                 torch.from_numpy(self.w2_site.vals.reshape(-1, 4, 4).copy()).to(self.device))
 
     def __call__(self, L, R, w1, w2, psi):
+        dev = self.fwd.device
+        X.need(w1, "w1", 16 * self.vjp.nnz1, "float64", dev)
+        X.need(w2, "w2", 16 * self.vjp.nnz2, "float64", dev)
         return _HeffApply.apply(self, L, R, w1, w2, psi)
 
 
@@ -85,6 +88,7 @@ class EnvUpdateOperator:
         return torch.from_numpy(np.asarray(s.mats, dtype=np.float64).reshape(-1, 4, 4).copy()).to(self.eng.device)
 
     def __call__(self, env_in, site, w):
+        X.need(w, "w", 16 * len(self.eng.mpo.sites[self.k].rows), "float64", self.plan.device)
         return _EnvUpdate.apply(self, env_in, site, w)
 
 

@@ -71,15 +71,40 @@ def _matrix(g):
     return mat, ro, co
 
 
-def split(psi, bl, br, M, direction, fixed=None):
+# Singular values closer than TIE_RTOL * (largest singular value) to the first
+# value of a run of near-equal values are treated as equal.  A spin-free
+# Hamiltonian gives exactly equal singular values for the members of a spin
+# multiplet (different 2Sz sectors); rounding would otherwise decide which of them
+# survive a cut through the multiplet.
+TIE_RTOL = 1e-8
+
+
+def _keep_order(cand):
+    """cand: (-s, Q, j) sorted ascending.  Runs of values within TIE_RTOL * s_max of
+    the run's first value are re-ordered by (sector, index)."""
+    if not cand:
+        return cand
+    tol = TIE_RTOL * -cand[0][0]
+    out, a = [], 0
+    while a < len(cand):
+        b = a + 1
+        while b < len(cand) and cand[b][0] - cand[a][0] <= tol:
+            b += 1
+        out.extend(sorted(cand[a:b], key=lambda c: (c[1], c[2])))
+        a = b
+    return out
+
+
+def split(psi, bl, br, M, direction, fixed=None, info=None):
     """SVD split of a two-site tensor.
 
     direction 0: psi = A C with A left-canonical (new bond sectors from U);
     direction 1: psi = C B with B right-canonical (from V^T).
     Keeps the M largest singular values over all sectors, counting the zero
-    singular values of the full (square) factor, ties by (sector, index); with
-    `fixed` = {Q: dim} the dims per sector are given instead.
-    Returns (new_bond, canonical tensor, center tensor, discarded weight).
+    singular values of the full (square) factor, ties (within TIE_RTOL) by
+    (sector, index); with `fixed` = {Q: dim} the dims per sector are given instead.
+    Returns (new_bond, canonical tensor, center tensor, discarded weight); with a
+    dict `info`, info["kept_s"] receives the kept singular values (descending).
     """
     groups = _fused_sectors(psi, bl, br)
     cand = []
@@ -94,7 +119,7 @@ def split(psi, bl, br, M, direction, fixed=None):
         for j in range(n):
             cand.append((-s_full[j], Q, j))
     if fixed is None:
-        cand.sort()
+        cand = _keep_order(sorted(cand))
         keep = cand[:M]
         kept = {}
         for _, Q, j in keep:
@@ -104,6 +129,8 @@ def split(psi, bl, br, M, direction, fixed=None):
         kept = {Q: min(m, len(fac[Q][1])) for Q, m in fixed.items() if Q in fac}
         disc = float(sum((fac[Q][1][kept.get(Q, 0):] ** 2).sum() for Q in fac))
     new_bond = sorted((Q, m) for Q, m in kept.items() if m > 0)
+    if info is not None:
+        info["kept_s"] = sorted((float(x) for Q, m in new_bond for x in fac[Q][1][:m]), reverse=True)
     nidx = {Q: i for i, (Q, _) in enumerate(new_bond)}
     canon, center = {}, {}
     for Q, m in new_bond:
@@ -412,6 +439,14 @@ class DMRG:
         self.log.append({"pass": pass_id, "i": i, "energy": theta, "rnorm": rnorm, "n_matvec": nmv})
         return psi
 
+    def _split_logged(self, psi, i, direction):
+        """Truncating split of the step's Ritz vector; the step's log record gets the
+        discarded weight, the new middle bond and its kept singular values."""
+        info = {}
+        nb, canon, centre, disc = split(psi, self.bonds[i], self.bonds[i + 2], self.M, direction, info=info)
+        self.log[-1].update(discarded=disc, bond=list(nb), kept_s=info["kept_s"])
+        return nb, canon, centre
+
     def sweep_left_to_right(self, pass_id, start):
         K = self.K
         for i in range(start, K - 1):
@@ -422,7 +457,7 @@ class DMRG:
                                     self.bonds[i + 2])
             psi = self._step(i, psi0, pass_id)
             if i < K - 2:
-                nb, A, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 0)
+                nb, A, C = self._split_logged(psi, i, 0)
                 self.bonds[i + 1] = nb
                 self.eng.prefetch_heff_plan(i + 1, self.bonds[i + 1], self.bonds[i + 3])
                 self.tensors[i] = A
@@ -430,7 +465,7 @@ class DMRG:
                 self.eng.update_left(i, self.bonds[i], self.bonds[i + 1],
                                      site_payload(self.bonds[i], self.bonds[i + 1], A, self.device))
             else:
-                nb, B, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 1)
+                nb, B, C = self._split_logged(psi, i, 1)
                 self.bonds[i + 1] = nb
                 self.tensors[i + 1] = B
                 self.center, self.center_site = C, i
@@ -442,7 +477,7 @@ class DMRG:
             psi0 = contract_two(self.tensors[i], self.center, self.bonds[i], self.bonds[i + 1], self.bonds[i + 2])
             psi = self._step(i, psi0, pass_id)
             if i > 0:
-                nb, B, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 1)
+                nb, B, C = self._split_logged(psi, i, 1)
                 self.bonds[i + 1] = nb
                 self.eng.prefetch_heff_plan(i - 1, self.bonds[i - 1], self.bonds[i + 1])
                 self.tensors[i + 1] = B
@@ -450,7 +485,7 @@ class DMRG:
                 self.eng.update_right(i + 1, self.bonds[i + 1], self.bonds[i + 2],
                                       site_payload(self.bonds[i + 1], self.bonds[i + 2], B, self.device))
             else:
-                nb, A, C, _ = split(psi, self.bonds[i], self.bonds[i + 2], self.M, 0)
+                nb, A, C = self._split_logged(psi, i, 0)
                 self.bonds[i + 1] = nb
                 self.tensors[i] = A
                 self.center, self.center_site = C, i + 1

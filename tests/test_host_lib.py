@@ -319,7 +319,9 @@ def test_autotune_coordinate_search_finds_separable_minimum():
 
     best, seen = A.coordinate_search(timer)
     assert best == {"kernel_variant": 1, "split_kseg_min": 1024, "t_budget_bytes": 1 << 31}
-    assert len(calls) == len(seen) == 12  # start + the other values of each axis, no repeats
+    # start + the other values of each axis, no repeats
+    assert len(calls) == len(seen) == 1 + sum(len(v) - 1 for _, v in A.AXES)
+    assert all(c["kernel_variant"] != 3 for c in calls)  # the persistent variant is not searched
 
 
 def test_autotune_signature_depends_on_shape():
