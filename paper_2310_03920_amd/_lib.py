@@ -432,6 +432,10 @@ class Plan:
         if self.ws is None or self.tables is None:
             raise RuntimeError(f"{what}: upload the plan to a device first")
 
+    def _lowered(self, what):
+        if getattr(self, "L32", None) is None:
+            raise RuntimeError(f"{what}: call lower_f32 first")
+
     def _env_items(self, L, R, dtype="float64"):
         return [(L, "L", int(self.info.in_nnz), dtype), (R, "R", int(self.info.in2_nnz), dtype)]
 
@@ -508,10 +512,6 @@ class HeffPlan(Plan):
         self.R32 = torch.empty(max(int(self.info.in2_nnz), 1), dtype=torch.float32, device=dev)
         check(lib().hx_heff_lower_f32(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(self.L32), _ptr(self.R32),
                                       _ptr(self.ws32), _stream()), "heff_lower_f32")
-
-    def _lowered(self, what):
-        if getattr(self, "L32", None) is None:
-            raise RuntimeError(f"{what}: call lower_f32 first")
 
     def apply_f32(self, psi32, sigma32):
         self._check_vecs(psi32, sigma32, "float32")
