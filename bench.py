@@ -37,10 +37,11 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAKS = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFLOPS}
 # HBM bytes of one FP64 sigma-vector at the default workload (36 orbitals, M = 1000,
-# middle step), from rocprofv3 FETCH_SIZE / WRITE_SIZE runs scaled by a copy of known
-# size, per plan options (kernel_variant, split_kseg_min, intermediate budget).  Only
-# valid for the kernel and tile order they were taken with; other options report null.
-MEASURED_TRAFFIC = {(1, 512, 1 << 31): 75.91e9, (1, 512, 1 << 30): 76.17e9, (1, 512, 1 << 29): 78.52e9}
+# middle step) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by what the counters
+# read for a device copy of known size), per plan options (kernel_variant,
+# split_kseg_min, intermediate budget), with the summary they come from.  Only valid
+# for the kernel and plan builder they were taken with; other options report null.
+MEASURED_TRAFFIC = {}
 
 
 def log(*a):
@@ -84,10 +85,15 @@ def build_environments(X, mpo, bonds, left, right, i, device):
     return Lenv, Renv
 
 
-def cpu_baseline(mpo, bonds, i, flops_apply, budget_s=15.0, seed=5):
-    """Time the FP64 oracle's row-sampled sigma on the host (same shapes and MPO,
-    seeded random environments and psi): GFLOP/s attributed per output row."""
-    from oracle import contract
+def cpu_baseline(mpo, bonds, i, stride=8, seed=5):
+    """Time the FP64 block-sparse oracle sigma (oracle.blocks: one numpy matmul per
+    block product, iterating over output column blocks) on the host, on the same
+    shapes and MPO with seeded random environments and psi.  The sample is the sum
+    over every `stride`-th middle-bond index b (the terms of different b are
+    independent); its FLOP count is the oracle's own count of block-product work.
+    Timed with the BLAS pool at all host threads and at one thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
+    from oracle import blocks
     from paper_2310_03920_amd.mpo import site_entries
     from synth.blocks import random_env, random_psi
     rng = np.random.default_rng(seed)
@@ -96,23 +102,25 @@ def cpu_baseline(mpo, bonds, i, flops_apply, budget_s=15.0, seed=5):
     R = random_env(rb, [tuple(x) for x in mpo.dq[i + 2]], rng)
     psi = random_psi(lb, rb, rng)
     W1, W2 = site_entries(mpo, i), site_entries(mpo, i + 1)
-    rows_all = [(il, s1, x) for il, (_, m) in enumerate(lb) for s1 in range(4) for x in range(m)]
-    order = rng.permutation(len(rows_all))
-    done, t0 = 0, time.time()
-    while time.time() - t0 < budget_s and done < len(rows_all):
-        contract.sigma_rows(lb, rb, L, W1, W2, R, psi, [rows_all[order[done]]])
-        done += 1
-    dt = time.time() - t0
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        threads = 1
-    gf = flops_apply * (done / len(rows_all)) / dt / 1e9
-    return {"value": gf, "unit": "GFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"{done} of {len(rows_all)} sigma rows (oracle.contract.sigma_rows, FP64 numpy) "
-                      f"in {dt:.1f}s; flops attributed uniformly per row",
-            "host_cpus": os.cpu_count()}
+    nmid = len(mpo.dq[i + 1])
+    bsel = list(range(0, nmid, stride))
+    mixed = blocks.prepare(L, W1, W2, R, bsel)
+    ncpu = os.cpu_count() or 1
+    legs = {}
+    for nt in (ncpu, 1):
+        with threadpool_limits(limits=nt):
+            used = max([d.get("num_threads", 1) for d in threadpool_info() if d.get("user_api") == "blas"] + [1])
+            fl = [0.0]
+            t0 = time.time()
+            blocks.heff_apply(lb, rb, L, W1, W2, R, psi, bsel=bsel, flops=fl, mixed=mixed)
+            dt = time.time() - t0
+        legs[nt] = (fl[0] / dt / 1e9, used, dt, fl[0])
+    rate, used, dt, fl = legs[ncpu]
+    return {"value": rate, "unit": "GFLOP/s", "cores": int(used), "kind": "oracle",
+            "sample": f"oracle.blocks sigma (FP64 numpy, one matmul per block product) restricted to "
+                      f"{len(bsel)} of {nmid} middle-bond indices (every {stride}th b): {fl / 1e9:.1f} GFLOP "
+                      f"of block products in {dt:.1f}s",
+            "value_1thread": legs[1][0], "seconds_1thread": legs[1][2], "host_cpus": ncpu}
 
 
 def batch_instances(X, M=256, K=16, count=16):
@@ -264,7 +272,7 @@ def bench_batch(args):
     t_one, w_one = timed(one_by_one, reps)
     t_bat, w_bat = timed(batched, reps)
     t_gr, w_gr = timed(graph.launch, reps)
-    fl = B.info.flops_apply
+    fl = B.info.flops_useful
     peak = PEAKS[args.mode]
     achieved = fl / t_gr / 1e12
     out = {
@@ -384,20 +392,21 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
     info = plan.info
     avg = float(np.mean(ms)) / 1e3
     peak = PEAKS[args.mode]
-    achieved = info.flops_apply / avg / 1e12
+    achieved = info.flops_useful / avg / 1e12
     src = torch.ones(1 << 26, dtype=torch.float64, device=device)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({
-        "metric": METRIC, "value": info.flops_apply / avg / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
+        "metric": METRIC, "value": info.flops_useful / avg / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * avg, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": args.mode, "data": "synthetic",
         "config": {"workload": f"sigma-vectors only at sites ({i},{i + 1}) of the {mpo.K}-orbital chain, "
                                f"M={args.bond_dim}, {args.roots} vector(s) per call, "
                                + ("NC-partition MPO" if args.partition == "nc" else f"NC->CN switch at cut {mpo.K // 2}"),
-                   "roots": args.roots, "tflop_per_call": info.flops_apply / 1e12,
+                   "roots": args.roots, "tflop_per_call": info.flops_useful / 1e12,
+                   "tflop_executed_per_call": info.flops_apply / 1e12,
                    "mpo_bond_dims": [len(mpo.cuts[k]) for k in (i, i + 1, i + 2)],
                    "chunks": int(info.n_chunks), "tiles": int(info.n_tiles),
                    "apply_ms_each": ms, "plan_opts": opts, "autotune_s": tune_s},
@@ -542,7 +551,7 @@ def main():
     plan.upload(device)
     eplan.upload(device)
     info, einfo = plan.info, eplan.info
-    log(f"plans in {plan_s:.1f}s: psi {info.psi_nnz}, {info.flops_apply / 1e12:.3f} TFLOP/apply, "
+    log(f"plans in {plan_s:.1f}s: psi {info.psi_nnz}, {info.flops_useful / 1e12:.3f} TFLOP/apply ({info.flops_apply / 1e12:.3f} executed), "
         f"tasks {info.n_tasks}, tiles {info.n_tiles}, chunks {info.n_chunks}, ws {info.ws_bytes / 1e9:.2f} GB")
 
     n = int(info.psi_nnz)
@@ -625,13 +634,39 @@ def main():
     main_ev = ev32 if args.mode != "f64" else ev
     apply_ms = [s.elapsed_time(e) for s, e in main_ev]
     nmv = sum(r[2] for r in res)
-    step_flops = [info.flops_prepare + r[2] * info.flops_apply + einfo.flops_apply for r in res]
+    step_flops = [info.flops_prepare + r[2] * info.flops_useful + einfo.flops_apply for r in res]
     total_t = sum(times)
     value = sum(step_flops) / total_t / 1e9
     avg_apply = float(np.mean(apply_ms)) / 1e3
-    achieved = info.flops_apply / avg_apply / 1e12
+    achieved = info.flops_useful / avg_apply / 1e12
     peak = PEAKS[args.mode]
     theta, rnorm = res[-1][0], res[-1][1]
+    # energy error of the mixed-precision step per block-product dtype (untimed, same warm
+    # start and FP64 reference; in --mode f32 / bf16 the timed steps already are one)
+    mixed = {}
+    if args.mode == "f64":
+        for md in ("f32", "bf16"):
+            low = plan.apply_bf16 if md == "bf16" else plan.apply_f32
+
+            def mv_low(v, out, low=low):
+                X.convert_f64_f32(v, v32)
+                low(v32, s32)
+                X.convert_f32_f64(s32, out)
+
+            try:
+                plan.lower_f32(Lenv, Renv)
+                t3 = time.perf_counter()
+                th, rn, nl, nh = dav.solve_mixed(mv_low, mv, psi0, diag, tol=args.tol, max_iter=args.max_iter,
+                                                 **PRECISIONS[md])
+                torch.cuda.synchronize()
+                mixed[md] = {"energy_err_vs_fp64": abs(th - e_ref), "rnorm": rn, "low_matvecs": nl,
+                             "f64_matvecs": nh, "solve_s": time.perf_counter() - t3}
+            except RuntimeError as exc:
+                mixed[md] = {"error": str(exc)}
+        plan.ws32 = plan.L32 = plan.R32 = None
+        log(f"mixed-precision steps: {mixed}")
+    traffic = (MEASURED_TRAFFIC.get((opts["kernel_variant"], opts["split_kseg_min"], opts["t_budget_bytes"]))
+               if (args.mode == "f64" and (K, M) == (36, 1000) and args.partition == "nc") else None)
     out = {
         "metric": METRIC,
         "value": value,
@@ -659,24 +694,29 @@ def main():
                          "f64_matvecs_per_step": counts["f64"] / args.steps, "precision": args.mode},
             "plan_build_s": plan_s, "chunks": int(info.n_chunks), "plan_opts": opts, "autotune_s": tune_s,
         },
-        "heff_apply": {"ms": 1e3 * avg_apply, "tflop": info.flops_apply / 1e12,
+        "heff_apply": {"ms": 1e3 * avg_apply, "tflop": info.flops_useful / 1e12,
+                       "tflop_executed": info.flops_apply / 1e12, "bytes_algorithmic": info.bytes_apply,
+                       "bytes_operands": 8.0 * (info.in_nnz + info.in2_nnz + 2 * info.psi_nnz),
                        "tflops": achieved, "launches": 2 * int(info.n_chunks)},
         "energy": theta,
         "rnorm": rnorm,
         "energy_err_vs_fp64": abs(theta - e_ref),
+        "energy_err_vs_fp64_by_dtype": ({args.mode: abs(theta - e_ref)} if args.mode != "f64"
+                                        else {"f64": abs(theta - e_ref),
+                                              **{k: v.get("energy_err_vs_fp64") for k, v in mixed.items()}}),
+        "mixed_precision_steps": mixed or None,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": (MEASURED_TRAFFIC.get((opts["kernel_variant"], opts["split_kseg_min"],
-                                                       opts["t_budget_bytes"]))
-                                 if (args.mode == "f64" and (K, M) == (36, 1000)) else None),
-                     "traffic_unit": "bytes per sigma-vector (HBM, counter-measured)",
+                     "traffic": traffic[0] if traffic else None,
+                     "traffic_source": traffic[1] if traffic else None,
+                     "traffic_unit": "HBM bytes per sigma-vector (rocprofv3 FETCH_SIZE + WRITE_SIZE, stored)",
                      "kernel": ({"f32": "bsgemm<float> (all launches of one hx_heff_apply_f32)",
                                  "bf16": "bsgemm<float, BF16 products> (all launches of one hx_heff_apply_bf16)"
                                  }[args.mode] if args.mode != "f64"
                                 else "bsgemm<double> (all launches of one hx_heff_apply)")},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(mpo, bonds, i, info.flops_apply)
+        out["cpu_baseline"] = cpu_baseline(mpo, bonds, i)
     print(json.dumps(out), flush=True)
 
 

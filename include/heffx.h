@@ -123,6 +123,10 @@ typedef struct {
     int64_t n_tiles;        /* output tiles of one apply */
     int32_t n_chunks;       /* number of intermediate chunks */
     int32_t n_mixed;        /* number of materialised mixed operators */
+    double flops_useful;    /* sigma-vector plans: the part of flops_apply whose results sigma
+                               reads (a stacked stage-1 intermediate is computed over the span
+                               of rows stage 2 reads, which may enclose rows it does not read);
+                               other plans: flops_apply */
 } hx_plan_info;
 
 /* ---- layouts (host only) ---------------------------------------------------- */

@@ -52,7 +52,7 @@ class HxPlanInfo(ctypes.Structure):
     _fields_ = [("psi_nnz", c_int64), ("in_nnz", c_int64), ("in2_nnz", c_int64), ("out_nnz", c_int64),
                 ("table_bytes", c_int64), ("ws_bytes", c_int64), ("flops_apply", c_double),
                 ("flops_prepare", c_double), ("bytes_apply", c_double), ("n_tasks", c_int64),
-                ("n_tiles", c_int64), ("n_chunks", c_int32), ("n_mixed", c_int32)]
+                ("n_tiles", c_int64), ("n_chunks", c_int32), ("n_mixed", c_int32), ("flops_useful", c_double)]
 
 
 _lib = None

@@ -162,6 +162,7 @@ struct Plan {
     int n_roots = 1;            // vectors per sigma-vector call (roots side by side in column blocks)
     int n_stages = 0;           // rounds emitted so far (Launch::stage)
     double flops_apply = 0, flops_prepare = 0, bytes_apply = 0;
+    double flops_useful = -1;   // sigma plans: block-product work whose results sigma reads (< 0: = flops_apply)
     int64_t n_tasks_apply = 0, n_tiles_apply = 0;
     int n_chunks = 0, n_mixed = 0;
     // device table layout (byte offsets inside the uploaded buffer)

@@ -898,16 +898,40 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
     ws += tmax;
     P.n_chunks = (int)chunks.size();
 
-    double fl = 0;
+    double fl = 0, useful = 0;
     int64_t nt = 0;
     double tbytes = 0;
+    // Rows of a stacked intermediate that stage 2 reads for middle operator b: a row
+    // block (l, s1) is read when a left transition of b starts from s1 and maps l into
+    // the bond.  Only the span from the first to the last such row is computed (the
+    // stacked GEMM stays one operand range); `used` counts the rows read.
+    auto read_span = [&](int b, const PsiCol& pc, int& lo, int& hi, int& used) {
+        lo = pc.rows;
+        hi = 0;
+        used = 0;
+        for (const auto& rbk : pc.rowblk) {
+            const int il = rbk[0], s1 = rbk[1], roff = rbk[2];
+            bool read = false;
+            for (auto& tr : ML.trans[b])
+                if (tr.si == s1 && lb.find(lb.qn[il][0] + tr.m.dn, lb.qn[il][1] + tr.m.ds) >= 0) {
+                    read = true;
+                    break;
+                }
+            if (!read) continue;
+            lo = std::min(lo, roff);
+            hi = std::max(hi, roff + lb.dim[il]);
+            used += lb.dim[il];
+        }
+    };
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
         // ---- stage 1: T_b[:, (s2', r')] = sum_{s2} psi[:, (s2, r)] Rmix_{b,s2'<-s2}[r', r]^T
-        //      on stacked column blocks (all row blocks of one fused sector at once)
+        //      on stacked column blocks (all row blocks of one fused sector at once,
+        //      restricted to the span of rows that stage 2 reads)
         std::vector<OutBlockTasks> tblocks;
         struct TInfo {
             int b, col, s2p, irp;  // col: the psi column block whose row structure T shares
             int64_t off;
+            int rows, r_lo, used;  // stacked rows of the column block; first row held; rows read
         };
         std::vector<TInfo> tinfo;
         int64_t toff = t_ws;
@@ -922,30 +946,38 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                     const size_t key = (size_t)tr.so * rb.nsec() + irp;
                     int ti;
                     if (tstamp[key] != b + 1) {
-                        // one T block (rows x R*np, roots side by side), one output block per root
-                        ti = (int)tinfo.size();
                         tstamp[key] = b + 1;
+                        int lo, hi, used;
+                        read_span(b, pc, lo, hi, used);
+                        if (used == 0) {  // nothing of this intermediate is read
+                            tslot[key] = -1;
+                            continue;
+                        }
+                        // one T block ((hi - lo) x R*np, roots side by side), one output block per root
+                        ti = (int)tinfo.size();
                         tslot[key] = ti;
                         for (int rho = 0; rho < R; ++rho) {
                             OutBlockTasks ob;
                             ob.coff = toff + (int64_t)rho * rb.dim[irp];
                             ob.ldc = R * rb.dim[irp];
-                            ob.m = pc.rows;
+                            ob.m = hi - lo;
                             ob.n = rb.dim[irp];
                             tblocks.push_back(std::move(ob));
                         }
-                        tinfo.push_back({b, cj, tr.so, irp, toff});
-                        toff += (int64_t)pc.rows * rb.dim[irp] * R;
+                        tinfo.push_back({b, cj, tr.so, irp, toff, pc.rows, lo, used});
+                        toff += (int64_t)(hi - lo) * rb.dim[irp] * R;
                     } else {
                         ti = tslot[key];
-                        if (tblocks[(size_t)ti * R].m != pc.rows) {
+                        if (ti < 0) continue;
+                        if (tinfo[ti].rows != pc.rows) {
                             set_error("internal: stacked intermediate rows inconsistent");
                             return HX_EINVAL;
                         }
                     }
+                    const TInfo& tin = tinfo[ti];
                     for (int rho = 0; rho < R; ++rho) {
                         Task t;
-                        t.aoff = pc.off * R + (int64_t)rho * rb.dim[pc.ir];
+                        t.aoff = pc.off * R + (int64_t)tin.r_lo * R * rb.dim[pc.ir] + (int64_t)rho * rb.dim[pc.ir];
                         t.lda = R * rb.dim[pc.ir];
                         t.boff = tr.m.base + sl.rel[pc.ir];
                         t.ldb = rb.dim[pc.ir];
@@ -953,6 +985,7 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                         t.k = rb.dim[pc.ir];
                         t.alpha = tr.m.alpha;
                         tblocks[(size_t)ti * R + rho].tasks.push_back(t);
+                        useful += 2.0 * tin.used * rb.dim[irp] * (double)t.k;
                     }
                 }
             }
@@ -987,18 +1020,20 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                     t.aoff = tr.m.base + sl.rel[il];
                     t.lda = lb.dim[il];
                     const int ta_ = tr.m.space;
-                    t.boff = ti.off + (int64_t)roff * rb.dim[ti.irp] * R;
+                    t.boff = ti.off + (int64_t)(roff - ti.r_lo) * rb.dim[ti.irp] * R;
                     t.ldb = R * rb.dim[ti.irp];
                     t.set_spaces(ta_, SP_WS);
                     t.k = lb.dim[il];
-                        t.alpha = tr.m.alpha;
+                    t.alpha = tr.m.alpha;
                     sblocks[si].tasks.push_back(t);
+                    useful += 2.0 * sblocks[si].m * (double)sblocks[si].n * t.k;
                 }
             }
         }
         flush_blocks(P, sblocks, NN, SP_OUT, ci == 0 ? 0 : 1, ci == 0, P.apply, &fl, &nt);
     }
     P.flops_apply = fl;
+    P.flops_useful = useful;
     P.n_tasks_apply = nt;
     for (auto& L : P.apply) P.n_tiles_apply += L.ntile;
 
@@ -2025,6 +2060,7 @@ static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
         o_ws += P.ws_doubles;
         o_tab += (int64_t)P.coef.size();
         M.flops_apply += P.flops_apply;
+        M.flops_useful = std::max(M.flops_useful, 0.0) + (P.flops_useful < 0 ? P.flops_apply : P.flops_useful);
         M.flops_prepare += P.flops_prepare;
         M.bytes_apply += P.bytes_apply;
         M.n_tasks_apply += P.n_tasks_apply;
@@ -2406,6 +2442,7 @@ int hx_plan_get_info(const hx_plan* plan, hx_plan_info* info) {
     info->table_bytes = P->table_bytes;
     info->ws_bytes = std::max<int64_t>(P->ws_doubles * 8, 256);
     info->flops_apply = P->flops_apply;
+    info->flops_useful = P->flops_useful < 0 ? P->flops_apply : P->flops_useful;
     info->flops_prepare = P->flops_prepare;
     info->bytes_apply = P->bytes_apply;
     info->n_tasks = P->n_tasks_apply;

@@ -180,7 +180,8 @@ def test_plan_rejects_unsorted_bond():
 
 
 def _count_flops(lbond, rbond, Ldq, Rdq, W1, W2):
-    """Independent count of 2 m n k over the two block-GEMM rounds."""
+    """Independent count of 2 m n k over the two block-GEMM rounds, counting only
+    intermediate blocks (il, s1, s2', r') that the second round reads."""
     lidx = {q: i for i, (q, _) in enumerate(lbond)}
     ridx = {q: i for i, (q, _) in enumerate(rbond)}
     SQ = M.SITE_QN
@@ -198,11 +199,17 @@ def _count_flops(lbond, rbond, Ldq, Rdq, W1, W2):
     psi = two_site_blocks(lbond, rbond)
     fl = 0.0
     for b in set(left) & set(right):
+        read = set()
+        for (so, si), as_ in left[b].items():
+            dq = Ldq[next(iter(as_))]
+            for il, (q, _) in enumerate(lbond):
+                if (q[0] + dq[0], q[1] + dq[1]) in lidx:
+                    read.add((il, si))
         tb = set()
         for (so, si), cs in right[b].items():
             dq = Rdq[next(iter(cs))]
             for (il, s1, s2, ir) in psi:
-                if s2 != si:
+                if s2 != si or (il, s1) not in read:
                     continue
                 q = rbond[ir][0]
                 irp = ridx.get((q[0] + dq[0], q[1] + dq[1]))
@@ -232,7 +239,8 @@ def test_plan_flop_count_matches_independent_count():
         W1, W2 = M.site_entries(m, i), M.site_entries(m, i + 1)
         p = X.HeffPlan(b[i], b[i + 2], m.dq[i], m.dq[i + 1], m.dq[i + 2], W1, W2)
         ref = _count_flops(b[i], b[i + 2], [tuple(x) for x in m.dq[i]], [tuple(x) for x in m.dq[i + 2]], W1, W2)
-        assert p.info.flops_apply == pytest.approx(ref, rel=1e-12)
+        assert p.info.flops_useful == pytest.approx(ref, rel=1e-12)
+        assert p.info.flops_useful <= p.info.flops_apply < 1.1 * p.info.flops_useful
         assert p.info.psi_nnz == sum(b[i][k[0]][1] * b[i + 2][k[3]][1] for k in two_site_blocks(b[i], b[i + 2]))
 
 
