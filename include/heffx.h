@@ -356,6 +356,30 @@ int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, v
 int hx_heff_apply_bf16(const hx_plan* plan, const float* L32, const float* R32, void* ws32, const float* psi32,
                        float* sigma32, hx_stream stream);
 
+/* ---- no-allocation sigma-vector ------------------------------------------------ */
+
+/* Size of the library's static device scratch array (per GPU, held until the process
+ * ends). */
+#define HX_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sigma = H_eff psi of an uploaded
+ * sigma-vector plan from L and R directly -- hx_heff_prepare then hx_heff_apply --
+ * with the workspace (mixed operators, intermediates, split-K partials) in a static
+ * device array of HX_NOALLOC_SCRATCH_BYTES owned by the library instead of a caller
+ * buffer.  Same kernels and summation order as prepare + apply, so sigma is bitwise
+ * that of the two calls.  The caller passes L, R, psi and sigma (device, the layouts
+ * of hx_heff_apply); sigma is overwritten.  Calls no hipMalloc / hipFree and issues
+ * no memset (nothing in the scratch needs clearing).  HX_EINVAL if the plan's
+ * ws_bytes exceed HX_NOALLOC_SCRATCH_BYTES, for a plan that is not a sigma-vector
+ * plan, a plan not uploaded, or null operands of nonzero length.  All calls on one
+ * GPU share that GPU's scratch array: calls that overlap in time on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.  The first
+ * call on a device looks up the array's device address (hipGetSymbolAddress) with
+ * that device current. */
+int hx_heff_apply_noalloc(const hx_plan* plan, const double* L, const double* R, const double* psi,
+                          double* sigma, hx_stream stream);
+
 /* ---- Davidson (Davidson 1975; the eigensolver of the sweep) ----------------- */
 
 /* Workspace (bytes) of hx_davidson_step for vectors of length n and basis size <= kmax. */

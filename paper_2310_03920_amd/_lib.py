@@ -25,7 +25,7 @@ EXPORTED = (
     "hx_heff_plan_batch", "hx_batch_offsets", "hx_heff_graph_create", "hx_graph_launch", "hx_graph_destroy",
     "hx_heff_vjp_plan_create", "hx_heff_apply_backward", "hx_heff_apply_bf16", "hx_davidson_restart2",
     "hx_heff1_plan_create", "hx_psi1_layout", "hx_heff1_vjp_plan_create", "hx_gather_index",
-    "hx_scatter_index", "hx_axpy", "hx_heff_apply_backward_f32",
+    "hx_scatter_index", "hx_axpy", "hx_heff_apply_backward_f32", "hx_heff_apply_noalloc",
     "hx_last_error",
 )
 
@@ -85,6 +85,7 @@ def lib():
     L.hx_heff_prepare.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.hx_heff_apply.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.hx_heff_diag.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
+    L.hx_heff_apply_noalloc.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.hx_env_update.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]
     L.hx_davidson_ws_bytes.argtypes = [c_int64, c_int32]
     L.hx_davidson_ws_bytes.restype = c_int64
@@ -493,6 +494,15 @@ class HeffPlan(Plan):
         self._uploaded("heff_apply")
         check(lib().hx_heff_apply(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(psi), _ptr(sigma), _stream()),
               "heff_apply")
+
+    def apply_noalloc(self, L, R, psi, sigma):
+        """prepare + apply with the library's static scratch array as workspace (no
+        device allocation in the call; calls on one GPU must not overlap)."""
+        self._check_vecs(psi, sigma, env=self._env_items(L, R))
+        if self.tables is None:
+            raise RuntimeError("heff_apply_noalloc: upload the plan to a device first")
+        check(lib().hx_heff_apply_noalloc(self.h, _ptr(L), _ptr(R), _ptr(psi), _ptr(sigma), _stream()),
+              "heff_apply_noalloc")
 
     def diag(self, L, R, out):
         nd = int(self.info.psi_nnz) // max(getattr(self, "n_roots", 1), 1)

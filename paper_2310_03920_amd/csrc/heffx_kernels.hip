@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <type_traits>
 #include <cstdio>
 #include <string>
@@ -1502,6 +1503,92 @@ void hx_graph_destroy(hx_graph* graph) {
     if (graph->e) (void)hipGraphExecDestroy(graph->e);
     if (graph->g) (void)hipGraphDestroy(graph->g);
     delete graph;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- no-allocation sigma-vector
+//
+// hx_heff_apply_noalloc: prepare + apply with the workspace in a fixed device array of
+// this file instead of a caller buffer, for callers that cannot allocate.  The array
+// is a device symbol: its host-side name is not a device address, so the address is
+// taken once per device with hipGetSymbolAddress and only that address reaches the
+// kernels.
+
+static __device__ __align__(256) double scratch[HX_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the scratch array on the current device (looked up on the first
+// call on that device).
+static int scratch_on_current_device(void** out) {
+    int dev = -1;
+    int rc = hip_check(hipGetDevice(&dev), "heff_apply_noalloc: current device");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("heff_apply_noalloc: device index out of range");
+        return HX_EUNSUP;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if ((rc = hip_check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "heff_apply_noalloc: scratch address")))
+            return rc;
+        if (!ptr) {
+            set_error("heff_apply_noalloc: scratch address is null");
+            return HX_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return HX_OK;
+}
+
+extern "C" {
+
+int hx_heff_apply_noalloc(const hx_plan* plan, const double* L, const double* R, const double* psi, double* sigma,
+                          hx_stream stream) {
+    if (!plan) {
+        set_error("heff_apply_noalloc: null plan");
+        return HX_EINVAL;
+    }
+    const Plan* P = reinterpret_cast<const Plan*>(plan);
+    if (P->kind != PK_HEFF) {
+        set_error("heff_apply_noalloc: needs a sigma-vector plan");
+        return HX_EINVAL;
+    }
+    const int64_t need = P->ws_doubles * (int64_t)sizeof(double);
+    if (need > (int64_t)HX_NOALLOC_SCRATCH_BYTES) {
+        set_error("heff_apply_noalloc: the plan's workspace (" + std::to_string(need) +
+                  " bytes) exceeds the static scratch of " + std::to_string((long long)HX_NOALLOC_SCRATCH_BYTES) +
+                  " bytes (use hx_heff_prepare + hx_heff_apply with a caller workspace)");
+        return HX_EINVAL;
+    }
+    int rc = check_ready(plan, PK_HEFF);
+    if (rc) return rc;
+    if ((P->psi_nnz && (!psi || !sigma)) || (P->in_nnz && !L) || (P->in2_nnz && !R)) {
+        set_error("heff_apply_noalloc: null operand");
+        return HX_EINVAL;
+    }
+    if (P->psi_nnz && psi == sigma) {
+        set_error("heff_apply_noalloc: psi and sigma must not alias");
+        return HX_EINVAL;
+    }
+    void* ws = nullptr;
+    if ((rc = scratch_on_current_device(&ws))) return rc;
+    // every region of the workspace (mixed operators, intermediates, split-K partials)
+    // is written before it is read within this call: nothing needs clearing
+    hipStream_t s = s_of(stream);
+    Bases B = make_bases(P, psi, sigma, L, R, ws);
+    for (const Launch& l : P->prep)
+        if ((rc = launch_gemm(P, l, B, s))) return rc;
+    for (const Launch& l : P->apply)
+        if ((rc = launch_gemm(P, l, B, s))) return rc;
+    return HX_OK;
 }
 
 }  // extern "C"

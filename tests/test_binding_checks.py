@@ -98,3 +98,17 @@ def test_davidson_step_refuses_bad_shapes():
         X.davidson_step(n, 2, kmax, V[:, :5], S, v, 1e-8, v, v, v, v, v)
     with pytest.raises(ValueError, match="diag: .* elements"):
         X.davidson_step(n, 2, kmax, V, S, v[:3], 1e-8, v, v, v, v, v)
+
+
+def test_noalloc_entry_point_rejects_a_workspace_above_its_static_scratch():
+    """The no-allocation sigma-vector refuses plans whose workspace exceeds the
+    library's static scratch (64 MiB) before touching the device."""
+    K, i = 16, 7
+    m = M.build_nc_mpo(*make_integrals(K, seed=0))
+    b = bond_sector_tables(K, K, 0, 256)
+    p = X.HeffPlan(b[i], b[i + 2], m.dq[i], m.dq[i + 1], m.dq[i + 2], M.site_entries(m, i),
+                   M.site_entries(m, i + 1))
+    assert p.info.ws_bytes > 64 << 20
+    rc = X.lib().hx_heff_apply_noalloc(p.h, None, None, None, None, None)
+    assert rc == X.HX_EINVAL
+    assert "exceeds the static scratch" in X.lib().hx_last_error().decode()
