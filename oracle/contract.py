@@ -213,3 +213,78 @@ def sigma_rows(lbond, rbond, L, W1e, W2e, R, psi, rows):
                             acc[(s2p, irp)] = acc.get((s2p, irp), 0.0) + op[s2p, s2] * contrib
         out[(ilp, s1p, x)] = acc
     return out
+
+
+def env_rows_left(bond_in, bond_out, L, We, A, rows):
+    """Selected rows of the left update L'_b[m, n] = sum_{a,s,t,x,y} A[x,s,m] L_a[x,y]
+    W_ab[s,t] A[y,t,n], at any size, straight from the block formats.
+
+    bond_in: bond k (L's bond); bond_out: bond k+1; L: environment on bond_in; We: MPO
+    entries (a, b, op) of site k; A: site tensor {(il, s, iq): block (dim il x dim iq)}.
+    rows: list of (b, iq, m) -- output operator, its row sector on bond_out, row.
+    Returns {(b, iq, m): {iq_n: row vector over sector iq_n}}; sums run over the MPO
+    entries in order, then s, t, then the blocks of A in key order."""
+    by_b = {}
+    for a, b, op in We:
+        by_b.setdefault(b, []).append((a, op))
+    idx_in = {q: j for j, (q, _) in enumerate(bond_in)}
+    out = {}
+    for (b, iq, m) in rows:
+        acc = {}
+        for a, op in by_b.get(b, []):
+            dq = L[a]["dq"]
+            for (ilx, s, iqm), blk in A.items():
+                if iqm != iq:
+                    continue
+                u = blk[:, m]                                   # over x in sector ilx
+                q = bond_in[ilx][0]
+                ily = idx_in.get((q[0] - dq[0], q[1] - dq[1]))  # L_a maps ily -> ilx
+                if ily is None or ily not in L[a]["blocks"]:
+                    continue
+                v = u @ L[a]["blocks"][ily]                     # over y in sector ily
+                for t in range(4):
+                    w = op[s, t]
+                    if w == 0.0:
+                        continue
+                    for (ily2, t2, iqn), blk2 in A.items():
+                        if ily2 == ily and t2 == t:
+                            acc[iqn] = acc.get(iqn, 0.0) + w * (v @ blk2)
+        out[(b, iq, m)] = acc
+    return out
+
+
+def env_rows_right(bond_in, bond_out, R, We, B, rows):
+    """Selected rows of the right update R'_a[m, n] = sum_{b,s,t,x,y} B[m,s,x] W_ab[s,t]
+    R_b[x,y] B[n,t,y], at any size, straight from the block formats.
+
+    bond_in: bond k+1 (R's bond); bond_out: bond k; R: environment on bond_in; We: MPO
+    entries (a, b, op) of site k; B: site tensor {(iq, s, ix): block (dim iq x dim ix)}.
+    rows: list of (a, iq, m) -- output operator, its row sector on bond_out, row.
+    Returns {(a, iq, m): {iq_n: row vector over sector iq_n}}."""
+    by_a = {}
+    for a, b, op in We:
+        by_a.setdefault(a, []).append((b, op))
+    idx_in = {q: j for j, (q, _) in enumerate(bond_in)}
+    out = {}
+    for (a, iq, m) in rows:
+        acc = {}
+        for b, op in by_a.get(a, []):
+            dq = R[b]["dq"]
+            for (iqm, s, ix), blk in B.items():
+                if iqm != iq:
+                    continue
+                u = blk[m, :]                                   # over x in sector ix
+                q = bond_in[ix][0]
+                iy = idx_in.get((q[0] - dq[0], q[1] - dq[1]))   # R_b maps iy -> ix
+                if iy is None or iy not in R[b]["blocks"]:
+                    continue
+                v = u @ R[b]["blocks"][iy]                      # over y in sector iy
+                for t in range(4):
+                    w = op[s, t]
+                    if w == 0.0:
+                        continue
+                    for (iqn, t2, iy2), blk2 in B.items():
+                        if iy2 == iy and t2 == t:
+                            acc[iqn] = acc.get(iqn, 0.0) + w * (blk2 @ v)
+        out[(a, iq, m)] = acc
+    return out

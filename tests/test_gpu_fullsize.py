@@ -88,6 +88,146 @@ def test_fullsize_sigma_rows_match_the_oracle(device, problem, budget_gb):
     del plan
 
 
+@pytest.mark.parametrize("mode,rtol", [("f32", 2e-4), ("bf16", 2e-2)])
+def test_fullsize_reduced_precision_sigma_rows_match_the_oracle(device, problem, mode, rtol):
+    """FP32 and BF16 block products (FP32 accumulation) at the benchmark shape and
+    launch configuration, against the FP64 oracle's rows: FP32 operands carry 2^-24
+    relative rounding, BF16 ones 2^-9 (operands and the stage-1 intermediate), with
+    FP32 accumulation over sums of up to ~10^4 products of random sign."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    p = problem
+    print(f"[full size] {mode} apply, variant 1, kseg 512, budget 1 GiB", flush=True)
+    mid = [tuple(x) for x in p["mpo"].dq[SITE + 1]]
+    plan = X.HeffPlan(p["lbB"], p["rbB"], p["Ldq"], mid, p["Rdq"], p["W1"], p["W2"],
+                      t_budget_bytes=1 << 30, split_kseg_min=512, kernel_variant=1).upload(device)
+    d = p["dev"]
+    plan.prepare(d["L"], d["R"])
+    plan.lower_f32(d["L"], d["R"])
+    psi32 = d["psi"].float()
+    sig32 = torch.full_like(psi32, float("nan"))
+    (plan.apply_bf16 if mode == "bf16" else plan.apply_f32)(psi32, sig32)
+    torch.cuda.synchronize()
+    got = X.unpack_psi(p["lbB"], p["rbB"], sig32.double().cpu().numpy())
+    scale = max(float(np.max(np.abs(v))) for r in p["ref"].values() for v in r.values())
+    worst = max(float(np.max(np.abs(got[(il, s1, s2, ir)][x] - vec)))
+                for (il, s1, x), cols in p["ref"].items() for (s2, ir), vec in cols.items())
+    print(f"[full size] {mode}: max |gpu - oracle| = {worst:.3e} (scale {scale:.3e}, ratio {worst / scale:.2e})",
+          flush=True)
+    assert worst <= rtol * scale
+    del plan
+
+
+def test_fullsize_environment_update_rows_match_the_oracle(device):
+    """The left environment update at the benchmark's middle site (site 17 of the
+    36-orbital chain, M = 1000, NC MPO: 2424 -> 2702 operators) with a seeded N(0,1)
+    environment and a seeded left-canonical site tensor, in the launch configuration
+    of the sweep engine, against the oracle's rows of L'_b by definition."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.engine import Engine
+    from paper_2310_03920_amd.mpo import build_nc_mpo, site_entries
+    from synth import random_left_canonical_mps
+    print("[full size] env update rows, 36 orbitals, M=1000, site 17", flush=True)
+    mpo = build_nc_mpo(*make_integrals(K, seed=0))
+    bonds = bond_sector_tables(K, K, 0, M, model="gaussian", width=1.0)
+    k = SITE
+    bi, bo = bonds[k], bonds[k + 1]
+    dqi, dqo = [tuple(x) for x in mpo.dq[k]], [tuple(x) for x in mpo.dq[k + 1]]
+    rng = np.random.default_rng(77)
+    Lenv = random_env(bi, dqi, rng)
+    A = random_left_canonical_mps(bonds, 3)[k]
+    biB, boB = X.Bond(bi), X.Bond(bo)
+    plan = X.EnvPlan(0, biB, boB, dqi, dqo, X.MpoSite(mpo.sites[k].rows, mpo.sites[k].cols, mpo.sites[k].mats),
+                     **Engine.PLAN_OPTS).upload(device)
+    Lt = torch.from_numpy(X.pack_env(biB, dqi, Lenv)).to(device)
+    At = torch.from_numpy(X.pack_site(biB, boB, A)).to(device)
+    out = torch.full((int(plan.info.out_nnz),), float("nan"), dtype=torch.float64, device=device)
+    plan.update(Lt, At, out)
+    torch.cuda.synchronize()
+    flat = out.cpu().numpy()
+    assert np.isfinite(flat).all()
+    op_off, blk_off = X.env_layout(boB, X.OpSet(dqo))
+    idx = {q: j for j, (q, _) in enumerate(bo)}
+    pick = np.random.default_rng(8)
+    rows = []
+    for b in (0, len(dqo) // 2, len(dqo) - 1, int(pick.integers(len(dqo)))):
+        dq = dqo[b]
+        dsts = [idx[(q[0] + dq[0], q[1] + dq[1])] for q, _ in bo if (q[0] + dq[0], q[1] + dq[1]) in idx]
+        iq = max(dsts, key=lambda j: bo[j][1])
+        rows += [(b, iq, 0), (b, iq, bo[iq][1] - 1)]
+    ref = contract.env_rows_left(bi, bo, Lenv, site_entries(mpo, k), A, rows)
+    worst, scale = 0.0, 0.0
+    for (b, iq, m), acc in ref.items():
+        for iqn, vec in acc.items():
+            o = int(blk_off[b, iqn])
+            g = flat[o + m * bo[iqn][1]:o + (m + 1) * bo[iqn][1]]
+            worst = max(worst, float(np.max(np.abs(g - vec))))
+            scale = max(scale, float(np.max(np.abs(vec))))
+    print(f"[full size] env rows {len(rows)}: max |gpu - oracle| = {worst:.3e} (scale {scale:.3e})", flush=True)
+    assert scale > 0 and worst <= 1e-11 * scale
+
+
+def _big_case(device, K_, M_, budget_gib, modes):
+    import time
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    from fullsize_data import compare_rows, middle_problem, sample_rows
+    t0 = time.time()
+    p = middle_problem(X, K_, M_)
+    rows = sample_rows(p["lb"], 4)
+    print(f"[full size] {K_} orbitals M={M_}: operands drawn in {time.time() - t0:.0f}s; oracle rows {rows}",
+          flush=True)
+    t0 = time.time()
+    ref = contract.sigma_rows(p["bonds"][p["i"]], p["bonds"][p["i"] + 2], p["L"], p["W1e"], p["W2e"], p["R"],
+                              p["psi"], rows)
+    print(f"[full size] oracle rows in {time.time() - t0:.0f}s", flush=True)
+    plan = X.HeffPlan(p["lb"], p["rb"], p["Ldq"], p["Mdq"], p["Rdq"], p["W1"], p["W2"],
+                      t_budget_bytes=int(budget_gib * (1 << 30)), split_kseg_min=512,
+                      kernel_variant=1).upload(device)
+    print(f"[full size] plan: {plan.info.n_chunks} chunks, {plan.info.flops_useful / 1e12:.2f} TFLOP", flush=True)
+    L = torch.from_numpy(p["Lf"]).to(device)
+    R = torch.from_numpy(p["Rf"]).to(device)
+    psi = torch.from_numpy(p["Pf"]).to(device)
+    plan.prepare(L, R)
+    res = {}
+    for mode in modes:
+        if mode == "f64":
+            sig = torch.full_like(psi, float("nan"))
+            plan.apply(L, R, psi, sig)
+            host = sig.cpu().numpy()
+        else:
+            if getattr(plan, "L32", None) is None:
+                plan.lower_f32(L, R)
+            s32 = torch.full_like(psi, float("nan"), dtype=torch.float32)
+            (plan.apply_bf16 if mode == "bf16" else plan.apply_f32)(psi.float(), s32)
+            host = s32.double().cpu().numpy()
+        torch.cuda.synchronize()
+        res[mode] = compare_rows(X, p["lb"], p["rb"], host, ref)
+        print(f"[full size] {K_}/{M_} {mode}: max |gpu - oracle| = {res[mode][0]:.3e} (scale {res[mode][1]:.3e})",
+              flush=True)
+    return res
+
+
+def test_fullsize_48_orbitals_m2000_sigma_rows_match_the_oracle(device):
+    """The batched-mode configuration's large instance: the middle of the 48-orbital
+    chain at M = 2000 (blocks up to 248 rows, MPO bond dimensions 4380 / 4754 / 5144,
+    26 intermediate chunks at a 4 GiB budget) in the profiled launch configuration,
+    FP64 / FP32 / BF16 block products against the oracle's rows."""
+    res = _big_case(device, 48, 2000, 4.0, ("f64", "f32", "bf16"))
+    for mode, tol in (("f64", 1e-11), ("f32", 2e-4), ("bf16", 2e-2)):
+        worst, scale = res[mode]
+        assert scale > 0 and worst <= tol * scale, mode
+
+
+def test_fullsize_36_orbitals_m2000_sigma_rows_match_the_oracle(device):
+    """The precision-mode configuration at its larger bond dimension (36 orbitals,
+    M = 2000, 2 GiB intermediate budget), FP64 against the oracle's rows."""
+    res = _big_case(device, 36, 2000, 2.0, ("f64",))
+    worst, scale = res["f64"]
+    assert scale > 0 and worst <= 1e-11 * scale
+
+
 def test_backward_at_config5_size_satisfies_euler_identities(device):
     """Adjoint at the middle of the 24-orbital chain, M = 500 (NC MPO, seeded N(0,1)
     environments, psi and cotangent g).  sigma is linear in each of psi, L, R, W1,

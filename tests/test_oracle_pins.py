@@ -414,3 +414,37 @@ def test_davidson_step_invariants_and_solve():
     e, xs, nmv, rn = davidson.solve(lambda v: H @ v, rng.standard_normal(n), d, tol=1e-10, kmax=8)
     assert rn < 1e-10
     assert abs(e - np.linalg.eigvalsh(H)[0]) < 1e-12
+
+
+def test_env_rows_match_dense_updates():
+    """Selected rows of both environment updates, from the block formats, equal the
+    dense definitions (themselves pinned by Kronecker brute force above)."""
+    rng = np.random.default_rng(9)
+    lb = [((0, 0), 2), ((1, 1), 2), ((1, -1), 1)]
+    nb = [((1, 1), 2), ((2, 0), 3), ((1, -1), 2), ((2, 2), 1)]
+    dqs = [(0, 0), (1, 1), (-1, 1)]
+    mid = [(0, 0), (1, -1), (0, 2)]
+    Le = random_env(lb, dqs, rng)
+    We = random_site_ops(dqs, mid, rng)
+    At = random_site_tensor(lb, nb, rng)
+    W = contract.dense_mpo(We, len(dqs), len(mid))
+    Lp = contract.env_update_left(contract.dense_env(Le, lb), W, mps.dense_site_tensor(At, lb, nb))
+    no, _ = mps.bond_offsets(nb)
+    rows = [(b, iq, m) for b in range(len(mid)) for iq, (_, d) in enumerate(nb) for m in range(d)]
+    got = contract.env_rows_left(lb, nb, Le, We, At, rows)
+    for (b, iq, m), acc in got.items():
+        full = np.zeros(Lp.shape[2])
+        for iqn, vec in acc.items():
+            full[no[iqn]:no[iqn] + len(vec)] += vec
+        np.testing.assert_allclose(full, Lp[b, no[iq] + m], atol=1e-12)
+    Re = random_env(nb, mid, rng)
+    Bt = random_site_tensor(lb, nb, rng)
+    Rp = contract.env_update_right(contract.dense_env(Re, nb), W, mps.dense_site_tensor(Bt, lb, nb))
+    lo, _ = mps.bond_offsets(lb)
+    rows = [(a, iq, m) for a in range(len(dqs)) for iq, (_, d) in enumerate(lb) for m in range(d)]
+    got = contract.env_rows_right(nb, lb, Re, We, Bt, rows)
+    for (a, iq, m), acc in got.items():
+        full = np.zeros(Rp.shape[2])
+        for iqn, vec in acc.items():
+            full[lo[iqn]:lo[iqn] + len(vec)] += vec
+        np.testing.assert_allclose(full, Rp[a, lo[iq] + m], atol=1e-12)
