@@ -93,7 +93,7 @@ typedef struct {
     int32_t kernel_variant;  /* block-GEMM pipeline: 0 = two LDS buffers, 16-deep K stages (default);
                                 1 = one LDS buffer, 16-deep (more workgroups per CU);
                                 2 = two LDS buffers, 8-deep (less K padding, more workgroups per CU);
-                                3 = as 1 with persistent workgroups that prefetch their next tile;
+                                3 = removed (persistent workgroups; rejected with HX_EINVAL);
                                 4, 5 = as 0, 1 with 128 x 32 tiles for narrow and 32 x 128 tiles for
                                 short blocks (one launch per tile shape);
                                 6 = as 1 with single-wave 32 x 32 tiles for blocks of at most

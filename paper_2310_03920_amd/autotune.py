@@ -2,8 +2,8 @@
 
 The kernel shape choices of a sigma-vector plan (hx_plan_opts) are tuned by
 measurement on the problem itself: the kernel variant (LDS buffering, 16- or
-8-deep K stages, persistent workgroups, and the tile shapes 64 x 64 / 128 x 32 /
-32 x 128), the minimum split-K segment and the intermediate budget (how many
+8-deep K stages, the tile shapes 64 x 64 / 128 x 32 / 32 x 128 and single-wave
+32 x 32 tiles), the minimum split-K segment and the intermediate budget (how many
 middle-bond operators share one T chunk).  The search is greedy coordinate descent from the defaults: each axis
 in turn is swept with the others fixed, and the best value kept.  Every
 candidate's sigma is checked against the default plan's result before its time
@@ -17,9 +17,6 @@ import os
 
 import numpy as np
 
-# Variant 3 (persistent workgroups) stays selectable by hand but is not searched:
-# it was never faster, and a since-removed generalisation of the kernel faulted
-# on its multi-tile path (see the design notes).
 AXES = (
     ("kernel_variant", (0, 1, 2, 4, 5, 6)),
     ("split_kseg_min", (512, 1024, 2048, 4096)),

@@ -10,6 +10,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libheffx.so")
 BUILD = os.path.join(HERE, "_build")
+PEAK = os.path.join(HERE, "mfma_peak")
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              # keep packed-FP32 instructions out of generated code
@@ -39,6 +40,8 @@ def build_library(verbose=True):
     tmp = LIB + ".tmp"
     _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs)
     os.replace(tmp, LIB)
+    # matrix-core throughput microbenchmark (roofline denominators measured on the GPU)
+    _run([hipcc] + [f for f in HIP_FLAGS if f != "-fPIC"] + ["-o", PEAK, os.path.join(CSRC, "mfma_peak.hip")])
     return LIB
 
 

@@ -124,14 +124,9 @@ constexpr int LDS_PAD = 1;
 // BF (T = float only): operands are rounded to BF16 at the LDS store and the
 // products run on v_mfma_f32_16x16x16_bf16 with FP32 accumulation; LDS then holds
 // each tile row's 16 k contiguously so a lane's 4 consecutive k are one 8-byte read.
-// PERS: persistent workgroups.  Workgroup w computes tiles w, w + G, w + 2G, ...
-// (G = grid size, a multiple of 8, so they all stay on the XCD the tile order chose)
-// and fetches the first K stage of its next tile during the last stage of the
-// current one, hiding the start-up latency of short-K tiles.
 // WR: waves stacked along the tile's rows (2: 64 x 64 tile, 4: 128 x 32, 1: 32 x 128);
 // each wave owns a 32 x 32 quadrant.
-template <typename T, bool TA, bool TB, int NSP, int KSV, int NBUF, bool BF = false, bool PERS = false,
-          int WR = 2>
+template <typename T, bool TA, bool TB, int NSP, int KSV, int NBUF, bool BF = false, int WR = 2>
 __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
                                               BasesT<T> B, int ntile) {
     using acc_t = typename std::conditional<std::is_same<T, double>::value, dbl4, flt4>::type;
@@ -169,8 +164,7 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     T ra[NEA], rb[NEB];
     T alpha = 0;
 
-    // Loader: the tile whose K stages are being fetched (the current one, or the next
-    // one during the current tile's last stage) and the stage held in ra / rb.
+    // Loader of the tile's K stages and the stage held in ra / rb.
     Cursor<T, TA, TB, NSP, KSV> cur;
     int lm = 0, ln = 0, lr0 = 0, lc0 = 0;       // extent and origin of the loader's tile
     int krem_ld = 0, m_ld = 0, n_ld = 0;         // valid depth / extent of the held stage
@@ -307,18 +301,13 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
 
     bind_loader(tl);
     if (tl.ktot > 0) load_stage();
-    for (;;) {
+    {
         const int m = tl.m, n = tl.n;
         const int nst = tl.ktot / KSV;
         // 16 x 16 MFMA blocks wholly outside the tile's extent are skipped (wave-uniform
         // branches), so matrix-core work follows the block shape at 16 x 16 granularity
         const bool r1 = wr0 + 16 < m, c1 = wc0 + 16 < n;
         const bool any = wr0 < m && wc0 < n;
-        const int tn = t + (int)gridDim.x;
-        const bool has_next = PERS && tn < ntile;
-        Tile nx = tl;
-        if (has_next) nx = tiles[tn];
-        bool next_loaded = false;
         acc00 = acc_t{0, 0, 0, 0};
         acc01 = acc_t{0, 0, 0, 0};
         acc10 = acc_t{0, 0, 0, 0};
@@ -329,13 +318,7 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
             __syncthreads();
             for (int s = 0; s < nst; ++s) {
                 const int buf = NBUF == 2 ? (s & 1) : 0;
-                if (s + 1 < nst) {
-                    load_stage();
-                } else if (has_next && nx.ktot > 0) {
-                    bind_loader(nx);  // first stage of the next tile, in flight across this one
-                    load_stage();
-                    next_loaded = true;
-                }
+                if (s + 1 < nst) load_stage();
                 mma_stage(buf, ACT, R1, C1);
                 if constexpr (NBUF == 2) {
                     if (s + 1 < nst) store_stage(buf ^ 1);
@@ -383,13 +366,6 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         put(acc01, wr0, wc0 + 16);
         put(acc10, wr0 + 16, wc0);
         put(acc11, wr0 + 16, wc0 + 16);
-        if (!has_next) break;
-        t = tn;
-        tl = nx;
-        if (!next_loaded) {
-            bind_loader(tl);
-            if (tl.ktot > 0) load_stage();
-        }
     }
 }
 
@@ -856,24 +832,23 @@ static Bases make_bases(const Plan* P, const double* psi, double* out, const dou
     return b;
 }
 
-template <typename T, int NSP, int KSV, int NBUF, bool BF = false, bool PERS = false, int WR = 2>
+template <typename T, int NSP, int KSV, int NBUF, bool BF = false, int WR = 2>
 static int launch_kind(int kind, int64_t ntile, const Tile* tiles, const Task* tasks, const BasesT<T>& B,
                        hipStream_t s) {
     const dim3 block(256);
-    // persistent: 6 resident workgroups per CU on 256 CUs (a multiple of the 8 XCDs)
-    const dim3 grid((unsigned)(PERS ? std::min<int64_t>(ntile, 256 * 6) : ntile));
+    const dim3 grid((unsigned)ntile);
     const int nt = (int)ntile;
     switch (kind) {
         case NN:
-            hipLaunchKernelGGL((bsgemm<T, false, false, NSP, KSV, NBUF, BF, PERS, WR>), grid, block, 0, s, tiles,
+            hipLaunchKernelGGL((bsgemm<T, false, false, NSP, KSV, NBUF, BF, WR>), grid, block, 0, s, tiles,
                                tasks, B, nt);
             return HX_OK;
         case NT:
-            hipLaunchKernelGGL((bsgemm<T, false, true, NSP, KSV, NBUF, BF, PERS, WR>), grid, block, 0, s, tiles,
+            hipLaunchKernelGGL((bsgemm<T, false, true, NSP, KSV, NBUF, BF, WR>), grid, block, 0, s, tiles,
                                tasks, B, nt);
             return HX_OK;
         case TN_:
-            hipLaunchKernelGGL((bsgemm<T, true, false, NSP, KSV, NBUF, BF, PERS, WR>), grid, block, 0, s, tiles,
+            hipLaunchKernelGGL((bsgemm<T, true, false, NSP, KSV, NBUF, BF, WR>), grid, block, 0, s, tiles,
                                tasks, B, nt);
             return HX_OK;
         default:
@@ -913,11 +888,11 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
         constexpr bool BFv = decltype(BFC)::value;
         switch (L.shape) {
             case SH_TALL:
-                return launch_kind<T, NSP, 16, NB, BFv, false, 4>(L.kind, nt, tiles, tasks, B, s);
+                return launch_kind<T, NSP, 16, NB, BFv, 4>(L.kind, nt, tiles, tasks, B, s);
             case SH_WIDE:
-                return launch_kind<T, NSP, 16, NB, BFv, false, 1>(L.kind, nt, tiles, tasks, B, s);
+                return launch_kind<T, NSP, 16, NB, BFv, 1>(L.kind, nt, tiles, tasks, B, s);
             default:
-                return launch_kind<T, NSP, 16, NB, BFv, false, 2>(L.kind, nt, tiles, tasks, B, s);
+                return launch_kind<T, NSP, 16, NB, BFv, 2>(L.kind, nt, tiles, tasks, B, s);
         }
     };
     using One = std::integral_constant<int, 1>;
@@ -935,9 +910,6 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
                     return HX_EUNSUP;
                 }
                 rk = shaped(One{}, BFc{});
-                break;
-            case 3:
-                rk = launch_kind<T, NSP, 16, 1, true, true>(L.kind, nt, tiles, tasks, B, s);
                 break;
             case 0:
             case 4:
@@ -957,9 +929,6 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
             break;
         case 2:
             rk = launch_kind<T, NSP, 8, 2>(L.kind, nt, tiles, tasks, B, s);
-            break;
-        case 3:
-            rk = launch_kind<T, NSP, 16, 1, false, true>(L.kind, nt, tiles, tasks, B, s);
             break;
         case 6:
             if (L.shape == SH_SMALL) {

@@ -465,8 +465,9 @@ static inline int32_t kpad(int32_t k, int ks) { return (k + ks - 1) / ks * ks; }
 static int apply_opts(Plan& P, const hx_plan_opts* o) {
     if (o && o->split_kseg_min > 0) P.split_kseg_min = o->split_kseg_min;
     const int v = o ? o->kernel_variant : 0;
-    if (v < 0 || v > 6) {
-        set_error("plan options: kernel_variant must be 0 .. 6");
+    if (v < 0 || v > 6 || v == 3) {
+        set_error(v == 3 ? "plan options: kernel_variant 3 (persistent workgroups) was removed"
+                         : "plan options: kernel_variant must be 0 .. 6");
         return HX_EINVAL;
     }
     P.variant = v;

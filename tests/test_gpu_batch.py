@@ -61,10 +61,10 @@ def _individual(device, plan, arrs, f32=False):
     return res
 
 
-@pytest.mark.parametrize("variant", [0, 3, 5, 6])
+@pytest.mark.parametrize("variant", [0, 5, 6])
 def test_batched_apply_and_diag_match_instances_bitwise(device, variant):
-    """Variant 3 (persistent workgroups): the batched stage-1 launch has more tiles
-    (2219) than workgroups (1536), so workgroups run several tiles and prefetch."""
+    """Each instance of a batched plan gives, bit for bit, its own plan's sigma and
+    diag, in FP64 and FP32, for the two-buffer, tile-shape and single-wave kernels."""
     import torch
     from paper_2310_03920_amd import _lib as X
     print(f"[batch] 5 instances, f64 + f32, variant {variant}", flush=True)

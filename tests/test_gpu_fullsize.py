@@ -61,16 +61,16 @@ def problem(device):
                 rows=rows, ref=ref)
 
 
-@pytest.mark.parametrize("budget_gb", [2.0, 1.0])
-def test_fullsize_sigma_rows_match_the_oracle(device, problem, budget_gb):
+@pytest.mark.parametrize("budget_gb,variant", [(2.0, 1), (1.0, 1)])
+def test_fullsize_sigma_rows_match_the_oracle(device, problem, budget_gb, variant):
     import torch
     from paper_2310_03920_amd import _lib as X
     p = problem
-    print(f"[full size] apply, variant 1, kseg 512, budget {budget_gb} GiB", flush=True)
+    print(f"[full size] apply, variant {variant}, kseg 512, budget {budget_gb} GiB", flush=True)
     mid = [tuple(x) for x in p["mpo"].dq[SITE + 1]]
     plan = X.HeffPlan(p["lbB"], p["rbB"], p["Ldq"], mid, p["Rdq"], p["W1"], p["W2"],
                       t_budget_bytes=int(budget_gb * (1 << 30)), split_kseg_min=512,
-                      kernel_variant=1).upload(device)
+                      kernel_variant=variant).upload(device)
     d = p["dev"]
     plan.prepare(d["L"], d["R"])
     sigma = torch.full_like(d["psi"], float("nan"))

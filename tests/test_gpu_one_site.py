@@ -25,7 +25,7 @@ def _check(got, ref_dense, lb, rb):
         assert np.abs(blk - ref).max() <= RTOL * scale, (il, s, ir)
 
 
-@pytest.mark.parametrize("seed,big,variant", [(0, False, 0), (1, True, 1), (2, True, 3), (2, True, 4)])
+@pytest.mark.parametrize("seed,big,variant", [(0, False, 0), (1, True, 1), (2, True, 5), (2, True, 4)])
 def test_one_site_apply_and_diag_random_operands(device, seed, big, variant):
     import torch
     from paper_2310_03920_amd import _lib as X

@@ -329,7 +329,16 @@ def test_autotune_coordinate_search_finds_separable_minimum():
     assert best == {"kernel_variant": 1, "split_kseg_min": 1024, "t_budget_bytes": 1 << 31}
     # start + the other values of each axis, no repeats
     assert len(calls) == len(seen) == 1 + sum(len(v) - 1 for _, v in A.AXES)
-    assert all(c["kernel_variant"] != 3 for c in calls)  # the persistent variant is not searched
+    assert all(c["kernel_variant"] != 3 for c in calls)  # the removed persistent variant is not searched
+
+
+def test_removed_persistent_variant_is_rejected():
+    K, i = 4, 1
+    m = M.build_nc_mpo(*make_integrals(K, seed=0))
+    b = bond_sector_tables(K, K, 0, 16)
+    with pytest.raises(RuntimeError, match="persistent workgroups"):
+        X.HeffPlan(b[i], b[i + 2], m.dq[i], m.dq[i + 1], m.dq[i + 2], M.site_entries(m, i),
+                   M.site_entries(m, i + 1), kernel_variant=3)
 
 
 def test_autotune_signature_depends_on_shape():
