@@ -463,6 +463,110 @@ def bench_sweep(args):
         "passes": passes, "peak_gpu_gb": torch.cuda.max_memory_allocated() / 1e9}))
 
 
+def mixed_compare(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device, seeds=5):
+    """Mixed-precision Davidson against plain FP64 at equal accuracy, at the middle
+    step: from `seeds` warm starts (each the Ritz vector of an untimed FP64 pre-solve
+    from its own seeded random vector), solve to |r| <= tol with FP64 sigma-vectors,
+    and with FP32 / BF16 sigma-vectors followed by FP64 refinement; time each solve
+    (sigma-vectors and Davidson steps) and compare its energy with a tight FP64
+    reference.  Prints one JSON line; `value` is FP64 time / best mixed time."""
+    import torch
+    from paper_2310_03920_amd.dmrg import PRECISIONS, Davidson
+    from synth.blocks import random_psi
+    plan = X.HeffPlan(bonds[i], bonds[i + 2], mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2],
+                      X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats),
+                      X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats),
+                      **opts).upload(device)
+    info = plan.info
+    n = int(info.psi_nnz)
+    lb, rb = X.Bond(bonds[i]), X.Bond(bonds[i + 2])
+    diag = torch.empty(n, dtype=torch.float64, device=device)
+    plan.prepare(Lenv, Renv)
+    plan.diag(Lenv, Renv, diag)
+    plan.lower_f32(Lenv, Renv)
+    dav = Davidson(n, args.kmax, device)
+    v32 = torch.empty(n, dtype=torch.float32, device=device)
+    s32 = torch.empty(n, dtype=torch.float32, device=device)
+
+    def mv(v, out):
+        plan.apply(Lenv, Renv, v, out)
+
+    def low(mode):
+        ap = plan.apply_bf16 if mode == "bf16" else plan.apply_f32
+
+        def mv_low(v, out):
+            X.convert_f64_f32(v, v32)
+            ap(v32, s32)
+            X.convert_f32_f64(s32, out)
+        return mv_low
+
+    # per-sigma times of each precision (HIP events around 10 applies each)
+    psi_t = torch.from_numpy(X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2], np.random.default_rng(1)))).to(device)
+    out_t = torch.empty_like(psi_t)
+    sig_ms = {}
+    for mode, fn in (("f64", mv), ("f32", low("f32")), ("bf16", low("bf16"))):
+        fn(psi_t, out_t)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        for _ in range(10):
+            fn(psi_t, out_t)
+        e.record()
+        e.synchronize()
+        sig_ms[mode] = s.elapsed_time(e) / 10
+    log(f"sigma-vector ms: {sig_ms}")
+    starts = []
+    for sd in range(seeds):
+        p0 = torch.from_numpy(X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2],
+                                                           np.random.default_rng(100 + sd)))).to(device)
+        _, r_pre, _ = dav.solve(mv, p0, diag, tol=1e-12, max_iter=args.pre_iter)
+        starts.append((dav.x.clone(), r_pre))
+    e_ref, r_ref, n_ref = dav.solve(mv, starts[0][0], diag, tol=1e-10, max_iter=800)
+    log(f"reference E = {e_ref:.12f} (|r| {r_ref:.1e}, {n_ref} sigma-vectors); warm starts |r| = "
+        f"{[round(r, 5) for _, r in starts]}")
+    runs = {"f64": [], "f32": [], "bf16": []}
+    for sd, (x0, r_pre) in enumerate(starts):
+        for mode in ("f64", "f32", "bf16"):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            if mode == "f64":
+                th, rn, nh = dav.solve(mv, x0, diag, tol=args.tol, max_iter=args.max_iter)
+                nl = 0
+            else:
+                th, rn, nl, nh = dav.solve_mixed(low(mode), mv, x0, diag, tol=args.tol, max_iter=args.max_iter,
+                                                 **PRECISIONS[mode])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            runs[mode].append({"seed": sd, "s": dt, "energy_err": abs(th - e_ref), "rnorm": rn, "low_sigma": nl,
+                               "f64_sigma": nh, "f64_equivalent_sigma": nh + nl * sig_ms[mode] / sig_ms["f64"]})
+            log(f"seed {sd} {mode}: {dt:.2f}s, |dE| {abs(th - e_ref):.1e}, |r| {rn:.1e}, sigma {nl} low + {nh} f64")
+    summ = {}
+    for mode, rs in runs.items():
+        ts = [r["s"] for r in rs]
+        summ[mode] = {"mean_s": float(np.mean(ts)), "min_s": float(np.min(ts)), "max_s": float(np.max(ts)),
+                      "mean_f64_equivalent_sigma": float(np.mean([r["f64_equivalent_sigma"] for r in rs])),
+                      "max_energy_err": float(max(r["energy_err"] for r in rs)),
+                      "max_rnorm": float(max(r["rnorm"] for r in rs))}
+    f64_mean = summ["f64"]["mean_s"]
+    spread = (summ["f64"]["max_s"] - summ["f64"]["min_s"]) / f64_mean
+    best = min(("f32", "bf16"), key=lambda m: summ[m]["mean_s"])
+    for mode in ("f32", "bf16"):
+        summ[mode]["speedup_vs_f64"] = f64_mean / summ[mode]["mean_s"]
+        summ[mode]["win_exceeds_f64_spread"] = bool(summ[mode]["mean_s"] < summ["f64"]["min_s"])
+    print(json.dumps({
+        "metric": "mixed-precision Davidson solve time vs FP64 at equal accuracy (middle step)",
+        "value": f64_mean / summ[best]["mean_s"], "unit": "x (FP64 time / best mixed time)", "n_gpus": 1,
+        "steps": seeds, "warmup": 0, "ms_per_step": 1e3 * summ[best]["mean_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": best, "data": "synthetic",
+        "config": {"workload": f"Davidson solves at sites ({i},{i + 1}) of the {mpo.K}-orbital chain, M={args.bond_dim}, "
+                               f"{seeds} seeded warm starts ({args.pre_iter} untimed FP64 iterations each), "
+                               f"to |r| <= {args.tol}",
+                   "sigma_ms": sig_ms, "reference_energy": e_ref, "reference_rnorm": r_ref,
+                   "f64_time_spread": spread, "plan_opts": opts, "autotune_s": tune_s,
+                   "precisions": {k: v for k, v in PRECISIONS.items()}},
+        "summary": summ, "runs": runs}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -478,11 +582,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["f64", "f32", "bf16"], default="f64",
                     help="precision of the block contractions; Davidson is FP64 in all")
-    ap.add_argument("--workload", choices=["middle", "batch", "apply", "sweep"], default="middle",
+    ap.add_argument("--workload", choices=["middle", "batch", "apply", "sweep", "mixed"], default="middle",
                     help="middle: one DMRG step at the chain's middle; batch: many small sigma-vectors; "
                          "apply: sigma-vectors only at the middle step (profiling), ending with a 512 MiB "
                          "device copy that calibrates HBM byte counters; sweep: whole two-site passes "
-                         "(24 orbitals, M=500 unless given)")
+                         "(24 orbitals, M=500 unless given); mixed: FP64 against FP32 / BF16 mixed-precision "
+                         "Davidson solves from 5 seeded warm starts at the middle step")
     ap.add_argument("--partition", choices=["nc", "nc-cn"], default="nc",
                     help="NC MPO at every cut (default), or NC up to the middle cut and CN after it")
     ap.add_argument("--instances", type=int, default=16)
@@ -539,6 +644,9 @@ def main():
     opts, tune_s = plan_options(args, X, mpo, bonds, i, Lenv, Renv, tb, device)
     if args.workload == "apply":
         apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device)
+        return
+    if args.workload == "mixed":
+        mixed_compare(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device)
         return
     t1 = time.time()
     plan = X.HeffPlan(bonds[i], bonds[i + 2], mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2],
