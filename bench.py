@@ -393,6 +393,9 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
     avg = float(np.mean(ms)) / 1e3
     peak = PEAKS[args.mode]
     achieved = info.flops_useful / avg / 1e12
+    parts = middle_bond_parts(args, X, mpo, bonds, i, Lenv, Renv, opts, psi, device) if args.bparts > 1 else None
+    # a plain device copy of known size (2^26 doubles read, 2^26 written) closes the
+    # run: the per-dispatch HBM counters of the sigma-vector are scaled by its counts
     src = torch.ones(1 << 26, dtype=torch.float64, device=device)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
@@ -412,7 +415,58 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
                    "apply_ms_each": ms, "plan_opts": opts, "autotune_s": tune_s},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None},
+        **({"middle_bond_parts": parts} if parts else {}),
     }), flush=True)
+
+
+def middle_bond_parts(args, X, mpo, bonds, i, Lenv, Renv, opts, psi, device):
+    """One GPU's share of the sigma-vector sharded over the MPO middle-bond index
+    (Sec. II.B.1): plans restricted to b = p (mod n) for p = 0..n-1, each timed
+    alone at the full operand shape, and the sum of the partial sigmas checked
+    against the whole.  FP64 only."""
+    import torch
+    if args.mode != "f64":
+        raise SystemExit("--bparts times the FP64 sigma-vector only")
+    W1 = X.MpoSite(mpo.sites[i].rows, mpo.sites[i].cols, mpo.sites[i].mats)
+    W2 = X.MpoSite(mpo.sites[i + 1].rows, mpo.sites[i + 1].cols, mpo.sites[i + 1].mats)
+    whole = torch.empty_like(psi)
+    ref = X.HeffPlan(bonds[i], bonds[i + 2], mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2], W1, W2,
+                     n_roots=args.roots, **opts).upload(device)
+    ref.prepare(Lenv, Renv)
+    ref.apply(Lenv, Renv, psi, whole)
+    del ref
+    total = torch.zeros_like(psi)
+    part = torch.empty_like(psi)
+    rows = []
+    for p in range(args.bparts):
+        plan = X.HeffPlan(bonds[i], bonds[i + 2], mpo.dq[i], mpo.dq[i + 1], mpo.dq[i + 2], W1, W2,
+                          n_roots=args.roots, b_part=p, b_nparts=args.bparts, **opts).upload(device)
+        plan.prepare(Lenv, Renv)
+        for _ in range(max(args.warmup, 1)):
+            plan.apply(Lenv, Renv, psi, part)
+        torch.cuda.synchronize()
+        total += part
+        ms = []
+        for _ in range(args.steps):
+            s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            s.record()
+            plan.apply(Lenv, Renv, psi, part)
+            e.record()
+            e.synchronize()
+            ms.append(s.elapsed_time(e))
+        t = float(np.mean(ms))
+        rows.append({"part": p, "ms": t, "tflop": plan.info.flops_useful / 1e12,
+                     "tflops_per_s": plan.info.flops_useful / t / 1e9})
+        log(f"middle-bond part {p}/{args.bparts}: {t:.2f} ms, {plan.info.flops_useful / 1e12:.3f} TFLOP")
+        del plan
+        torch.cuda.empty_cache()
+    err = float((total - whole).abs().max()) / float(whole.abs().max())
+    worst = max(r["ms"] for r in rows)
+    return {"n_parts": args.bparts, "rule": "b mod n_parts", "parts": rows, "max_part_ms": worst,
+            "sum_part_ms": sum(r["ms"] for r in rows),
+            "flop_imbalance": max(r["tflop"] for r in rows) / (sum(r["tflop"] for r in rows) / len(rows)),
+            "time_imbalance": worst / (sum(r["ms"] for r in rows) / len(rows)),
+            "sum_of_parts_rel_err": err}
 
 
 def bench_sweep(args):
@@ -593,6 +647,9 @@ def main():
     ap.add_argument("--instances", type=int, default=16)
     ap.add_argument("--roots", type=int, default=1, help="apply workload: vectors per sigma-vector call")
     ap.add_argument("--kseg", type=int, default=0, help="split-K minimum segment (0 = default)")
+    ap.add_argument("--bparts", type=int, default=1,
+                    help="apply workload, FP64: also time the sigma-vector restricted to b = p (mod n) "
+                         "for each of n middle-bond parts (one GPU's share of a sharded sigma)")
     ap.add_argument("--variant", type=int, default=None,
                     help="block-GEMM kernel variant (0 .. 6); default: chosen by the autotuner")
     ap.add_argument("--no-autotune", action="store_true",

@@ -106,7 +106,18 @@ typedef struct {
                                 off = the single-root offset of the column block; the second GEMM
                                 round runs on R times the columns.  diag stays single-root.  Adjoint
                                 plans need R = 1. */
-    int32_t reserved[5];
+    int32_t b_part;
+    int32_t b_nparts;        /* sigma-vector plans: with b_nparts > 1 the plan keeps only the terms of
+                                the middle-bond operators b with b mod b_nparts == b_part (the MPO
+                                column / row index shared by W1 and W2): prepare, apply and diag
+                                give that part's share, and the shares of the b_nparts parts sum to
+                                the whole -- the split of the sigma-vector over the paper's normal
+                                and complementary operators (Sec. II.B.1 (iii)) that several GPUs
+                                would each take one part of, with one sum of sigma afterwards.
+                                b_nparts 0 or 1 (and b_part 0) = all operators.  Other plan kinds:
+                                HX_EUNSUP for b_nparts > 1; HX_EINVAL for b_part outside
+                                [0, b_nparts). */
+    int32_t reserved[3];
 } hx_plan_opts;
 
 typedef struct {

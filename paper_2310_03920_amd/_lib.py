@@ -45,7 +45,7 @@ class HxMpoSite(ctypes.Structure):
 
 class HxPlanOpts(ctypes.Structure):
     _fields_ = [("t_budget_bytes", c_int64), ("split_kseg_min", c_int32), ("kernel_variant", c_int32),
-                ("n_roots", c_int32), ("reserved", c_int32 * 5)]
+                ("n_roots", c_int32), ("b_part", c_int32), ("b_nparts", c_int32), ("reserved", c_int32 * 3)]
 
 
 class HxPlanInfo(ctypes.Structure):
@@ -412,6 +412,7 @@ class Plan:
         self.info = info
         self.tables = None
         self.ws = None
+        self._ready = False
 
     def upload(self, device="cuda"):
         import torch
@@ -423,6 +424,7 @@ class Plan:
         check(lib().hx_plan_upload(self.h, c_void_p(self._tab_ptr), _stream()), "plan_upload")
         nws = max(int(self.info.ws_bytes) // 8, 1)
         self.ws = torch.empty(nws, dtype=torch.float64, device=device)
+        self._ready = False
         return self
 
     @property
@@ -432,6 +434,13 @@ class Plan:
     def _uploaded(self, what):
         if self.ws is None or self.tables is None:
             raise RuntimeError(f"{what}: upload the plan to a device first")
+
+    def _prepared(self, what):
+        """Sigma-vector, diagonal and adjoint calls read the mixed operators that
+        prepare() leaves in the workspace."""
+        self._uploaded(what)
+        if not self._ready:
+            raise RuntimeError(f"{what}: call prepare(L, R) first")
 
     def _lowered(self, what):
         if getattr(self, "L32", None) is None:
@@ -452,23 +461,25 @@ class Plan:
             pass
 
 
-def _opts(t_budget_bytes=0, split_kseg_min=0, kernel_variant=0, n_roots=1):
+def _opts(t_budget_bytes=0, split_kseg_min=0, kernel_variant=0, n_roots=1, b_part=0, b_nparts=1):
     o = HxPlanOpts()
     o.t_budget_bytes = int(t_budget_bytes)
     o.split_kseg_min = int(split_kseg_min)
     o.kernel_variant = int(kernel_variant)
     o.n_roots = int(n_roots)
+    o.b_part = int(b_part)
+    o.b_nparts = int(b_nparts)
     return o
 
 
 class HeffPlan(Plan):
     def __init__(self, lbond, rbond, Ldq, mid_dq, Rdq, W1, W2, t_budget_bytes=0, split_kseg_min=0,
-                 kernel_variant=0, n_roots=1):
+                 kernel_variant=0, n_roots=1, b_part=0, b_nparts=1):
         lb, rb = (b if isinstance(b, Bond) else Bond(b) for b in (lbond, rbond))
         Lo, Mo, Ro = OpSet(Ldq), OpSet(mid_dq), OpSet(Rdq)
         w1 = W1 if isinstance(W1, MpoSite) else MpoSite.from_entries(W1)
         w2 = W2 if isinstance(W2, MpoSite) else MpoSite.from_entries(W2)
-        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant, n_roots)
+        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant, n_roots, b_part, b_nparts)
         self.n_roots = int(n_roots)
         h = c_void_p()
         check(lib().hx_heff_plan_create(ctypes.byref(lb.c), ctypes.byref(rb.c), ctypes.byref(Lo.c),
@@ -482,6 +493,7 @@ class HeffPlan(Plan):
         self._check_env(L, R)
         self._uploaded("heff_prepare")
         check(lib().hx_heff_prepare(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _stream()), "heff_prepare")
+        self._ready = True
 
     def _check_vecs(self, psi, sigma, dtype="float64", env=()):
         n = int(self.info.psi_nnz)
@@ -491,7 +503,7 @@ class HeffPlan(Plan):
 
     def apply(self, L, R, psi, sigma):
         self._check_vecs(psi, sigma, env=self._env_items(L, R))
-        self._uploaded("heff_apply")
+        self._prepared("heff_apply")
         check(lib().hx_heff_apply(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(psi), _ptr(sigma), _stream()),
               "heff_apply")
 
@@ -507,14 +519,14 @@ class HeffPlan(Plan):
     def diag(self, L, R, out):
         nd = int(self.info.psi_nnz) // max(getattr(self, "n_roots", 1), 1)
         need_all(self.device, *self._env_items(L, R), (out, "diag", nd, "float64"))
-        self._uploaded("heff_diag")
+        self._prepared("heff_diag")
         check(lib().hx_heff_diag(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(out), _stream()), "heff_diag")
 
     # FP32 mode: operands rounded once per (L, R); Davidson stays FP64
     def lower_f32(self, L, R):
         import torch
         self._check_env(L, R)
-        self._uploaded("heff_lower_f32")
+        self._prepared("heff_lower_f32")
         dev = self.ws.device
         if getattr(self, "ws32", None) is None:
             self.ws32 = torch.empty(max(int(self.info.ws_bytes) // 8, 1), dtype=torch.float32, device=dev)
@@ -578,6 +590,7 @@ class HeffVjpPlan(Plan):
         self._check_env(L, R)
         self._uploaded("heff_prepare")
         check(lib().hx_heff_prepare(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _stream()), "heff_prepare")
+        self._ready = True
 
     def _check_backward(self, psi, g, g_psi, g_L, g_R, g_W1, g_W2, dtype, env=()):
         n = int(self.info.psi_nnz)
@@ -589,7 +602,7 @@ class HeffVjpPlan(Plan):
 
     def backward(self, L, R, psi, g, g_psi, g_L, g_R, g_W1, g_W2):
         self._check_backward(psi, g, g_psi, g_L, g_R, g_W1, g_W2, "float64", env=self._env_items(L, R))
-        self._uploaded("heff_apply_backward")
+        self._prepared("heff_apply_backward")
         check(lib().hx_heff_apply_backward(self.h, _ptr(L), _ptr(R), _ptr(self.ws), _ptr(psi), _ptr(g), _ptr(g_psi),
                                            _ptr(g_L), _ptr(g_R), _ptr(g_W1), _ptr(g_W2), _stream()),
               "heff_apply_backward")
@@ -670,11 +683,11 @@ class BatchPlan(HeffPlan):
 
 class EnvPlan(Plan):
     def __init__(self, direction, bond_in, bond_out, dq_in, dq_out, W, t_budget_bytes=0, split_kseg_min=0,
-                 kernel_variant=0):
+                 kernel_variant=0, b_part=0, b_nparts=1):
         bi, bo = (b if isinstance(b, Bond) else Bond(b) for b in (bond_in, bond_out))
         oi, oo = OpSet(dq_in), OpSet(dq_out)
         w = W if isinstance(W, MpoSite) else MpoSite.from_entries(W)
-        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant)
+        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant, 1, b_part, b_nparts)
         h = c_void_p()
         check(lib().hx_env_plan_create(int(direction), ctypes.byref(bi.c), ctypes.byref(bo.c), ctypes.byref(oi.c),
                                        ctypes.byref(oo.c), ctypes.byref(w.c), ctypes.byref(opts), ctypes.byref(h)),

@@ -160,6 +160,7 @@ struct Plan {
     int variant = 0;            // block-GEMM pipeline variant (see hx_plan_opts.kernel_variant)
     int kstage = 16;            // K-stage depth of that variant; task K is padded to it
     int n_roots = 1;            // vectors per sigma-vector call (roots side by side in column blocks)
+    int b_part = 0, b_nparts = 1;  // sigma-vector plans: only middle-bond indices b = b_part (mod b_nparts)
     int n_stages = 0;           // rounds emitted so far (Launch::stage)
     double flops_apply = 0, flops_prepare = 0, bytes_apply = 0;
     double flops_useful = -1;   // sigma plans: block-product work whose results sigma reads (< 0: = flops_apply)

@@ -478,6 +478,13 @@ static int apply_opts(Plan& P, const hx_plan_opts* o) {
         return HX_EINVAL;
     }
     P.n_roots = r;
+    const int np = o ? o->b_nparts : 0, pp = o ? o->b_part : 0;
+    if (np < 0 || (np > 1 && (pp < 0 || pp >= np)) || (np <= 1 && pp != 0)) {
+        set_error("plan options: need 0 <= b_part < b_nparts (or b_nparts <= 1 and b_part = 0)");
+        return HX_EINVAL;
+    }
+    P.b_nparts = np > 1 ? np : 1;
+    P.b_part = np > 1 ? pp : 0;
     return HX_OK;
 }
 
@@ -812,6 +819,15 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
         }
     }
     const std::vector<Entry>& e2 = one_site ? e2_one : e2_in;
+    // middle-bond part (hx_plan_opts.b_part / b_nparts): only the b dealt to this part
+    // get left mixers, so only they become active below
+    std::vector<Entry> e1_part;
+    const std::vector<Entry>* e1p = &e1;
+    if (P.b_nparts > 1) {
+        for (const Entry& e : e1)
+            if (e.tgt % P.b_nparts == P.b_part) e1_part.push_back(e);
+        e1p = &e1_part;
+    }
     const int R = P.n_roots;  // roots side by side in every column block (see heffx.h)
     P.psi_nnz = psi.nnz * R;
     P.in_nnz = Ll.op_off.back();
@@ -819,8 +835,13 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
 
     Mixer ML{&lb, &Lo, &Ll, SP_L, {}, {}, {}, 0, 0};
     Mixer MR{&rb, &Ro, &Rl, SP_R, {}, {}, {}, 0, 0};
-    build_mixer(ML, e1, (int)Mo.dq.size());
-    build_mixer(MR, e2, (int)Mo.dq.size());
+    build_mixer(ML, *e1p, (int)Mo.dq.size());
+    std::vector<Entry> e2_part;
+    if (P.b_nparts > 1) {
+        for (const Entry& e : e2)
+            if (e.tgt % P.b_nparts == P.b_part) e2_part.push_back(e);
+    }
+    build_mixer(MR, P.b_nparts > 1 ? e2_part : e2, (int)Mo.dq.size());
     int64_t ws = 0;
     ws = place_mixer(ML, ws);
     ws = place_mixer(MR, ws);
@@ -1320,6 +1341,10 @@ static int build_heff_vjp(Plan& P, const Bond& lb, const Bond& rb, const OpSet& 
         int rc0 = apply_opts(P, opts);
         if (rc0) return rc0;
     }
+    if (P.b_nparts != 1) {
+        set_error("vjp plan: middle-bond parts (b_nparts > 1) are for sigma-vector plans only");
+        return HX_EUNSUP;
+    }
     if (P.n_roots != 1) {
         set_error("vjp plan: n_roots must be 1");
         return HX_EUNSUP;
@@ -1790,6 +1815,10 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
     {
         int rc0 = apply_opts(P, opts);
         if (rc0) return rc0;
+    }
+    if (P.b_nparts != 1) {
+        set_error("env plan: middle-bond parts (b_nparts > 1) are for sigma-vector plans only");
+        return HX_EUNSUP;
     }
     EnvLayout Lin = env_layout(bin, oin), Lout = env_layout(bout, oout);
     SiteLayout S = dir == 0 ? site_layout(bin, bout) : site_layout(bout, bin);

@@ -304,3 +304,68 @@ def test_sigma_with_gpu_environments_equals_PtHP(device, i, switch):
     a = float(torch.dot(ft, st))
     b = float(torch.dot(hf, pt))
     assert abs(a - b) <= 1e-12 * (abs(a) + abs(b) + 1)
+
+
+@pytest.mark.parametrize("nparts", [3, 4])
+def test_middle_bond_parts_sum_to_sigma_and_match_the_oracle(device, nparts):
+    """Plans restricted to the middle-bond operators b = p (mod nparts): each part's
+    sigma and diag equal the block-sparse oracle's sum over the same b, and the parts
+    add up to the whole (the per-GPU share of a split over normal and complementary
+    operators, with one sum of sigma)."""
+    import torch
+    from oracle import blocks
+    from paper_2310_03920_amd import _lib as X
+    print(f"[b parts] {nparts}", flush=True)
+    lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = prob = _problem(4, True)
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
+    Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
+    pt = torch.from_numpy(X.pack_psi(lbB, rbB, psi)).to(device)
+    total = torch.zeros_like(pt)
+    dtotal = torch.zeros_like(pt)
+    full = _dense_sigma(*prob)
+    for p in range(nparts):
+        plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, kernel_variant=1, split_kseg_min=16,
+                          b_part=p, b_nparts=nparts).upload(device)
+        st = torch.full_like(pt, float("nan"))
+        dt = torch.full_like(pt, float("nan"))
+        plan.prepare(Lt, Rt)
+        plan.apply(Lt, Rt, pt, st)
+        plan.diag(Lt, Rt, dt)
+        torch.cuda.synchronize()
+        got = X.unpack_psi(lbB, rbB, st.cpu().numpy())
+        ref = blocks.heff_apply(lb, rb, L, W1, W2, R, psi, bsel=range(p, len(Mdq), nparts))
+        ref = {k: ref.get(k, np.zeros_like(v)) for k, v in full.items()}
+        scale = max(float(np.abs(v).max()) for v in full.values())
+        for k in full:
+            assert np.abs(got[k] - ref[k]).max() <= RTOL * scale, (p, k)
+        total += st
+        dtotal += dt
+    _close(X.unpack_psi(lbB, rbB, total.cpu().numpy()), full)
+    d = contract.heff_diag(contract.dense_env(L, lb), contract.dense_mpo(W1, len(Ldq), len(Mdq)),
+                           contract.dense_mpo(W2, len(Mdq), len(Rdq)), contract.dense_env(R, rb))
+    _close(X.unpack_psi(lbB, rbB, dtotal.cpu().numpy()), mps.two_site_blocks_from_dense(d, lb, rb, two_site_blocks(lb, rb)))
+
+
+def test_binding_refuses_apply_before_prepare(device):
+    """The mixed operators that sigma, diag and the adjoint read are written by
+    prepare(L, R); an uploaded plan that was never prepared is refused on the host."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = _problem(2)
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
+    Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
+    pt = torch.from_numpy(X.pack_psi(lbB, rbB, psi)).to(device)
+    st = torch.empty_like(pt)
+    plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2).upload(device)
+    for call in (lambda: plan.apply(Lt, Rt, pt, st), lambda: plan.diag(Lt, Rt, st),
+                 lambda: plan.lower_f32(Lt, Rt)):
+        with pytest.raises(RuntimeError, match="prepare"):
+            call()
+    plan.prepare(Lt, Rt)
+    plan.apply(Lt, Rt, pt, st)
+    plan.upload(device)  # a fresh workspace holds no mixed operators
+    with pytest.raises(RuntimeError, match="prepare"):
+        plan.apply(Lt, Rt, pt, st)
+    torch.cuda.synchronize()

@@ -87,3 +87,33 @@ def test_flop_count_equals_independent_and_plan_counts(i):
     assert fl[0] == pytest.approx(_count_flops(lb, rb, Ldq, Rdq, W1e, W2e), rel=1e-12)
     plan = X.HeffPlan(lb, rb, m.dq[i], m.dq[i + 1], m.dq[i + 2], W1e, W2e)
     assert fl[0] == pytest.approx(plan.info.flops_useful, rel=1e-12)
+
+
+def test_middle_bond_part_plans_split_the_work_of_the_whole():
+    """Plans restricted to b = p (mod n) split the useful block-product work of the
+    whole plan exactly (every product belongs to one b), and each part's count equals
+    the block-sparse oracle's own count over the same b; bad part options are refused."""
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.mpo import build_nc_mpo, site_entries
+    K, M, i, n = 8, 64, 3, 5
+    m = build_nc_mpo(*make_integrals(K, seed=0))
+    b = bond_sector_tables(K, K, 0, M)
+    lb, rb = b[i], b[i + 2]
+    W1e, W2e = site_entries(m, i), site_entries(m, i + 1)
+    args = (lb, rb, m.dq[i], m.dq[i + 1], m.dq[i + 2], W1e, W2e)
+    whole = X.HeffPlan(*args).info.flops_useful
+    rng = np.random.default_rng(2)
+    Ldq, Rdq = [tuple(x) for x in m.dq[i]], [tuple(x) for x in m.dq[i + 2]]
+    L, R, psi = random_env(lb, Ldq, rng), random_env(rb, Rdq, rng), random_psi(lb, rb, rng)
+    parts = 0.0
+    for p in range(n):
+        fp = X.HeffPlan(*args, b_part=p, b_nparts=n).info.flops_useful
+        fl = [0.0]
+        blocks.heff_apply(lb, rb, L, W1e, W2e, R, psi, bsel=range(p, len(m.dq[i + 1]), n), flops=fl)
+        assert fp == pytest.approx(fl[0], rel=1e-12)
+        parts += fp
+    assert parts == pytest.approx(whole, rel=1e-12)
+    with pytest.raises(RuntimeError, match="b_part"):
+        X.HeffPlan(*args, b_part=5, b_nparts=5)
+    with pytest.raises(RuntimeError, match="sigma-vector plans only"):
+        X.EnvPlan(0, b[i], b[i + 1], m.dq[i], m.dq[i + 1], W1e, b_part=1, b_nparts=2)
