@@ -41,7 +41,8 @@ PEAKS = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFL
 # read for a device copy of known size), per plan options (kernel_variant,
 # split_kseg_min, intermediate budget), with the summary they come from.  Only valid
 # for the kernel and plan builder they were taken with; other options report null.
-MEASURED_TRAFFIC = {(1, 512, 1 << 30): (77.24e9, "profiles/bsgemm_f64_apply_traffic_K36_M1000.md")}
+# (kernel_variant, split_kseg_min, intermediate budget, merged intermediates off)
+MEASURED_TRAFFIC = {(1, 512, 1 << 30, 1): (77.24e9, "profiles/bsgemm_f64_apply_traffic_K36_M1000.md")}
 
 
 def log(*a):
@@ -314,7 +315,8 @@ def plan_options(args, X, mpo, bonds, i, Lenv, Renv, tb, device):
     from paper_2310_03920_amd import autotune
     from synth.blocks import random_psi
     opts = {"t_budget_bytes": tb, "split_kseg_min": args.kseg or 2048,
-            "kernel_variant": 0 if args.variant is None else args.variant}
+            "kernel_variant": 0 if args.variant is None else args.variant,
+            "t_merge_off": int(args.no_t_merge)}
     if args.no_autotune:
         return opts, 0.0
     axes = [a for a in autotune.AXES if not (a[0] == "kernel_variant" and args.variant is not None)
@@ -647,6 +649,8 @@ def main():
     ap.add_argument("--instances", type=int, default=16)
     ap.add_argument("--roots", type=int, default=1, help="apply workload: vectors per sigma-vector call")
     ap.add_argument("--kseg", type=int, default=0, help="split-K minimum segment (0 = default)")
+    ap.add_argument("--no-t-merge", action="store_true",
+                    help="keep one first-round intermediate per middle operator (no merged intermediates)")
     ap.add_argument("--bparts", type=int, default=1,
                     help="apply workload, FP64: also time the sigma-vector restricted to b = p (mod n) "
                          "for each of n middle-bond parts (one GPU's share of a sharded sigma)")
@@ -830,7 +834,8 @@ def main():
                 mixed[md] = {"error": str(exc)}
         plan.ws32 = plan.L32 = plan.R32 = None
         log(f"mixed-precision steps: {mixed}")
-    traffic = (MEASURED_TRAFFIC.get((opts["kernel_variant"], opts["split_kseg_min"], opts["t_budget_bytes"]))
+    traffic = (MEASURED_TRAFFIC.get((opts["kernel_variant"], opts["split_kseg_min"], opts["t_budget_bytes"],
+                                     opts.get("t_merge_off", 0)))
                if (args.mode == "f64" and (K, M) == (36, 1000) and args.partition == "nc") else None)
     out = {
         "metric": METRIC,

@@ -117,7 +117,16 @@ typedef struct {
                                 b_nparts 0 or 1 (and b_part 0) = all operators.  Other plan kinds:
                                 HX_EUNSUP for b_nparts > 1; HX_EINVAL for b_part outside
                                 [0, b_nparts). */
-    int32_t reserved[3];
+    int32_t t_merge_off;     /* sigma-vector plans: nonzero keeps one first-round intermediate per middle
+                                operator b.  By default (0) the intermediates T_b that share their
+                                whole first-round task list on the psi side (same psi rows, same
+                                contraction lengths; single-root plans) are laid side by side as one
+                                wide matrix, and the right mixed operators they multiply are copied,
+                                scaled by their coefficients, into one stacked operand per task at
+                                hx_heff_prepare, so one GEMM with full-width tiles replaces many narrow
+                                ones.  The workspace grows by the stacked copies; results differ only
+                                in rounding. */
+    int32_t reserved[2];
 } hx_plan_opts;
 
 typedef struct {

@@ -45,7 +45,8 @@ class HxMpoSite(ctypes.Structure):
 
 class HxPlanOpts(ctypes.Structure):
     _fields_ = [("t_budget_bytes", c_int64), ("split_kseg_min", c_int32), ("kernel_variant", c_int32),
-                ("n_roots", c_int32), ("b_part", c_int32), ("b_nparts", c_int32), ("reserved", c_int32 * 3)]
+                ("n_roots", c_int32), ("b_part", c_int32), ("b_nparts", c_int32), ("t_merge_off", c_int32),
+                ("reserved", c_int32 * 2)]
 
 
 class HxPlanInfo(ctypes.Structure):
@@ -427,6 +428,22 @@ class Plan:
         self._ready = False
         return self
 
+    def release_workspace(self):
+        """Free the device workspace and the FP32 copies; the tables stay on the
+        device.  prepare() needs ensure_workspace() first."""
+        self.ws = None
+        self.ws32 = self.L32 = self.R32 = None
+        self._ready = False
+
+    def ensure_workspace(self):
+        """Allocate the workspace again after release_workspace()."""
+        import torch
+        if self.ws is None and self.tables is not None:
+            nws = max(int(self.info.ws_bytes) // 8, 1)
+            self.ws = torch.empty(nws, dtype=torch.float64, device=self.tables.device)
+            self._ready = False
+        return self
+
     @property
     def device(self):
         return None if self.ws is None else self.ws.device
@@ -461,7 +478,7 @@ class Plan:
             pass
 
 
-def _opts(t_budget_bytes=0, split_kseg_min=0, kernel_variant=0, n_roots=1, b_part=0, b_nparts=1):
+def _opts(t_budget_bytes=0, split_kseg_min=0, kernel_variant=0, n_roots=1, b_part=0, b_nparts=1, t_merge_off=0):
     o = HxPlanOpts()
     o.t_budget_bytes = int(t_budget_bytes)
     o.split_kseg_min = int(split_kseg_min)
@@ -469,17 +486,18 @@ def _opts(t_budget_bytes=0, split_kseg_min=0, kernel_variant=0, n_roots=1, b_par
     o.n_roots = int(n_roots)
     o.b_part = int(b_part)
     o.b_nparts = int(b_nparts)
+    o.t_merge_off = int(bool(t_merge_off))
     return o
 
 
 class HeffPlan(Plan):
     def __init__(self, lbond, rbond, Ldq, mid_dq, Rdq, W1, W2, t_budget_bytes=0, split_kseg_min=0,
-                 kernel_variant=0, n_roots=1, b_part=0, b_nparts=1):
+                 kernel_variant=0, n_roots=1, b_part=0, b_nparts=1, t_merge_off=0):
         lb, rb = (b if isinstance(b, Bond) else Bond(b) for b in (lbond, rbond))
         Lo, Mo, Ro = OpSet(Ldq), OpSet(mid_dq), OpSet(Rdq)
         w1 = W1 if isinstance(W1, MpoSite) else MpoSite.from_entries(W1)
         w2 = W2 if isinstance(W2, MpoSite) else MpoSite.from_entries(W2)
-        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant, n_roots, b_part, b_nparts)
+        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant, n_roots, b_part, b_nparts, t_merge_off)
         self.n_roots = int(n_roots)
         h = c_void_p()
         check(lib().hx_heff_plan_create(ctypes.byref(lb.c), ctypes.byref(rb.c), ctypes.byref(Lo.c),
@@ -553,11 +571,11 @@ class Heff1Plan(HeffPlan):
     """One-site sigma-vector plan (psi in the one-site layout)."""
 
     def __init__(self, lbond, rbond, Ldq, Rdq, W, t_budget_bytes=0, split_kseg_min=0, kernel_variant=0,
-                 n_roots=1):
+                 n_roots=1, t_merge_off=0):
         lb, rb = (b if isinstance(b, Bond) else Bond(b) for b in (lbond, rbond))
         Lo, Ro = OpSet(Ldq), OpSet(Rdq)
         w = W if isinstance(W, MpoSite) else MpoSite.from_entries(W)
-        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant, n_roots)
+        opts = _opts(t_budget_bytes, split_kseg_min, kernel_variant, n_roots, t_merge_off=t_merge_off)
         self.n_roots = int(n_roots)
         h = c_void_p()
         check(lib().hx_heff1_plan_create(ctypes.byref(lb.c), ctypes.byref(rb.c), ctypes.byref(Lo.c),

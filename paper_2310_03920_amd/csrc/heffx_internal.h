@@ -132,6 +132,7 @@ struct Plan {
     std::vector<double> coef;     // mixing coefficient matrices (space SP_TAB)
     // sequences of launches
     std::vector<Launch> prep;     // mixing (heff_prepare / first part of env update)
+    std::vector<GatherLaunch> prep_gather;  // after the mixing: stacked first-round operands
     std::vector<Launch> apply;    // sigma (heff) or E1/E2 chunks (env)
     std::vector<FillLaunch> diag_fill;
     std::vector<GatherLaunch> diag_gather;
@@ -161,6 +162,7 @@ struct Plan {
     int kstage = 16;            // K-stage depth of that variant; task K is padded to it
     int n_roots = 1;            // vectors per sigma-vector call (roots side by side in column blocks)
     int b_part = 0, b_nparts = 1;  // sigma-vector plans: only middle-bond indices b = b_part (mod b_nparts)
+    bool t_merge = true;        // sigma-vector plans: merge first-round intermediates with equal psi-side tasks
     int n_stages = 0;           // rounds emitted so far (Launch::stage)
     double flops_apply = 0, flops_prepare = 0, bytes_apply = 0;
     double flops_useful = -1;   // sigma plans: block-product work whose results sigma reads (< 0: = flops_apply)

@@ -1019,6 +1019,20 @@ int hx_plan_upload(hx_plan* plan, void* dev_tables, hx_stream stream) {
     return HX_OK;
 }
 
+// The mixing GEMMs, then the copies that stack the first-round operands of merged
+// intermediates (read from the mixed operators and the right environment).
+static int run_prepare(const Plan* P, const Bases& B, hipStream_t s) {
+    int rc;
+    for (const Launch& l : P->prep)
+        if ((rc = launch_gemm(P, l, B, s))) return rc;
+    const Gather* g = reinterpret_cast<const Gather*>(static_cast<const char*>(P->dev) + P->off_gathers);
+    for (const GatherLaunch& gl : P->prep_gather) {
+        hipLaunchKernelGGL(gather_scale<double>, dim3((unsigned)gl.ng), dim3(256), 0, s, g + gl.g0, B);
+        if ((rc = hip_check(hipGetLastError(), "stacked operand copies"))) return rc;
+    }
+    return HX_OK;
+}
+
 int hx_heff_prepare(const hx_plan* plan, const double* L, const double* R, void* ws, hx_stream stream) {
     int rc = check_ready(plan, PK_HEFF, PK_HEFF_VJP);
     if (rc) return rc;
@@ -1028,9 +1042,7 @@ int hx_heff_prepare(const hx_plan* plan, const double* L, const double* R, void*
         return HX_EINVAL;
     }
     Bases B = make_bases(P, nullptr, nullptr, L, R, ws);
-    for (const Launch& l : P->prep)
-        if ((rc = launch_gemm(P, l, B, static_cast<hipStream_t>(stream)))) return rc;
-    return HX_OK;
+    return run_prepare(P, B, static_cast<hipStream_t>(stream));
 }
 
 int hx_heff_apply(const hx_plan* plan, const double* L, const double* R, void* ws, const double* psi, double* sigma,
@@ -1553,8 +1565,7 @@ int hx_heff_apply_noalloc(const hx_plan* plan, const double* L, const double* R,
     // is written before it is read within this call: nothing needs clearing
     hipStream_t s = s_of(stream);
     Bases B = make_bases(P, psi, sigma, L, R, ws);
-    for (const Launch& l : P->prep)
-        if ((rc = launch_gemm(P, l, B, s))) return rc;
+    if ((rc = run_prepare(P, B, s))) return rc;
     for (const Launch& l : P->apply)
         if ((rc = launch_gemm(P, l, B, s))) return rc;
     return HX_OK;

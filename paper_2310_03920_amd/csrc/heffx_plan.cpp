@@ -437,24 +437,30 @@ static int64_t place_mixer(Mixer& M, int64_t ws0) {
 
 struct Builder {
     Plan* P;
+    // Tiles of a block in the order they are dispatched: along the longer side
+    // innermost-last, i.e. a wide block column strip by column strip (the row tiles
+    // of one strip share its B panel, and the block's few A panels stay cached),
+    // a tall block row strip by row strip.
     void add_block_tiles(int shape, int64_t coff, int ldc, int m, int n, int8_t cspace, int8_t beta,
                          int32_t tbeg, int32_t tend, int32_t ktot) {
         const int tm = shape_rows(shape), tn = shape_cols(shape);
-        for (int r0 = 0; r0 < m; r0 += tm)
-            for (int c0 = 0; c0 < n; c0 += tn) {
-                Tile t;
-                t.coff = coff + (int64_t)r0 * ldc + c0;
-                t.ldc = ldc;
-                t.m = std::min(tm, m - r0);
-                t.n = std::min(tn, n - c0);
-                t.r0 = r0;
-                t.c0 = c0;
-                t.tbeg = tbeg;
-                t.tend = tend;
-                t.ktot = ktot;
-                t.set_out(cspace, beta);
-                P->tiles.push_back(t);
-            }
+        const int nr = (m + tm - 1) / tm, nc = (n + tn - 1) / tn;
+        const bool by_col = n > m;
+        for (int q = 0; q < nr * nc; ++q) {
+            const int r0 = (by_col ? q % nr : q / nc) * tm, c0 = (by_col ? q / nr : q % nc) * tn;
+            Tile t;
+            t.coff = coff + (int64_t)r0 * ldc + c0;
+            t.ldc = ldc;
+            t.m = std::min(tm, m - r0);
+            t.n = std::min(tn, n - c0);
+            t.r0 = r0;
+            t.c0 = c0;
+            t.tbeg = tbeg;
+            t.tend = tend;
+            t.ktot = ktot;
+            t.set_out(cspace, beta);
+            P->tiles.push_back(t);
+        }
     }
 };
 
@@ -485,6 +491,7 @@ static int apply_opts(Plan& P, const hx_plan_opts* o) {
     }
     P.b_nparts = np > 1 ? np : 1;
     P.b_part = np > 1 ? pp : 0;
+    P.t_merge = !(o && o->t_merge_off != 0);
     return HX_OK;
 }
 
@@ -608,6 +615,28 @@ static void sort_tiles(Plan& P, int64_t t0, int64_t n) {
         tile_group[t] = g;
         groups[g].count++;
         groups[g].work += (double)tl.ktot * tl.m * tl.n;
+    }
+    // A group of many tiles (a wide block) is cut into runs of at most GMAX
+    // consecutive members, so that the XCD queues stay balanced; a run keeps the
+    // tiles that share a B panel together (the block's tile order).
+    constexpr int64_t GMAX = 16;
+    {
+        std::vector<int64_t> seen(groups.size(), 0);
+        std::vector<size_t> sub(groups.size(), SIZE_MAX);  // current run of each group
+        std::vector<Group> runs;
+        for (int64_t t = 0; t < n; ++t) {
+            const size_t g = tile_group[t];
+            if (seen[g] % GMAX == 0) {
+                sub[g] = runs.size();
+                runs.push_back({t, 0, 0.0});
+            }
+            ++seen[g];
+            const Tile& tl = P.tiles[t0 + t];
+            runs[sub[g]].count++;
+            runs[sub[g]].work += (double)tl.ktot * tl.m * tl.n;
+            tile_group[t] = sub[g];
+        }
+        groups.swap(runs);
     }
     // members of each group in increasing tile order (counting sort)
     std::vector<int64_t> mstart(groups.size() + 1, 0), mpos, mlist(n);
@@ -795,6 +824,33 @@ static bool check_task_index_range(const Plan& P) {
     return true;
 }
 
+// Every copy of the listed gather launches stays inside its source and destination
+// buffers (sizes of the plan's operand spaces).
+static bool check_gathers(const Plan& P, const std::vector<GatherLaunch>& seq, const char* what) {
+    auto space_size = [&](int sp) -> int64_t {
+        switch (sp) {
+            case SP_L: case SP_GL: return P.in_nnz;
+            case SP_R: case SP_GR: return P.in2_nnz;
+            case SP_WS: return P.ws_doubles;
+            case SP_TAB: return (int64_t)P.coef.size();
+            case SP_GW1: return 16 * P.w1_nnz;
+            case SP_GW2: return 16 * P.w2_nnz;
+            default: return P.psi_nnz;
+        }
+    };
+    for (const GatherLaunch& gl : seq)
+        for (int64_t q = gl.g0; q < gl.g0 + gl.ng; ++q) {
+            const Gather& g = P.gathers[q];
+            const int64_t last = (int64_t)std::max(g.count - 1, 0);
+            if (g.count < 0 || g.soff < 0 || g.doff < 0 || g.soff + last * g.sstride >= space_size(g.sspace) ||
+                g.doff + last * g.dstride >= space_size(g.dspace)) {
+                set_error(std::string("internal: ") + what + " copy out of range");
+                return false;
+            }
+        }
+    return true;
+}
+
 // one_site: the one-site H_eff (Sec. II.A.2) -- the second site is absent, Mo == Ro and
 // e2 is ignored: the right "mixed" operator of middle operator b is R_b itself.
 static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, const OpSet& Mo,
@@ -945,6 +1001,13 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
             used += lb.dim[il];
         }
     };
+    // Stacked first-round operands (merged intermediates, below) follow the
+    // intermediate region; prepare fills them with gathers after the mixing.
+    const bool merge_t = P.t_merge && R == 1;
+    const int64_t stack_base = t_ws + tmax;
+    int64_t stack_len = 0;
+    GatherLaunch stack_gl;
+    stack_gl.g0 = (int64_t)P.gathers.size();
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
         // ---- stage 1: T_b[:, (s2', r')] = sum_{s2} psi[:, (s2, r)] Rmix_{b,s2'<-s2}[r', r]^T
         //      on stacked column blocks (all row blocks of one fused sector at once,
@@ -954,6 +1017,7 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
             int b, col, s2p, irp;  // col: the psi column block whose row structure T shares
             int64_t off;
             int rows, r_lo, used;  // stacked rows of the column block; first row held; rows read
+            int ld;                // row pitch of the intermediate (wider when merged)
         };
         std::vector<TInfo> tinfo;
         int64_t toff = t_ws;
@@ -986,7 +1050,7 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                             ob.n = rb.dim[irp];
                             tblocks.push_back(std::move(ob));
                         }
-                        tinfo.push_back({b, cj, tr.so, irp, toff, pc.rows, lo, used});
+                        tinfo.push_back({b, cj, tr.so, irp, toff, pc.rows, lo, used, R * rb.dim[irp]});
                         toff += (int64_t)(hi - lo) * rb.dim[irp] * R;
                     } else {
                         ti = tslot[key];
@@ -1013,6 +1077,86 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
             }
         }
         for (auto& ob : tblocks) tbytes += 2.0 * 8.0 * ob.m * ob.n;
+        if (merge_t && tinfo.size() > 1) {
+            // Intermediates whose task lists agree on the psi side (rows, contraction
+            // lengths, order) differ only in the right operator: T_b1 | T_b2 | ... =
+            // psi-side product with the stacked operators [a1 Rmix_b1; a2 Rmix_b2; ...].
+            // A group becomes one (rows x sum n) matrix; its members are column slices.
+            std::map<std::vector<int64_t>, int> gid;
+            std::vector<std::vector<int>> groups;
+            for (int ti = 0; ti < (int)tinfo.size(); ++ti) {
+                const OutBlockTasks& ob = tblocks[ti];
+                std::vector<int64_t> sig;
+                sig.reserve(1 + 4 * ob.tasks.size());
+                sig.push_back(ob.m);
+                for (const Task& t : ob.tasks) {
+                    sig.push_back(t.aoff);
+                    sig.push_back(t.lda);
+                    sig.push_back(t.k);
+                    sig.push_back(t.aspace());
+                }
+                auto ins = gid.emplace(std::move(sig), (int)groups.size());
+                if (ins.second) groups.emplace_back();
+                groups[(size_t)ins.first->second].push_back(ti);
+            }
+            std::vector<OutBlockTasks> merged;
+            merged.reserve(groups.size());
+            int64_t goff = t_ws;
+            for (const auto& g : groups) {
+                const OutBlockTasks& f = tblocks[(size_t)g[0]];
+                int W = 0;
+                for (int ti : g) W += tblocks[(size_t)ti].n;
+                OutBlockTasks ob;
+                ob.coff = goff;
+                ob.ldc = W;
+                ob.m = f.m;
+                ob.n = W;
+                int col = 0;
+                for (int ti : g) {
+                    tinfo[(size_t)ti].off = goff + col;
+                    tinfo[(size_t)ti].ld = W;
+                    col += tblocks[(size_t)ti].n;
+                }
+                if (g.size() == 1) {
+                    ob.tasks = f.tasks;
+                } else {
+                    for (size_t j = 0; j < f.tasks.size(); ++j) {
+                        Task t = f.tasks[j];
+                        const int K = t.k;
+                        int64_t row = 0;
+                        for (int ti : g) {
+                            const Task& u = tblocks[(size_t)ti].tasks[j];
+                            const int n = tblocks[(size_t)ti].n;
+                            if (u.ldb != K) {
+                                set_error("internal: first-round operand block not contiguous");
+                                return HX_EINVAL;
+                            }
+                            Gather gg;
+                            gg.soff = u.boff;
+                            gg.sspace = (int8_t)u.bspace();
+                            gg.sstride = 1;
+                            gg.doff = stack_base + stack_len + row * K;
+                            gg.dspace = SP_WS;
+                            gg.dstride = 1;
+                            gg.count = n * K;
+                            gg.alpha = u.alpha;
+                            gg.pad = 0;
+                            P.gathers.push_back(gg);
+                            row += n;
+                        }
+                        t.boff = stack_base + stack_len;
+                        t.ldb = K;
+                        t.set_spaces(t.aspace(), SP_WS);
+                        t.alpha = 1.0;
+                        stack_len += (int64_t)W * K;
+                        ob.tasks.push_back(t);
+                    }
+                }
+                goff += (int64_t)f.m * W;
+                merged.push_back(std::move(ob));
+            }
+            tblocks.swap(merged);
+        }
         flush_blocks(P, tblocks, NT, SP_WS, 0, false, P.apply, &fl, &nt);
 
         // ---- stage 2: sigma[l',s1',s2',r'] += sum Lmix_{b,s1'<-s1}[l',l] T_b[(l,s1), (s2',r')]
@@ -1042,8 +1186,8 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
                     t.aoff = tr.m.base + sl.rel[il];
                     t.lda = lb.dim[il];
                     const int ta_ = tr.m.space;
-                    t.boff = ti.off + (int64_t)(roff - ti.r_lo) * rb.dim[ti.irp] * R;
-                    t.ldb = R * rb.dim[ti.irp];
+                    t.boff = ti.off + (int64_t)(roff - ti.r_lo) * ti.ld;
+                    t.ldb = ti.ld;
                     t.set_spaces(ta_, SP_WS);
                     t.k = lb.dim[il];
                     t.alpha = tr.m.alpha;
@@ -1058,6 +1202,12 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
     P.flops_useful = useful;
     P.n_tasks_apply = nt;
     for (auto& L : P.apply) P.n_tiles_apply += L.ntile;
+    stack_gl.ng = (int64_t)P.gathers.size() - stack_gl.g0;
+    if (stack_gl.ng) {
+        P.prep_gather.push_back(stack_gl);
+        P.mix_ranges.push_back({stack_base, stack_base + stack_len});  // lowered with the mixed operators
+        ws = stack_base + stack_len;
+    }
 
     // algorithmic bytes of one apply: psi, sigma, T traffic and every referenced operator once
     {
@@ -1166,6 +1316,8 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
     ws += P.part_tiles * TM * TN;
     P.ws_doubles = ws;
     if (!check_task_index_range(P)) return HX_EINVAL;
+    if (!check_gathers(P, P.prep_gather, "stacked operand") || !check_gathers(P, P.diag_gather, "diagonal"))
+        return HX_EINVAL;
     return HX_OK;
 }
 
@@ -1999,6 +2151,71 @@ static int build_env(Plan& P, int dir, const Bond& bin, const Bond& bout, const 
     return HX_OK;
 }
 
+// Every element a GEMM launch of the plan can touch lies inside its operand space:
+// for each tile, the output rows and columns of its extent, and for each of its
+// tasks the A rows x k and k x B columns that the kernel loads (its loads stay
+// inside the tile's extent and the task's k).  Split-K partial tiles and their
+// reductions stay inside the partial region.  Checked once per plan on the host.
+static int check_gemm_bounds(const Plan& P) {
+    const bool env = P.kind == PK_ENV_LEFT || P.kind == PK_ENV_RIGHT;
+    int64_t size[SP_N];
+    size[SP_PSI] = env ? P.in_nnz : P.psi_nnz;
+    size[SP_OUT] = env ? P.out_nnz : P.psi_nnz;
+    size[SP_L] = env ? 0 : P.in_nnz;
+    size[SP_R] = P.in2_nnz;
+    size[SP_WS] = P.ws_doubles;
+    size[SP_TAB] = (int64_t)P.coef.size();
+    size[SP_PART] = P.ws_doubles - P.part_base;
+    size[SP_G] = P.kind == PK_HEFF_VJP ? P.psi_nnz : 0;
+    size[SP_GL] = P.kind == PK_HEFF_VJP ? P.in_nnz : 0;
+    size[SP_GR] = P.kind == PK_HEFF_VJP ? P.in2_nnz : 0;
+    size[SP_GW1] = P.kind == PK_HEFF_VJP ? 16 * P.w1_nnz : 0;
+    size[SP_GW2] = P.kind == PK_HEFF_VJP ? 16 * P.w2_nnz : 0;
+    auto inside = [&](int sp, int64_t first, int64_t last) {
+        return sp >= 0 && sp < SP_N && first >= 0 && last >= first && last < size[sp];
+    };
+    auto bad = [](const char* what) {
+        set_error(std::string("internal: plan table out of range (") + what + ")");
+        return HX_EINVAL;
+    };
+    for (const std::vector<Launch>* seq : {&P.prep, &P.apply, &P.diag_gemm})
+        for (const Launch& L : *seq) {
+            const bool ta = L.kind == TN_, tb = L.kind == NT;
+            for (int64_t t = L.tile0; t < L.tile0 + L.ntile; ++t) {
+                const Tile& tl = P.tiles[(size_t)t];
+                if (tl.m <= 0 || tl.n <= 0) continue;
+                if (tl.m > shape_rows(L.shape) || tl.n > shape_cols(L.shape)) return bad("tile extent");
+                if (!inside(tl.cspace(), tl.coff, tl.coff + (int64_t)(tl.m - 1) * tl.ldc + tl.n - 1))
+                    return bad("tile output");
+                if (tl.tbeg < 0 || tl.tend < tl.tbeg || tl.tend > (int64_t)P.tasks.size()) return bad("task range");
+                int64_t kt = 0;
+                for (int j = tl.tbeg; j < tl.tend; ++j) {
+                    const Task& k = P.tasks[(size_t)j];
+                    kt += kpad(k.k, P.kstage);
+                    if (k.k <= 0) continue;
+                    const int64_t r1 = tl.r0 + tl.m - 1, c1 = tl.c0 + tl.n - 1;
+                    const int64_t a0 = k.aoff + (ta ? tl.r0 : (int64_t)tl.r0 * k.lda);
+                    const int64_t a1 = k.aoff + (ta ? (int64_t)(k.k - 1) * k.lda + r1 : r1 * k.lda + k.k - 1);
+                    const int64_t b0 = k.boff + (tb ? (int64_t)tl.c0 * k.ldb : tl.c0);
+                    const int64_t b1 = k.boff + (tb ? c1 * k.ldb + k.k - 1 : (int64_t)(k.k - 1) * k.ldb + c1);
+                    if (!inside(k.aspace(), a0, a1)) return bad("A operand");
+                    if (!inside(k.bspace(), b0, b1)) return bad("B operand");
+                }
+                if (kt != tl.ktot) return bad("tile depth");
+            }
+            for (int64_t r = L.red0; r < L.red0 + L.nred; ++r) {
+                const Reduce& rd = P.reduces[(size_t)r];
+                if (rd.m <= 0 || rd.n <= 0) continue;
+                if (!inside(rd.cspace, rd.coff, rd.coff + (int64_t)(rd.m - 1) * rd.ldc + rd.n - 1))
+                    return bad("reduction output");
+                if (!inside(SP_PART, rd.pbase, rd.pbase + (int64_t)(rd.np - 1) * TM * TN +
+                                                   (int64_t)(rd.m - 1) * rd.pld + rd.n - 1))
+                    return bad("reduction partials");
+            }
+        }
+    return HX_OK;
+}
+
 static void finalize_tables(Plan& P);
 // XCD ordering of every recorded launch.  Each range is reordered in place and
 // ranges are disjoint, so large plans spread them over host threads (largest
@@ -2083,7 +2300,7 @@ static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
         M.inst_psi.push_back(o_psi);
         M.inst_L.push_back(o_L);
         M.inst_R.push_back(o_R);
-        M.mix_ranges.push_back({o_ws, o_ws + P.mix_end});
+        for (const auto& r : P.mix_ranges) M.mix_ranges.push_back({o_ws + r.first, o_ws + r.second});
         o_psi += P.psi_nnz;
         o_L += P.in_nnz;
         o_R += P.in2_nnz;
@@ -2186,19 +2403,25 @@ static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
             g.off += off[i][f.space];
             M.diag_fill.push_back(g);
         }
-        GatherLaunch gl;
-        gl.g0 = (int64_t)M.gathers.size();
-        for (const Gather& g0 : in[i]->gathers) {
-            Gather g = g0;
-            int a, b;
-            g.soff = remap_space(i, g.sspace, g.soff, a);
-            g.doff = remap_space(i, g.dspace, g.doff, b);
-            g.sspace = (int8_t)a;
-            g.dspace = (int8_t)b;
-            M.gathers.push_back(g);
-        }
-        gl.ng = (int64_t)M.gathers.size() - gl.g0;
-        if (gl.ng) M.diag_gather.push_back(gl);
+        // each gather list of the instance becomes one launch of the merged list
+        auto copy_list = [&](const std::vector<GatherLaunch>& src, std::vector<GatherLaunch>& dst) {
+            GatherLaunch gl;
+            gl.g0 = (int64_t)M.gathers.size();
+            for (const GatherLaunch& sl : src)
+                for (int64_t q = sl.g0; q < sl.g0 + sl.ng; ++q) {
+                    Gather g = in[i]->gathers[(size_t)q];
+                    int a, b;
+                    g.soff = remap_space(i, g.sspace, g.soff, a);
+                    g.doff = remap_space(i, g.dspace, g.doff, b);
+                    g.sspace = (int8_t)a;
+                    g.dspace = (int8_t)b;
+                    M.gathers.push_back(g);
+                }
+            gl.ng = (int64_t)M.gathers.size() - gl.g0;
+            if (gl.ng) dst.push_back(gl);
+        };
+        copy_list(in[i]->diag_gather, M.diag_gather);
+        copy_list(in[i]->prep_gather, M.prep_gather);
     }
     for (auto& L : M.apply) M.n_tiles_apply += L.ntile;
     if (!check_task_index_range(M)) return HX_EINVAL;
@@ -2291,6 +2514,7 @@ int hx_heff_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_ops
         return HX_EINVAL;
     Plan* P = new Plan();
     int rc = build_heff(*P, lb, rb, Lo, Mo, Ro, e1, e2, opts);
+    if (rc == HX_OK) rc = check_gemm_bounds(*P);
     if (rc != HX_OK) {
         delete P;
         return rc;
@@ -2315,6 +2539,7 @@ int hx_heff1_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_op
     if (!parse_mpo(W, Lo, Ro, true, e1, "heff1 W")) return HX_EINVAL;
     Plan* P = new Plan();
     int rc = build_heff(*P, lb, rb, Lo, Ro, Ro, e1, {}, opts, true);
+    if (rc == HX_OK) rc = check_gemm_bounds(*P);
     if (rc != HX_OK) {
         delete P;
         return rc;
@@ -2364,6 +2589,7 @@ int hx_heff_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx
     if (!parse_mpo(W1, Lo, Mo, true, e1, "vjp W1") || !parse_mpo(W2, Mo, Ro, false, e2, "vjp W2")) return HX_EINVAL;
     Plan* P = new Plan();
     int rc = build_heff_vjp(*P, lb, rb, Lo, Mo, Ro, e1, e2, opts);
+    if (rc == HX_OK) rc = check_gemm_bounds(*P);
     if (rc != HX_OK) {
         delete P;
         return rc;
@@ -2388,6 +2614,7 @@ int hx_heff1_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const h
     if (!parse_mpo(W, Lo, Ro, true, e1, "vjp1 W")) return HX_EINVAL;
     Plan* P = new Plan();
     int rc = build_heff_vjp(*P, lb, rb, Lo, Ro, Ro, e1, {}, opts, true);
+    if (rc == HX_OK) rc = check_gemm_bounds(*P);
     if (rc != HX_OK) {
         delete P;
         return rc;
@@ -2413,6 +2640,7 @@ int hx_env_plan_create(int direction, const hx_bond* bond_in, const hx_bond* bon
     if (!ok) return HX_EINVAL;
     Plan* P = new Plan();
     int rc = build_env(*P, direction, bi, bo, oi, oo, ents, opts);
+    if (rc == HX_OK) rc = check_gemm_bounds(*P);
     if (rc != HX_OK) {
         delete P;
         return rc;
@@ -2438,6 +2666,7 @@ int hx_heff_plan_batch(const hx_plan* const* plans, int32_t n, hx_plan** out) {
     }
     Plan* M = new Plan();
     int rc = merge_plans(in, *M);
+    if (rc == HX_OK) rc = check_gemm_bounds(*M);
     if (rc != HX_OK) {
         delete M;
         return rc;

@@ -436,6 +436,9 @@ class DMRG:
         else:
             theta, rnorm, nmv = dav.solve(mv, psi_t, diag, tol=self.tol, max_iter=self.max_iter)
         psi = X.unpack_psi(Lb, Rb, dav.x.cpu().numpy())
+        # the plan stays cached for the site; its workspace (mixed and stacked
+        # operators, intermediates) is only needed during the step
+        plan.release_workspace()
         self.log.append({"pass": pass_id, "i": i, "energy": theta, "rnorm": rnorm, "n_matvec": nmv})
         return psi
 
@@ -513,6 +516,7 @@ class DMRG:
 
         theta, rnorm, nmv = dav.solve(mv, psi_t, diag, tol=self.tol, max_iter=self.max_iter)
         self.center = X.unpack_psi1(Lb, Rb, dav.x.cpu().numpy())
+        plan.release_workspace()
         self.log.append({"pass": pass_id, "i": i, "one_site": True, "energy": theta, "rnorm": rnorm,
                          "n_matvec": nmv})
         return theta

@@ -101,7 +101,7 @@ class Engine:
             self._keep_latest(self._heff_plans, ("heff", i), key)
             p.upload(self.device)
             self._heff_plans[key] = p
-        return p
+        return p.ensure_workspace()
 
     def heff1_plan(self, i, bond_i, bond_i1):
         """One-site sigma-vector plan at site i (left environment at cut i, right at cut i+1)."""
@@ -112,7 +112,7 @@ class Engine:
             p = X.Heff1Plan(bond_i, bond_i1, self.mpo.dq[i], self.mpo.dq[i + 1], self._w[i],
                             t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
             self._heff_plans[key] = p
-        return p
+        return p.ensure_workspace()
 
     def vjp_plan(self, i, bond_i, bond_i2):
         """Adjoint plan of the sigma-vector at sites (i, i+1) (built per call)."""

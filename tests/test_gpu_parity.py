@@ -58,12 +58,13 @@ def _close(got, ref, rtol=RTOL):
         assert err <= rtol * scale, (k, err, scale)
 
 
-def _run_heff(device, lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi, budget=0, diag=False, kseg=0, variant=0):
+def _run_heff(device, lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi, budget=0, diag=False, kseg=0, variant=0,
+              merge_off=0):
     import torch
     from paper_2310_03920_amd import _lib as X
     lbB, rbB = X.Bond(lb), X.Bond(rb)
     plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, t_budget_bytes=budget,
-                      split_kseg_min=kseg, kernel_variant=variant).upload(device)
+                      split_kseg_min=kseg, kernel_variant=variant, t_merge_off=merge_off).upload(device)
     Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
     Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
     pt = torch.from_numpy(X.pack_psi(lbB, rbB, psi)).to(device)
@@ -114,6 +115,46 @@ def test_heff_apply_kernel_variants(device, variant):
     d = contract.heff_diag(contract.dense_env(L, lb), contract.dense_mpo(W1, len(Ldq), len(Mdq)),
                            contract.dense_mpo(W2, len(Mdq), len(Rdq)), contract.dense_env(R, rb))
     _close(res["diag"], mps.two_site_blocks_from_dense(d, lb, rb, two_site_blocks(lb, rb)))
+
+
+@pytest.mark.parametrize("merge_off,budget", [(0, 0), (1, 0), (0, 256 * 1024)])
+def test_heff_apply_merged_and_separate_intermediates(device, merge_off, budget):
+    """First-round intermediates merged into wide matrices (stacked right operands
+    copied at prepare) or kept one per middle operator: sigma and diag equal the
+    oracle either way, also with chunked intermediates."""
+    print(f"[heff_apply merge_off={merge_off} budget={budget}]", flush=True)
+    lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = prob = _problem(5, True)
+    res = _run_heff(device, *prob, budget=budget, diag=True, merge_off=merge_off, variant=1, kseg=64)
+    _close(res["sigma"], _dense_sigma(*prob))
+    d = contract.heff_diag(contract.dense_env(L, lb), contract.dense_mpo(W1, len(Ldq), len(Mdq)),
+                           contract.dense_mpo(W2, len(Mdq), len(Rdq)), contract.dense_env(R, rb))
+    _close(res["diag"], mps.two_site_blocks_from_dense(d, lb, rb, two_site_blocks(lb, rb)))
+
+
+def test_released_workspace_is_allocated_and_prepared_again(device):
+    """A cached plan whose workspace was released gives the same sigma after
+    ensure_workspace() and prepare(); before prepare it is refused."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = _problem(5, True)
+    lbB, rbB = X.Bond(lb), X.Bond(rb)
+    plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2).upload(device)
+    Lt = torch.from_numpy(X.pack_env(lbB, Ldq, L)).to(device)
+    Rt = torch.from_numpy(X.pack_env(rbB, Rdq, R)).to(device)
+    pt = torch.from_numpy(X.pack_psi(lbB, rbB, psi)).to(device)
+    s1, s2 = torch.empty_like(pt), torch.empty_like(pt)
+    plan.prepare(Lt, Rt)
+    plan.apply(Lt, Rt, pt, s1)
+    plan.release_workspace()
+    with pytest.raises(RuntimeError, match="upload"):
+        plan.apply(Lt, Rt, pt, s2)
+    plan.ensure_workspace()
+    with pytest.raises(RuntimeError, match="prepare"):
+        plan.apply(Lt, Rt, pt, s2)
+    plan.prepare(Lt, Rt)
+    plan.apply(Lt, Rt, pt, s2)
+    torch.cuda.synchronize()
+    assert torch.equal(s1, s2)
 
 
 @pytest.mark.parametrize("roots,variant", [(3, 0), (2, 1)])

@@ -117,3 +117,24 @@ def test_middle_bond_part_plans_split_the_work_of_the_whole():
         X.HeffPlan(*args, b_part=5, b_nparts=5)
     with pytest.raises(RuntimeError, match="sigma-vector plans only"):
         X.EnvPlan(0, b[i], b[i + 1], m.dq[i], m.dq[i + 1], W1e, b_part=1, b_nparts=2)
+
+
+@pytest.mark.parametrize("i", [2, 3])
+def test_merged_intermediates_change_tiles_not_work(i):
+    """Merging first-round intermediates that share their psi-side tasks leaves the
+    block-product work (executed and useful) unchanged and cuts the tile count; the
+    stacked operand copies enlarge the workspace."""
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.mpo import build_nc_mpo, site_entries
+    K, M = 8, 64
+    m = build_nc_mpo(*make_integrals(K, seed=0))
+    b = bond_sector_tables(K, K, 0, M)
+    args = (b[i], b[i + 2], m.dq[i], m.dq[i + 1], m.dq[i + 2], site_entries(m, i), site_entries(m, i + 1))
+    sep = X.HeffPlan(*args, t_merge_off=1).info
+    mer = X.HeffPlan(*args).info
+    assert mer.flops_apply == sep.flops_apply
+    assert mer.flops_useful == sep.flops_useful
+    assert mer.n_tiles < sep.n_tiles
+    assert mer.ws_bytes > sep.ws_bytes
+    multi = X.HeffPlan(*args, n_roots=2).info  # several roots: intermediates stay separate
+    assert multi.flops_apply == pytest.approx(2 * sep.flops_apply, rel=1e-12)
