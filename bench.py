@@ -161,7 +161,8 @@ def bench_batch(args):
                                  t_budget_bytes=1 << 40, **opts))
         return ps
 
-    opts = {"split_kseg_min": args.kseg or 2048, "kernel_variant": 0 if args.variant is None else args.variant}
+    opts = {"split_kseg_min": args.kseg or 2048, "kernel_variant": 0 if args.variant is None else args.variant,
+            "t_merge_off": int(args.no_t_merge)}
     plans = make_plans(opts)
     log(f"{len(plans)} plans in {time.time() - t0:.1f}s")
     gen = torch.Generator(device=device)
