@@ -574,39 +574,60 @@ constexpr int KMAX = 32;
 
 // Deterministic dots: pass 1 writes per-block partial sums, pass 2 sums them in
 // a fixed tree order.  part[blk * KMAX + j].
+// Sum of v over the 64 lanes of a wavefront (butterfly: every lane holds the sum,
+// in an order fixed by the lane pattern).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m);
+    return v;
+}
+
+// part[block][j] = partial a_j . b over the block's grid-stride elements, j < k:
+// one sweep over b (each a_j and b read once), k sums per thread in registers, then
+// per j a wavefront sum and a fixed-order sum over the block's 4 wavefronts.
 __global__ __launch_bounds__(DOT_THREADS) void dots_pass1(int64_t n, int k, const double* __restrict__ a,
                                                           int64_t lda, const double* __restrict__ b,
                                                           double* __restrict__ part) {
-    __shared__ double red[DOT_THREADS];
-    for (int j = 0; j < k; ++j) {
-        const double* aj = a + (int64_t)j * lda;
-        double s = 0.0;
-        for (int64_t e = (int64_t)blockIdx.x * DOT_THREADS + threadIdx.x; e < n; e += (int64_t)DOT_BLOCKS * DOT_THREADS)
-            s += aj[e] * b[e];
-        red[threadIdx.x] = s;
-        __syncthreads();
-        for (int w = DOT_THREADS / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
+    __shared__ double red[DOT_THREADS / 64][KMAX];
+    double s[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) s[j] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * DOT_THREADS + threadIdx.x; e < n; e += (int64_t)DOT_BLOCKS * DOT_THREADS) {
+        const double bv = b[e];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+            if (j < k) s[j] += a[(int64_t)j * lda + e] * bv;
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) {
+        if (j < k) {
+            const double t = wave_sum(s[j]);
+            if (lane == 0) red[w][j] = t;
         }
-        if (threadIdx.x == 0) part[blockIdx.x * KMAX + j] = red[0];
-        __syncthreads();
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        double t = red[0][threadIdx.x];
+        for (int q = 1; q < DOT_THREADS / 64; ++q) t += red[q][threadIdx.x];
+        part[blockIdx.x * KMAX + threadIdx.x] = t;
     }
 }
 
-// out[j * ostride] = sum over blocks (fixed tree); if `scale` != 0 multiply by it.
+// out[j * ostride] = sum over the DOT_BLOCKS partials of dot j (fixed order).
 __global__ __launch_bounds__(DOT_BLOCKS) void dots_pass2(int k, const double* __restrict__ part, double* out,
                                                          int ostride) {
-    __shared__ double red[DOT_BLOCKS];
+    __shared__ double red[DOT_BLOCKS / 64][KMAX];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int j = 0; j < k; ++j) {
-        red[threadIdx.x] = part[threadIdx.x * KMAX + j];
-        __syncthreads();
-        for (int w = DOT_BLOCKS / 2; w > 0; w >>= 1) {
-            if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) out[(int64_t)j * ostride] = red[0];
-        __syncthreads();
+        const double t = wave_sum(part[threadIdx.x * KMAX + j]);
+        if (lane == 0) red[w][j] = t;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < k) {
+        double t = red[0][threadIdx.x];
+        for (int q = 1; q < DOT_BLOCKS / 64; ++q) t += red[q][threadIdx.x];
+        out[(int64_t)threadIdx.x * ostride] = t;
     }
 }
 

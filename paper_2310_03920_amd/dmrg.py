@@ -220,16 +220,20 @@ class Davidson:
         return theta, rnorm, nmv
 
     def solve_mixed(self, mv32, mv64, psi0, diag, tol=1e-8, max_iter=30, low_tol=1e-5, guard=1e-8, floor=1e-3):
-        """Reduced-precision sigma-vectors until |r| < low_tol (or stagnation below
-        `floor`, near the rounding floor of that precision), then FP64 sigma-vectors
-        restarted from that Ritz vector until |r| < tol.
+        """Reduced-precision sigma-vectors until |r| < low_tol or the phase stops
+        paying, then FP64 sigma-vectors restarted from that Ritz vector until
+        |r| < tol.  The phase stops paying when the last 6 iterations gained less
+        than 2x, either below `floor` (near the rounding floor of that precision)
+        or without ever halving the residual the phase started from (a warm start
+        already below what that precision resolves).
         Returns (theta, rnorm, n_matvec_low, n_matvec_f64)."""
         hist = []
 
         def watch(it, theta, rn):
-            # stagnation: below the floor and no 2x gain over the last 6 iterations
             hist.append(rn)
-            return rn < floor and len(hist) >= 7 and rn > 0.5 * hist[-7]
+            if len(hist) < 7 or rn <= 0.5 * hist[-7]:
+                return False
+            return rn < floor or rn > 0.5 * hist[0]
 
         _, _, n32 = self.solve(mv32, psi0, diag, tol=low_tol, max_iter=max_iter, guard=guard,
                                on_iter=watch)
