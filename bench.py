@@ -504,10 +504,26 @@ def bench_sweep(args):
         dt = time.perf_counter() - t
         st = d.log[n0:]
         passes.append({"s": dt, "site_steps": len(st), "matvecs": int(sum(x["n_matvec"] for x in st)),
+                       "sigma_tflop": sum(x["n_matvec"] * x["sigma_flop"] for x in st) / 1e12,
                        "energy_last": st[-1]["energy"], "energy_min": min(x["energy"] for x in st)})
         log(f"pass {p}: {dt:.2f}s, {len(st)} site steps, {passes[-1]['matvecs']} sigma-vectors, "
             f"E = {st[-1]['energy']:.10f}")
     avg = sum(x["s"] for x in passes) / len(passes)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle's block-sparse sigma at the middle site pair of the final MPS
+        # bonds, on every 4th middle-bond index, scaled to the sigma work of an
+        # average pass (sigma-vectors only: the host Davidson, split and
+        # environment updates of a CPU sweep would come on top)
+        i_mid = K // 2 - 1
+        cb = cpu_baseline(d.mpo, d.bonds, i_mid, stride=4)
+        work = sum(x["sigma_tflop"] for x in passes) / len(passes) * 1e12
+        cpu = {"value": work / (cb["value"] * 1e9), "unit": "s/pass", "cores": cb["cores"], "kind": "oracle",
+               "sample": cb["sample"] + f" at sites ({i_mid},{i_mid + 1}); {cb['value']:.1f} GFLOP/s applied to the "
+                         f"{work / 1e12:.2f} TFLOP of sigma-vector work of an average pass (sigma-vectors only)",
+               "value_1thread": work / (cb["value_1thread"] * 1e9), "oracle_gflops": cb["value"],
+               "oracle_gflops_1thread": cb["value_1thread"], "host_cpus": cb["host_cpus"]}
+        log(f"cpu baseline: {cpu['value']:.1f} s/pass at {cb['value']:.1f} GFLOP/s ({cb['cores']} threads)")
     print(json.dumps({
         "metric": "two-site DMRG pass wall time", "value": avg, "unit": "s/pass", "n_gpus": 1,
         "steps": args.steps, "warmup": 0, "ms_per_step": 1e3 * avg, "higher_is_better": False,
@@ -517,7 +533,7 @@ def bench_sweep(args):
                                + ("NC-partition MPO" if switch is None else f"NC-partition MPO up to cut {switch}, CN after"),
                    "orbitals": K, "bond_dim": M, "davidson": {"tol": args.tol, "max_iter": args.max_iter},
                    "mpo_bond_dims": [len(x) for x in d.mpo.dq]},
-        "passes": passes, "peak_gpu_gb": torch.cuda.max_memory_allocated() / 1e9}))
+        "passes": passes, "peak_gpu_gb": torch.cuda.max_memory_allocated() / 1e9, "cpu_baseline": cpu}))
 
 
 def mixed_compare(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device, seeds=5):

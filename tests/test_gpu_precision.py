@@ -120,13 +120,13 @@ def test_mixed_davidson_reaches_fp64_energy(device):
     e32, _, _ = Davidson(n, 24, device).solve(mv32, psi0, diag, tol=1e-5, max_iter=200)
     em, rm, n32, n64 = Davidson(n, 24, device).solve_mixed(mv32, mv, psi0, diag, tol=1e-9, max_iter=200)
     eb, rb_, nb16, nb64 = Davidson(n, 24, device).solve_mixed(mvb, mv, psi0, diag, tol=1e-9, max_iter=200,
-                                                              low_tol=3e-3, floor=3e-2)
+                                                              low_tol=3e-3)
     print(f"bf16 mixed: E {eb:.12f} ({nb16} bf16 + {nb64} f64 matvecs)", flush=True)
     assert rb_ < 1e-9 and abs(eb - e64) < 1e-10
     # a warm start already below what BF16 products resolve: the BF16 phase gives up
     # within a few iterations instead of running to max_iter
     ew, rw, nw16, nw64 = Davidson(n, 24, device).solve_mixed(mvb, mv, dav.x.clone(), diag, tol=1e-9, max_iter=200,
-                                                             low_tol=1e-12, floor=3e-2)
+                                                             low_tol=1e-12)
     print(f"bf16 mixed from the converged vector: {nw16} bf16 + {nw64} f64 matvecs", flush=True)
     assert nw16 <= 16 and rw < 1e-9 and abs(ew - e64) < 1e-10
     e_fci = fock.fci_energy(h, g, K, 0)
