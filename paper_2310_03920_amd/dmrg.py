@@ -14,6 +14,9 @@ Passes alternate: left-to-right i = i0..K-2, right-to-left i = K-3..0, where a
 pass's end pair is split towards the next pass.
 """
 
+import os
+import threading
+
 import numpy as np
 
 from . import _lib as X
@@ -95,6 +98,29 @@ def _keep_order(cand):
     return out
 
 
+_svd_pool = None
+_svd_lock = threading.Lock()
+
+
+def _sector_svds(mats):
+    """Full SVDs of the fused-sector matrices, several at once on a host thread pool
+    with one BLAS thread each (LAPACK releases the GIL), largest first; the results
+    do not depend on the scheduling."""
+    global _svd_pool
+    if len(mats) < 2:
+        return [np.linalg.svd(m, full_matrices=True) for m in mats]
+    from threadpoolctl import threadpool_limits
+    with _svd_lock:
+        if _svd_pool is None:
+            from concurrent.futures import ThreadPoolExecutor
+            _svd_pool = ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1)),
+                                           thread_name_prefix="heffx-svd")
+        order = sorted(range(len(mats)), key=lambda j: -mats[j].size)
+        with threadpool_limits(limits=1, user_api="blas"):
+            done = dict(zip(order, _svd_pool.map(lambda j: np.linalg.svd(mats[j], full_matrices=True), order)))
+    return [done[j] for j in range(len(mats))]
+
+
 def split(psi, bl, br, M, direction, fixed=None, info=None):
     """SVD split of a two-site tensor.
 
@@ -109,9 +135,10 @@ def split(psi, bl, br, M, direction, fixed=None, info=None):
     groups = _fused_sectors(psi, bl, br)
     cand = []
     fac = {}
-    for Q in sorted(groups):
-        mat, ro, co = _matrix(groups[Q])
-        U, S, Vt = np.linalg.svd(mat, full_matrices=True)
+    qs = sorted(groups)
+    mats = [_matrix(groups[Q]) for Q in qs]
+    svds = _sector_svds([m for m, _, _ in mats])
+    for Q, (mat, ro, co), (U, S, Vt) in zip(qs, mats, svds):
         n = U.shape[0] if direction == 0 else Vt.shape[0]
         s_full = np.zeros(n)
         s_full[:len(S)] = S
