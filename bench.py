@@ -505,6 +505,8 @@ def bench_sweep(args):
         st = d.log[n0:]
         passes.append({"s": dt, "site_steps": len(st), "matvecs": int(sum(x["n_matvec"] for x in st)),
                        "sigma_tflop": sum(x["n_matvec"] * x["sigma_flop"] for x in st) / 1e12,
+                       "host_wall_s": {k: sum(x.get(k, 0.0) for x in st)
+                                       for k in ("t_contract", "t_plan", "t_solve", "t_split", "t_env")},
                        "energy_last": st[-1]["energy"], "energy_min": min(x["energy"] for x in st)})
         log(f"pass {p}: {dt:.2f}s, {len(st)} site steps, {passes[-1]['matvecs']} sigma-vectors, "
             f"E = {st[-1]['energy']:.10f}")

@@ -16,6 +16,7 @@ pass's end pair is split towards the next pass.
 
 import os
 import threading
+import time
 
 import numpy as np
 
@@ -433,8 +434,10 @@ class DMRG:
 
     def _step(self, i, psi0, pass_id):
         import torch
+        t0 = time.perf_counter()
         bl, br = self.bonds[i], self.bonds[i + 2]
         plan = self.eng.heff_plan(i, bl, br)
+        t1 = time.perf_counter()
         Lb, Rb = X.Bond(bl), X.Bond(br)
         L, R = self.eng.left[i], self.eng.right[i + 2]
         n = int(plan.info.psi_nnz)
@@ -468,7 +471,8 @@ class DMRG:
         # operators, intermediates) is only needed during the step
         plan.release_workspace()
         self.log.append({"pass": pass_id, "i": i, "energy": theta, "rnorm": rnorm, "n_matvec": nmv,
-                         "sigma_flop": float(plan.info.flops_useful)})
+                         "sigma_flop": float(plan.info.flops_useful),
+                         "t_plan": t1 - t0, "t_solve": time.perf_counter() - t1})
         return psi
 
     def _split_logged(self, psi, i, direction):
@@ -479,21 +483,34 @@ class DMRG:
         self.log[-1].update(discarded=disc, bond=list(nb), kept_s=info["kept_s"])
         return nb, canon, centre
 
+    def _timed(self, key, t0):
+        """Host wall time since t0 into the step's log record (GPU work is
+        asynchronous: an environment update shows up in the next step's solve)."""
+        t = time.perf_counter()
+        self.log[-1][key] = self.log[-1].get(key, 0.0) + t - t0
+        return t
+
     def sweep_left_to_right(self, pass_id, start):
         K = self.K
         for i in range(start, K - 1):
+            t0 = time.perf_counter()
             if i == 0 and self.center is None:
                 psi0 = contract_two(self.tensors[0], self.tensors[1], self.bonds[0], self.bonds[1], self.bonds[2])
             else:
                 psi0 = contract_two(self.center, self.tensors[i + 1], self.bonds[i], self.bonds[i + 1],
                                     self.bonds[i + 2])
+            tc = time.perf_counter() - t0
             psi = self._step(i, psi0, pass_id)
+            self.log[-1]["t_contract"] = tc
+            t0 = time.perf_counter()
             if i < K - 2:
                 nb, A, C = self._split_logged(psi, i, 0)
                 self.bonds[i + 1] = nb
+                self.eng.prefetch_env_plan(0, i, self.bonds[i], self.bonds[i + 1])
                 self.eng.prefetch_heff_plan(i + 1, self.bonds[i + 1], self.bonds[i + 3])
                 self.tensors[i] = A
                 self.center, self.center_site = C, i + 1
+                t0 = self._timed("t_split", t0)
                 self.eng.update_left(i, self.bonds[i], self.bonds[i + 1],
                                      site_payload(self.bonds[i], self.bonds[i + 1], A, self.device))
             else:
@@ -501,19 +518,27 @@ class DMRG:
                 self.bonds[i + 1] = nb
                 self.tensors[i + 1] = B
                 self.center, self.center_site = C, i
+                t0 = self._timed("t_split", t0)
                 self.eng.update_right(i + 1, self.bonds[i + 1], self.bonds[i + 2],
                                       site_payload(self.bonds[i + 1], self.bonds[i + 2], B, self.device))
+            self._timed("t_env", t0)
 
     def sweep_right_to_left(self, pass_id):
         for i in range(self.K - 3, -1, -1):
+            t0 = time.perf_counter()
             psi0 = contract_two(self.tensors[i], self.center, self.bonds[i], self.bonds[i + 1], self.bonds[i + 2])
+            tc = time.perf_counter() - t0
             psi = self._step(i, psi0, pass_id)
+            self.log[-1]["t_contract"] = tc
+            t0 = time.perf_counter()
             if i > 0:
                 nb, B, C = self._split_logged(psi, i, 1)
                 self.bonds[i + 1] = nb
+                self.eng.prefetch_env_plan(1, i + 1, self.bonds[i + 1], self.bonds[i + 2])
                 self.eng.prefetch_heff_plan(i - 1, self.bonds[i - 1], self.bonds[i + 1])
                 self.tensors[i + 1] = B
                 self.center, self.center_site = C, i
+                t0 = self._timed("t_split", t0)
                 self.eng.update_right(i + 1, self.bonds[i + 1], self.bonds[i + 2],
                                       site_payload(self.bonds[i + 1], self.bonds[i + 2], B, self.device))
             else:
@@ -521,8 +546,10 @@ class DMRG:
                 self.bonds[i + 1] = nb
                 self.tensors[i] = A
                 self.center, self.center_site = C, i + 1
+                t0 = self._timed("t_split", t0)
                 self.eng.update_left(i, self.bonds[i], self.bonds[i + 1],
                                      site_payload(self.bonds[i], self.bonds[i + 1], A, self.device))
+            self._timed("t_env", t0)
 
     # -- one-site passes (Sec. II.A.2): the bond spaces are the ones the two-site
     # passes chose; each step solves the one-site H_eff and moves the centre with an

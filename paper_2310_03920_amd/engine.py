@@ -60,17 +60,34 @@ class Engine:
             cache.pop(old, None)
         self._latest[slot] = key
 
+    def _build_env(self, direction, k, bond_k, bond_k1):
+        if direction == 0:
+            return X.EnvPlan(0, bond_k, bond_k1, self.mpo.dq[k], self.mpo.dq[k + 1], self._w[k],
+                             t_budget_bytes=self.t_budget, **self.opts)
+        return X.EnvPlan(1, bond_k1, bond_k, self.mpo.dq[k + 1], self.mpo.dq[k], self._w[k],
+                         t_budget_bytes=self.t_budget, **self.opts)
+
+    def _submit(self, fn, *args):
+        if self._pool is None:
+            from concurrent.futures import ThreadPoolExecutor
+            self._pool = ThreadPoolExecutor(max_workers=2, thread_name_prefix="heffx-plan")
+        return self._pool.submit(fn, *args)
+
+    def prefetch_env_plan(self, direction, k, bond_k, bond_k1):
+        """Start the host build of an environment-update plan on a worker thread (as
+        prefetch_heff_plan); env_plan collects it."""
+        key = ("env", direction, k, self._bkey(bond_k), self._bkey(bond_k1))
+        if (direction, k, self._bkey(bond_k), self._bkey(bond_k1)) in self._env_plans or key in self._pending:
+            return
+        self._pending[key] = self._submit(self._build_env, direction, k, list(bond_k), list(bond_k1))
+
     def env_plan(self, direction, k, bond_k, bond_k1):
         key = (direction, k, self._bkey(bond_k), self._bkey(bond_k1))
         p = self._env_plans.get(key)
         if p is None:
             self._keep_latest(self._env_plans, ("env", direction, k), key)
-            if direction == 0:
-                p = X.EnvPlan(0, bond_k, bond_k1, self.mpo.dq[k], self.mpo.dq[k + 1], self._w[k],
-                              t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
-            else:
-                p = X.EnvPlan(1, bond_k1, bond_k, self.mpo.dq[k + 1], self.mpo.dq[k], self._w[k],
-                              t_budget_bytes=self.t_budget, **self.opts).upload(self.device)
+            fut = self._pending.pop(("env",) + key, None)
+            p = (fut.result() if fut is not None else self._build_env(direction, k, bond_k, bond_k1)).upload(self.device)
             self._env_plans[key] = p
         return p
 
@@ -87,10 +104,7 @@ class Engine:
         key = (i, self._bkey(bond_i), self._bkey(bond_i2))
         if key in self._heff_plans or key in self._pending:
             return
-        if self._pool is None:
-            from concurrent.futures import ThreadPoolExecutor
-            self._pool = ThreadPoolExecutor(max_workers=1, thread_name_prefix="heffx-plan")
-        self._pending[key] = self._pool.submit(self._build_heff, i, list(bond_i), list(bond_i2))
+        self._pending[key] = self._submit(self._build_heff, i, list(bond_i), list(bond_i2))
 
     def heff_plan(self, i, bond_i, bond_i2):
         key = (i, self._bkey(bond_i), self._bkey(bond_i2))
