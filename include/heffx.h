@@ -367,9 +367,11 @@ int hx_heff_apply_f32(const hx_plan* plan, const float* L32, const float* R32, v
                       float* sigma32, hx_stream stream);
 
 /* sigma32 = H_eff psi32 with the block products in BF16 on the matrix cores
- * (v_mfma_f32_16x16x16_bf16, FP32 accumulation): operands are read in FP32 from
- * the same buffers as hx_heff_apply_f32 and rounded to BF16 (nearest even) when
- * staged, the stage-1 intermediate is kept in FP32 between the two rounds.
+ * (FP32 accumulation; v_mfma_f32_16x16x32_bf16 on 32-deep K stages with the
+ * one-buffer kernel variants 1, 5 and 6, v_mfma_f32_16x16x16_bf16 on 16-deep stages
+ * with variants 0 and 4): operands are read in FP32 from the same buffers as
+ * hx_heff_apply_f32 and rounded to BF16 (nearest even) when staged, the stage-1
+ * intermediate is kept in FP32 between the two rounds.
  * Relative operand precision 2^-9, so sigma carries ~1e-3 relative error; the
  * Davidson work stays FP64 (mixed-precision mode).  Needs a 16-deep kernel
  * variant (HX_EUNSUP for kernel_variant 2). */

@@ -27,6 +27,7 @@ using namespace hx;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
 
 // FP32 -> BF16 with round-to-nearest-even on the bit pattern (finite inputs).
 __device__ __forceinline__ unsigned short to_bf16(float x) {
@@ -130,13 +131,16 @@ template <typename T, bool TA, bool TB, int NSP, int KSV, int NBUF, bool BF = fa
 __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, const Task* __restrict__ tasks,
                                               BasesT<T> B, int ntile) {
     using acc_t = typename std::conditional<std::is_same<T, double>::value, dbl4, flt4>::type;
-    static_assert(KSV == 8 || KSV == 16, "stage depth");
-    static_assert(!BF || (std::is_same<T, float>::value && KSV == 16), "BF16 products: FP32 storage, 16-deep stages");
+    static_assert(KSV == 8 || KSV == 16 || (KSV == 32 && std::is_same<T, float>::value), "stage depth");
+    static_assert(!BF || (std::is_same<T, float>::value && KSV >= 16), "BF16 products: FP32 storage, 16-deep stages");
     static_assert(WR == 1 || WR == 2 || WR == 4, "wave layout");
+    // KSV 32 (FP32 storage): a stage is two consecutive 16-deep K segments of the
+    // plan (every task's K is padded to 16), each inside one task, possibly two tasks
+    constexpr int KP = KSV == 32 ? 16 : KSV;  // K segment of the plan walked by the cursor
     constexpr int TMS = 32 * WR, TNS = 32 * (4 / WR);  // tile extent
     constexpr int NEA = TMS * KSV / 256;  // elements of A each thread stages per K stage
     constexpr int NEB = TNS * KSV / 256;  // ... and of B
-    constexpr int LDB = KSV + 4; // BF16 row pitch (8-byte aligned rows)
+    constexpr int LDB = KSV == 32 ? 40 : KSV + 4; // BF16 row pitch (8- / 16-byte aligned rows)
     __shared__ T As[BF ? 1 : NBUF][BF ? 1 : KSV][BF ? 1 : TMS + LDS_PAD];
     __shared__ T Bs[BF ? 1 : NBUF][BF ? 1 : KSV][BF ? 1 : TNS + LDS_PAD];
     __shared__ __attribute__((aligned(16))) unsigned short Ah[BF ? NBUF : 1][BF ? TMS : 1][BF ? LDB : 1];
@@ -165,10 +169,13 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     T alpha = 0;
 
     // Loader of the tile's K stages and the stage held in ra / rb.
-    Cursor<T, TA, TB, NSP, KSV> cur;
+    Cursor<T, TA, TB, NSP, KP> cur;
     int lm = 0, ln = 0, lr0 = 0, lc0 = 0;       // extent and origin of the loader's tile
     int krem_ld = 0, m_ld = 0, n_ld = 0;         // valid depth / extent of the held stage
+    int krem_ld2 = 0;                            // KSV 32: valid depth of its second segment
+    T alpha2 = 0;                                // ... and that segment's coefficient
     int kst0 = 0, kst1 = 0;                      // valid depth of the stage in LDS buffer 0 / 1
+    int kst0b = 0;                               // KSV 32, one buffer: of its second segment
     auto bind_loader = [&](const Tile& x) {
         lm = x.m;
         ln = x.n;
@@ -187,6 +194,22 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         int krem;
         cur.next(tasks, B, lr0, lc0, qa, qb, krem, alpha);
         const int lda = cur.lda, ldb = cur.ldb;
+        // KSV 32: the second segment (qa2, qb2; lda2, ldb2); without one (the tile's
+        // last stage), the first segment's addresses stand in and are zeroed at the store
+        const T *qa2 = qa, *qb2 = qb;
+        int krem2 = 0, lda2 = lda, ldb2 = ldb;
+        if constexpr (KSV == 32) {
+            const T *pa, *pb;
+            T al;
+            cur.next(tasks, B, lr0, lc0, pa, pb, krem2, al);
+            if (krem2 > 0) {
+                qa2 = pa;
+                qb2 = pb;
+                lda2 = cur.lda;
+                ldb2 = cur.ldb;
+                alpha2 = al;
+            }
+        }
 #pragma unroll
         for (int e = 0; e < NEA; ++e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
@@ -194,6 +217,12 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
                 T va = 0;
                 if (ka < krem && r < lm) va = qa[TA ? ka * lda + r : r * lda + ka];
                 ra[e] = va;
+            } else if constexpr (KSV == 32) {
+                const bool h = ka >= KP;  // the element's segment
+                const int kk = ka & (KP - 1), kr = h ? krem2 : krem, ld = h ? lda2 : lda;
+                const T* q = h ? qa2 : qa;
+                const int rc = min(r, lm - 1), kac = max(min(kk, kr - 1), 0);
+                ra[e] = q[TA ? kac * ld + rc : rc * ld + kac];
             } else {
                 const int rc = min(r, lm - 1), kac = min(ka, krem - 1);
                 ra[e] = qa[TA ? kac * lda + rc : rc * lda + kac];
@@ -206,12 +235,19 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
                 T vb = 0;
                 if (kb < krem && c < ln) vb = qb[TB ? c * ldb + kb : kb * ldb + c];
                 rb[e] = vb;
+            } else if constexpr (KSV == 32) {
+                const bool h = kb >= KP;
+                const int kk = kb & (KP - 1), kr = h ? krem2 : krem, ld = h ? ldb2 : ldb;
+                const T* q = h ? qb2 : qb;
+                const int cc = min(c, ln - 1), kbc = max(min(kk, kr - 1), 0);
+                rb[e] = q[TB ? cc * ld + kbc : kbc * ld + cc];
             } else {
                 const int cc = min(c, ln - 1), kbc = min(kb, krem - 1);
                 rb[e] = qb[TB ? cc * ldb + kbc : kbc * ldb + cc];
             }
         }
         krem_ld = krem;
+        krem_ld2 = krem2;
         m_ld = lm;
         n_ld = ln;
     };
@@ -220,12 +256,17 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
             kst0 = krem_ld;
         else
             kst1 = krem_ld;
+        kst0b = krem_ld2;
         // FP64 loads are already zero outside the block (guarded loads)
         constexpr bool guarded = std::is_same<T, double>::value;
+        // valid depth and coefficient of the segment holding stage row k
+        auto seg_krem = [&](int k) { return (KSV == 32 && k >= KP) ? krem_ld2 : krem_ld; };
+        auto seg_k = [&](int k) { return KSV == 32 ? (k & (KP - 1)) : k; };
 #pragma unroll
         for (int e = 0; e < NEA; ++e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
-            const T fa = (guarded || (ka < krem_ld && r < m_ld)) ? alpha : (T)0;
+            const T al = (KSV == 32 && ka >= KP) ? alpha2 : alpha;
+            const T fa = (guarded || (seg_k(ka) < seg_krem(ka) && r < m_ld)) ? al : (T)0;
             if constexpr (BF)
                 Ah[buf][r][ka] = to_bf16(fa * ra[e]);
             else
@@ -234,7 +275,7 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
 #pragma unroll
         for (int e = 0; e < NEB; ++e) {
             const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
-            const T vb = (guarded || (kb < krem_ld && c < n_ld)) ? rb[e] : (T)0;
+            const T vb = (guarded || (seg_k(kb) < seg_krem(kb) && c < n_ld)) ? rb[e] : (T)0;
             if constexpr (BF)
                 Bh[buf][c][kb] = to_bf16(vb);
             else
@@ -250,7 +291,21 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     auto mma_stage = [&](int buf, auto ACT, auto R1, auto C1) {
         if constexpr (ACT.value) {
             constexpr bool r1c = decltype(R1)::value, c1c = decltype(C1)::value;
-            if constexpr (BF) {
+            if constexpr (BF && KSV == 32) {
+                // one v_mfma_f32_16x16x32_bf16 per 16 x 16 block and stage: lane l holds
+                // 8 consecutive k of its row (A) and of its column (B), the same k for both
+                const int kq = 8 * (lane >> 4), rl = lane & 15;
+                const bf16x8 a0 = *reinterpret_cast<const bf16x8*>(&Ah[buf][wr0 + rl][kq]);
+                const bf16x8 b0 = *reinterpret_cast<const bf16x8*>(&Bh[buf][wc0 + rl][kq]);
+                bf16x8 a1 = {0, 0, 0, 0, 0, 0, 0, 0}, b1 = {0, 0, 0, 0, 0, 0, 0, 0};
+                if constexpr (r1c) a1 = *reinterpret_cast<const bf16x8*>(&Ah[buf][wr0 + 16 + rl][kq]);
+                if constexpr (c1c) b1 = *reinterpret_cast<const bf16x8*>(&Bh[buf][wc0 + 16 + rl][kq]);
+                acc00 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc00, 0, 0, 0);
+                if constexpr (c1c) acc01 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc01, 0, 0, 0);
+                if constexpr (r1c) acc10 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc10, 0, 0, 0);
+                if constexpr (r1c && c1c)
+                    acc11 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc11, 0, 0, 0);
+            } else if constexpr (BF) {
                 const int kq = 4 * (lane >> 4), rl = lane & 15;
                 const bf16x4 a0 = *reinterpret_cast<const bf16x4*>(&Ah[buf][wr0 + rl][kq]);
                 const bf16x4 b0 = *reinterpret_cast<const bf16x4*>(&Bh[buf][wc0 + rl][kq]);
@@ -264,35 +319,43 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
                     acc11 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc11, 0, 0, 0);
             } else {
                 // 4-deep steps past the stage's valid depth (the zero padding of a
-                // task's last stage) are skipped: a uniform branch per step
-                const int kcur = NBUF == 1 ? kst0 : KSV;  // (two buffers: no skipping; a per-buffer
-                                                          // depth would put the operand arrays in scratch)
-                constexpr int NK = KSV / 4;
-                T a0[NK], a1[NK], b0[NK], b1[NK];
-                auto rd = [&](int ks) {
-                    const int kr = ks * 4 + (lane >> 4);
-                    a0[ks] = As[buf][kr][wr0 + (lane & 15)];
-                    b0[ks] = Bs[buf][kr][wc0 + (lane & 15)];
-                    if constexpr (r1c) a1[ks] = As[buf][kr][wr0 + 16 + (lane & 15)];
-                    if constexpr (c1c) b1[ks] = Bs[buf][kr][wc0 + 16 + (lane & 15)];
-                };
-                rd(0);
+                // task's last stage) are skipped: a uniform branch per step.  KSV 32 runs
+                // its two 16-deep segments one after the other, each with its own
+                // operand registers, so no more of them are live than at KSV 16.
+                constexpr int NH = KSV == 32 ? 2 : 1;   // segments of the stage
+                constexpr int NK = (KSV == 32 ? 16 : KSV) / 4;  // 4-deep steps per segment
 #pragma unroll
-                for (int ks = 0; ks < NK; ++ks) {
-                    if (ks * 4 >= kcur) continue;  // (no break: keeps the loop fully unrolled)
-                    if (ks + 1 < NK && (ks + 1) * 4 < kcur) rd(ks + 1);
-                    if constexpr (std::is_same<T, double>::value) {
-                        acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], b0[ks], acc00, 0, 0, 0);
-                        if constexpr (c1c) acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], b1[ks], acc01, 0, 0, 0);
-                        if constexpr (r1c) acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[ks], b0[ks], acc10, 0, 0, 0);
-                        if constexpr (r1c && c1c)
-                            acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[ks], b1[ks], acc11, 0, 0, 0);
-                    } else {
-                        acc00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], b0[ks], acc00, 0, 0, 0);
-                        if constexpr (c1c) acc01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], b1[ks], acc01, 0, 0, 0);
-                        if constexpr (r1c) acc10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], b0[ks], acc10, 0, 0, 0);
-                        if constexpr (r1c && c1c)
-                            acc11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], b1[ks], acc11, 0, 0, 0);
+                for (int hs = 0; hs < NH; ++hs) {
+                    // (two buffers: no skipping; a per-buffer depth would put the operand
+                    // arrays in scratch)
+                    const int kcur = NBUF == 1 ? (hs == 0 ? kst0 : kst0b) : KSV;
+                    T a0[NK], a1[NK], b0[NK], b1[NK];
+                    auto rd = [&](int ks) {
+                        const int kr = hs * 16 + ks * 4 + (lane >> 4);
+                        a0[ks] = As[buf][kr][wr0 + (lane & 15)];
+                        b0[ks] = Bs[buf][kr][wc0 + (lane & 15)];
+                        if constexpr (r1c) a1[ks] = As[buf][kr][wr0 + 16 + (lane & 15)];
+                        if constexpr (c1c) b1[ks] = Bs[buf][kr][wc0 + 16 + (lane & 15)];
+                    };
+                    if (kcur <= 0) continue;  // (the stage's second segment may be empty)
+                    rd(0);
+#pragma unroll
+                    for (int ks = 0; ks < NK; ++ks) {
+                        if (ks * 4 >= kcur) continue;  // (no break: keeps the loop fully unrolled)
+                        if (ks + 1 < NK && (ks + 1) * 4 < kcur) rd(ks + 1);
+                        if constexpr (std::is_same<T, double>::value) {
+                            acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], b0[ks], acc00, 0, 0, 0);
+                            if constexpr (c1c) acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[ks], b1[ks], acc01, 0, 0, 0);
+                            if constexpr (r1c) acc10 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[ks], b0[ks], acc10, 0, 0, 0);
+                            if constexpr (r1c && c1c)
+                                acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[ks], b1[ks], acc11, 0, 0, 0);
+                        } else {
+                            acc00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], b0[ks], acc00, 0, 0, 0);
+                            if constexpr (c1c) acc01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[ks], b1[ks], acc01, 0, 0, 0);
+                            if constexpr (r1c) acc10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], b0[ks], acc10, 0, 0, 0);
+                            if constexpr (r1c && c1c)
+                                acc11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[ks], b1[ks], acc11, 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -303,7 +366,7 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
     if (tl.ktot > 0) load_stage();
     {
         const int m = tl.m, n = tl.n;
-        const int nst = tl.ktot / KSV;
+        const int nst = (tl.ktot + KSV - 1) / KSV;
         // 16 x 16 MFMA blocks wholly outside the tile's extent are skipped (wave-uniform
         // branches), so matrix-core work follows the block shape at 16 x 16 granularity
         const bool r1 = wr0 + 16 < m, c1 = wc0 + 16 < n;
@@ -907,13 +970,17 @@ static int launch_gemm(const Plan* P, const Launch& L, const BasesT<T>& B, hipSt
     auto shaped = [&](auto KIND_NBUF, auto BFC) -> int {
         constexpr int NB = decltype(KIND_NBUF)::value;
         constexpr bool BFv = decltype(BFC)::value;
+        // BF16 products with one LDS buffer: 32-deep stages (two 16-deep segments of
+        // the plan) on the full-rate v_mfma_f32_16x16x32_bf16.  (FP32 products in
+        // 32-deep stages measured slower: 86-94 registers, 5 waves per SIMD against 8.)
+        constexpr int KS = (BFv && NB == 1) ? 32 : 16;
         switch (L.shape) {
             case SH_TALL:
-                return launch_kind<T, NSP, 16, NB, BFv, 4>(L.kind, nt, tiles, tasks, B, s);
+                return launch_kind<T, NSP, KS, NB, BFv, 4>(L.kind, nt, tiles, tasks, B, s);
             case SH_WIDE:
-                return launch_kind<T, NSP, 16, NB, BFv, 1>(L.kind, nt, tiles, tasks, B, s);
+                return launch_kind<T, NSP, KS, NB, BFv, 1>(L.kind, nt, tiles, tasks, B, s);
             default:
-                return launch_kind<T, NSP, 16, NB, BFv, 2>(L.kind, nt, tiles, tasks, B, s);
+                return launch_kind<T, NSP, KS, NB, BFv, 2>(L.kind, nt, tiles, tasks, B, s);
         }
     };
     using One = std::integral_constant<int, 1>;
