@@ -125,6 +125,18 @@ def cpu_baseline(mpo, bonds, i, stride=8, seed=5):
             "value_1thread": legs[1][0], "seconds_1thread": legs[1][2], "host_cpus": ncpu}
 
 
+def calibration_copy(device):
+    """A plain device copy of known size (2^26 doubles read, 2^26 written) that closes
+    a run: per-dispatch HBM byte counters of the run's kernels are scaled by what the
+    same counters read for it."""
+    import torch
+    src = torch.ones(1 << 26, dtype=torch.float64, device=device)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def batch_instances(X, M=256, K=16, count=16):
     """The mixed-size batch: `count` independent two-site problems of a K-orbital
     chain at bond dimension M; instance j (1-based) has integrals seed j,
@@ -153,13 +165,16 @@ def bench_batch(args):
     t0 = time.time()
     insts = batch_instances(X, M=args.bond_dim, K=args.orbitals, count=args.instances)
 
+    # intermediate budget per instance: by default every instance in one chunk
+    budget = int(args.batch_t_budget_mb * (1 << 20)) if args.batch_t_budget_mb else 1 << 40
+
     def make_plans(opts):
         ps = []
         for d in insts:
             m = d["mpo"]
             i = d["i"]
             ps.append(X.HeffPlan(d["lbond"], d["rbond"], m.dq[i], m.dq[i + 1], m.dq[i + 2], d["W1"], d["W2"],
-                                 t_budget_bytes=1 << 40, **opts))
+                                 t_budget_bytes=budget, **opts))
         return ps
 
     opts = {"split_kseg_min": args.kseg or 2048, "kernel_variant": 0 if args.variant is None else args.variant,
@@ -275,6 +290,7 @@ def bench_batch(args):
     t_one, w_one = timed(one_by_one, reps)
     t_bat, w_bat = timed(batched, reps)
     t_gr, w_gr = timed(graph.launch, reps)
+    calibration_copy(device)
     fl = B.info.flops_useful
     peak = PEAKS[args.mode]
     achieved = fl / t_gr / 1e12
@@ -298,6 +314,7 @@ def bench_batch(args):
                         f"sigma-vector replayed from a HIP graph",
             "instances": len(plans), "bond_dim": args.bond_dim, "orbitals": args.orbitals,
             "psi_nnz_total": int(B.info.psi_nnz), "tiles": int(B.info.n_tiles), "plan_opts": opts,
+            "t_budget_per_instance_bytes": budget, "rounds_chunks": int(B.info.n_chunks),
             "autotune_s": tune_s,
         },
         "batch": {"gflop": fl / 1e9, "one_by_one_ms": 1e3 * t_one, "batched_ms": 1e3 * t_bat,
@@ -398,13 +415,7 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
     peak = PEAKS[args.mode]
     achieved = info.flops_useful / avg / 1e12
     parts = middle_bond_parts(args, X, mpo, bonds, i, Lenv, Renv, opts, psi, device) if args.bparts > 1 else None
-    # a plain device copy of known size (2^26 doubles read, 2^26 written) closes the
-    # run: the per-dispatch HBM counters of the sigma-vector are scaled by its counts
-    src = torch.ones(1 << 26, dtype=torch.float64, device=device)
-    dst = torch.empty_like(src)
-    torch.cuda.synchronize()
-    dst.copy_(src)
-    torch.cuda.synchronize()
+    calibration_copy(device)
     print(json.dumps({
         "metric": METRIC, "value": info.flops_useful / avg / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": 1e3 * avg, "higher_is_better": True,
@@ -655,6 +666,8 @@ def main():
     ap.add_argument("--kmax", type=int, default=24, help="Davidson subspace size (at most 32)")
     ap.add_argument("--pre-iter", type=int, default=100)
     ap.add_argument("--t-budget-gb", type=float, default=1.0)
+    ap.add_argument("--batch-t-budget-mb", type=float, default=0.0,
+                    help="batch: intermediate budget per instance in MiB (0: one chunk per instance)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", choices=["f64", "f32", "bf16"], default="f64",
                     help="precision of the block contractions; Davidson is FP64 in all")

@@ -288,10 +288,14 @@ int hx_heff_apply_backward_f32(const hx_plan* plan, const float* L32, const floa
 
 /* ---- batching: many independent sigma-vector problems per launch ----------- */
 
-/* Merge n single-chunk sigma-vector plans (each built by hx_heff_plan_create
- * with an intermediate budget large enough for one chunk; HX_EUNSUP otherwise)
- * into one plan whose prepare, apply and diag stages each issue the same
- * number of launches as ONE instance, every launch covering all instances.
+/* Merge n sigma-vector plans (each built by hx_heff_plan_create; HX_EUNSUP for
+ * other plan kinds) into one plan whose prepare, apply and diag stages issue
+ * their launches round by round: the k-th launch of the merged sequence covers
+ * the next launch of every instance that has one (of the same GEMM form and
+ * tile shape).  Single-chunk instances give the same number of launches as ONE
+ * instance, each covering all instances; an instance split into several
+ * intermediate chunks takes part in as many rounds as its own sequence has, so
+ * a small budget per instance keeps each round's intermediates small.
  * This is the data parallelism across independent two-site problems (several
  * states, sites or molecules) that the sweep of Sec. II.A.2 does not expose
  * within one step.  Instance i's operands are placed in concatenated buffers:

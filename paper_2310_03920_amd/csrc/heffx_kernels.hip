@@ -29,12 +29,10 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef short bf16x8 __attribute__((ext_vector_type(8)));
 
-// FP32 -> BF16 with round-to-nearest-even on the bit pattern (finite inputs).
-__device__ __forceinline__ unsigned short to_bf16(float x) {
-    unsigned int u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
-}
+// FP32 -> BF16 bit pattern, round to nearest even (v_cvt_pk_bf16_f32, low half).
+// Each value is converted on its own: this compiler lowers a two-element vector
+// conversion to one instruction that reads the first element twice.
+__device__ __forceinline__ unsigned short to_bf16(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
 
 template <typename T>
 struct BasesT {
@@ -262,24 +260,34 @@ __global__ __launch_bounds__(256) void bsgemm(const Tile* __restrict__ tiles, co
         // valid depth and coefficient of the segment holding stage row k
         auto seg_krem = [&](int k) { return (KSV == 32 && k >= KP) ? krem_ld2 : krem_ld; };
         auto seg_k = [&](int k) { return KSV == 32 ? (k & (KP - 1)) : k; };
-#pragma unroll
-        for (int e = 0; e < NEA; ++e) {
+        auto a_val = [&](int e) {
             const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
             const T al = (KSV == 32 && ka >= KP) ? alpha2 : alpha;
             const T fa = (guarded || (seg_k(ka) < seg_krem(ka) && r < m_ld)) ? al : (T)0;
-            if constexpr (BF)
-                Ah[buf][r][ka] = to_bf16(fa * ra[e]);
-            else
-                As[buf][ka][r] = fa * ra[e];
-        }
-#pragma unroll
-        for (int e = 0; e < NEB; ++e) {
+            return fa * ra[e];
+        };
+        auto b_val = [&](int e) {
             const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
-            const T vb = (guarded || (seg_k(kb) < seg_krem(kb) && c < n_ld)) ? rb[e] : (T)0;
-            if constexpr (BF)
-                Bh[buf][c][kb] = to_bf16(vb);
-            else
-                Bs[buf][kb][c] = vb;
+            return (guarded || (seg_k(kb) < seg_krem(kb) && c < n_ld)) ? rb[e] : (T)0;
+        };
+        if constexpr (BF) {
+#pragma unroll
+            for (int e = 0; e < NEA; ++e) Ah[buf][a_r + a_dr * e][a_k + a_dk * e] = to_bf16(a_val(e));
+#pragma unroll
+            for (int e = 0; e < NEB; ++e) Bh[buf][b_c + b_dc * e][b_k + b_dk * e] = to_bf16(b_val(e));
+        } else {
+#pragma unroll
+            for (int e = 0; e < NEA; ++e) {
+                const int r = a_r + a_dr * e, ka = a_k + a_dk * e;
+                const T al = (KSV == 32 && ka >= KP) ? alpha2 : alpha;
+                const T fa = (guarded || (seg_k(ka) < seg_krem(ka) && r < m_ld)) ? al : (T)0;
+                As[buf][ka][r] = fa * ra[e];
+            }
+#pragma unroll
+            for (int e = 0; e < NEB; ++e) {
+                const int c = b_c + b_dc * e, kb = b_k + b_dk * e;
+                Bs[buf][kb][c] = (guarded || (seg_k(kb) < seg_krem(kb) && c < n_ld)) ? rb[e] : (T)0;
+            }
         }
     };
 

@@ -2285,11 +2285,11 @@ static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
             set_error("plan_batch: instances use different kernel variants");
             return HX_EUNSUP;
         }
-        if (P.kind != PK_HEFF || P.n_chunks != 1) {
-            set_error("plan_batch: every instance must be a single-chunk sigma-vector plan "
-                      "(raise t_budget_bytes)");
+        if (P.kind != PK_HEFF) {
+            set_error("plan_batch: every instance must be a sigma-vector plan");
             return HX_EUNSUP;
         }
+        M.n_chunks = std::max(M.n_chunks, P.n_chunks);
         off[i].fill(0);
         off[i][SP_PSI] = off[i][SP_OUT] = o_psi;
         off[i][SP_L] = o_L;
@@ -2325,10 +2325,11 @@ static int merge_plans(const std::vector<const Plan*>& in, Plan& M) {
         sp_out = sp == SP_PART ? SP_WS : sp;
         return off_in + off[i][sp];
     };
-    // merge the k-th launches of each instance's sequence into one launch
-    // Each instance's launches stay in their order; the next launches of all instances
-    // that share kind and tile shape are merged into one (instances touch disjoint data,
-    // so only the order within an instance matters).
+    // Merge the instances' launch sequences round by round: each instance's launches
+    // stay in their order; the next launches of all instances that share kind and tile
+    // shape are merged into one (instances touch disjoint data, so only the order
+    // within an instance matters).  Chunked instances (several intermediate chunks)
+    // take part in as many rounds as they have launches.
     auto merge_seq = [&](std::vector<Launch> Plan::*seq, std::vector<Launch>& out) -> int {
         std::vector<size_t> pos(in.size(), 0);
         for (;;) {

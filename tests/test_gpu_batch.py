@@ -16,15 +16,16 @@ pytestmark = pytest.mark.gpu
 CASES = [(0, False, 0), (1, True, 0), (2, False, 8), (3, True, 16), (4, True, 0)]
 
 
-def _instances(device, cases=CASES, variant=0):
+def _instances(device, cases=CASES, variant=0, budget=None):
     import torch
     from paper_2310_03920_amd import _lib as X
     out = []
+    extra = {} if budget is None else {"t_budget_bytes": budget}
     for seed, big, kseg in cases:
         prob = _problem(seed, big)
         lb, rb, Ldq, Mdq, Rdq, L, R, W1, W2, psi = prob
         lbB, rbB = X.Bond(lb), X.Bond(rb)
-        plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, split_kseg_min=kseg, kernel_variant=variant)
+        plan = X.HeffPlan(lbB, rbB, Ldq, Mdq, Rdq, W1, W2, split_kseg_min=kseg, kernel_variant=variant, **extra)
         arrs = (X.pack_env(lbB, Ldq, L), X.pack_env(rbB, Rdq, R), X.pack_psi(lbB, rbB, psi))
         out.append((prob, plan, arrs))
     return out
@@ -61,14 +62,18 @@ def _individual(device, plan, arrs, f32=False):
     return res
 
 
-@pytest.mark.parametrize("variant", [0, 5, 6])
-def test_batched_apply_and_diag_match_instances_bitwise(device, variant):
+@pytest.mark.parametrize("variant,budget", [(0, None), (5, None), (6, None), (1, 96 * 1024)])
+def test_batched_apply_and_diag_match_instances_bitwise(device, variant, budget):
     """Each instance of a batched plan gives, bit for bit, its own plan's sigma and
-    diag, in FP64 and FP32, for the two-buffer, tile-shape and single-wave kernels."""
+    diag, in FP64 and FP32, for the two-buffer, tile-shape and single-wave kernels,
+    and for instances split into several intermediate chunks (merged round by round)."""
     import torch
     from paper_2310_03920_amd import _lib as X
-    print(f"[batch] 5 instances, f64 + f32, variant {variant}", flush=True)
-    insts = _instances(device, variant=variant)
+    print(f"[batch] 5 instances, f64 + f32, variant {variant}, budget {budget}", flush=True)
+    insts = _instances(device, variant=variant, budget=budget)
+    if budget is not None:
+        chunks = [plan.info.n_chunks for _, plan, _ in insts]
+        assert max(chunks) > 2 and len(set(chunks)) > 1, chunks
     ref = [_individual(device, plan, arrs, f32=True) for _, plan, arrs in insts]
     B = X.BatchPlan([plan for _, plan, _ in insts]).upload(device)
     assert B.info.flops_apply == pytest.approx(sum(p.info.flops_apply for _, p, _ in insts), rel=1e-12)

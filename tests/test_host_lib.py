@@ -287,15 +287,25 @@ def test_batch_plan_concatenates_instances():
     assert B.offsets == [(int(a), int(b), int(c)) for a, b, c in zip(po, lo, ro)]
 
 
-def test_batch_plan_rejects_chunked_instance():
+def test_batch_plan_merges_chunked_instances_round_by_round():
+    """Instances split into different numbers of intermediate chunks merge into one
+    plan with all their work and tiles; the merged sequence is as long as the longest
+    instance's (one launch per round and form), not the sum."""
     K = 8
     m = M.build_nc_mpo(*make_integrals(K, seed=0))
     b = bond_sector_tables(K, K, 0, 64)
-    p = X.HeffPlan(b[3], b[5], m.dq[3], m.dq[4], m.dq[5], M.site_entries(m, 3), M.site_entries(m, 4),
-                   t_budget_bytes=64 * 1024)
-    assert p.info.n_chunks > 1
-    with pytest.raises(RuntimeError, match="single-chunk"):
-        X.BatchPlan([p])
+    args = (b[3], b[5], m.dq[3], m.dq[4], m.dq[5], M.site_entries(m, 3), M.site_entries(m, 4))
+    ps = [X.HeffPlan(*args, t_budget_bytes=64 * 1024), X.HeffPlan(*args, t_budget_bytes=256 * 1024),
+          X.HeffPlan(*args)]
+    chunks = [p.info.n_chunks for p in ps]
+    assert chunks[0] > chunks[1] > 1 and chunks[2] == 1
+    B = X.BatchPlan(ps)
+    assert B.info.n_chunks == chunks[0]
+    assert B.info.flops_apply == pytest.approx(sum(p.info.flops_apply for p in ps), rel=1e-12)
+    assert B.info.n_tiles == sum(p.info.n_tiles for p in ps)
+    assert B.info.ws_bytes == sum(p.info.ws_bytes for p in ps)
+    with pytest.raises(RuntimeError, match="sigma-vector plan"):
+        X.BatchPlan([X.EnvPlan(0, b[3], b[4], m.dq[3], m.dq[4], M.site_entries(m, 3))])
 
 
 def test_vjp_plan_builds_for_every_site_of_the_nc_mpo():
