@@ -420,7 +420,13 @@ int64_t hx_davidson_ws_bytes(int64_t n, int32_t kmax);
  *   raised to `guard` (sign kept, + for 0); t orthogonalised against V twice
  *   (classical Gram-Schmidt) and normalised.
  * Outputs (device): x, hx, t (length n) and scal[0] = theta, scal[1] = ||r||,
- * scal[2] = ||t|| before normalisation.  1 <= k <= kmax <= 32. */
+ * scal[2] = ||t|| before normalisation.  1 <= k <= kmax <= 32.
+ * The last 32*32 + 1 doubles of ws keep all eigenvectors of this call's k x k
+ * eigensolve (row-major 32 x 32, component i of eigenvector j at [32 i + j]) and
+ * then k.  When the next call has k + 1 (the basis grew by one vector), its
+ * Jacobi rotations start from those eigenvectors, bordered by a unit vector, and
+ * need fewer sweeps; they are used only if orthonormal to 1e-12, so any content
+ * of that region gives the same eigenpair up to rounding. */
 int hx_davidson_step(int64_t n, int32_t k, int32_t kmax, const double* V, int64_t ldv,
                      const double* S, int64_t lds, const double* diag, double guard, void* ws,
                      double* x, double* hx, double* t, double* scal, hx_stream stream);

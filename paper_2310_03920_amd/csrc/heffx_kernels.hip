@@ -708,17 +708,27 @@ __global__ __launch_bounds__(DOT_BLOCKS) void dots_pass2(int k, const double* __
 //   [1056, 1088)      c (Gram-Schmidt coefficients)
 //   [1088, 1096)      scalars: theta, |r|^2, |t|^2, ...
 //   [1096, ...)       partial sums (DOT_BLOCKS x KMAX)
+//   then              Q (KMAX x KMAX): eigenvectors of the last eigensolve, columns
+//                     (Q[i][j] = component i of eigenvector j); then k of that solve
 constexpr int64_t DW_G = 0, DW_Y = 1024, DW_C = 1056, DW_S = 1088, DW_P = 1096;
-constexpr int64_t DW_TOTAL = DW_P + (int64_t)DOT_BLOCKS * KMAX;
+constexpr int64_t DW_Q = DW_P + (int64_t)DOT_BLOCKS * KMAX, DW_KQ = DW_Q + (int64_t)KMAX * KMAX;
+constexpr int64_t DW_TOTAL = DW_KQ + 1;
 
 // Lowest eigenpair of the symmetrised k x k projected matrix by Jacobi rotations
 // (one wavefront).  Each step rotates k/2 disjoint index pairs at once (round-robin
 // pairing, k - 1 steps per sweep, a dummy index when k is odd): one lane computes each
 // pair's rotation, then the row and the column updates of all pairs run in parallel.
-// theta -> ws[DW_S], y -> ws[DW_Y..].
+// The rotations start from an orthogonal basis W and act on W^T A W, so the
+// accumulated W R holds the eigenvectors of A for any orthogonal W.  When the last
+// solve was for k - 1 (the basis grew by one vector, the leading block of A is
+// unchanged) W = diag(Q, 1) with that solve's eigenvectors Q: W^T A W is then diagonal
+// but for its last row and column, and few sweeps remain.  Q is used only if its
+// columns are orthonormal to 1e-12; otherwise W = I.
+// theta -> ws[DW_S], y -> ws[DW_Y..]; all eigenvectors -> ws[DW_Q..], k -> ws[DW_KQ].
 __global__ __launch_bounds__(64) void dav_eig(int k, double* ws, double* scal) {
     __shared__ double A[KMAX][KMAX + 1];
     __shared__ double V[KMAX][KMAX + 1];
+    __shared__ double C[KMAX][KMAX + 1];
     __shared__ double rc[KMAX / 2], rs[KMAX / 2];
     __shared__ int rp[KMAX / 2], rq[KMAX / 2];
     const int t = threadIdx.x;
@@ -732,12 +742,53 @@ __global__ __launch_bounds__(64) void dav_eig(int k, double* ws, double* scal) {
         return i == 0 ? 0 : 1 + ((i - 1 - step) % m + m) % m;
     };
     const double* G = ws + DW_G;
+    double* Q = ws + DW_Q;
+    const int kw = (k >= 2 && ws[DW_KQ] == (double)(k - 1)) ? k - 1 : 0;  // warm-start block
     for (int idx = t; idx < k * k; idx += 64) {
         int i = idx / k, j = idx % k;
         A[i][j] = 0.5 * (G[i * KMAX + j] + G[j * KMAX + i]);
-        V[i][j] = (i == j) ? 1.0 : 0.0;
+        V[i][j] = (i < kw && j < kw) ? Q[i * KMAX + j] : (i == j ? 1.0 : 0.0);
     }
     __syncthreads();
+    if (kw > 0) {
+        // W = diag(Q, 1) must be orthogonal: max |W^T W - I|
+        double dev = 0.0;
+        for (int idx = t; idx < k * k; idx += 64) {
+            const int i = idx / k, j = idx % k;
+            double g = 0.0;
+            for (int l = 0; l < k; ++l) g += V[l][i] * V[l][j];
+            dev = fmax(dev, fabs(g - (i == j ? 1.0 : 0.0)));
+        }
+        for (int m = 32; m > 0; m >>= 1) dev = fmax(dev, __shfl_xor(dev, m));
+        if (dev <= 1e-12) {  // (the same on every lane)
+            for (int idx = t; idx < k * k; idx += 64) {  // C = A W
+                const int i = idx / k, j = idx % k;
+                double g = 0.0;
+                for (int l = 0; l < k; ++l) g += A[i][l] * V[l][j];
+                C[i][j] = g;
+            }
+            __syncthreads();
+            for (int idx = t; idx < k * k; idx += 64) {  // A = W^T C (A is free now)
+                const int i = idx / k, j = idx % k;
+                double g = 0.0;
+                for (int l = 0; l < k; ++l) g += V[l][i] * C[l][j];
+                A[i][j] = g;
+            }
+            __syncthreads();
+            for (int idx = t; idx < k * k; idx += 64) {  // symmetrised copy ...
+                const int i = idx / k, j = idx % k;
+                C[i][j] = 0.5 * (A[i][j] + A[j][i]);
+            }
+            __syncthreads();
+            for (int idx = t; idx < k * k; idx += 64) A[idx / k][idx % k] = C[idx / k][idx % k];  // ... back
+        } else {
+            for (int idx = t; idx < k * k; idx += 64) {
+                const int i = idx / k, j = idx % k;
+                V[i][j] = (i == j) ? 1.0 : 0.0;
+            }
+        }
+        __syncthreads();
+    }
     for (int sweep = 0; sweep < 60; ++sweep) {
         double off = 0.0, dia = 0.0;
         for (int idx = t; idx < k * k; idx += 64) {
@@ -807,7 +858,9 @@ __global__ __launch_bounds__(64) void dav_eig(int k, double* ws, double* scal) {
             __syncthreads();
         }
     }
+    for (int idx = t; idx < k * k; idx += 64) Q[(idx / k) * KMAX + idx % k] = V[idx / k][idx % k];
     if (t == 0) {
+        ws[DW_KQ] = (double)k;
         int best = 0;
         for (int i = 1; i < k; ++i)
             if (A[i][i] < A[best][best]) best = i;

@@ -853,6 +853,16 @@ static bool check_gathers(const Plan& P, const std::vector<GatherLaunch>& seq, c
 
 // one_site: the one-site H_eff (Sec. II.A.2) -- the second site is absent, Mo == Ro and
 // e2 is ignored: the right "mixed" operator of middle operator b is R_b itself.
+// Hash of an intermediate's psi-side task signature (groups keep first-seen order,
+// so the plan does not depend on the hash).
+struct SigHash {
+    size_t operator()(const std::vector<int64_t>& v) const {
+        uint64_t h = 1469598103934665603ull;
+        for (int64_t x : v) h = (h ^ (uint64_t)x) * 1099511628211ull;
+        return (size_t)(h ^ (h >> 29));
+    }
+};
+
 static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, const OpSet& Mo,
                       const OpSet& Ro, const std::vector<Entry>& e1, const std::vector<Entry>& e2_in,
                       const hx_plan_opts* opts, bool one_site = false) {
@@ -1082,7 +1092,8 @@ static int build_heff(Plan& P, const Bond& lb, const Bond& rb, const OpSet& Lo, 
             // lengths, order) differ only in the right operator: T_b1 | T_b2 | ... =
             // psi-side product with the stacked operators [a1 Rmix_b1; a2 Rmix_b2; ...].
             // A group becomes one (rows x sum n) matrix; its members are column slices.
-            std::map<std::vector<int64_t>, int> gid;
+            std::unordered_map<std::vector<int64_t>, int, SigHash> gid;
+            gid.reserve(tinfo.size());
             std::vector<std::vector<int>> groups;
             for (int ti = 0; ti < (int)tinfo.size(); ++ti) {
                 const OutBlockTasks& ob = tblocks[ti];

@@ -263,10 +263,15 @@ def test_dots_match_numpy(device):
         np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=1e-13, atol=1e-13 * np.abs(a).sum())
 
 
-def test_davidson_step_matches_oracle(device):
+@pytest.mark.parametrize("tail", ["kept", "garbage", "rotated"])
+def test_davidson_step_matches_oracle(device, tail):
+    """Steps k = 1 .. 8 on a growing basis equal the oracle's Davidson step.  The
+    eigensolve of step k starts from step k-1's eigenvectors kept in the workspace
+    tail; with that tail overwritten by non-orthonormal values (ignored) or by an
+    unrelated orthogonal matrix (a valid start) the results are the same."""
     import torch
     from paper_2310_03920_amd import _lib as X
-    print("[davidson_step]", flush=True)
+    print(f"[davidson_step] tail {tail}", flush=True)
     rng = np.random.default_rng(3)
     n, kmax = 3001, 8
     H = np.diag(np.linspace(-3, 5, n))
@@ -285,7 +290,15 @@ def test_davidson_step_matches_oracle(device):
     V[0], S[0] = v, H @ v
     Vt = torch.from_numpy(V).to(device)
     St = torch.from_numpy(S).to(device)
+    qn = 32 * 32 + 1  # eigenvector tail of the workspace: 32 x 32 row-major, then k
     for k in range(1, kmax + 1):
+        if k >= 3 and tail != "kept":
+            q = np.zeros((32, 32))
+            if tail == "garbage":
+                q[:k - 1, :k - 1] = rng.standard_normal((k - 1, k - 1))
+            else:
+                q[:k - 1, :k - 1] = np.linalg.qr(rng.standard_normal((k - 1, k - 1)))[0]
+            ws[-qn:] = torch.from_numpy(np.append(q.ravel(), k - 1.0)).to(device)
         X.davidson_step(n, k, kmax, Vt, St, dt, 1e-8, ws, x, hx, t, scal)
         theta, rn, xr, hxr, tr, tn = davidson.step(V[:k], S[:k], d, 1e-8)
         sc = scal.cpu().numpy()
