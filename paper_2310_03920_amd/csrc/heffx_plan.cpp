@@ -619,7 +619,7 @@ static void sort_tiles(Plan& P, int64_t t0, int64_t n) {
     // A group of many tiles (a wide block) is cut into runs of at most GMAX
     // consecutive members, so that the XCD queues stay balanced; a run keeps the
     // tiles that share a B panel together (the block's tile order).
-    constexpr int64_t GMAX = 16;
+    constexpr int64_t GMAX = 32;
     {
         std::vector<int64_t> seen(groups.size(), 0);
         std::vector<size_t> sub(groups.size(), SIZE_MAX);  // current run of each group
