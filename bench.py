@@ -43,7 +43,9 @@ PEAKS = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFL
 # for the kernel and plan builder they were taken with; other options report null.
 # (kernel_variant, split_kseg_min, intermediate budget, merged intermediates off)
 MEASURED_TRAFFIC = {(1, 512, 1 << 30, 0): (86.22e9, "profiles/bsgemm_f64_apply_traffic_K36_M1000.md"),
-                    (1, 512, 1 << 31, 0): (85.04e9, "profiles/bsgemm_f64_apply_traffic_K36_M1000.md")}
+                    (1, 512, 1 << 31, 0): (85.04e9, "profiles/bsgemm_f64_apply_traffic_K36_M1000.md"),
+                    (1, 1024, 1 << 30, 0): (85.06e9, "profiles/bsgemm_f64_apply_traffic_K36_M1000.md"),
+                    (1, 1024, 1 << 31, 0): (85.23e9, "profiles/bsgemm_f64_apply_traffic_K36_M1000.md")}
 
 
 def log(*a):
