@@ -197,6 +197,9 @@ class Davidson:
         self.t = torch.zeros(n, **f64)
         self.scal = torch.zeros(4, **f64)
         self.ws = torch.zeros(max(X.davidson_ws_bytes(n, kmax) // 8, 1), **f64)
+        # theta, |r|, |t| of a step, copied to pinned host memory behind an event
+        self._scal_h = torch.zeros(3, dtype=torch.float64, pin_memory=True)
+        self._scal_ev = torch.cuda.Event()
 
     def solve(self, matvec, psi0, diag, tol=1e-8, max_iter=30, guard=1e-8, on_iter=None, thick=True):
         """Lowest eigenpair of the operator `matvec(v, out)`; returns (theta, rnorm, n_matvec).
@@ -218,9 +221,25 @@ class Davidson:
         def step(kk, c):
             X.davidson_step(n, kk, kmax, V, S, diag, guard, self.ws, self.xb[c], self.hxb[c], self.t, self.scal)
 
+        prev_r = None
         for it in range(max_iter):
             step(k, cur)
-            theta, rnorm, tnorm = (float(v) for v in self.scal[:3].cpu())
+            # While the last residual is far above tol, the next expansion (the one
+            # the loop issues next unless it stops here) is queued before the host
+            # reads this step's scalars, so the GPU does not wait for the host's
+            # decision; the iterates are unchanged, and that sigma-vector is wasted
+            # only when this step ends the solve.
+            ahead = k < kmax and it < max_iter - 1 and prev_r is not None and prev_r > 100.0 * tol
+            if ahead:
+                self._scal_h.copy_(self.scal[:3], non_blocking=True)
+                self._scal_ev.record()
+                V[k].copy_(self.t)
+                matvec(V[k], S[k])
+                self._scal_ev.synchronize()
+                theta, rnorm, tnorm = self._scal_h.tolist()
+            else:
+                theta, rnorm, tnorm = (float(v) for v in self.scal[:3].cpu())
+            prev_r = rnorm
             stop = bool(on_iter(it, theta, rnorm)) if on_iter else False
             if stop or rnorm < tol or it == max_iter - 1 or not (tnorm > 1e-14):
                 break
@@ -239,8 +258,9 @@ class Davidson:
                         k = 2
                 cur = 1 - cur
                 step(k, cur)
-            V[k].copy_(self.t)
-            matvec(V[k], S[k])
+            if not ahead:
+                V[k].copy_(self.t)
+                matvec(V[k], S[k])
             nmv += 1
             k += 1
             cur = 1 - cur
