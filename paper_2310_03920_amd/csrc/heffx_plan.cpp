@@ -2508,6 +2508,23 @@ int64_t hx_site_layout(const hx_bond* lbond, const hx_bond* rbond, int64_t max_b
     return n;
 }
 
+// Runs a plan build; a C++ exception (host memory exhausted, or an internal
+// failure) becomes an error code and message instead of crossing the C ABI.
+extern "C++" {
+template <typename F>
+static int guarded(F&& f) {
+    try {
+        return f();
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory while building the plan");
+        return HX_EINVAL;
+    } catch (const std::exception& e) {
+        set_error(std::string("internal: ") + e.what());
+        return HX_EINVAL;
+    }
+}
+}
+
 int hx_heff_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_opset* Lops, const hx_opset* mid,
                         const hx_opset* Rops, const hx_mpo_site* W1, const hx_mpo_site* W2,
                         const hx_plan_opts* opts, hx_plan** out) {
@@ -2525,13 +2542,16 @@ int hx_heff_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_ops
     if (!parse_mpo(W1, Lo, Mo, true, e1, "heff W1") || !parse_mpo(W2, Mo, Ro, false, e2, "heff W2"))
         return HX_EINVAL;
     Plan* P = new Plan();
-    int rc = build_heff(*P, lb, rb, Lo, Mo, Ro, e1, e2, opts);
-    if (rc == HX_OK) rc = check_gemm_bounds(*P);
+    int rc = guarded([&] {
+        int r = build_heff(*P, lb, rb, Lo, Mo, Ro, e1, e2, opts);
+        if (r == HX_OK) r = check_gemm_bounds(*P);
+        if (r == HX_OK) finalize_tables(*P);
+        return r;
+    });
     if (rc != HX_OK) {
         delete P;
         return rc;
     }
-    finalize_tables(*P);
     *out = reinterpret_cast<hx_plan*>(P);
     return HX_OK;
 }
@@ -2550,13 +2570,16 @@ int hx_heff1_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx_op
     std::vector<Entry> e1;
     if (!parse_mpo(W, Lo, Ro, true, e1, "heff1 W")) return HX_EINVAL;
     Plan* P = new Plan();
-    int rc = build_heff(*P, lb, rb, Lo, Ro, Ro, e1, {}, opts, true);
-    if (rc == HX_OK) rc = check_gemm_bounds(*P);
+    int rc = guarded([&] {
+        int r = build_heff(*P, lb, rb, Lo, Ro, Ro, e1, {}, opts, true);
+        if (r == HX_OK) r = check_gemm_bounds(*P);
+        if (r == HX_OK) finalize_tables(*P);
+        return r;
+    });
     if (rc != HX_OK) {
         delete P;
         return rc;
     }
-    finalize_tables(*P);
     *out = reinterpret_cast<hx_plan*>(P);
     return HX_OK;
 }
@@ -2600,13 +2623,16 @@ int hx_heff_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const hx
     std::vector<Entry> e1, e2;
     if (!parse_mpo(W1, Lo, Mo, true, e1, "vjp W1") || !parse_mpo(W2, Mo, Ro, false, e2, "vjp W2")) return HX_EINVAL;
     Plan* P = new Plan();
-    int rc = build_heff_vjp(*P, lb, rb, Lo, Mo, Ro, e1, e2, opts);
-    if (rc == HX_OK) rc = check_gemm_bounds(*P);
+    int rc = guarded([&] {
+        int r = build_heff_vjp(*P, lb, rb, Lo, Mo, Ro, e1, e2, opts);
+        if (r == HX_OK) r = check_gemm_bounds(*P);
+        if (r == HX_OK) finalize_tables(*P);
+        return r;
+    });
     if (rc != HX_OK) {
         delete P;
         return rc;
     }
-    finalize_tables(*P);
     *out = reinterpret_cast<hx_plan*>(P);
     return HX_OK;
 }
@@ -2625,13 +2651,16 @@ int hx_heff1_vjp_plan_create(const hx_bond* lbond, const hx_bond* rbond, const h
     std::vector<Entry> e1;
     if (!parse_mpo(W, Lo, Ro, true, e1, "vjp1 W")) return HX_EINVAL;
     Plan* P = new Plan();
-    int rc = build_heff_vjp(*P, lb, rb, Lo, Ro, Ro, e1, {}, opts, true);
-    if (rc == HX_OK) rc = check_gemm_bounds(*P);
+    int rc = guarded([&] {
+        int r = build_heff_vjp(*P, lb, rb, Lo, Ro, Ro, e1, {}, opts, true);
+        if (r == HX_OK) r = check_gemm_bounds(*P);
+        if (r == HX_OK) finalize_tables(*P);
+        return r;
+    });
     if (rc != HX_OK) {
         delete P;
         return rc;
     }
-    finalize_tables(*P);
     *out = reinterpret_cast<hx_plan*>(P);
     return HX_OK;
 }
@@ -2651,13 +2680,16 @@ int hx_env_plan_create(int direction, const hx_bond* bond_in, const hx_bond* bon
     bool ok = direction == 0 ? parse_mpo(W, oi, oo, true, ents, "env W") : parse_mpo(W, oo, oi, false, ents, "env W");
     if (!ok) return HX_EINVAL;
     Plan* P = new Plan();
-    int rc = build_env(*P, direction, bi, bo, oi, oo, ents, opts);
-    if (rc == HX_OK) rc = check_gemm_bounds(*P);
+    int rc = guarded([&] {
+        int r = build_env(*P, direction, bi, bo, oi, oo, ents, opts);
+        if (r == HX_OK) r = check_gemm_bounds(*P);
+        if (r == HX_OK) finalize_tables(*P);
+        return r;
+    });
     if (rc != HX_OK) {
         delete P;
         return rc;
     }
-    finalize_tables(*P);
     *out = reinterpret_cast<hx_plan*>(P);
     return HX_OK;
 }
@@ -2677,13 +2709,16 @@ int hx_heff_plan_batch(const hx_plan* const* plans, int32_t n, hx_plan** out) {
         in.push_back(reinterpret_cast<const Plan*>(plans[i]));
     }
     Plan* M = new Plan();
-    int rc = merge_plans(in, *M);
-    if (rc == HX_OK) rc = check_gemm_bounds(*M);
+    int rc = guarded([&] {
+        int r = merge_plans(in, *M);
+        if (r == HX_OK) r = check_gemm_bounds(*M);
+        if (r == HX_OK) finalize_tables(*M);
+        return r;
+    });
     if (rc != HX_OK) {
         delete M;
         return rc;
     }
-    finalize_tables(*M);
     *out = reinterpret_cast<hx_plan*>(M);
     return HX_OK;
 }
