@@ -39,7 +39,8 @@
  * device calls are asynchronous on the caller's stream.
  *
  * Errors: every int-returning call returns 0 on success, HX_EINVAL for a
- * malformed table or argument, HX_EHIP for a HIP failure, HX_EUNSUP for an
+ * malformed table or argument (and, from the plan builders, for host memory
+ * exhausted while building), HX_EHIP for a HIP failure, HX_EUNSUP for an
  * unsupported request; hx_last_error() returns a thread-local message.  A device
  * buffer may be NULL exactly when the plan gives it length zero (e.g. psi and
  * sigma of a two-site space with no allowed block: the call is then a no-op).
