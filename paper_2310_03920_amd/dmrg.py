@@ -201,14 +201,17 @@ class Davidson:
         self._scal_h = torch.zeros(3, dtype=torch.float64, pin_memory=True)
         self._scal_ev = torch.cuda.Event()
 
-    def solve(self, matvec, psi0, diag, tol=1e-8, max_iter=30, guard=1e-8, on_iter=None, thick=True):
+    def solve(self, matvec, psi0, diag, tol=1e-8, max_iter=30, guard=1e-8, on_iter=None, thick=True,
+              queue_ahead=True):
         """Lowest eigenpair of the operator `matvec(v, out)`; returns (theta, rnorm, n_matvec).
 
         When the basis is full it restarts from the Ritz vector and, with `thick`,
         also the previous iteration's Ritz vector (orthogonalised against it; its
         H-image follows by linear combination, so the restart costs no
         sigma-vector; skipped when the two are nearly parallel, where that
-        combination would lose precision).  The Ritz vector is left in self.x."""
+        combination would lose precision).  With `queue_ahead`, steps far from
+        convergence queue the next expansion before the host reads their scalars
+        (same iterates).  The Ritz vector is left in self.x."""
         n, kmax = self.n, self.kmax
         V, S = self.V, self.S
         V[0].copy_(psi0)
@@ -229,7 +232,8 @@ class Davidson:
             # reads this step's scalars, so the GPU does not wait for the host's
             # decision; the iterates are unchanged, and that sigma-vector is wasted
             # only when this step ends the solve.
-            ahead = k < kmax and it < max_iter - 1 and prev_r is not None and prev_r > 100.0 * tol
+            ahead = (queue_ahead and k < kmax and it < max_iter - 1 and prev_r is not None
+                     and prev_r > 100.0 * tol)
             if ahead:
                 self._scal_h.copy_(self.scal[:3], non_blocking=True)
                 self._scal_ev.record()

@@ -199,3 +199,46 @@ def test_thick_restart_converges_to_the_same_eigenpair_in_fewer_steps(device):
     mv(d.x, hx)
     assert abs(float(d.x.norm()) - 1.0) < 1e-12
     assert float((hx - e_thick * d.x).norm()) < 2e-9
+
+
+def test_queued_expansion_leaves_the_iterates_unchanged(device):
+    """Queueing a step's expansion before its scalars are read (far from convergence)
+    gives bitwise the same Ritz value, Ritz vector and sigma-vector count as reading
+    them first, through thick restarts (kmax 5)."""
+    import torch
+    from paper_2310_03920_amd import _lib as X
+    from paper_2310_03920_amd.dmrg import Davidson
+    from paper_2310_03920_amd.engine import Engine, site_payload
+    from paper_2310_03920_amd.mpo import build_nc_mpo
+    print("[queued expansion]", flush=True)
+    K, i = 8, 3
+    h, g = make_integrals(K, seed=0)
+    bonds = bond_sector_tables(K, K, 0, 64)
+    left = random_left_canonical_mps(bonds, 1)
+    right = random_right_canonical_mps(bonds, 2)
+    eng = Engine(build_nc_mpo(h, g), device=device)
+    eng.init_boundaries()
+    for k in range(i):
+        eng.update_left(k, bonds[k], bonds[k + 1], site_payload(bonds[k], bonds[k + 1], left[k], device))
+    for k in range(K - 1, i + 1, -1):
+        eng.update_right(k, bonds[k], bonds[k + 1], site_payload(bonds[k], bonds[k + 1], right[k], device))
+    plan = eng.heff_plan(i, bonds[i], bonds[i + 2])
+    L, R = eng.left[i], eng.right[i + 2]
+    n = int(plan.info.psi_nnz)
+    plan.prepare(L, R)
+    diag = torch.empty(n, dtype=torch.float64, device=device)
+    plan.diag(L, R, diag)
+    lb, rb = X.Bond(bonds[i]), X.Bond(bonds[i + 2])
+    psi0 = torch.from_numpy(X.pack_psi(lb, rb, random_psi(bonds[i], bonds[i + 2], np.random.default_rng(5)))).to(device)
+
+    def mv(v, out):
+        plan.apply(L, R, v, out)
+
+    res = {}
+    for ahead in (False, True):
+        d = Davidson(n, 5, device)
+        e, r, nmv = d.solve(mv, psi0, diag, tol=1e-9, max_iter=400, queue_ahead=ahead)
+        res[ahead] = (e, r, nmv, d.x.clone())
+    assert res[True][:3] == res[False][:3]
+    assert torch.equal(res[True][3], res[False][3])
+    assert res[True][1] < 1e-9
