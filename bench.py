@@ -36,6 +36,7 @@ PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_BF16_TFLOPS = 2500.0
 PEAKS = {"f64": PEAK_FP64_TFLOPS, "f32": PEAK_FP32_TFLOPS, "bf16": PEAK_BF16_TFLOPS}
+PEAK_HBM_GBS = 8000.0
 # HBM bytes of one FP64 sigma-vector at the default workload (36 orbitals, M = 1000,
 # middle step) from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by what the counters
 # read for a device copy of known size), per plan options (kernel_variant,
@@ -46,6 +47,10 @@ MEASURED_TRAFFIC = {(1, 512, 1 << 30, 0): (86.22e9, "profiles/bsgemm_f64_apply_t
                     (1, 512, 1 << 31, 0): (85.04e9, "profiles/bsgemm_f64_apply_traffic_K36_M1000.md"),
                     (1, 1024, 1 << 30, 0): (85.06e9, "profiles/bsgemm_f64_apply_traffic_K36_M1000.md"),
                     (1, 1024, 1 << 31, 0): (85.23e9, "profiles/bsgemm_f64_apply_traffic_K36_M1000.md")}
+# The same for one batched sigma-vector of the default batch (16 instances, 16 orbitals,
+# M = 256, every instance in one intermediate chunk), keyed by (kernel_variant,
+# split_kseg_min, merged intermediates off).
+MEASURED_BATCH_TRAFFIC = {(6, 512, 0): (14.67e9, "profiles/bsgemm_batch_16x_K16_M256.md")}
 
 
 def log(*a):
@@ -296,6 +301,10 @@ def bench_batch(args):
     fl = B.info.flops_useful
     peak = PEAKS[args.mode]
     achieved = fl / t_gr / 1e12
+    gbs = B.info.bytes_apply / t_gr / 1e9
+    default_batch = (args.instances, args.orbitals, args.bond_dim, budget) == (16, 16, 256, 1 << 40)
+    traffic = (MEASURED_BATCH_TRAFFIC.get((opts["kernel_variant"], opts["split_kseg_min"], opts.get("t_merge_off", 0)))
+               if args.mode == "f64" and default_batch else None)
     out = {
         "metric": METRIC,
         "value": fl / w_gr / 1e9,
@@ -322,8 +331,14 @@ def bench_batch(args):
         "batch": {"gflop": fl / 1e9, "one_by_one_ms": 1e3 * t_one, "batched_ms": 1e3 * t_bat,
                   "graph_ms": 1e3 * t_gr, "one_by_one_wall_ms": 1e3 * w_one, "batched_wall_ms": 1e3 * w_bat,
                   "graph_wall_ms": 1e3 * w_gr, "speedup_vs_one_by_one": t_one / t_gr},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+        # the batch's arithmetic intensity is below the FP64 ridge: its roof is HBM bandwidth
+        # over its algorithmic bytes (each operand block, psi, sigma and the intermediates once)
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": gbs / PEAK_HBM_GBS, "traffic": traffic[0] if traffic else None,
+                     "traffic_source": traffic[1] if traffic else None,
+                     "traffic_unit": "HBM bytes per batched sigma-vector (rocprofv3 FETCH_SIZE + WRITE_SIZE, stored)",
+                     "bytes_algorithmic": float(B.info.bytes_apply),
+                     "flops": {"achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak},
                      "kernel": "bsgemm (every launch of one batched sigma-vector, graph replay)"},
     }
     print(json.dumps(out), flush=True)
