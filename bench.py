@@ -432,6 +432,10 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
     peak = PEAKS[args.mode]
     achieved = info.flops_useful / avg / 1e12
     parts = middle_bond_parts(args, X, mpo, bonds, i, Lenv, Renv, opts, psi, device) if args.bparts > 1 else None
+    # counter traffic stored for this plan (FP64, the default 36-orbital M = 1000 workload)
+    traffic = (MEASURED_TRAFFIC.get((opts["kernel_variant"], opts["split_kseg_min"], opts["t_budget_bytes"],
+                                     opts.get("t_merge_off", 0)))
+               if args.mode == "f64" and (mpo.K, args.bond_dim) == (36, 1000) and args.partition == "nc" else None)
     calibration_copy(device)
     print(json.dumps({
         "metric": METRIC, "value": info.flops_useful / avg / 1e9, "unit": "GFLOP/s", "n_gpus": 1,
@@ -446,7 +450,8 @@ def apply_only(args, X, mpo, bonds, i, Lenv, Renv, opts, tune_s, device):
                    "chunks": int(info.n_chunks), "tiles": int(info.n_tiles),
                    "apply_ms_each": ms, "plan_opts": opts, "autotune_s": tune_s},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None},
+                     "frac": achieved / peak, "traffic": traffic[0] if traffic else None,
+                     "traffic_source": traffic[1] if traffic else None},
         **({"middle_bond_parts": parts} if parts else {}),
     }), flush=True)
 
