@@ -15,7 +15,7 @@ then
   sigma[l', s1' | s2', r'] += sum_{s1, l} Lhat_b[s1' <- s1][l' <- l] T_b[l, s1 | s2', r'].
 Each block product m x k times k x n is one numpy matmul and is counted as 2 m n k
 floating-point operations (the method's own work: blocks the symmetry forbids,
-zero site-matrix entries and intermediate blocks that round 2 does not read are
+zero site-matrix entries and intermediate blocks that the second product does not read are
 never touched; forming Lhat / Rhat is counted apart).
 `bsel` restricts the sum to a subset of b (the terms of different b are
 independent, so sigma is the sum of the restricted results over a partition of b).
@@ -77,14 +77,14 @@ def heff_apply(lbond, rbond, L, W1e, W2e, R, psi, bsel=None, cols=None, flops=No
         psi_by_s2.setdefault(s2, []).append((il, s1, ir, blk))
     if cols is None:
         cols = sorted({(s2, ir) for (_, _, s2, ir) in psi})
-    # row blocks (il, s1) of T_b that round 2 reads: some left transition of b starts
+    # row blocks (il, s1) of T_b that the second product reads: some left transition of b starts
     # from s1 and its mixed operator has a block with source il
     reads = {b: {(il, si) for (so, si), ops in Lhat[b].items() for il in ops} for b in bs}
     count = 0.0
     sigma = {}
     for (s2p, irp) in cols:
         for b in bs:
-            # round 1: T_b[(il, s1)] for this output column block
+            # first product: T_b[(il, s1)] for this output column block
             T = {}
             for (so, si), ops in Rhat[b].items():
                 if so != s2p:
@@ -104,7 +104,7 @@ def heff_apply(lbond, rbond, L, W1e, W2e, R, psi, bsel=None, cols=None, flops=No
                     T[(il, s1)] = T[(il, s1)] + prod if (il, s1) in T else prod
             if not T:
                 continue
-            # round 2: sigma[(il', s1', s2', ir')] += Lhat_b[s1' <- s1][il' <- il] T_b[(il, s1)]
+            # second product: sigma[(il', s1', s2', ir')] += Lhat_b[s1' <- s1][il' <- il] T_b[(il, s1)]
             for (so, si), ops in Lhat[b].items():
                 for (il, s1), t in T.items():
                     if s1 != si:
