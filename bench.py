@@ -521,7 +521,7 @@ def bench_sweep(args):
     t0 = time.time()
     switch = K // 2 if args.partition == "nc-cn" else None
     d = DMRG(h, g, K, 0, M, seed=0, device="cuda", tol=args.tol, max_iter=args.max_iter, mpo_switch=switch,
-             precision=args.mode)
+             precision=args.mode, kmax=args.kmax)
     torch.cuda.synchronize()
     log(f"set-up (MPO, random MPS, right environments) {time.time() - t0:.1f}s; "
         f"MPO bond dims {[len(x) for x in d.mpo.dq]}")
