@@ -555,6 +555,42 @@ static void split_launch(Plan& P, Launch& L) {
 // their operand blocks, so they form a group kept on one XCD, consecutive in its
 // dispatch order.  Groups are taken by decreasing work (longest first) and each
 // goes to the XCD queue holding the fewest tiles; the queues are then interleaved.
+// Indices 0 .. n-1 by decreasing weight (weights >= 0 and finite), ties in
+// increasing index.  Large inputs use a stable radix sort on the bit patterns
+// (their order is the numeric one for non-negative doubles): the same order as the
+// comparison sort, in linear time.
+static std::vector<size_t> heaviest_first(const std::vector<double>& w) {
+    const size_t n = w.size();
+    std::vector<size_t> idx(n);
+    std::iota(idx.begin(), idx.end(), (size_t)0);
+    if (n < 65536) {
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t a, size_t b) { return w[a] > w[b]; });
+        return idx;
+    }
+    std::vector<uint64_t> key(n), kt(n);
+    std::vector<size_t> it(n);
+    for (size_t i = 0; i < n; ++i) {
+        uint64_t b;
+        std::memcpy(&b, &w[i], sizeof b);
+        key[i] = ~b;  // ascending in ~bits = descending weight
+    }
+    std::vector<size_t> cnt(65537);
+    for (int shift = 0; shift < 64; shift += 16) {
+        std::fill(cnt.begin(), cnt.end(), 0);
+        for (size_t i = 0; i < n; ++i) ++cnt[((key[i] >> shift) & 0xffff) + 1];
+        if (cnt[((key[0] >> shift) & 0xffff) + 1] == n) continue;  // one digit value: order kept
+        for (size_t d = 1; d < cnt.size(); ++d) cnt[d] += cnt[d - 1];
+        for (size_t i = 0; i < n; ++i) {
+            const size_t d = cnt[(key[i] >> shift) & 0xffff]++;
+            it[d] = idx[i];
+            kt[d] = key[i];
+        }
+        idx.swap(it);
+        key.swap(kt);
+    }
+    return idx;
+}
+
 static void sort_tiles(Plan& P, int64_t t0, int64_t n) {
     constexpr int NXCD = 8;
     if (n <= 1) return;
@@ -644,11 +680,9 @@ static void sort_tiles(Plan& P, int64_t t0, int64_t n) {
     for (size_t g = 0; g < groups.size(); ++g) mstart[g + 1] += mstart[g];
     mpos.assign(mstart.begin(), mstart.end() - 1);
     for (int64_t t = 0; t < n; ++t) mlist[mpos[tile_group[t]]++] = t;
-    std::vector<std::pair<double, size_t>> byw(groups.size());  // heaviest first, ties in tile order
-    for (size_t g = 0; g < byw.size(); ++g) byw[g] = {-groups[g].work, g};
-    std::sort(byw.begin(), byw.end());
-    std::vector<size_t> order(groups.size());
-    for (size_t g = 0; g < order.size(); ++g) order[g] = byw[g].second;
+    std::vector<double> gw(groups.size());
+    for (size_t g = 0; g < gw.size(); ++g) gw[g] = groups[g].work;
+    const std::vector<size_t> order = heaviest_first(gw);  // ties in tile order
     std::vector<std::vector<int64_t>> queue(NXCD);
     for (size_t g : order) {
         int q = 0;
