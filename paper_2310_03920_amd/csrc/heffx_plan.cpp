@@ -660,6 +660,7 @@ static void sort_tiles(Plan& P, int64_t t0, int64_t n) {
         std::vector<int64_t> seen(groups.size(), 0);
         std::vector<size_t> sub(groups.size(), SIZE_MAX);  // current run of each group
         std::vector<Group> runs;
+        runs.reserve(groups.size() + (size_t)(n / GMAX));
         for (int64_t t = 0; t < n; ++t) {
             const size_t g = tile_group[t];
             if (seen[g] % GMAX == 0) {
@@ -684,6 +685,7 @@ static void sort_tiles(Plan& P, int64_t t0, int64_t n) {
     for (size_t g = 0; g < gw.size(); ++g) gw[g] = groups[g].work;
     const std::vector<size_t> order = heaviest_first(gw);  // ties in tile order
     std::vector<std::vector<int64_t>> queue(NXCD);
+    for (auto& q : queue) q.reserve((size_t)(n / NXCD) + 256);
     for (size_t g : order) {
         int q = 0;
         for (int x = 1; x < NXCD; ++x)
